@@ -1,0 +1,167 @@
+/*
+ * pfmm.h -- C ABI of the MI355X space-time FMM for the heat equation.
+ *
+ * Operators (Watschinger, Merta, Of, Zapletal, "A parallel fast multipole
+ * method for a space-time boundary element method for the heat equation"):
+ *
+ *   V_h  single-layer Galerkin matrix, piecewise constant in space and time
+ *        (Section 2, matrix V_h; kernel eq. heat_kernel), applied by the
+ *        space-time FMM of Section 3 (Algorithm 2).
+ *   K_h  double-layer Galerkin matrix with the kernel alpha dG/dn_y
+ *        (Section 2, operator K), here with the same piecewise-constant trial
+ *        space as V_h, applied by the same FMM with the source expansion
+ *        differentiated along the normal.
+ *
+ * Vectors are indexed by (k_t - 1) E_x + k_x (time-major, Section 2) with
+ * 0-based steps and triangles: index = step * n_triangles + triangle.
+ *
+ * Every call returns a pfmm_status.  Nothing throws or aborts across the
+ * ABI.  On a non-OK status pfmm_last_error() returns a thread-local message
+ * describing the failure.
+ *
+ * Memory: mesh and time arrays are HOST pointers, copied during
+ * pfmm_build_tree (the caller may free them afterwards).  Vectors passed to
+ * the apply calls are DEVICE pointers on the tree's device.  The tree owns
+ * every device buffer it allocates; applies allocate nothing.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Applies are stream-ordered and asynchronous.  A tree may be used
+ * by one stream at a time; concurrent applies on one tree race.
+ *
+ * Buffer lengths cannot be checked: passing shorter buffers than documented
+ * is undefined behaviour.
+ */
+#ifndef PFMM_H
+#define PFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PFMM_OK = 0,
+    PFMM_EINVAL = -1,        /* invalid argument, parameter or mesh            */
+    PFMM_ENOMEM = -2,        /* host or device allocation failed / over budget */
+    PFMM_EDEVICE = -3,       /* HIP runtime error or no usable gfx950 device   */
+    PFMM_ENOTCONV = -4,      /* iterative solver did not converge              */
+    PFMM_ENONFINITE = -5,    /* non-finite input detected                      */
+    PFMM_EUNSUPPORTED = -6   /* valid input outside what this build supports   */
+} pfmm_status;
+
+typedef enum {
+    PFMM_FP64 = 0            /* farfield and nearfield in FP64                 */
+} pfmm_precision;
+
+/* which operators pfmm_build_tree assembles (bit mask) */
+enum { PFMM_OP_V = 1, PFMM_OP_K = 2 };
+
+typedef struct pfmm_tree pfmm_tree;   /* opaque */
+
+typedef struct {
+    double   alpha;          /* heat capacity constant alpha > 0 (Section 2).       default 1   */
+    int32_t  m_t;            /* Lagrange degree in time, 0..16 (eq. kernel_approx). default 6   */
+    int32_t  m_x;            /* Chebyshev total degree in space, 0..16.             default 6   */
+    int32_t  n_max;          /* refine a box iff it holds >= n_max elements (Alg. 1) default 64 */
+    double   c_st;           /* box-size coupling constant (eq. rel_h_t_h_x).      default 0.9 */
+    int32_t  n_tr;           /* spatial cut, grid distance (eq. 03:Iarea); -1 none. default 5   */
+    int32_t  q_reg;          /* Gauss points per direction, regular panel pairs.   default 4   */
+    int32_t  q_sing;         /* Gauss points per direction, touching panel pairs.  default 5   */
+    int32_t  precision;      /* pfmm_precision.                                    default FP64 */
+    int32_t  operators;      /* PFMM_OP_V | PFMM_OP_K.                             default both */
+    int32_t  check_finite;   /* 1: reject non-finite mesh/time input.              default 1   */
+    int32_t  reserved;
+    uint64_t device_mem_budget; /* bytes the tree may allocate; 0 = 90% of free memory */
+} pfmm_params;
+
+typedef struct {
+    int32_t  depth;              /* largest level of the box cluster tree            */
+    int32_t  n_levels_far;       /* levels >= 2 that carry expansions                */
+    int64_t  boxes;              /* boxes of the tree (all levels)                   */
+    int64_t  leaves;             /* leaf boxes                                       */
+    int64_t  near_entries;       /* stored causal nearfield entries per operator     */
+    int64_t  m2l_pairs;          /* (target, source) pairs of all interaction lists  */
+    int64_t  near_row_groups;    /* (leaf, time step) row groups of the nearfield    */
+    int64_t  distinct_integrals; /* entries of the distinct panel-integral table    */
+    uint64_t device_bytes;       /* device memory owned by the tree                  */
+} pfmm_stats;
+
+/* Fill *out with the default parameters above.  Returns PFMM_EINVAL on NULL. */
+pfmm_status pfmm_default_params(pfmm_params* out);
+
+/*
+ * Build the space-time box cluster tree (Algorithm 1), its nearfield and
+ * interaction lists (eqs. 03:ILtemp, 03:Iarea, def_st_nearfield,
+ * def_st_interaction_list), the expansion tables, and assemble the stored
+ * nearfield blocks of the requested operators on the GPU (Section 3.4,
+ * eq. eval_sl_nf_block).
+ *
+ *  vertices    host, n_vertices x 3 doubles, row-major
+ *  triangles   host, n_triangles x 3 int32, 0-based vertex indices; the
+ *              surface must be closed and consistently oriented (outward
+ *              normals by the right-hand rule)
+ *  time_nodes  host, n_steps + 1 strictly increasing doubles; the steps must
+ *              be uniform (relative deviation <= 1e-12), and n_steps must be
+ *              divisible by 2^depth of the resulting tree, otherwise
+ *              PFMM_EUNSUPPORTED
+ *  p           parameters (NULL = defaults)
+ *  device      HIP device ordinal
+ *  stream      hipStream_t as void* used for the assembly
+ *  out         receives the tree; *out is NULL on failure
+ *
+ * Errors: PFMM_EINVAL (bad arguments/mesh), PFMM_ENONFINITE, PFMM_ENOMEM
+ * (over budget, checked before allocating), PFMM_EDEVICE, PFMM_EUNSUPPORTED.
+ */
+pfmm_status pfmm_build_tree(const double* vertices, int64_t n_vertices,
+                            const int32_t* triangles, int64_t n_triangles,
+                            const double* time_nodes, int64_t n_steps,
+                            const pfmm_params* p, int32_t device, void* stream,
+                            pfmm_tree** out);
+
+/*
+ * f = V_h w by the FMM (Algorithm 2).  w_dev and f_dev are device arrays of
+ * n_steps * n_triangles doubles in the natural order; f is overwritten.
+ * w_dev and f_dev must not alias.  Asynchronous on `stream`.
+ * Errors: PFMM_EINVAL (NULL, or V not built), PFMM_EDEVICE (launch failure).
+ */
+pfmm_status pfmm_apply_V(pfmm_tree* t, const double* w_dev, double* f_dev, void* stream);
+
+/* f = K_h u, same conventions as pfmm_apply_V (K must have been built). */
+pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void* stream);
+
+/* Counts and sizes of a built tree. */
+pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out);
+
+/*
+ * Host-only planning: build the tree and lists of Algorithm 1 / Section 3.3
+ * on the CPU and report their counts, without touching any GPU.  Same
+ * argument conventions as pfmm_build_tree; device_bytes reports the memory a
+ * build would allocate.
+ */
+pfmm_status pfmm_plan_stats(const double* vertices, int64_t n_vertices,
+                            const int32_t* triangles, int64_t n_triangles,
+                            const double* time_nodes, int64_t n_steps,
+                            const pfmm_params* p, pfmm_stats* out);
+
+/*
+ * Stage timing with HIP events recorded on the apply stream.  When enabled,
+ * each apply records an event pair around every stage; pfmm_profile_read
+ * synchronises those events and returns accumulated milliseconds and launch
+ * counts per stage (indices: 0 permute, 1 S2M, 2 M2M, 3 M2L, 4 L2L, 5 L2T,
+ * 6 nearfield, 7 unpermute), then resets them.  n_stages receives 8.
+ */
+pfmm_status pfmm_profile_enable(pfmm_tree* t, int32_t enable);
+pfmm_status pfmm_profile_read(pfmm_tree* t, double* ms, int64_t* counts, int32_t* n_stages);
+
+/* Release every host and device resource of the tree.  NULL is a no-op. */
+void pfmm_destroy(pfmm_tree* t);
+
+/* Thread-local message for the last non-OK status on this thread ("" if none). */
+const char* pfmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFMM_H */

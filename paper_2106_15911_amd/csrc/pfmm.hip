@@ -1,0 +1,1198 @@
+// MI355X (gfx950) space-time FMM for the heat equation: device kernels and
+// the C ABI declared in include/pfmm.h.
+//
+// Apply pipeline (Algorithm 2 of the paper), all on one stream:
+//   permute w into tree order (time-major, spatially sorted triangles)
+//   S2M on leaves, M2M for levels p-1..2, M2L for levels 2..p,
+//   L2L for levels 3..p, L2T on leaves (overwrites f),
+//   nearfield product over the stored causal blocks (adds to f),
+//   permute f back to the natural order.
+// Everything is FP64.  Each output value is owned by exactly one thread, so
+// applies are deterministic (no floating-point atomics).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "near_kernels.hpp"
+#include "pfmm.h"
+#include "plan.hpp"
+#include "tables.hpp"
+
+using namespace pfmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+pfmm_status fail(pfmm_status s, const std::string& m) {
+    g_err = m;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(PFMM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr int kChunk = 32;          // M2L output rows per wave
+constexpr int kWave = 64;
+
+// number of multi-indices in N^3 with total degree <= n
+__device__ __forceinline__ int pfmm_binom3(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
+
+// ------------------------------------------------------------------ permutations
+
+__global__ void k_permute_in(const double* __restrict__ w, double* __restrict__ wd,
+                             const int* __restrict__ inv_sigma, int E_x, int64_t N) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int64_t t = i / E_x;
+    int p = (int)(i - t * E_x);
+    wd[i] = w[t * E_x + inv_sigma[p]];
+}
+
+__global__ void k_permute_out(const double* __restrict__ fd, double* __restrict__ f,
+                              const int* __restrict__ sigma, int E_x, int64_t N) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int64_t t = i / E_x;
+    int k = (int)(i - t * E_x);
+    f[i] = fd[t * E_x + sigma[k]];
+}
+
+__global__ void k_fill(double* __restrict__ x, double v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+// ------------------------------------------------------------------ far field
+
+struct CoefMaps {
+    const int* coef_a;      // Nc
+    const int* coef_deg;    // Nc
+    const int* coef_k;      // Nc x 3
+    const int* coef_kpos;   // Nc: position of the multi-index in the Nk list
+    const int* kidx;        // Nk x 3 (degree-sorted multi-indices)
+    const int* kposmap;     // (m+1)^3 -> position in the Nk list
+    const int* cidx;        // (m_t+1) x Nk -> coefficient index
+    int Nc, Nk, mt, mx;
+};
+
+// S2M (eq. s2m): mu[a, kappa] = sum_{elements} w A_t[j][a] A_x[r][kappa].
+__global__ void k_s2m(const double* __restrict__ wd, double* __restrict__ mu,
+                      const int* __restrict__ leaf_xs, const int64_t* __restrict__ ax_off,
+                      const int* __restrict__ tb, const int* __restrict__ te,
+                      const double* __restrict__ At, const double* __restrict__ Ax, CoefMaps cm,
+                      int n_int, int steps, int E_x) {
+    const int li = blockIdx.x / n_int, k = blockIdx.x % n_int;
+    const int xs = leaf_xs[li];
+    const int t0 = tb[xs], nX = te[xs] - t0;
+    const int s0 = k * steps;
+    const double* A = Ax + ax_off[li];
+    const double* T = At + (int64_t)k * steps * (cm.mt + 1);
+    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
+        const int a = cm.coef_a[c], kp = cm.coef_kpos[c];
+        double acc = 0.0;
+        for (int j = 0; j < steps; ++j) {
+            const double* wrow = wd + (int64_t)(s0 + j) * E_x + t0;
+            double sp = 0.0;
+            for (int r = 0; r < nX; ++r) sp += wrow[r] * A[(int64_t)r * cm.Nk + kp];
+            acc += T[j * (cm.mt + 1) + a] * sp;
+        }
+        mu[((int64_t)xs * cm.Nc + c) * n_int + k] = acc;
+    }
+}
+
+// M2M (eqs. temp_m2m, st_m2m) from level l+1 into the non-leaf boxes of level l.
+// qt: child level table [n_int_c][a_c][a_p]; qx: child slot tables [3][kappa][nu].
+__global__ void k_m2m(const double* __restrict__ mu_c, double* __restrict__ mu_p,
+                      const int* __restrict__ par_xs, const int* __restrict__ ch_ptr, const int* __restrict__ ch,
+                      const double* __restrict__ qt, const double* __restrict__ qx, CoefMaps cm,
+                      int n_int_p, int n_int_c) {
+    extern __shared__ double sm[];
+    double* sc = sm;                 // child moments, Nc
+    double* st = sm + cm.Nc;         // temporally transformed, Nc
+    double* so = sm + 2 * cm.Nc;     // parent moments being accumulated, Nc
+    const int pi = blockIdx.x / n_int_p, k = blockIdx.x % n_int_p;
+    const int xs = par_xs[pi];
+    const int nt1 = cm.mt + 1, nx1 = cm.mx + 1;
+    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) so[c] = 0.0;
+    for (int ci = ch_ptr[xs]; ci < ch_ptr[xs + 1]; ++ci) {
+        const int xc = ch[ci];
+        const double* Q = qx + (int64_t)xc * 3 * nx1 * nx1;
+        for (int b = 0; b < 2; ++b) {
+            const int kc = 2 * k + b;
+            __syncthreads();
+            for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) sc[c] = mu_c[((int64_t)xc * cm.Nc + c) * n_int_c + kc];
+            __syncthreads();
+            const double* q = qt + (int64_t)kc * nt1 * nt1;
+            for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
+                const int ap = cm.coef_a[c], kp = cm.coef_kpos[c];
+                double s = 0.0;
+                for (int ac = 0; ac < nt1; ++ac) s += q[ac * nt1 + ap] * sc[cm.cidx[ac * cm.Nk + kp]];
+                st[c] = s;
+            }
+            __syncthreads();
+            for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
+                const int ap = cm.coef_a[c];
+                const int n1 = cm.coef_k[3 * c], n2 = cm.coef_k[3 * c + 1], n3 = cm.coef_k[3 * c + 2];
+                double s = 0.0;
+                for (int k1 = 0; k1 <= n1; ++k1) {
+                    const double q1 = Q[k1 * nx1 + n1];
+                    for (int k2 = 0; k2 <= n2; ++k2) {
+                        const double q12 = q1 * Q[nx1 * nx1 + k2 * nx1 + n2];
+                        for (int k3 = 0; k3 <= n3; ++k3) {
+                            const int kp = cm.kposmap[(k1 * nx1 + k2) * nx1 + k3];
+                            s += q12 * Q[2 * nx1 * nx1 + k3 * nx1 + n3] * st[cm.cidx[ap * cm.Nk + kp]];
+                        }
+                    }
+                }
+                so[c] += s;
+            }
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x)
+        mu_p[((int64_t)xs * cm.Nc + c) * n_int_p + k] = so[c];
+}
+
+// M2L operator generation: op[(class, Delta)][chunk][c_in][r] =
+//   C_ab prod_j E_{kappa_j, nu_j}(r_j, d_ab)  if |kappa| + |nu| <= m_x  (eq. exp_coeffs_3d)
+__global__ void k_m2l_opgen(double* __restrict__ ops, const double* __restrict__ E1, const double* __restrict__ Cab,
+                            const int* __restrict__ off3, const int* __restrict__ chunk_cols,
+                            const int64_t* __restrict__ chunk_off, CoefMaps cm, int n_chunks, int64_t op_size,
+                            int R, int64_t total) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int64_t opi = i / op_size;
+    int64_t e = i - opi * op_size;
+    int j = 0;
+    while (j + 1 < n_chunks && chunk_off[j + 1] <= e) ++j;
+    e -= chunk_off[j];
+    const int cin = (int)(e / kChunk), rr = (int)(e % kChunk);
+    const int row = j * kChunk + rr;
+    const int cls = (int)(opi / 2), D = (int)(opi % 2);
+    double v = 0.0;
+    if (row < cm.Nc && cin < chunk_cols[j]) {
+        const int b = cm.coef_a[row], a = cm.coef_a[cin];
+        if (cm.coef_deg[row] + cm.coef_deg[cin] <= cm.mx) {
+            const int nt1 = cm.mt + 1, nx1 = cm.mx + 1, nR = 2 * R + 1;
+            v = Cab[((int64_t)D * nt1 + a) * nt1 + b];
+            for (int ax = 0; ax < 3; ++ax) {
+                const int o = off3[3 * cls + ax] + R;
+                const double* E = E1 + ((((int64_t)D * nR + o) * nt1 + a) * nt1 + b) * nx1 * nx1;
+                v *= E[cm.coef_k[3 * cin + ax] * nx1 + cm.coef_k[3 * row + ax]];
+            }
+        }
+    }
+    ops[i] = v;
+}
+
+// M2L (eq. m2l): lambda[X, rows of chunk, k] = sum over sources (Y, Delta) of
+// op(X-Y, Delta)[rows, c] * mu[Y, c, k - Delta].  One wave per
+// (target slot, 64 intervals, 32-row chunk); lane = interval.
+__global__ void __launch_bounds__(64) k_m2l(const double* __restrict__ mu, double* __restrict__ lam,
+                                            const double* __restrict__ ops, const int* __restrict__ ptr,
+                                            const int* __restrict__ src, const int* __restrict__ cls,
+                                            const int* __restrict__ chunk_cols, const int64_t* __restrict__ chunk_off,
+                                            int Nc, int n_int, int64_t op_size) {
+    const int xs = blockIdx.x;
+    const int k = blockIdx.y * kWave + threadIdx.x;
+    const int j = blockIdx.z;
+    const int ncol = chunk_cols[j];
+    double acc[kChunk];
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) acc[r] = 0.0;
+    for (int s = ptr[xs]; s < ptr[xs + 1]; ++s) {
+        const int ys = src[s];
+        const int oc = cls[s];
+        for (int D = 2; D <= 3; ++D) {
+            const int ks = k - D;
+            const bool valid = (k < n_int) && (ks >= 0) && (D == 2 || (k & 1));
+            const double* op = ops + (int64_t)(2 * oc + (D - 2)) * op_size + chunk_off[j];
+            const double* m = mu + (int64_t)ys * Nc * n_int + (valid ? ks : 0);
+            for (int c = 0; c < ncol; ++c) {
+                const double mv = valid ? m[(int64_t)c * n_int] : 0.0;
+                const double* o = op + c * kChunk;
+#pragma unroll
+                for (int r = 0; r < kChunk; ++r) acc[r] = fma(o[r], mv, acc[r]);
+            }
+        }
+    }
+    if (k < n_int) {
+#pragma unroll
+        for (int r = 0; r < kChunk; ++r) {
+            const int row = j * kChunk + r;
+            if (row < Nc) lam[((int64_t)xs * Nc + row) * n_int + k] = acc[r];
+        }
+    }
+}
+
+// L2L (transpose of eqs. temp_m2m / st_m2m) from level l-1 into every box of level l.
+__global__ void k_l2l(const double* __restrict__ lam_p, double* __restrict__ lam_c, const int* __restrict__ parent,
+                      const double* __restrict__ qt, const double* __restrict__ qx, CoefMaps cm,
+                      int n_int_c, int n_int_p) {
+    extern __shared__ double sm[];
+    double* sp = sm;             // parent locals
+    double* ss = sm + cm.Nc;     // spatially transformed
+    const int xs = blockIdx.x / n_int_c, k = blockIdx.x % n_int_c;
+    const int ps = parent[xs], kp = k >> 1;
+    const int nt1 = cm.mt + 1, nx1 = cm.mx + 1;
+    const double* Q = qx + (int64_t)xs * 3 * nx1 * nx1;
+    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) sp[c] = lam_p[((int64_t)ps * cm.Nc + c) * n_int_p + kp];
+    __syncthreads();
+    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
+        const int bp = cm.coef_a[c], deg = cm.coef_deg[c];
+        const int n1 = cm.coef_k[3 * c], n2 = cm.coef_k[3 * c + 1], n3 = cm.coef_k[3 * c + 2];
+        const int nd = pfmm_binom3(cm.mx - deg);
+        double s = 0.0;
+        for (int di = 0; di < nd; ++di) {
+            const int p1 = n1 + cm.kidx[3 * di], p2 = n2 + cm.kidx[3 * di + 1], p3 = n3 + cm.kidx[3 * di + 2];
+            const double q = Q[n1 * nx1 + p1] * Q[nx1 * nx1 + n2 * nx1 + p2] * Q[2 * nx1 * nx1 + n3 * nx1 + p3];
+            s += q * sp[cm.cidx[bp * cm.Nk + cm.kposmap[(p1 * nx1 + p2) * nx1 + p3]]];
+        }
+        ss[c] = s;
+    }
+    __syncthreads();
+    const double* q = qt + (int64_t)k * nt1 * nt1;
+    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
+        const int bc = cm.coef_a[c], kp2 = cm.coef_kpos[c];
+        double s = 0.0;
+        for (int bp = 0; bp < nt1; ++bp) s += q[bc * nt1 + bp] * ss[cm.cidx[bp * cm.Nk + kp2]];
+        lam_c[((int64_t)xs * cm.Nc + c) * n_int_c + k] += s;
+    }
+}
+
+// L2T (eq. l2t): f at the elements of a leaf (overwrites f).
+__global__ void k_l2t(const double* __restrict__ lam, double* __restrict__ fd,
+                      const int* __restrict__ leaf_xs, const int64_t* __restrict__ ax_off,
+                      const int* __restrict__ tb, const int* __restrict__ te,
+                      const double* __restrict__ At, const double* __restrict__ Ax, CoefMaps cm,
+                      int n_int, int steps, int E_x) {
+    extern __shared__ double sm[];
+    const int li = blockIdx.x / n_int, k = blockIdx.x % n_int;
+    const int xs = leaf_xs[li];
+    const int t0 = tb[xs], nX = te[xs] - t0;
+    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) sm[c] = lam[((int64_t)xs * cm.Nc + c) * n_int + k];
+    __syncthreads();
+    const double* A = Ax + ax_off[li];
+    const double* T = At + (int64_t)k * steps * (cm.mt + 1);
+    const int nt1 = cm.mt + 1;
+    for (int e = threadIdx.x; e < steps * nX; e += blockDim.x) {
+        const int j = e / nX, r = e % nX;
+        double acc = 0.0;
+        for (int b = 0; b < nt1; ++b) {
+            double sp = 0.0;
+            for (int kp = 0; kp < cm.Nk; ++kp) sp += sm[cm.cidx[b * cm.Nk + kp]] * A[(int64_t)r * cm.Nk + kp];
+            acc += T[j * nt1 + b] * sp;
+        }
+        fd[(int64_t)(k * steps + j) * E_x + t0 + r] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ nearfield
+
+struct NearGeom {
+    const double* verts;    // natural vertices
+    const int* tris;        // natural triangles
+    const double* area;
+    const double* normal;
+    const double* centroid;
+    const double* maxedge;
+    const int* inv_sigma;   // position -> natural triangle
+    double h, alpha;
+};
+
+struct GroupDev {
+    int tb, te, dmax, usize;
+    int64_t uoff, toff, mapoff;
+};
+
+__device__ __forceinline__ void tri_vertices(const NearGeom& G, int t, double P[3][3]) {
+    for (int v = 0; v < 3; ++v) {
+        const double* x = G.verts + 3 * G.tris[3 * t + v];
+        P[v][0] = x[0]; P[v][1] = x[1]; P[v][2] = x[2];
+    }
+}
+
+__device__ __forceinline__ bool coplanar(const NearGeom& G, int a, int b) {
+    const double* na = G.normal + 3 * a;
+    const double* nb = G.normal + 3 * b;
+    const double* ca = G.centroid + 3 * a;
+    const double* cb = G.centroid + 3 * b;
+    const double L = fmax(G.maxedge[a], G.maxedge[b]);
+    const double dn = na[0] * nb[0] + na[1] * nb[1] + na[2] * nb[2];
+    const double dc = (ca[0] - cb[0]) * nb[0] + (ca[1] - cb[1]) * nb[1] + (ca[2] - cb[2]) * nb[2];
+    return fabs(1.0 - fabs(dn)) < 1e-10 && fabs(dc) < 1e-10 * L;
+}
+
+// Regular panel pairs: tensor collapsed-Gauss rule, all d = 0..dmax.
+template <bool K, int DMAX>
+__global__ void k_near_regular(double* __restrict__ table, const GroupDev* __restrict__ groups,
+                               const int* __restrict__ blk_group, const int64_t* __restrict__ blk_base,
+                               const int* __restrict__ upos, NearGeom G, QuadRules Q) {
+    const int g = blk_group[blockIdx.x];
+    const GroupDev gr = groups[g];
+    const int nX = gr.te - gr.tb;
+    const int64_t idx = blk_base[blockIdx.x] + threadIdx.x;
+    if (idx >= (int64_t)nX * gr.usize) return;
+    const int r = (int)(idx / gr.usize), u = (int)(idx % gr.usize);
+    const int kx = G.inv_sigma[gr.tb + r];
+    const int jx = G.inv_sigma[upos[gr.uoff + u]];
+    double acc[DMAX + 1];
+#pragma unroll
+    for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0;
+    if (kx != jx && !(K && coplanar(G, kx, jx))) {
+        double P[3][3], S[3][3];
+        tri_vertices(G, kx, P);
+        tri_vertices(G, jx, S);
+        const double* ny = G.normal + 3 * jx;
+        const double aP = 2.0 * G.area[kx], aS = 2.0 * G.area[jx];
+        const int q = Q.q_reg;
+        for (int i1 = 0; i1 < q; ++i1)
+            for (int j1 = 0; j1 < q; ++j1) {
+                const double s1 = Q.g_reg[i1], t1 = Q.g_reg[i1] * Q.g_reg[j1];
+                const double w1 = aP * (Q.w_reg[i1] * Q.w_reg[j1] * Q.g_reg[i1]);
+                double x[3];
+                for (int c = 0; c < 3; ++c) x[c] = P[0][c] + s1 * (P[1][c] - P[0][c]) + t1 * (P[2][c] - P[1][c]);
+                for (int i2 = 0; i2 < q; ++i2)
+                    for (int j2 = 0; j2 < q; ++j2) {
+                        const double s2 = Q.g_reg[i2], t2 = Q.g_reg[i2] * Q.g_reg[j2];
+                        const double w2 = aS * (Q.w_reg[i2] * Q.w_reg[j2] * Q.g_reg[i2]);
+                        double dv[3];
+                        for (int c = 0; c < 3; ++c) dv[c] = x[c] - (S[0][c] + s2 * (S[1][c] - S[0][c]) + t2 * (S[2][c] - S[1][c]));
+                        accumulate_point<K, DMAX>(acc, dv, ny, w1 * w2, gr.dmax, G.h, G.alpha, Q);
+                    }
+            }
+    }
+    double* out = table + gr.toff;
+    for (int d = 0; d <= gr.dmax && d <= DMAX; ++d) out[((int64_t)d * nX + r) * gr.usize + u] = acc[d];
+}
+
+struct TouchDev { int group, r, u, nshared; };
+
+__constant__ double c_edge_tets[6][3][3] = {
+    {{0, 1, 0}, {1, 0, 0}, {1, 0, 1}},
+    {{0, 1, 0}, {1, 0, 1}, {0, 1, 1}},
+    {{0, 0, 1}, {1, 0, 1}, {0, 1, 1}},
+    {{0, 1, 0}, {-1, 1, 0}, {0, 1, 1}},
+    {{0, 0, 1}, {-1, 0, 0}, {-1, 1, 0}},
+    {{0, 0, 1}, {-1, 1, 0}, {0, 1, 1}},
+};
+__constant__ double c_hex[6][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 0}, {-1, -1}, {0, -1}};
+
+// Touching panel pairs: identical (all d), common edge / vertex (d = 0, 1).
+template <bool K, int DMAX>
+__global__ void k_near_singular(double* __restrict__ table, const GroupDev* __restrict__ groups,
+                                const TouchDev* __restrict__ touch, int n_touch, const int* __restrict__ upos,
+                                NearGeom G, QuadRules Q) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_touch) return;
+    const TouchDev tp = touch[i];
+    const GroupDev gr = groups[tp.group];
+    const int nX = gr.te - gr.tb;
+    const int kx = G.inv_sigma[gr.tb + tp.r];
+    const int jx = G.inv_sigma[upos[gr.uoff + tp.u]];
+    const int dlast = (tp.nshared == 3) ? gr.dmax : min(1, gr.dmax);
+    double acc[DMAX + 1];
+#pragma unroll
+    for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0;
+    const double* ny = G.normal + 3 * jx;
+    const int q = Q.q_sing;
+    if (!(K && coplanar(G, kx, jx))) {
+        const int* ta = G.tris + 3 * kx;
+        const int* tb = G.tris + 3 * jx;
+        if (tp.nshared == 3) {
+            double P[3][3];
+            tri_vertices(G, kx, P);
+            const double a2 = 2.0 * G.area[kx];
+            for (int sct = 0; sct < 6; ++sct) {
+                const double va0 = c_hex[sct][0], va1 = c_hex[sct][1];
+                const double vb0 = c_hex[(sct + 1) % 6][0], vb1 = c_hex[(sct + 1) % 6][1];
+                for (int ir = 0; ir < q; ++ir)
+                    for (int iu = 0; iu < q; ++iu) {
+                        const double rho = Q.g_sing[ir], u = Q.g_sing[iu];
+                        const double z1 = rho * (va0 + u * (vb0 - va0));
+                        const double z2 = rho * (va1 + u * (vb1 - va1));
+                        double dv[3];
+                        for (int c = 0; c < 3; ++c) dv[c] = -(z1 * (P[1][c] - P[0][c]) + z2 * (P[2][c] - P[1][c]));
+                        const double W = a2 * a2 * 0.5 * (1.0 - rho) * (1.0 - rho) * rho * (Q.w_sing[ir] * Q.w_sing[iu]);
+                        accumulate_point<K, DMAX>(acc, dv, ny, W, dlast, G.h, G.alpha, Q);
+                    }
+            }
+        } else if (tp.nshared == 2) {
+            int ia = 0;
+            for (int v = 0; v < 3; ++v) {
+                bool sh = false;
+                for (int w = 0; w < 3; ++w) sh |= ta[v] == tb[w];
+                if (!sh) ia = v;
+            }
+            int q2 = 0;
+            for (int w = 0; w < 3; ++w) {
+                bool sh = false;
+                for (int v = 0; v < 3; ++v) sh |= tb[w] == ta[v];
+                if (!sh) q2 = tb[w];
+            }
+            const double* E0 = G.verts + 3 * ta[(ia + 1) % 3];
+            const double* E1 = G.verts + 3 * ta[(ia + 2) % 3];
+            const double* P2 = G.verts + 3 * ta[ia];
+            const double* Q2 = G.verts + 3 * q2;
+            double e[3], c1[3], c2[3];
+            for (int c = 0; c < 3; ++c) { e[c] = E1[c] - E0[c]; c1[c] = P2[c] - E1[c]; c2[c] = Q2[c] - E1[c]; }
+            const double aa = 2.0 * G.area[kx] * 2.0 * G.area[jx];
+            for (int tt = 0; tt < 6; ++tt) {
+                const double (*tv)[3] = c_edge_tets[tt];
+                const double det = fabs(tv[0][0] * (tv[1][1] * tv[2][2] - tv[1][2] * tv[2][1])
+                                        - tv[0][1] * (tv[1][0] * tv[2][2] - tv[1][2] * tv[2][0])
+                                        + tv[0][2] * (tv[1][0] * tv[2][1] - tv[1][1] * tv[2][0]));
+                for (int ir = 0; ir < q; ++ir)
+                    for (int i1 = 0; i1 < q; ++i1)
+                        for (int i2 = 0; i2 < q; ++i2) {
+                            const double rho = Q.g_sing[ir], u1 = Q.g_sing[i1], u2 = Q.g_sing[i2];
+                            double p[3];
+                            for (int c = 0; c < 3; ++c)
+                                p[c] = rho * (tv[0][c] + u1 * (tv[1][c] - tv[0][c]) + (u1 * u2) * (tv[2][c] - tv[1][c]));
+                            double dv[3];
+                            for (int c = 0; c < 3; ++c) dv[c] = -p[0] * e[c] + p[1] * c1[c] - p[2] * c2[c];
+                            const double W = aa * det * (1.0 - rho) * rho * rho * u1 * (Q.w_sing[ir] * Q.w_sing[i1] * Q.w_sing[i2]);
+                            accumulate_point<K, DMAX>(acc, dv, ny, W, dlast, G.h, G.alpha, Q);
+                        }
+            }
+        } else {
+            int va = 0, vb = 0;
+            for (int v = 0; v < 3; ++v)
+                for (int w = 0; w < 3; ++w)
+                    if (ta[v] == tb[w]) { va = v; vb = w; }
+            const double* V0 = G.verts + 3 * ta[va];
+            const double* P1 = G.verts + 3 * ta[(va + 1) % 3];
+            const double* P2 = G.verts + 3 * ta[(va + 2) % 3];
+            const double* Q1 = G.verts + 3 * tb[(vb + 1) % 3];
+            const double* Q2 = G.verts + 3 * tb[(vb + 2) % 3];
+            double a1[3], b1[3], a2[3], b2[3];
+            for (int c = 0; c < 3; ++c) { a1[c] = P1[c] - V0[c]; b1[c] = P2[c] - P1[c]; a2[c] = Q1[c] - V0[c]; b2[c] = Q2[c] - Q1[c]; }
+            const double aa = 2.0 * G.area[kx] * 2.0 * G.area[jx];
+            for (int ix = 0; ix < q; ++ix)
+                for (int ie = 0; ie < q; ++ie)
+                    for (int i1 = 0; i1 < q; ++i1)
+                        for (int i2 = 0; i2 < q; ++i2) {
+                            const double xi = Q.g_sing[ix], eta = Q.g_sing[ie];
+                            const double u1 = Q.g_sing[i1], u2 = Q.g_sing[i2];
+                            const double W = aa * xi * xi * xi * eta *
+                                             (Q.w_sing[ix] * Q.w_sing[ie] * Q.w_sing[i1] * Q.w_sing[i2]);
+                            double A1[3], A2[3], dA[3], dB[3];
+                            for (int c = 0; c < 3; ++c) {
+                                A1[c] = a1[c] + u1 * b1[c];
+                                A2[c] = a2[c] + u2 * b2[c];
+                                dA[c] = xi * (A1[c] - eta * A2[c]);
+                                dB[c] = xi * (eta * A1[c] - A2[c]);
+                            }
+                            accumulate_point<K, DMAX>(acc, dA, ny, W, dlast, G.h, G.alpha, Q);
+                            accumulate_point<K, DMAX>(acc, dB, ny, W, dlast, G.h, G.alpha, Q);
+                        }
+        }
+    }
+    double* out = table + gr.toff;
+    for (int d = 0; d <= dlast && d <= DMAX; ++d) out[((int64_t)d * nX + tp.r) * gr.usize + tp.u] = acc[d];
+}
+
+struct NearLayout {
+    const int* rg_leaf;      // row group -> leaf
+    const int* rg_kt;
+    const int64_t* rg_boff;
+    const int* lf_tb;        // leaf -> first triangle position
+    const int* lf_nx;
+    const int* lf_rect0;
+    const int* lf_rect1;
+    const int* lf_group;
+    const int* rc_j0;
+    const int* rc_j1;
+    const int* rc_set;
+    const int* set_off;
+    const int* set_size;
+    const int* set_pos;
+    int E_x;
+    int64_t n_rows;
+};
+
+// Expand the distinct-integral table into the causal block storage:
+// B[boff + c * nX + r] = T[d = kt - jt][r][u(y)].  One wave per row group.
+__global__ void __launch_bounds__(256) k_near_expand(double* __restrict__ B, const double* __restrict__ table,
+                                                     const GroupDev* __restrict__ groups, const int* __restrict__ umap,
+                                                     NearLayout L) {
+    const int64_t rg = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (rg >= L.n_rows) return;
+    const int lane = threadIdx.x % kWave;
+    const int leaf = L.rg_leaf[rg], kt = L.rg_kt[rg];
+    const int nX = L.lf_nx[leaf];
+    const int cpi = kWave / nX;
+    const int cs = lane / nX, r = lane % nX;
+    if (cs >= cpi) return;
+    const GroupDev gr = groups[L.lf_group[leaf]];
+    const int* um = umap + gr.mapoff;
+    const double* T = table + gr.toff;
+    double* out = B + L.rg_boff[rg];
+    int64_t colbase = 0;
+    for (int q = L.lf_rect0[leaf]; q < L.lf_rect1[leaf]; ++q) {
+        const int j0 = L.rc_j0[q];
+        const int ns = min(L.rc_j1[q], kt + 1) - j0;
+        if (ns <= 0) continue;
+        const int S = L.set_size[L.rc_set[q]];
+        const int* pos = L.set_pos + L.set_off[L.rc_set[q]];
+        const int64_t total = (int64_t)ns * S;
+        int jt = j0, i = cs;
+        while (i >= S) { i -= S; ++jt; }
+        for (int64_t c = cs; c < total; c += cpi) {
+            const int d = kt - jt;
+            out[(colbase + c) * nX + r] = T[((int64_t)d * nX + r) * gr.usize + um[pos[i]]];
+            i += cpi;
+            while (i >= S) { i -= S; ++jt; }
+        }
+        colbase += total;
+    }
+}
+
+// Nearfield product f[kt, rows] += B * w over the causal columns.  One wave
+// per row group; lane = (column slot, row); partial sums reduced in LDS.
+__global__ void __launch_bounds__(256) k_near_apply(const double* __restrict__ B, const double* __restrict__ wd,
+                                                    double* __restrict__ fd, NearLayout L) {
+    __shared__ double red[256];
+    const int wv = threadIdx.x / kWave;
+    const int64_t rg = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
+    const int lane = threadIdx.x % kWave;
+    double acc = 0.0;
+    int nX = 1, cpi = 64, r = 0, cs = 0, kt = 0, t0 = 0;
+    if (rg < L.n_rows) {
+        const int leaf = L.rg_leaf[rg];
+        kt = L.rg_kt[rg];
+        nX = L.lf_nx[leaf];
+        t0 = L.lf_tb[leaf];
+        cpi = kWave / nX;
+        cs = lane / nX;
+        r = lane % nX;
+        if (cs < cpi) {
+            const double* blk = B + L.rg_boff[rg];
+            int64_t colbase = 0;
+            for (int q = L.lf_rect0[leaf]; q < L.lf_rect1[leaf]; ++q) {
+                const int j0 = L.rc_j0[q];
+                const int ns = min(L.rc_j1[q], kt + 1) - j0;
+                if (ns <= 0) continue;
+                const int S = L.set_size[L.rc_set[q]];
+                const int* pos = L.set_pos + L.set_off[L.rc_set[q]];
+                const int64_t total = (int64_t)ns * S;
+                int jt = j0, i = cs;
+                while (i >= S) { i -= S; ++jt; }
+                for (int64_t c = cs; c < total; c += cpi) {
+                    acc = fma(blk[(colbase + c) * nX + r], wd[(int64_t)jt * L.E_x + pos[i]], acc);
+                    i += cpi;
+                    while (i >= S) { i -= S; ++jt; }
+                }
+                colbase += total;
+            }
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (rg < L.n_rows && lane < nX) {
+        double s = 0.0;
+        for (int c = 0; c < cpi; ++c) s += red[wv * kWave + c * nX + lane];
+        fd[(int64_t)kt * L.E_x + t0 + lane] += s;
+    }
+}
+
+}  // namespace
+
+// ====================================================================== tree
+
+namespace {
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+};
+
+struct DevLevel {
+    int l = 0, nx = 0, n_int = 0, steps = 0, n_leafx = 0, n_par = 0;
+    double* mu = nullptr;
+    double* lam = nullptr;
+    int* leaf_xs = nullptr;
+    int64_t* ax_off = nullptr;
+    int* tb = nullptr;
+    int* te = nullptr;
+    int* parent = nullptr;
+    int* par_xs = nullptr;        // slots with children (non-leaf)
+    int* ch_ptr = nullptr;
+    int* ch = nullptr;
+    int* m2l_ptr = nullptr;
+    int* m2l_src = nullptr;
+    int* m2l_cls = nullptr;
+    double* ops = nullptr;
+    int64_t at_off = 0, qt_off = -1, qx_off = -1;
+    int n_off = 0;
+};
+
+struct NearOp {
+    double* B = nullptr;          // causal block storage
+    double* table = nullptr;      // distinct integrals
+};
+
+}  // namespace
+
+struct pfmm_tree {
+    int device = 0;
+    Plan P;
+    FarTables F;
+    std::vector<void*> allocs;
+    uint64_t bytes = 0;
+    // device data
+    int* sigma = nullptr;
+    int* inv_sigma = nullptr;
+    double* wd = nullptr;
+    double* fd = nullptr;
+    double *At = nullptr, *Ax = nullptr, *AxK = nullptr, *qt = nullptr, *qx = nullptr;
+    int* chunk_cols = nullptr;
+    int64_t* chunk_off = nullptr;
+    CoefMaps cm{};
+    std::vector<DevLevel> lv;
+    bool low_leaves = false;      // leaves at levels < 2 (no far field)
+    NearLayout nl{};
+    GroupDev* groups = nullptr;
+    int* umap = nullptr;
+    NearOp opV, opK;
+    bool hasV = false, hasK = false;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev;   // pairs per stage
+    std::vector<std::pair<int, int>> ev_used;   // (stage, event index)
+    double prof_ms[8] = {0};
+    int64_t prof_cnt[8] = {0};
+};
+
+namespace {
+
+template <class T>
+pfmm_status upload(pfmm_tree* t, T** dst, const T* src, size_t n) {
+    *dst = nullptr;
+    if (n == 0) return PFMM_OK;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) return fail(PFMM_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    t->allocs.push_back(p);
+    t->bytes += n * sizeof(T);
+    HIP_TRY(hipMemcpy(p, src, n * sizeof(T), hipMemcpyHostToDevice));
+    *dst = (T*)p;
+    return PFMM_OK;
+}
+
+template <class T>
+pfmm_status dalloc(pfmm_tree* t, T** dst, size_t n) {
+    *dst = nullptr;
+    if (n == 0) return PFMM_OK;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) return fail(PFMM_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    t->allocs.push_back(p);
+    t->bytes += n * sizeof(T);
+    *dst = (T*)p;
+    return PFMM_OK;
+}
+
+#define PF_TRY(expr)                                  \
+    do {                                              \
+        pfmm_status s_ = (expr);                      \
+        if (s_ != PFMM_OK) return s_;                 \
+    } while (0)
+
+int dmax_class(int dmax) {
+    if (dmax <= 7) return 7;
+    if (dmax <= 15) return 15;
+    return 31;
+}
+
+// Device memory the build will need (bytes), computed before allocating.
+uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask) {
+    uint64_t b = 0;
+    const uint64_t N = (uint64_t)P.E_t * P.E_x;
+    b += 2 * N * 8;                                   // w, f in tree order
+    for (int l = 2; l <= P.depth; ++l) {
+        const FarLevel& L = F.lv[l];
+        b += 2ull * L.nx * P.Nc * L.n_int * 8;        // mu, lambda
+        b += (uint64_t)L.n_off * 2 * F.op_size * 8;   // M2L operators
+    }
+    int nop = ((ops_mask & PFMM_OP_V) ? 1 : 0) + ((ops_mask & PFMM_OP_K) ? 1 : 0);
+    b += (uint64_t)nop * ((uint64_t)P.near_entries * 8 + (uint64_t)P.table_size * 8);
+    b += P.umap.size() * 4 + P.set_pos.size() * 4 + P.upos.size() * 4;
+    b += (F.At.size() + F.Ax.size() + F.AxK.size() + F.qt.size() + F.qx.size() + F.E1.size()) * 8;
+    b += P.rows.size() * 16;
+    return b;
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
+    Plan& P = t->P;
+    PF_TRY(dalloc(t, &op.table, (size_t)P.table_size));
+    PF_TRY(dalloc(t, &op.B, (size_t)P.near_entries));
+    // quadrature rules
+    QuadRules Q{};
+    std::vector<double> g, w;
+    gauss_legendre01(P.q_reg, g, w);
+    for (int i = 0; i < P.q_reg; ++i) { Q.g_reg[i] = g[i]; Q.w_reg[i] = w[i]; }
+    gauss_legendre01(P.q_sing, g, w);
+    for (int i = 0; i < P.q_sing; ++i) { Q.g_sing[i] = g[i]; Q.w_sing[i] = w[i]; }
+    gauss_legendre01(kHat, g, w);
+    for (int i = 0; i < kHat; ++i) { Q.g_hat[i] = g[i]; Q.w_hat[i] = w[i]; }
+    Q.q_reg = P.q_reg;
+    Q.q_sing = P.q_sing;
+    // geometry
+    static_assert(sizeof(TouchDev) == sizeof(TouchPair), "layout");
+    NearGeom G{};
+    double *verts, *area, *normal, *centroid, *maxedge;
+    int* tris;
+    PF_TRY(upload(t, &verts, P.verts.data(), P.verts.size()));
+    PF_TRY(upload(t, &tris, P.tris.data(), P.tris.size()));
+    PF_TRY(upload(t, &area, P.area.data(), P.area.size()));
+    PF_TRY(upload(t, &normal, P.normal.data(), P.normal.size()));
+    PF_TRY(upload(t, &centroid, P.centroid.data(), P.centroid.size()));
+    PF_TRY(upload(t, &maxedge, P.maxedge.data(), P.maxedge.size()));
+    G.verts = verts; G.tris = tris; G.area = area; G.normal = normal; G.centroid = centroid; G.maxedge = maxedge;
+    G.inv_sigma = t->inv_sigma;
+    G.h = P.h; G.alpha = P.alpha;
+    int* upos;
+    PF_TRY(upload(t, &upos, P.upos.data(), P.upos.size()));
+    // regular blocks
+    std::vector<int> bg;
+    std::vector<int64_t> bb;
+    int dmx = 0;
+    for (size_t i = 0; i < P.groups.size(); ++i) {
+        const AsmGroup& A = P.groups[i];
+        dmx = std::max(dmx, A.dmax);
+        int64_t n = (int64_t)(A.te - A.tb) * A.usize;
+        for (int64_t s = 0; s < n; s += 256) { bg.push_back((int)i); bb.push_back(s); }
+    }
+    if (dmx > 31) return fail(PFMM_EUNSUPPORTED, "nearfield time offsets above 31 steps");
+    int* d_bg;
+    int64_t* d_bb;
+    PF_TRY(upload(t, &d_bg, bg.data(), bg.size()));
+    PF_TRY(upload(t, &d_bb, bb.data(), bb.size()));
+    const int dc = dmax_class(dmx);
+#define LAUNCH_REG(KK, DD) hipLaunchKernelGGL((k_near_regular<KK, DD>), dim3((unsigned)bg.size()), dim3(256), 0, st, \
+                                              op.table, t->groups, d_bg, d_bb, upos, G, Q)
+    if (!bg.empty()) {
+        if (K) {
+            if (dc == 7) LAUNCH_REG(true, 7); else if (dc == 15) LAUNCH_REG(true, 15); else LAUNCH_REG(true, 31);
+        } else {
+            if (dc == 7) LAUNCH_REG(false, 7); else if (dc == 15) LAUNCH_REG(false, 15); else LAUNCH_REG(false, 31);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+#undef LAUNCH_REG
+    TouchDev* d_touch;
+    PF_TRY(upload(t, (TouchPair**)&d_touch, P.touch.data(), P.touch.size()));
+    const int nT = (int)P.touch.size();
+#define LAUNCH_SING(KK, DD) hipLaunchKernelGGL((k_near_singular<KK, DD>), dim3((nT + 63) / 64), dim3(64), 0, st, \
+                                               op.table, t->groups, d_touch, nT, upos, G, Q)
+    if (nT > 0) {
+        if (K) {
+            if (dc == 7) LAUNCH_SING(true, 7); else if (dc == 15) LAUNCH_SING(true, 15); else LAUNCH_SING(true, 31);
+        } else {
+            if (dc == 7) LAUNCH_SING(false, 7); else if (dc == 15) LAUNCH_SING(false, 15); else LAUNCH_SING(false, 31);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+#undef LAUNCH_SING
+    // expand into the causal blocks
+    const int64_t nrg = (int64_t)P.rows.size();
+    if (nrg > 0) {
+        hipLaunchKernelGGL(k_near_expand, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, op.B, op.table, t->groups,
+                           t->umap, t->nl);
+        HIP_TRY(hipGetLastError());
+    }
+    return PFMM_OK;
+}
+
+pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
+    Plan& P = t->P;
+    FarTables& F = t->F;
+    const int64_t N = (int64_t)P.E_t * P.E_x;
+    PF_TRY(upload(t, &t->sigma, P.sigma.data(), P.sigma.size()));
+    PF_TRY(upload(t, &t->inv_sigma, P.inv_sigma.data(), P.inv_sigma.size()));
+    PF_TRY(dalloc(t, &t->wd, (size_t)N));
+    PF_TRY(dalloc(t, &t->fd, (size_t)N));
+    // coefficient maps
+    {
+        const int nx1 = P.m_x + 1;
+        std::vector<int> kpos(P.Nc), kposmap(nx1 * nx1 * nx1, -1), cidx((P.m_t + 1) * P.Nk, -1);
+        for (int i = 0; i < P.Nk; ++i) kposmap[(P.kidx_k[3 * i] * nx1 + P.kidx_k[3 * i + 1]) * nx1 + P.kidx_k[3 * i + 2]] = i;
+        for (int c = 0; c < P.Nc; ++c) {
+            kpos[c] = kposmap[(P.coef_k[3 * c] * nx1 + P.coef_k[3 * c + 1]) * nx1 + P.coef_k[3 * c + 2]];
+            cidx[P.coef_a[c] * P.Nk + kpos[c]] = c;
+        }
+        int *a, *deg, *k3, *kp, *ki, *kpm, *ci;
+        PF_TRY(upload(t, &a, P.coef_a.data(), P.coef_a.size()));
+        PF_TRY(upload(t, &deg, P.coef_deg.data(), P.coef_deg.size()));
+        PF_TRY(upload(t, &k3, P.coef_k.data(), P.coef_k.size()));
+        PF_TRY(upload(t, &kp, kpos.data(), kpos.size()));
+        PF_TRY(upload(t, &ki, P.kidx_k.data(), P.kidx_k.size()));
+        PF_TRY(upload(t, &kpm, kposmap.data(), kposmap.size()));
+        PF_TRY(upload(t, &ci, cidx.data(), cidx.size()));
+        t->cm = CoefMaps{a, deg, k3, kp, ki, kpm, ci, P.Nc, P.Nk, P.m_t, P.m_x};
+    }
+    PF_TRY(upload(t, &t->At, F.At.data(), F.At.size()));
+    PF_TRY(upload(t, &t->Ax, F.Ax.data(), F.Ax.size()));
+    PF_TRY(upload(t, &t->AxK, F.AxK.data(), F.AxK.size()));
+    PF_TRY(upload(t, &t->qt, F.qt.data(), F.qt.size()));
+    PF_TRY(upload(t, &t->qx, F.qx.data(), F.qx.size()));
+    PF_TRY(upload(t, &t->chunk_cols, F.chunk_cols.data(), F.chunk_cols.size()));
+    PF_TRY(upload(t, &t->chunk_off, F.chunk_off.data(), F.chunk_off.size()));
+    double *E1, *Cab;
+    PF_TRY(upload(t, &E1, F.E1.data(), F.E1.size()));
+    PF_TRY(upload(t, &Cab, F.Cab.data(), F.Cab.size()));
+    // levels
+    t->lv.assign(P.depth + 1, DevLevel());
+    for (int l = 0; l < 2 && l <= P.depth; ++l) {
+        const Level& L = P.lev[l];
+        for (size_t i = 0; i < L.leaf.size(); ++i)
+            if (L.present[i] && L.leaf[i]) t->low_leaves = true;
+    }
+    for (int l = 2; l <= P.depth; ++l) {
+        const Level& L = P.lev[l];
+        const FarLevel& FL = F.lv[l];
+        DevLevel& D = t->lv[l];
+        D.l = l; D.nx = L.nx(); D.n_int = L.n_int; D.steps = FL.steps;
+        D.n_leafx = (int)FL.leaf_xs.size();
+        D.at_off = FL.at_off; D.qt_off = FL.qt_off; D.qx_off = FL.qx_off; D.n_off = FL.n_off;
+        PF_TRY(dalloc(t, &D.mu, (size_t)D.nx * P.Nc * D.n_int));
+        PF_TRY(dalloc(t, &D.lam, (size_t)D.nx * P.Nc * D.n_int));
+        PF_TRY(upload(t, &D.leaf_xs, FL.leaf_xs.data(), FL.leaf_xs.size()));
+        PF_TRY(upload(t, &D.ax_off, FL.ax_off.data(), FL.ax_off.size()));
+        PF_TRY(upload(t, &D.tb, L.tb.data(), L.tb.size()));
+        PF_TRY(upload(t, &D.te, L.te.data(), L.te.size()));
+        PF_TRY(upload(t, &D.parent, L.parent.data(), L.parent.size()));
+        std::vector<int> par;
+        for (int xs = 0; xs < L.nx(); ++xs)
+            if (FL.children_ptr[xs + 1] > FL.children_ptr[xs]) par.push_back(xs);
+        D.n_par = (int)par.size();
+        PF_TRY(upload(t, &D.par_xs, par.data(), par.size()));
+        PF_TRY(upload(t, &D.ch_ptr, FL.children_ptr.data(), FL.children_ptr.size()));
+        PF_TRY(upload(t, &D.ch, FL.children.data(), FL.children.size()));
+        PF_TRY(upload(t, &D.m2l_ptr, FL.m2l_ptr.data(), FL.m2l_ptr.size()));
+        PF_TRY(upload(t, &D.m2l_src, FL.m2l_src.data(), FL.m2l_src.size()));
+        PF_TRY(upload(t, &D.m2l_cls, FL.m2l_cls.data(), FL.m2l_cls.size()));
+        // operators
+        if (FL.n_off > 0) {
+            const int64_t total = (int64_t)FL.n_off * 2 * F.op_size;
+            PF_TRY(dalloc(t, &D.ops, (size_t)total));
+            int* off3;
+            PF_TRY(upload(t, &off3, FL.off3.data(), FL.off3.size()));
+            hipLaunchKernelGGL(k_m2l_opgen, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, D.ops,
+                               E1 + FL.e1_off, Cab + FL.cab_off, off3, t->chunk_cols, t->chunk_off, t->cm,
+                               F.n_chunks, F.op_size, FL.R, total);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    // nearfield layout
+    {
+        const size_t nL = P.leaves.size();
+        std::vector<int> rl(P.rows.size()), rk(P.rows.size());
+        std::vector<int64_t> rb(P.rows.size());
+        for (size_t i = 0; i < P.rows.size(); ++i) { rl[i] = P.rows[i].leaf; rk[i] = P.rows[i].kt; rb[i] = P.rows[i].boff; }
+        std::vector<int> ltb(nL), lnx(nL), lr0(nL), lr1(nL), lg(nL);
+        for (size_t i = 0; i < nL; ++i) {
+            const LeafRec& R = P.leaves[i];
+            ltb[i] = R.tb; lnx[i] = R.te - R.tb; lr0[i] = R.rect0; lr1[i] = R.rect1; lg[i] = R.group;
+            if (lnx[i] > kWave) return fail(PFMM_EUNSUPPORTED, "a leaf holds more than 64 triangles (lower n_max)");
+        }
+        std::vector<int> j0(P.rects.size()), j1(P.rects.size()), rs(P.rects.size());
+        for (size_t i = 0; i < P.rects.size(); ++i) { j0[i] = P.rects[i].j0; j1[i] = P.rects[i].j1; rs[i] = P.rects[i].set; }
+        NearLayout& NL = t->nl;
+        int *a1, *a2, *a4, *a5, *a6, *a7, *a8, *a9, *a10, *a11, *a12, *a13, *a14;
+        int64_t* a3;
+        PF_TRY(upload(t, &a1, rl.data(), rl.size()));
+        PF_TRY(upload(t, &a2, rk.data(), rk.size()));
+        PF_TRY(upload(t, &a3, rb.data(), rb.size()));
+        PF_TRY(upload(t, &a4, ltb.data(), ltb.size()));
+        PF_TRY(upload(t, &a5, lnx.data(), lnx.size()));
+        PF_TRY(upload(t, &a6, lr0.data(), lr0.size()));
+        PF_TRY(upload(t, &a7, lr1.data(), lr1.size()));
+        PF_TRY(upload(t, &a8, lg.data(), lg.size()));
+        PF_TRY(upload(t, &a9, j0.data(), j0.size()));
+        PF_TRY(upload(t, &a10, j1.data(), j1.size()));
+        PF_TRY(upload(t, &a11, rs.data(), rs.size()));
+        PF_TRY(upload(t, &a12, P.set_off.data(), P.set_off.size()));
+        PF_TRY(upload(t, &a13, P.set_size.data(), P.set_size.size()));
+        PF_TRY(upload(t, &a14, P.set_pos.data(), P.set_pos.size()));
+        NL = NearLayout{a1, a2, a3, a4, a5, a6, a7, a8, a9, a10, a11, a12, a13, a14, P.E_x, (int64_t)P.rows.size()};
+        std::vector<GroupDev> gd(P.groups.size());
+        for (size_t i = 0; i < P.groups.size(); ++i) {
+            const AsmGroup& A = P.groups[i];
+            gd[i] = GroupDev{A.tb, A.te, A.dmax, A.usize, A.uoff, A.toff, A.mapoff};
+        }
+        PF_TRY(upload(t, &t->groups, gd.data(), gd.size()));
+        PF_TRY(upload(t, &t->umap, P.umap.data(), P.umap.size()));
+    }
+    if (ops_mask & PFMM_OP_V) { PF_TRY(assemble_near(t, false, t->opV, st)); t->hasV = true; }
+    if (ops_mask & PFMM_OP_K) { PF_TRY(assemble_near(t, true, t->opK, st)); t->hasK = true; }
+    HIP_TRY(hipStreamSynchronize(st));
+    return PFMM_OK;
+}
+
+void prof_begin(pfmm_tree* t, int stage, hipStream_t st, int& idx) {
+    idx = -1;
+    if (!t->prof) return;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    (void)hipEventRecord(a, st);
+    t->ev.push_back(a);
+    t->ev.push_back(b);
+    idx = (int)t->ev.size() - 2;
+    t->ev_used.emplace_back(stage, idx);
+}
+
+void prof_end(pfmm_tree* t, hipStream_t st, int idx) {
+    if (idx >= 0) (void)hipEventRecord(t->ev[idx + 1], st);
+}
+
+pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t st) {
+    Plan& P = t->P;
+    const int64_t N = (int64_t)P.E_t * P.E_x;
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    const CoefMaps& cm = t->cm;
+    int ev;
+    prof_begin(t, 0, st, ev);
+    hipLaunchKernelGGL(k_permute_in, dim3(nb), dim3(256), 0, st, w, t->wd, t->inv_sigma, P.E_x, N);
+    prof_end(t, st, ev);
+    if (t->low_leaves || !P.has_far)
+        hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, st, t->fd, 0.0, N);
+    if (P.has_far) {
+        // S2M
+        prof_begin(t, 1, st, ev);
+        for (int l = 2; l <= P.depth; ++l) {
+            DevLevel& D = t->lv[l];
+            if (D.n_leafx == 0) continue;
+            hipLaunchKernelGGL(k_s2m, dim3(D.n_leafx * D.n_int), dim3(256), 0, st, t->wd, D.mu, D.leaf_xs, D.ax_off,
+                               D.tb, D.te, t->At + D.at_off, K ? t->AxK : t->Ax, cm, D.n_int, D.steps, P.E_x);
+        }
+        prof_end(t, st, ev);
+        // M2M, levels p-1 .. 2
+        prof_begin(t, 2, st, ev);
+        for (int l = P.depth - 1; l >= 2; --l) {
+            DevLevel& D = t->lv[l];
+            DevLevel& C = t->lv[l + 1];
+            if (D.n_par == 0) continue;
+            hipLaunchKernelGGL(k_m2m, dim3(D.n_par * D.n_int), dim3(256), 3 * P.Nc * sizeof(double), st, C.mu, D.mu,
+                               D.par_xs, D.ch_ptr, D.ch, t->qt + C.qt_off, t->qx + C.qx_off, cm, D.n_int, C.n_int);
+        }
+        prof_end(t, st, ev);
+        // M2L, levels 2 .. p
+        prof_begin(t, 3, st, ev);
+        for (int l = 2; l <= P.depth; ++l) {
+            DevLevel& D = t->lv[l];
+            dim3 grid(D.nx, (D.n_int + kWave - 1) / kWave, t->F.n_chunks);
+            hipLaunchKernelGGL(k_m2l, grid, dim3(kWave), 0, st, D.mu, D.lam, D.ops, D.m2l_ptr, D.m2l_src, D.m2l_cls,
+                               t->chunk_cols, t->chunk_off, P.Nc, D.n_int, t->F.op_size);
+        }
+        prof_end(t, st, ev);
+        // L2L, levels 3 .. p
+        prof_begin(t, 4, st, ev);
+        for (int l = 3; l <= P.depth; ++l) {
+            DevLevel& D = t->lv[l];
+            DevLevel& Pp = t->lv[l - 1];
+            hipLaunchKernelGGL(k_l2l, dim3(D.nx * D.n_int), dim3(256), 2 * P.Nc * sizeof(double), st, Pp.lam, D.lam,
+                               D.parent, t->qt + D.qt_off, t->qx + D.qx_off, cm, D.n_int, Pp.n_int);
+        }
+        prof_end(t, st, ev);
+        // L2T
+        prof_begin(t, 5, st, ev);
+        for (int l = 2; l <= P.depth; ++l) {
+            DevLevel& D = t->lv[l];
+            if (D.n_leafx == 0) continue;
+            hipLaunchKernelGGL(k_l2t, dim3(D.n_leafx * D.n_int), dim3(256), P.Nc * sizeof(double), st, D.lam, t->fd,
+                               D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, t->Ax, cm, D.n_int, D.steps, P.E_x);
+        }
+        prof_end(t, st, ev);
+    }
+    // nearfield
+    prof_begin(t, 6, st, ev);
+    const int64_t nrg = (int64_t)P.rows.size();
+    if (nrg > 0)
+        hipLaunchKernelGGL(k_near_apply, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, K ? t->opK.B : t->opV.B,
+                           t->wd, t->fd, t->nl);
+    prof_end(t, st, ev);
+    prof_begin(t, 7, st, ev);
+    hipLaunchKernelGGL(k_permute_out, dim3(nb), dim3(256), 0, st, t->fd, f, t->sigma, P.E_x, N);
+    prof_end(t, st, ev);
+    HIP_TRY(hipGetLastError());
+    return PFMM_OK;
+}
+
+void fill_stats(const Plan& P, uint64_t bytes, pfmm_stats* out) {
+    out->depth = P.depth;
+    out->n_levels_far = P.depth >= 2 ? P.depth - 1 : 0;
+    out->boxes = P.n_boxes;
+    out->leaves = P.n_leaves;
+    out->near_entries = P.near_entries;
+    out->m2l_pairs = P.m2l_pairs;
+    out->near_row_groups = (int64_t)P.rows.size();
+    out->distinct_integrals = P.distinct;
+    out->device_bytes = bytes;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+pfmm_status pfmm_default_params(pfmm_params* out) {
+    if (!out) return fail(PFMM_EINVAL, "NULL params");
+    std::memset(out, 0, sizeof(*out));
+    out->alpha = 1.0;
+    out->m_t = 6;
+    out->m_x = 6;
+    out->n_max = 64;
+    out->c_st = 0.9;
+    out->n_tr = 5;
+    out->q_reg = 4;
+    out->q_sing = 5;
+    out->precision = PFMM_FP64;
+    out->operators = PFMM_OP_V | PFMM_OP_K;
+    out->check_finite = 1;
+    out->device_mem_budget = 0;
+    return PFMM_OK;
+}
+
+pfmm_status pfmm_plan_stats(const double* vertices, int64_t n_vertices, const int32_t* triangles, int64_t n_triangles,
+                            const double* time_nodes, int64_t n_steps, const pfmm_params* p, pfmm_stats* out) {
+    if (!out) return fail(PFMM_EINVAL, "NULL stats");
+    pfmm_params prm;
+    if (p) prm = *p; else pfmm_default_params(&prm);
+    try {
+        Plan P;
+        std::string msg;
+        pfmm_status s = build_plan(vertices, n_vertices, triangles, n_triangles, time_nodes, n_steps, prm, P, msg);
+        if (s != PFMM_OK) return fail(s, msg);
+        FarTables F;
+        build_far_tables(P, F);
+        fill_stats(P, estimate_bytes(P, F, prm.operators), out);
+    } catch (const std::bad_alloc&) {
+        return fail(PFMM_ENOMEM, "host allocation failed while planning");
+    } catch (const std::exception& e) {
+        return fail(PFMM_EINVAL, e.what());
+    }
+    return PFMM_OK;
+}
+
+pfmm_status pfmm_build_tree(const double* vertices, int64_t n_vertices, const int32_t* triangles, int64_t n_triangles,
+                            const double* time_nodes, int64_t n_steps, const pfmm_params* p, int32_t device,
+                            void* stream, pfmm_tree** out) {
+    if (!out) return fail(PFMM_EINVAL, "NULL output pointer");
+    *out = nullptr;
+    pfmm_params prm;
+    if (p) prm = *p; else pfmm_default_params(&prm);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(PFMM_EDEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(PFMM_EINVAL, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(PFMM_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    HIP_TRY(hipSetDevice(device));
+    std::unique_ptr<pfmm_tree> t(new (std::nothrow) pfmm_tree());
+    if (!t) return fail(PFMM_ENOMEM, "host allocation failed");
+    t->device = device;
+    try {
+        std::string msg;
+        pfmm_status s = build_plan(vertices, n_vertices, triangles, n_triangles, time_nodes, n_steps, prm, t->P, msg);
+        if (s != PFMM_OK) return fail(s, msg);
+        build_far_tables(t->P, t->F);
+    } catch (const std::bad_alloc&) {
+        return fail(PFMM_ENOMEM, "host allocation failed while planning");
+    }
+    if (t->P.Nc > 2048) return fail(PFMM_EUNSUPPORTED, "(m_t+1) * C(m_x+3,3) must be <= 2048");
+    const uint64_t need = estimate_bytes(t->P, t->F, prm.operators);
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    const uint64_t budget = prm.device_mem_budget ? prm.device_mem_budget : (uint64_t)(0.9 * (double)fr);
+    if (need > budget)
+        return fail(PFMM_ENOMEM, "tree needs " + std::to_string(need) + " device bytes, budget " + std::to_string(budget));
+    hipStream_t st = as_stream(stream);
+    pfmm_status s = setup_device(t.get(), st, prm.operators);
+    if (s != PFMM_OK) {
+        pfmm_destroy(t.release());
+        return s;
+    }
+    *out = t.release();
+    return PFMM_OK;
+}
+
+pfmm_status pfmm_apply_V(pfmm_tree* t, const double* w_dev, double* f_dev, void* stream) {
+    if (!t || !w_dev || !f_dev) return fail(PFMM_EINVAL, "NULL argument");
+    if (!t->hasV) return fail(PFMM_EINVAL, "V_h was not built for this tree");
+    if (hipSetDevice(t->device) != hipSuccess) return fail(PFMM_EDEVICE, "hipSetDevice failed");
+    return apply(t, false, w_dev, f_dev, as_stream(stream));
+}
+
+pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void* stream) {
+    if (!t || !u_dev || !f_dev) return fail(PFMM_EINVAL, "NULL argument");
+    if (!t->hasK) return fail(PFMM_EINVAL, "K_h was not built for this tree");
+    if (hipSetDevice(t->device) != hipSuccess) return fail(PFMM_EDEVICE, "hipSetDevice failed");
+    return apply(t, true, u_dev, f_dev, as_stream(stream));
+}
+
+pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out) {
+    if (!t || !out) return fail(PFMM_EINVAL, "NULL argument");
+    fill_stats(t->P, t->bytes, out);
+    return PFMM_OK;
+}
+
+pfmm_status pfmm_profile_enable(pfmm_tree* t, int32_t enable) {
+    if (!t) return fail(PFMM_EINVAL, "NULL tree");
+    t->prof = enable != 0;
+    return PFMM_OK;
+}
+
+pfmm_status pfmm_profile_read(pfmm_tree* t, double* ms, int64_t* counts, int32_t* n_stages) {
+    if (!t) return fail(PFMM_EINVAL, "NULL tree");
+    for (auto& u : t->ev_used) {
+        const int stage = u.first, i = u.second;
+        if (hipEventSynchronize(t->ev[i + 1]) != hipSuccess) return fail(PFMM_EDEVICE, "event synchronize failed");
+        float m = 0.f;
+        if (hipEventElapsedTime(&m, t->ev[i], t->ev[i + 1]) == hipSuccess) {
+            t->prof_ms[stage] += m;
+            t->prof_cnt[stage] += 1;
+        }
+    }
+    for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
+    t->ev.clear();
+    t->ev_used.clear();
+    for (int s = 0; s < 8; ++s) {
+        if (ms) ms[s] = t->prof_ms[s];
+        if (counts) counts[s] = t->prof_cnt[s];
+        t->prof_ms[s] = 0;
+        t->prof_cnt[s] = 0;
+    }
+    if (n_stages) *n_stages = 8;
+    return PFMM_OK;
+}
+
+void pfmm_destroy(pfmm_tree* t) {
+    if (!t) return;
+    (void)hipSetDevice(t->device);
+    for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
+    for (void* p : t->allocs) (void)hipFree(p);
+    delete t;
+}
+
+const char* pfmm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

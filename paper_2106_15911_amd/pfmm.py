@@ -1,0 +1,178 @@
+"""ctypes binding of libpfmm.so: argument marshalling only.
+
+Device vectors are torch tensors (float64, on the tree's GPU); their data
+pointers and the current HIP stream are handed to the C ABI.  Every step of
+the computation runs in the library's kernels.  Loading fails loudly when the
+library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+STATUS_NAMES = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_ENOMEM", -3: "PFMM_EDEVICE",
+                -4: "PFMM_ENOTCONV", -5: "PFMM_ENONFINITE", -6: "PFMM_EUNSUPPORTED"}
+PROFILE_STAGES = ["permute", "s2m", "m2m", "m2l", "l2l", "l2t", "nearfield", "unpermute"]
+OP_V, OP_K = 1, 2
+
+
+class PfmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("m_t", ctypes.c_int32), ("m_x", ctypes.c_int32),
+                ("n_max", ctypes.c_int32), ("c_st", ctypes.c_double), ("n_tr", ctypes.c_int32),
+                ("q_reg", ctypes.c_int32), ("q_sing", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("operators", ctypes.c_int32), ("check_finite", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("device_mem_budget", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("n_levels_far", ctypes.c_int32), ("boxes", ctypes.c_int64),
+                ("leaves", ctypes.c_int64), ("near_entries", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
+                ("near_row_groups", ctypes.c_int64), ("distinct_integrals", ctypes.c_int64),
+                ("device_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def lib_path():
+    return os.path.join(_HERE, "libpfmm.so")
+
+
+def load_library():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(python paper_2106_15911_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    P, I64, I32, VP = ctypes.POINTER, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    dp, ip = P(ctypes.c_double), P(ctypes.c_int32)
+    sig = {
+        "pfmm_default_params": ([P(Params)], I32),
+        "pfmm_build_tree": ([dp, I64, ip, I64, dp, I64, P(Params), I32, VP, P(VP)], I32),
+        "pfmm_apply_V": ([VP, VP, VP, VP], I32),
+        "pfmm_apply_K": ([VP, VP, VP, VP], I32),
+        "pfmm_tree_stats": ([VP, P(Stats)], I32),
+        "pfmm_plan_stats": ([dp, I64, ip, I64, dp, I64, P(Params), P(Stats)], I32),
+        "pfmm_profile_enable": ([VP, I32], I32),
+        "pfmm_profile_read": ([VP, dp, P(I64), P(I32)], I32),
+        "pfmm_destroy": ([VP], None),
+        "pfmm_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        raise PfmmError(status, load_library().pfmm_last_error().decode())
+
+
+def default_params(**kw):
+    p = Params()
+    _check(load_library().pfmm_default_params(ctypes.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _mesh_args(vertices, triangles, time_nodes):
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    t = np.ascontiguousarray(triangles, dtype=np.int32)
+    tn = np.ascontiguousarray(time_nodes, dtype=np.float64)
+    if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3 or tn.ndim != 1:
+        raise ValueError("vertices (n,3), triangles (m,3), time_nodes (E_t+1,)")
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    return (v, t, tn), (v.ctypes.data_as(dp), v.shape[0], t.ctypes.data_as(ip), t.shape[0],
+                        tn.ctypes.data_as(dp), tn.shape[0] - 1)
+
+
+def plan_stats(vertices, triangles, time_nodes, params=None):
+    """Host-only planning (no GPU): counts of the tree and its lists."""
+    keep, args = _mesh_args(vertices, triangles, time_nodes)
+    st = Stats()
+    _check(load_library().pfmm_plan_stats(*args, ctypes.byref(params) if params is not None else None,
+                                          ctypes.byref(st)))
+    return st.as_dict()
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Tree:
+    """A built tree on one GPU; apply_V / apply_K take and return torch tensors."""
+
+    def __init__(self, vertices, triangles, time_nodes, params=None, device=0, stream=None):
+        import torch
+        self.lib = load_library()
+        keep, args = _mesh_args(vertices, triangles, time_nodes)
+        self.n_dofs = int(args[3]) * int(args[5])
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.pfmm_build_tree(*args, ctypes.byref(params) if params is not None else None,
+                                            device, _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def _apply(self, fn, x, out, stream):
+        import torch
+        if x.dtype != torch.float64 or x.device != self.device or x.numel() != self.n_dofs:
+            raise ValueError(f"expected a float64 tensor of {self.n_dofs} entries on {self.device}")
+        x = x.contiguous()
+        if out is None:
+            out = torch.empty_like(x)
+        _check(fn(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def apply_V(self, w, out=None, stream=None):
+        return self._apply(self.lib.pfmm_apply_V, w, out, stream)
+
+    def apply_K(self, u, out=None, stream=None):
+        return self._apply(self.lib.pfmm_apply_K, u, out, stream)
+
+    def stats(self):
+        st = Stats()
+        _check(self.lib.pfmm_tree_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def profile_enable(self, on=True):
+        _check(self.lib.pfmm_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self):
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        n = ctypes.c_int32()
+        _check(self.lib.pfmm_profile_read(self.handle, ms, cnt, ctypes.byref(n)))
+        return {PROFILE_STAGES[i]: (ms[i], cnt[i]) for i in range(n.value)}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pfmm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
