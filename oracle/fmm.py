@@ -120,7 +120,15 @@ class FMMOracle:
         self.area, self.normal = 0.5 * a2, n / a2[:, None]
         self._ax_cache = {}
         self._op_cache = {}
+        self._e1_cache = {}
+        self._at_cache = {}
+        self._qt_cache = {}
+        self._qx_cache = {}
         self._B = None
+        # index set of eq. m2l: all (nu, kappa) with |kappa + nu| <= m_x
+        deg = self.mi.sum(1)
+        pn, pk = np.nonzero(deg[:, None] + deg[None, :] <= m_x)
+        self._pn, self._pk = pn, pk
 
     # ---------------- temporal tables
     def tnodes(self, b):
@@ -129,6 +137,9 @@ class FMMOracle:
 
     def A_t(self, b):
         """A_t[j, a] = int_{step j} L_{J,a}(tau) dtau for the steps of box b."""
+        key = (b.level, b.k)
+        if key in self._at_cache:
+            return self._at_cache[key]
         g, w = gauss_legendre01(self.m_t // 2 + 2)
         nodes = self.tnodes(b)
         rows = []
@@ -136,7 +147,8 @@ class FMMOracle:
             t0, t1 = self.tr.t[j], self.tr.t[j + 1]
             tau = t0 + (t1 - t0) * g
             rows.append(lagrange(nodes, tau) @ (w * (t1 - t0)))
-        return np.array(rows)
+        self._at_cache[key] = np.array(rows)
+        return self._at_cache[key]
 
     # ---------------- spatial tables
     def _ref_coords(self, b, y):
@@ -174,10 +186,16 @@ class FMMOracle:
     # ---------------- re-expansion coefficients
     def qt(self, c, p):
         """q^(t)[a_c, a_p] = L_{I_p, a_p}(xi_{I_c, a_c}) (eq. temp_m2m)."""
-        return lagrange(self.tnodes(p), self.tnodes(c)).T
+        key = (c.level, c.k)
+        if key not in self._qt_cache:
+            self._qt_cache[key] = lagrange(self.tnodes(p), self.tnodes(c)).T
+        return self._qt_cache[key]
 
     def qx(self, c, p):
         """q^(x)[kappa, nu] over multi-indices, kappa <= nu componentwise (eq. st_m2m)."""
+        key = (c.level, c.ix)
+        if key in self._qx_cache:
+            return self._qx_cache[key]
         m = self.m_x
         lc, Hc = self.tr.box_lower(c), self.tr.hx_padded(c.level)
         lp, Hp = self.tr.box_lower(p), self.tr.hx_padded(p.level)
@@ -193,7 +211,8 @@ class FMMOracle:
         full = Q[0][mi[:, 0][:, None], mi[:, 0][None, :]] * Q[1][mi[:, 1][:, None], mi[:, 1][None, :]] \
             * Q[2][mi[:, 2][:, None], mi[:, 2][None, :]]
         mask = np.all(mi[:, None, :] <= mi[None, :, :], axis=2)
-        return np.where(mask, full, 0.0)
+        self._qx_cache[key] = np.where(mask, full, 0.0)
+        return self._qx_cache[key]
 
     # ---------------- M2L operator
     def m2l_operator(self, Z, S):
@@ -241,12 +260,36 @@ class FMMOracle:
                 mu[p.id] = acc
         return mu
 
+    def _e1_tables(self, Z, S):
+        """Per axis j: E_{kappa_j, nu_j}(r_j, d_ab) for all (a, b), and C_ab (eq. exp_coeffs_3d)."""
+        tr = self.tr
+        H = tr.hx_padded(Z.level)
+        r = (tr.box_lower(Z) - tr.box_lower(S)) / H
+        tkey = (Z.level, Z.s0 - S.s0, Z.s1 - Z.s0, S.s1 - S.s0)
+        dt = self.tnodes(Z)[None, :] - self.tnodes(S)[:, None]          # [a, b]
+        C = (4.0 * np.pi * self.alpha * dt) ** -1.5
+        dab = 4.0 * self.alpha * dt / (H * H)
+        E = []
+        for j in range(3):
+            key = tkey + (int(Z.ix[j]) - int(S.ix[j]),)
+            if key not in self._e1_cache:
+                self._e1_cache[key] = E1d(r[j], dab, self.m_x)          # [a, b, kappa_j, nu_j]
+            E.append(self._e1_cache[key])
+        return C, E
+
     def m2l(self, Z, mu):
+        """lambda_{b,nu}(Z) = sum_S sum_a sum_{|kappa+nu|<=m_x} E_{a,kappa,b,nu} mu_{a,kappa}(S) (eq. m2l)."""
         lam_ = np.zeros((self.m_t + 1, self.Nk))
-        n = (self.m_t + 1) * self.Nk
+        pn, pk = self._pn, self._pk
+        mi = self.mi
         for S in self.tr.interaction(Z):
-            op = self.m2l_operator(Z, S)
-            lam_ += (op.reshape(n, n) @ mu[S.id].reshape(n)).reshape(lam_.shape)
+            C, E = self._e1_tables(Z, S)
+            # coefficient of every admissible (a, b, nu, kappa) of the truncated sum
+            coef = (C[:, :, None] * E[0][:, :, mi[pk, 0], mi[pn, 0]] * E[1][:, :, mi[pk, 1], mi[pn, 1]]
+                    * E[2][:, :, mi[pk, 2], mi[pn, 2]])                   # [a, b, pair]
+            contrib = np.einsum("abp,ap->bp", coef, mu[S.id][:, pk])     # [b, pair]
+            for b in range(self.m_t + 1):
+                lam_[b] += np.bincount(pn, weights=contrib[b], minlength=self.Nk)
         return lam_
 
     def l2l(self, c, p, lam_p):
@@ -355,12 +398,15 @@ class FMMOracle:
                 At = self.A_t(Z)[kt - Z.s0]
                 Ax = self.A_x(Z, "V")[list(Z.tris).index(kx)]
                 out[i] += At @ lam_ @ Ax
-            # nearfield row
-            for S in tr.nearfield(Z, memo):
-                if S.s0 > kt:
-                    continue
-                dmax = kt - S.s0
-                ent = self.entries(np.full(len(S.tris), kx), S.tris, dmax)   # (nSx, dmax+1)
-                for jt in range(S.s0, min(S.s1, kt + 1)):
-                    out[i] += ent[:, kt - jt] @ w[jt * tr.E_x + S.tris]
+            # nearfield row: every source element (j_t <= k_t) of the leaf's nearfield boxes
+            srcs = [S for S in tr.nearfield(Z, memo) if S.s0 <= kt]
+            if srcs:
+                dmax = kt - min(S.s0 for S in srcs)
+                jx_all = np.unique(np.concatenate([S.tris for S in srcs]))
+                ent = self.entries(np.full(len(jx_all), kx), jx_all, dmax)     # (n, dmax+1)
+                where = {int(j): i for i, j in enumerate(jx_all)}
+                for S in srcs:
+                    idx = np.array([where[int(j)] for j in S.tris])
+                    for jt in range(S.s0, min(S.s1, kt + 1)):
+                        out[i] += ent[idx, kt - jt] @ w[jt * tr.E_x + S.tris]
         return out, mu
