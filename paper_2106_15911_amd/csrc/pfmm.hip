@@ -236,6 +236,136 @@ __global__ void __launch_bounds__(64) k_m2l(const double* __restrict__ mu, doubl
     }
 }
 
+// M2L on FP64 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// A workgroup owns the locals of one target slot X for 64 consecutive
+// intervals k0..k0+63 (all rows of eq. m2l).  Waves 0-3 take intervals
+// k0..k0+31, waves 4-7 take k0+32..k0+63; within a half, the 16 even and the
+// 16 odd intervals form two 16-column MFMA tiles, so the second source
+// interval of odd targets (Delta = 3) costs no wasted columns.  The output
+// rows (coefficient order: degree, time index, multi-index) are cut into
+// 16-row tiles; tile t only needs the first tile_ks[t] 4-column K-steps
+// (|kappa + nu| <= m_x), and the tiles are spread over the 4 waves of a
+// half by their K-step counts (slot_tile, computed on the host).
+// Operator tiles are generated on the fly from the 1D coefficient tables of
+// eq. exp_coeffs_1d held in LDS: A = C_ab E_x E_y E_z.
+// MFMA register layout (checked on gfx950): A[i][k] lane i+16k, B[k][j]
+// lane j+16k, D[i][j] lane j+16(i%4), register i/4.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kM2LGroups = 6;   // wave groups per interval half (row tiles are spread over them)
+
+template <int MAXS>
+__global__ void __launch_bounds__(64 * kM2LGroups, 2) k_m2l_mfma(
+    const double* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
+    const int* __restrict__ cls, const int* __restrict__ off3, const double* __restrict__ E1,
+    const double* __restrict__ Cab, const int* __restrict__ packinfo, const int* __restrict__ slot_tile,
+    const int* __restrict__ tile_ks, int Nc, int n_int, int mt, int mx, int R) {
+    extern __shared__ double smem[];
+    const int nt1 = mt + 1, nx1 = mx + 1;
+    const int nx2 = nx1 * nx1;
+    const int TS = nt1 * nt1 * nx2;
+    double* sEx = smem;
+    double* sEy = smem + TS;
+    double* sEz = smem + 2 * TS;
+    int* sInfo = (int*)(smem + 3 * TS);          // packed (time index, multi-index, degree) per coefficient
+    const int lane = threadIdx.x % kWave;
+    const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int half = blockIdx.z;
+    const int X = blockIdx.x;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int kE = blockIdx.y * 64 + 32 * half + 2 * lr;
+    const int kO = kE + 1;
+    for (int c = threadIdx.x; c < Nc; c += blockDim.x) sInfo[c] = packinfo[c];
+    // per slot: tile, K-steps (wave-uniform); row part of the table index per
+    // axis and the row degree packed as (x | y << 16) and (z | deg << 16)
+    int tiles[MAXS], ks[MAXS], rXY[MAXS], rZD[MAXS];
+    int ksmax = 0;
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        tiles[i] = __builtin_amdgcn_readfirstlane(slot_tile[grp * MAXS + i]);
+        ks[i] = tiles[i] >= 0 ? __builtin_amdgcn_readfirstlane(tile_ks[tiles[i]]) : 0;
+        ksmax = max(ksmax, ks[i]);
+        const int row = 16 * (tiles[i] >= 0 ? tiles[i] : 0) + lr;
+        const int ri = (tiles[i] >= 0 && row < Nc) ? packinfo[row] : -1;
+        const int b = ri & 15;
+        rXY[i] = (b * nx2 + ((ri >> 4) & 15)) | ((b * nx2 + ((ri >> 8) & 15)) << 16);
+        rZD[i] = (b * nx2 + ((ri >> 12) & 15)) | ((ri >= 0 ? ((ri >> 16) & 255) : 255) << 16);
+    }
+    d4_t accE[MAXS], accO[MAXS];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        accE[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+        accO[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+    }
+    const int nR = 2 * R + 1;
+    for (int si = ptr[X]; si < ptr[X + 1]; ++si) {
+        const int Y = src[si];
+        const int c3 = cls[si];
+        const double* muY = mu + (int64_t)Y * Nc * n_int;
+        for (int D = 2; D <= 3; ++D) {
+            __syncthreads();
+            {
+                const double* ex = E1 + ((int64_t)(D - 2) * nR + off3[3 * c3] + R) * TS;
+                const double* ey = E1 + ((int64_t)(D - 2) * nR + off3[3 * c3 + 1] + R) * TS;
+                const double* ez = E1 + ((int64_t)(D - 2) * nR + off3[3 * c3 + 2] + R) * TS;
+                const double* cab = Cab + (int64_t)(D - 2) * nt1 * nt1;
+                for (int e = threadIdx.x; e < TS; e += blockDim.x) {
+                    sEx[e] = cab[e / nx2] * ex[e];
+                    sEy[e] = ey[e];
+                    sEz[e] = ez[e];
+                }
+            }
+            __syncthreads();
+            const bool vE = (D == 2) && (kE < n_int) && (kE >= D);
+            const bool vO = (kO < n_int) && (kO >= D);
+            if (D == 3 && !__any(vO)) continue;
+            const double* pE = muY + (kE - D);
+            const double* pO = muY + (kO - D);
+            // software pipeline: operands of K-step s+1 are loaded while s computes
+            int ci = lq < Nc ? sInfo[lq] : -1;
+            double bE = (ci >= 0 && vE) ? pE[(int64_t)lq * n_int] : 0.0;
+            double bO = (ci >= 0 && vO) ? pO[(int64_t)lq * n_int] : 0.0;
+            for (int s = 0; s < ksmax; ++s) {
+                const int cn = 4 * (s + 1) + lq;
+                const int ci_n = (s + 1 < ksmax && cn < Nc) ? sInfo[cn] : -1;
+                const double bE_n = (ci_n >= 0 && vE) ? pE[(int64_t)cn * n_int] : 0.0;
+                const double bO_n = (ci_n >= 0 && vO) ? pO[(int64_t)cn * n_int] : 0.0;
+                const int ca = ci & 15;
+                const int cdeg = ci >= 0 ? ((ci >> 16) & 255) : 1 << 10;
+                const int cb = ca * nt1 * nx2;
+                const int cX = cb + ((ci >> 4) & 15) * nx1;
+                const int cY = cb + ((ci >> 8) & 15) * nx1;
+                const int cZ = cb + ((ci >> 12) & 15) * nx1;
+#pragma unroll
+                for (int i = 0; i < MAXS; ++i) {
+                    if (s < ks[i]) {
+                        double A = 0.0;
+                        if ((rZD[i] >> 16) + cdeg <= mx)
+                            A = sEx[cX + (rXY[i] & 0xffff)] * sEy[cY + (rXY[i] >> 16)] * sEz[cZ + (rZD[i] & 0xffff)];
+                        if (D == 2) accE[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, bE, accE[i], 0, 0, 0);
+                        accO[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, bO, accO[i], 0, 0, 0);
+                    }
+                }
+                ci = ci_n;
+                bE = bE_n;
+                bO = bO_n;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        if (tiles[i] < 0) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * tiles[i] + lq + 4 * r;
+            if (row >= Nc) continue;
+            if (kE < n_int) lam[((int64_t)X * Nc + row) * n_int + kE] = accE[i][r];
+            if (kO < n_int) lam[((int64_t)X * Nc + row) * n_int + kO] = accO[i][r];
+        }
+    }
+}
+
 // L2L (transpose of eqs. temp_m2m / st_m2m) from level l-1 into every box of level l.
 __global__ void k_l2l(const double* __restrict__ lam_p, double* __restrict__ lam_c, const int* __restrict__ parent,
                       const double* __restrict__ qt, const double* __restrict__ qx, CoefMaps cm,
@@ -635,8 +765,9 @@ struct DevLevel {
     int* m2l_src = nullptr;
     int* m2l_cls = nullptr;
     double* ops = nullptr;
-    int64_t at_off = 0, qt_off = -1, qx_off = -1;
-    int n_off = 0;
+    int* off3 = nullptr;
+    int64_t at_off = 0, qt_off = -1, qx_off = -1, e1_off = 0, cab_off = 0;
+    int n_off = 0, R = 0;
 };
 
 struct NearOp {
@@ -660,6 +791,12 @@ struct pfmm_tree {
     double *At = nullptr, *Ax = nullptr, *AxK = nullptr, *qt = nullptr, *qx = nullptr;
     int* chunk_cols = nullptr;
     int64_t* chunk_off = nullptr;
+    double* E1 = nullptr;
+    double* Cab = nullptr;
+    int* packinfo = nullptr;      // per coefficient: a | k1<<4 | k2<<8 | k3<<12 | deg<<16
+    int* slot_tile = nullptr;     // [groups][mfma_slots] row tiles per wave group (-1 = none)
+    int* tile_ks = nullptr;       // K-steps per 16-row tile
+    int mfma_slots = 0;           // 0: matrix-core M2L not used
     CoefMaps cm{};
     std::vector<DevLevel> lv;
     bool low_leaves = false;      // leaves at levels < 2 (no far field)
@@ -725,7 +862,7 @@ uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask) {
     for (int l = 2; l <= P.depth; ++l) {
         const FarLevel& L = F.lv[l];
         b += 2ull * L.nx * P.Nc * L.n_int * 8;        // mu, lambda
-        b += (uint64_t)L.n_off * 2 * F.op_size * 8;   // M2L operators
+        b += (uint64_t)L.n_off * 2 * F.op_size * 8;   // explicit M2L operators (upper bound: fallback path)
     }
     int nop = ((ops_mask & PFMM_OP_V) ? 1 : 0) + ((ops_mask & PFMM_OP_K) ? 1 : 0);
     b += (uint64_t)nop * ((uint64_t)P.near_entries * 8 + (uint64_t)P.table_size * 8);
@@ -853,9 +990,49 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
     PF_TRY(upload(t, &t->qx, F.qx.data(), F.qx.size()));
     PF_TRY(upload(t, &t->chunk_cols, F.chunk_cols.data(), F.chunk_cols.size()));
     PF_TRY(upload(t, &t->chunk_off, F.chunk_off.data(), F.chunk_off.size()));
-    double *E1, *Cab;
-    PF_TRY(upload(t, &E1, F.E1.data(), F.E1.size()));
-    PF_TRY(upload(t, &Cab, F.Cab.data(), F.Cab.size()));
+    PF_TRY(upload(t, &t->E1, F.E1.data(), F.E1.size()));
+    PF_TRY(upload(t, &t->Cab, F.Cab.data(), F.Cab.size()));
+    double* E1 = t->E1;
+    double* Cab = t->Cab;
+    // matrix-core M2L: 16-row tiles, their K-step counts, LPT split over 4 wave groups
+    {
+        const int Nc = P.Nc, ntile = (Nc + 15) / 16;
+        std::vector<int> pk(Nc), ks(ntile);
+        for (int c = 0; c < Nc; ++c)
+            pk[c] = P.coef_a[c] | (P.coef_k[3 * c] << 4) | (P.coef_k[3 * c + 1] << 8) | (P.coef_k[3 * c + 2] << 12) |
+                    (P.coef_deg[c] << 16);
+        for (int tt = 0; tt < ntile; ++tt) {
+            const int dmin = P.coef_deg[16 * tt];
+            const int cols = (P.m_t + 1) * binom(P.m_x - dmin + 3, 3);
+            ks[tt] = (cols + 3) / 4;
+        }
+        std::vector<int> order(ntile);
+        for (int i = 0; i < ntile; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ks[a] > ks[b]; });
+        std::vector<std::vector<int>> grp(kM2LGroups);
+        std::vector<int64_t> load(kM2LGroups, 0);
+        for (int tt : order) {
+            int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            grp[g].push_back(tt);
+            load[g] += ks[tt];
+        }
+        size_t ms = 0;
+        for (auto& g : grp) ms = std::max(ms, g.size());
+        int slots = ms <= 2 ? 2 : ms <= 4 ? 4 : ms <= 7 ? 7 : ms <= 10 ? 10 : 0;
+        if (P.m_t > 15 || P.m_x > 15) slots = 0;
+        const size_t shm = (size_t)3 * (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1) * sizeof(double) +
+                           (size_t)P.Nc * sizeof(int);
+        if (shm > 65536) slots = 0;       // coefficient tables must fit the default LDS allocation
+        t->mfma_slots = slots;
+        if (slots) {
+            std::vector<int> st(kM2LGroups * slots, -1);
+            for (int g = 0; g < kM2LGroups; ++g)
+                for (size_t i = 0; i < grp[g].size(); ++i) st[g * slots + i] = grp[g][i];
+            PF_TRY(upload(t, &t->packinfo, pk.data(), pk.size()));
+            PF_TRY(upload(t, &t->slot_tile, st.data(), st.size()));
+            PF_TRY(upload(t, &t->tile_ks, ks.data(), ks.size()));
+        }
+    }
     // levels
     t->lv.assign(P.depth + 1, DevLevel());
     for (int l = 0; l < 2 && l <= P.depth; ++l) {
@@ -870,6 +1047,8 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         D.l = l; D.nx = L.nx(); D.n_int = L.n_int; D.steps = FL.steps;
         D.n_leafx = (int)FL.leaf_xs.size();
         D.at_off = FL.at_off; D.qt_off = FL.qt_off; D.qx_off = FL.qx_off; D.n_off = FL.n_off;
+        D.e1_off = FL.e1_off; D.cab_off = FL.cab_off; D.R = FL.R;
+        PF_TRY(upload(t, &D.off3, FL.off3.data(), FL.off3.size()));
         PF_TRY(dalloc(t, &D.mu, (size_t)D.nx * P.Nc * D.n_int));
         PF_TRY(dalloc(t, &D.lam, (size_t)D.nx * P.Nc * D.n_int));
         PF_TRY(upload(t, &D.leaf_xs, FL.leaf_xs.data(), FL.leaf_xs.size()));
@@ -887,14 +1066,12 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         PF_TRY(upload(t, &D.m2l_ptr, FL.m2l_ptr.data(), FL.m2l_ptr.size()));
         PF_TRY(upload(t, &D.m2l_src, FL.m2l_src.data(), FL.m2l_src.size()));
         PF_TRY(upload(t, &D.m2l_cls, FL.m2l_cls.data(), FL.m2l_cls.size()));
-        // operators
-        if (FL.n_off > 0) {
+        // explicit operators: only for the vector-unit M2L used above the matrix-core limits
+        if (FL.n_off > 0 && t->mfma_slots == 0) {
             const int64_t total = (int64_t)FL.n_off * 2 * F.op_size;
             PF_TRY(dalloc(t, &D.ops, (size_t)total));
-            int* off3;
-            PF_TRY(upload(t, &off3, FL.off3.data(), FL.off3.size()));
             hipLaunchKernelGGL(k_m2l_opgen, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, D.ops,
-                               E1 + FL.e1_off, Cab + FL.cab_off, off3, t->chunk_cols, t->chunk_off, t->cm,
+                               E1 + FL.e1_off, Cab + FL.cab_off, D.off3, t->chunk_cols, t->chunk_off, t->cm,
                                F.n_chunks, F.op_size, FL.R, total);
             HIP_TRY(hipGetLastError());
         }
@@ -997,9 +1174,26 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         prof_begin(t, 3, st, ev);
         for (int l = 2; l <= P.depth; ++l) {
             DevLevel& D = t->lv[l];
-            dim3 grid(D.nx, (D.n_int + kWave - 1) / kWave, t->F.n_chunks);
-            hipLaunchKernelGGL(k_m2l, grid, dim3(kWave), 0, st, D.mu, D.lam, D.ops, D.m2l_ptr, D.m2l_src, D.m2l_cls,
-                               t->chunk_cols, t->chunk_off, P.Nc, D.n_int, t->F.op_size);
+            if (t->mfma_slots) {
+                const int nt1 = P.m_t + 1, nx1 = P.m_x + 1;
+                const size_t shm = (size_t)3 * nt1 * nt1 * nx1 * nx1 * sizeof(double) + (size_t)P.Nc * sizeof(int);
+                dim3 grid(D.nx, (D.n_int + 63) / 64, D.n_int > 32 ? 2 : 1);
+                dim3 block(64 * kM2LGroups);
+#define M2L_MFMA(S) hipLaunchKernelGGL(k_m2l_mfma<S>, grid, block, shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src,      \
+                                       D.m2l_cls, D.off3, t->E1 + D.e1_off, t->Cab + D.cab_off, t->packinfo,      \
+                                       t->slot_tile, t->tile_ks, P.Nc, D.n_int, P.m_t, P.m_x, D.R)
+                switch (t->mfma_slots) {
+                    case 2: M2L_MFMA(2); break;
+                    case 4: M2L_MFMA(4); break;
+                    case 7: M2L_MFMA(7); break;
+                    default: M2L_MFMA(10); break;
+                }
+#undef M2L_MFMA
+            } else {
+                dim3 grid(D.nx, (D.n_int + kWave - 1) / kWave, t->F.n_chunks);
+                hipLaunchKernelGGL(k_m2l, grid, dim3(kWave), 0, st, D.mu, D.lam, D.ops, D.m2l_ptr, D.m2l_src,
+                                   D.m2l_cls, t->chunk_cols, t->chunk_off, P.Nc, D.n_int, t->F.op_size);
+            }
         }
         prof_end(t, st, ev);
         // L2L, levels 3 .. p
