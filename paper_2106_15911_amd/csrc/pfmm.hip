@@ -253,14 +253,23 @@ __global__ void __launch_bounds__(64) k_m2l(const double* __restrict__ mu, doubl
 // lane j+16k, D[i][j] lane j+16(i%4), register i/4.
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kM2LGroups = 6;   // wave groups per interval half (row tiles are spread over them)
+constexpr int kM2LWaves = 16;   // waves per workgroup (one interval half)
+constexpr int kM2LSlots = 3;    // accumulator slots (row-tile segments) per wave
 
+// Work split of one (X, interval half) output block.  Each 16-row tile's
+// K-range (its staircase length) is cut at multiples of a target length;
+// every wave owns up to kM2LSlots segments that start at the same K-step
+// (so they share the moment operands), sorted by length.  Segments after the
+// first of a tile are partial sums, added to the first segment through LDS
+// at the end.  wave_meta[w] = (K-step start, number of segments);
+// seg[w][i] = (tile, length, partial index or -1); red_slot gives, for each
+// partial segment, the owner wave and slot that adds it.
 template <int MAXS>
-__global__ void __launch_bounds__(64 * kM2LGroups, 2) k_m2l_mfma(
+__global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
     const double* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
     const int* __restrict__ cls, const int* __restrict__ off3, const double* __restrict__ E1,
-    const double* __restrict__ Cab, const int* __restrict__ packinfo, const int* __restrict__ slot_tile,
-    const int* __restrict__ tile_ks, int Nc, int n_int, int mt, int mx, int R) {
+    const double* __restrict__ Cab, const int* __restrict__ packinfo, const int* __restrict__ wave_meta,
+    const int* __restrict__ seg, int n_partial, int Nc, int n_int, int mt, int mx, int R) {
     extern __shared__ double smem[];
     const int nt1 = mt + 1, nx1 = mx + 1;
     const int nx2 = nx1 * nx1;
@@ -268,29 +277,33 @@ __global__ void __launch_bounds__(64 * kM2LGroups, 2) k_m2l_mfma(
     double* sEx = smem;
     double* sEy = smem + TS;
     double* sEz = smem + 2 * TS;
-    int* sInfo = (int*)(smem + 3 * TS);          // packed (time index, multi-index, degree) per coefficient
+    int* sCol = (int*)(smem + 3 * TS);           // per coefficient: table column offsets (x | y<<16), (z | deg<<16)
     const int lane = threadIdx.x % kWave;
-    const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int half = blockIdx.z;
     const int X = blockIdx.x;
     const int lr = lane & 15, lq = lane >> 4;
     const int kE = blockIdx.y * 64 + 32 * half + 2 * lr;
     const int kO = kE + 1;
-    for (int c = threadIdx.x; c < Nc; c += blockDim.x) sInfo[c] = packinfo[c];
-    // per slot: tile, K-steps (wave-uniform); row part of the table index per
-    // axis and the row degree packed as (x | y << 16) and (z | deg << 16)
-    int tiles[MAXS], ks[MAXS], rXY[MAXS], rZD[MAXS];
-    int ksmax = 0;
+    for (int c = threadIdx.x; c < Nc; c += blockDim.x) {
+        const int ci = packinfo[c];
+        const int cb = (ci & 15) * nt1 * nx2;
+        sCol[2 * c] = (cb + ((ci >> 4) & 15) * nx1) | ((cb + ((ci >> 8) & 15) * nx1) << 16);
+        sCol[2 * c + 1] = (cb + ((ci >> 12) & 15) * nx1) | (((ci >> 16) & 255) << 16);
+    }
+    const int sbeg = __builtin_amdgcn_readfirstlane(wave_meta[2 * w]);
+    int tiles[MAXS], ks[MAXS], part[MAXS], rXY[MAXS], rZD[MAXS];
 #pragma unroll
     for (int i = 0; i < MAXS; ++i) {
-        tiles[i] = __builtin_amdgcn_readfirstlane(slot_tile[grp * MAXS + i]);
-        ks[i] = tiles[i] >= 0 ? __builtin_amdgcn_readfirstlane(tile_ks[tiles[i]]) : 0;
-        ksmax = max(ksmax, ks[i]);
+        tiles[i] = __builtin_amdgcn_readfirstlane(seg[(w * MAXS + i) * 3]);
+        ks[i] = __builtin_amdgcn_readfirstlane(seg[(w * MAXS + i) * 3 + 1]);   // segment end (exclusive, absolute)
+        part[i] = __builtin_amdgcn_readfirstlane(seg[(w * MAXS + i) * 3 + 2]);
         const int row = 16 * (tiles[i] >= 0 ? tiles[i] : 0) + lr;
-        const int ri = (tiles[i] >= 0 && row < Nc) ? packinfo[row] : -1;
+        const bool rv = tiles[i] >= 0 && row < Nc;
+        const int ri = rv ? packinfo[row] : 0;
         const int b = ri & 15;
         rXY[i] = (b * nx2 + ((ri >> 4) & 15)) | ((b * nx2 + ((ri >> 8) & 15)) << 16);
-        rZD[i] = (b * nx2 + ((ri >> 12) & 15)) | ((ri >= 0 ? ((ri >> 16) & 255) : 255) << 16);
+        rZD[i] = (b * nx2 + ((ri >> 12) & 15)) | ((rv ? ((ri >> 16) & 255) : 255) << 16);
     }
     d4_t accE[MAXS], accO[MAXS];
 #pragma unroll
@@ -320,42 +333,74 @@ __global__ void __launch_bounds__(64 * kM2LGroups, 2) k_m2l_mfma(
             const bool vE = (D == 2) && (kE < n_int) && (kE >= D);
             const bool vO = (kO < n_int) && (kO >= D);
             if (D == 3 && !__any(vO)) continue;
-            const double* pE = muY + (kE - D);
-            const double* pO = muY + (kO - D);
-            // software pipeline: operands of K-step s+1 are loaded while s computes
-            int ci = lq < Nc ? sInfo[lq] : -1;
-            double bE = (ci >= 0 && vE) ? pE[(int64_t)lq * n_int] : 0.0;
-            double bO = (ci >= 0 && vO) ? pO[(int64_t)lq * n_int] : 0.0;
-            for (int s = 0; s < ksmax; ++s) {
-                const int cn = 4 * (s + 1) + lq;
-                const int ci_n = (s + 1 < ksmax && cn < Nc) ? sInfo[cn] : -1;
-                const double bE_n = (ci_n >= 0 && vE) ? pE[(int64_t)cn * n_int] : 0.0;
-                const double bO_n = (ci_n >= 0 && vO) ? pO[(int64_t)cn * n_int] : 0.0;
-                const int ca = ci & 15;
-                const int cdeg = ci >= 0 ? ((ci >> 16) & 255) : 1 << 10;
-                const int cb = ca * nt1 * nx2;
-                const int cX = cb + ((ci >> 4) & 15) * nx1;
-                const int cY = cb + ((ci >> 8) & 15) * nx1;
-                const int cZ = cb + ((ci >> 12) & 15) * nx1;
+            const int64_t oE = vE ? (kE - D) : 0, oO = vO ? (kO - D) : 0;
+            const double mE = vE ? 1.0 : 0.0, mO = vO ? 1.0 : 0.0;
+            int cxy0, czd0, cxy1, czd1;
+            double e0, o0, e1, o1;
+            auto fetch = [&](int step, int& cxy, int& czd, double& e, double& o) {
+                const int cn = 4 * step + lq;
+                const bool ok = cn < Nc;
+                const int cc = ok ? cn : 0;
+                cxy = sCol[2 * cc];
+                czd = ok ? sCol[2 * cc + 1] : (sCol[2 * cc + 1] | (255 << 16));
+                e = muY[(int64_t)cc * n_int + oE];
+                o = muY[(int64_t)cc * n_int + oO];
+            };
+            fetch(sbeg, cxy0, czd0, e0, o0);
+            int s = sbeg;
 #pragma unroll
-                for (int i = 0; i < MAXS; ++i) {
-                    if (s < ks[i]) {
-                        double A = 0.0;
-                        if ((rZD[i] >> 16) + cdeg <= mx)
-                            A = sEx[cX + (rXY[i] & 0xffff)] * sEy[cY + (rXY[i] >> 16)] * sEz[cZ + (rZD[i] & 0xffff)];
-                        if (D == 2) accE[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, bE, accE[i], 0, 0, 0);
-                        accO[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, bO, accO[i], 0, 0, 0);
+            for (int n = MAXS; n >= 1; --n) {
+                const int s_end = ks[n - 1];
+                for (; s < s_end; ++s) {
+                    fetch(s + 1, cxy1, czd1, e1, o1);
+                    const int cdeg = czd0 >> 16;
+                    const double bE = e0 * mE, bO = o0 * mO;
+                    const int cX = cxy0 & 0xffff, cY = cxy0 >> 16, cZ = czd0 & 0xffff;
+                    double A[MAXS];
+#pragma unroll
+                    for (int i = 0; i < n; ++i) {
+                        const double ex = sEx[cX + (rXY[i] & 0xffff)];
+                        const double ey = sEy[cY + (rXY[i] >> 16)];
+                        const double ez = sEz[cZ + (rZD[i] & 0xffff)];
+                        const double msk = ((rZD[i] >> 16) + cdeg <= mx) ? 1.0 : 0.0;
+                        A[i] = (ex * ey) * (ez * msk);
                     }
+#pragma unroll
+                    for (int i = 0; i < n; ++i) {
+                        if (D == 2) accE[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bE, accE[i], 0, 0, 0);
+                        accO[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bO, accO[i], 0, 0, 0);
+                    }
+                    cxy0 = cxy1; czd0 = czd1; e0 = e1; o0 = o1;
                 }
-                ci = ci_n;
-                bE = bE_n;
-                bO = bO_n;
             }
         }
     }
+    // partial segments: park in LDS, owners add them in a fixed order
+    __syncthreads();
+    double* red = smem;   // [n_partial][8][64]
 #pragma unroll
     for (int i = 0; i < MAXS; ++i) {
-        if (tiles[i] < 0) continue;
+        if (tiles[i] >= 0 && part[i] >= 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                red[((int64_t)part[i] * 8 + r) * kWave + lane] = accE[i][r];
+                red[((int64_t)part[i] * 8 + 4 + r) * kWave + lane] = accO[i][r];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        if (tiles[i] < 0 || part[i] >= 0) continue;
+        // add every partial segment of this tile (they follow in seg order)
+        for (int q = 0; q < n_partial; ++q) {
+            if (seg[(kM2LWaves * MAXS) * 3 + q] != tiles[i]) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                accE[i][r] += red[((int64_t)q * 8 + r) * kWave + lane];
+                accO[i][r] += red[((int64_t)q * 8 + 4 + r) * kWave + lane];
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * tiles[i] + lq + 4 * r;
@@ -797,6 +842,7 @@ struct pfmm_tree {
     int* slot_tile = nullptr;     // [groups][mfma_slots] row tiles per wave group (-1 = none)
     int* tile_ks = nullptr;       // K-steps per 16-row tile
     int mfma_slots = 0;           // 0: matrix-core M2L not used
+    int n_partial = 0;            // split-K partial segments
     CoefMaps cm{};
     std::vector<DevLevel> lv;
     bool low_leaves = false;      // leaves at levels < 2 (no far field)
@@ -994,43 +1040,92 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
     PF_TRY(upload(t, &t->Cab, F.Cab.data(), F.Cab.size()));
     double* E1 = t->E1;
     double* Cab = t->Cab;
-    // matrix-core M2L: 16-row tiles, their K-step counts, LPT split over 4 wave groups
+    // matrix-core M2L: 16-row tiles, their K-step counts, split-K segments over waves
     {
         const int Nc = P.Nc, ntile = (Nc + 15) / 16;
         std::vector<int> pk(Nc), ks(ntile);
         for (int c = 0; c < Nc; ++c)
             pk[c] = P.coef_a[c] | (P.coef_k[3 * c] << 4) | (P.coef_k[3 * c + 1] << 8) | (P.coef_k[3 * c + 2] << 12) |
                     (P.coef_deg[c] << 16);
+        int64_t total = 0;
         for (int tt = 0; tt < ntile; ++tt) {
             const int dmin = P.coef_deg[16 * tt];
             const int cols = (P.m_t + 1) * binom(P.m_x - dmin + 3, 3);
             ks[tt] = (cols + 3) / 4;
+            total += ks[tt];
         }
-        std::vector<int> order(ntile);
-        for (int i = 0; i < ntile; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ks[a] > ks[b]; });
-        std::vector<std::vector<int>> grp(kM2LGroups);
-        std::vector<int64_t> load(kM2LGroups, 0);
-        for (int tt : order) {
-            int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            grp[g].push_back(tt);
-            load[g] += ks[tt];
+        // find the smallest block length T whose split fits kM2LWaves waves x kM2LSlots slots
+        std::vector<std::array<int, 3>> best;   // per wave later
+        std::vector<int> wmeta, segtab, redtile;
+        bool ok = false;
+        for (int T = (int)((total + kM2LWaves - 1) / kM2LWaves); T <= 4096 && !ok; ++T) {
+            // segments per K-block b: [b*T, min((b+1)*T, ks))
+            int nblk = 0;
+            for (int tt = 0; tt < ntile; ++tt) nblk = std::max(nblk, (ks[tt] + T - 1) / T);
+            std::vector<std::vector<std::array<int, 2>>> blk(nblk);   // (tile, end)
+            for (int tt = 0; tt < ntile; ++tt)
+                for (int b = 0; b * T < ks[tt]; ++b) blk[b].push_back({tt, std::min((b + 1) * T, ks[tt])});
+            // waves per block: LPT with at most kM2LSlots segments and load <= T
+            std::vector<int> meta;
+            std::vector<std::vector<std::array<int, 2>>> waves;
+            bool fit = true;
+            for (int b = 0; b < nblk && fit; ++b) {
+                auto& sg = blk[b];
+                std::stable_sort(sg.begin(), sg.end(), [](const std::array<int, 2>& x, const std::array<int, 2>& y) { return x[1] > y[1]; });
+                std::vector<std::vector<std::array<int, 2>>> wv;
+                std::vector<int> load;
+                for (auto& g : sg) {
+                    const int len = g[1] - b * T;
+                    int pick = -1;
+                    for (size_t i = 0; i < wv.size(); ++i)
+                        if ((int)wv[i].size() < kM2LSlots && load[i] + len <= T && (pick < 0 || load[i] < load[pick])) pick = (int)i;
+                    if (pick < 0) { wv.push_back({}); load.push_back(0); pick = (int)wv.size() - 1; }
+                    wv[pick].push_back(g);
+                    load[pick] += len;
+                }
+                for (auto& x : wv) { waves.push_back(x); meta.push_back(b * T); }
+                if ((int)waves.size() > kM2LWaves) fit = false;
+            }
+            if (!fit) continue;
+            ok = true;
+            // tables: per wave (start, count); per slot (tile, end, partial index)
+            wmeta.assign(2 * kM2LWaves, 0);
+            segtab.assign((size_t)kM2LWaves * kM2LSlots * 3, -1);
+            for (int wv = 0; wv < kM2LWaves; ++wv) {
+                wmeta[2 * wv] = wv < (int)waves.size() ? meta[wv] : 0;
+                wmeta[2 * wv + 1] = wv < (int)waves.size() ? (int)waves[wv].size() : 0;
+                for (int i = 0; i < kM2LSlots; ++i) {
+                    int* e = &segtab[((size_t)wv * kM2LSlots + i) * 3];
+                    if (wv < (int)waves.size() && i < (int)waves[wv].size()) {
+                        e[0] = waves[wv][i][0];
+                        e[1] = waves[wv][i][1];
+                        e[2] = -1;
+                        if (meta[wv] > 0) { e[2] = (int)redtile.size(); redtile.push_back(e[0]); }
+                    } else {
+                        e[0] = -1; e[1] = meta[wv < (int)waves.size() ? wv : 0] * 0; e[2] = -1;
+                    }
+                }
+            }
         }
-        size_t ms = 0;
-        for (auto& g : grp) ms = std::max(ms, g.size());
-        int slots = ms <= 2 ? 2 : ms <= 4 ? 4 : ms <= 7 ? 7 : ms <= 10 ? 10 : 0;
+        // a wave's segments must be sorted by end (descending) for the phase loop; empty slots end at start
+        int slots = ok ? kM2LSlots : 0;
         if (P.m_t > 15 || P.m_x > 15) slots = 0;
         const size_t shm = (size_t)3 * (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1) * sizeof(double) +
-                           (size_t)P.Nc * sizeof(int);
-        if (shm > 65536) slots = 0;       // coefficient tables must fit the default LDS allocation
+                           (size_t)2 * P.Nc * sizeof(int);
+        if (shm > 65536 || redtile.size() * 8 * 64 * sizeof(double) > shm) slots = 0;
         t->mfma_slots = slots;
         if (slots) {
-            std::vector<int> st(kM2LGroups * slots, -1);
-            for (int g = 0; g < kM2LGroups; ++g)
-                for (size_t i = 0; i < grp[g].size(); ++i) st[g * slots + i] = grp[g][i];
+            for (int wv = 0; wv < kM2LWaves; ++wv)
+                for (int i = 0; i < kM2LSlots; ++i) {
+                    int* e = &segtab[((size_t)wv * kM2LSlots + i) * 3];
+                    if (e[0] < 0) e[1] = wmeta[2 * wv];
+                }
+            std::vector<int> segall(segtab);
+            segall.insert(segall.end(), redtile.begin(), redtile.end());
+            t->n_partial = (int)redtile.size();
             PF_TRY(upload(t, &t->packinfo, pk.data(), pk.size()));
-            PF_TRY(upload(t, &t->slot_tile, st.data(), st.size()));
-            PF_TRY(upload(t, &t->tile_ks, ks.data(), ks.size()));
+            PF_TRY(upload(t, &t->slot_tile, segall.data(), segall.size()));
+            PF_TRY(upload(t, &t->tile_ks, wmeta.data(), wmeta.size()));
         }
     }
     // levels
@@ -1176,18 +1271,13 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
             DevLevel& D = t->lv[l];
             if (t->mfma_slots) {
                 const int nt1 = P.m_t + 1, nx1 = P.m_x + 1;
-                const size_t shm = (size_t)3 * nt1 * nt1 * nx1 * nx1 * sizeof(double) + (size_t)P.Nc * sizeof(int);
+                const size_t shm = (size_t)3 * nt1 * nt1 * nx1 * nx1 * sizeof(double) + (size_t)2 * P.Nc * sizeof(int);
                 dim3 grid(D.nx, (D.n_int + 63) / 64, D.n_int > 32 ? 2 : 1);
-                dim3 block(64 * kM2LGroups);
+                dim3 block(64 * kM2LWaves);
 #define M2L_MFMA(S) hipLaunchKernelGGL(k_m2l_mfma<S>, grid, block, shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src,      \
                                        D.m2l_cls, D.off3, t->E1 + D.e1_off, t->Cab + D.cab_off, t->packinfo,      \
-                                       t->slot_tile, t->tile_ks, P.Nc, D.n_int, P.m_t, P.m_x, D.R)
-                switch (t->mfma_slots) {
-                    case 2: M2L_MFMA(2); break;
-                    case 4: M2L_MFMA(4); break;
-                    case 7: M2L_MFMA(7); break;
-                    default: M2L_MFMA(10); break;
-                }
+                                       t->tile_ks, t->slot_tile, t->n_partial, P.Nc, D.n_int, P.m_t, P.m_x, D.R)
+                M2L_MFMA(kM2LSlots);
 #undef M2L_MFMA
             } else {
                 dim3 grid(D.nx, (D.n_int + kWave - 1) / kWave, t->F.n_chunks);
