@@ -85,6 +85,9 @@ typedef struct {
     int64_t  near_row_groups;    /* (leaf, time step) row groups of the nearfield    */
     int64_t  distinct_integrals; /* entries of the distinct panel-integral table    */
     uint64_t device_bytes;       /* device memory owned by the tree                  */
+    int32_t  m2l_matrix_cores;   /* 1: M2L on FP64 matrix cores, 0: vector units,
+                                    -1: not decided (host-only planning)           */
+    int32_t  reserved;
 } pfmm_stats;
 
 /* Fill *out with the default parameters above.  Returns PFMM_EINVAL on NULL. */

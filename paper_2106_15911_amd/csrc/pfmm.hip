@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -269,7 +270,8 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
     const double* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
     const int* __restrict__ cls, const int* __restrict__ off3, const double* __restrict__ E1,
     const double* __restrict__ Cab, const int* __restrict__ packinfo, const int* __restrict__ wave_meta,
-    const int* __restrict__ seg, int n_partial, int Nc, int n_int, int mt, int mx, int R) {
+    const int* __restrict__ seg, int n_partial, int Nc, int n_int, int mt, int mx, int R, int nsplit,
+    int halves, double* __restrict__ lam_parts) {
     extern __shared__ double smem[];
     const int nt1 = mt + 1, nx1 = mx + 1;
     const int nx2 = nx1 * nx1;
@@ -280,8 +282,10 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
     int* sCol = (int*)(smem + 3 * TS);           // per coefficient: table column offsets (x | y<<16), (z | deg<<16)
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int half = blockIdx.z;
+    const int half = blockIdx.z % halves;
+    const int split = blockIdx.z / halves;     // which share of the source list this workgroup takes
     const int X = blockIdx.x;
+    if (split > 0) lam = lam_parts + (int64_t)(split - 1) * ((int64_t)gridDim.x * Nc * n_int);
     const int lr = lane & 15, lq = lane >> 4;
     const int kE = blockIdx.y * 64 + 32 * half + 2 * lr;
     const int kO = kE + 1;
@@ -292,7 +296,7 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
         sCol[2 * c + 1] = (cb + ((ci >> 12) & 15) * nx1) | (((ci >> 16) & 255) << 16);
     }
     const int sbeg = __builtin_amdgcn_readfirstlane(wave_meta[2 * w]);
-    int tiles[MAXS], ks[MAXS], part[MAXS], rXY[MAXS], rZD[MAXS];
+    int tiles[MAXS], ks[MAXS], part[MAXS], rX[MAXS], rY[MAXS], rZ[MAXS], rD[MAXS];
 #pragma unroll
     for (int i = 0; i < MAXS; ++i) {
         tiles[i] = __builtin_amdgcn_readfirstlane(seg[(w * MAXS + i) * 3]);
@@ -302,8 +306,10 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
         const bool rv = tiles[i] >= 0 && row < Nc;
         const int ri = rv ? packinfo[row] : 0;
         const int b = ri & 15;
-        rXY[i] = (b * nx2 + ((ri >> 4) & 15)) | ((b * nx2 + ((ri >> 8) & 15)) << 16);
-        rZD[i] = (b * nx2 + ((ri >> 12) & 15)) | ((rv ? ((ri >> 16) & 255) : 255) << 16);
+        rX[i] = b * nx2 + ((ri >> 4) & 15);
+        rY[i] = b * nx2 + ((ri >> 8) & 15);
+        rZ[i] = b * nx2 + ((ri >> 12) & 15);
+        rD[i] = mx - (rv ? ((ri >> 16) & 255) : 255);   // largest column degree this row accepts
     }
     d4_t accE[MAXS], accO[MAXS];
 #pragma unroll
@@ -312,7 +318,10 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
         accO[i] = d4_t{0.0, 0.0, 0.0, 0.0};
     }
     const int nR = 2 * R + 1;
-    for (int si = ptr[X]; si < ptr[X + 1]; ++si) {
+    const int sb = ptr[X], se = ptr[X + 1];
+    const int s_lo = sb + (int)(((int64_t)(se - sb) * split) / nsplit);
+    const int s_hi = sb + (int)(((int64_t)(se - sb) * (split + 1)) / nsplit);
+    for (int si = s_lo; si < s_hi; ++si) {
         const int Y = src[si];
         const int c3 = cls[si];
         const double* muY = mu + (int64_t)Y * Nc * n_int;
@@ -346,33 +355,60 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
                 e = muY[(int64_t)cc * n_int + oE];
                 o = muY[(int64_t)cc * n_int + oO];
             };
-            fetch(sbeg, cxy0, czd0, e0, o0);
-            int s = sbeg;
+            // one K-step with n active slots, operands taken from (cxy, czd, e, o)
+            auto step = [&](auto nc, int cxy, int czd, double e, double o) {
+                constexpr int n = decltype(nc)::value;
+                const int cdeg = czd >> 16;
+                const double bE = e * mE, bO = o * mO;
+                const int cX = cxy & 0xffff, cY = cxy >> 16, cZ = czd & 0xffff;
+                double A[n];
 #pragma unroll
-            for (int n = MAXS; n >= 1; --n) {
-                const int s_end = ks[n - 1];
-                for (; s < s_end; ++s) {
-                    fetch(s + 1, cxy1, czd1, e1, o1);
-                    const int cdeg = czd0 >> 16;
-                    const double bE = e0 * mE, bO = o0 * mO;
-                    const int cX = cxy0 & 0xffff, cY = cxy0 >> 16, cZ = czd0 & 0xffff;
-                    double A[MAXS];
-#pragma unroll
-                    for (int i = 0; i < n; ++i) {
-                        const double ex = sEx[cX + (rXY[i] & 0xffff)];
-                        const double ey = sEy[cY + (rXY[i] >> 16)];
-                        const double ez = sEz[cZ + (rZD[i] & 0xffff)];
-                        const double msk = ((rZD[i] >> 16) + cdeg <= mx) ? 1.0 : 0.0;
-                        A[i] = (ex * ey) * (ez * msk);
-                    }
-#pragma unroll
-                    for (int i = 0; i < n; ++i) {
-                        if (D == 2) accE[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bE, accE[i], 0, 0, 0);
-                        accO[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bO, accO[i], 0, 0, 0);
-                    }
-                    cxy0 = cxy1; czd0 = czd1; e0 = e1; o0 = o1;
+                for (int i = 0; i < n; ++i) {
+                    const double ex = sEx[cX + rX[i]];
+                    const double ey = sEy[cY + rY[i]];
+                    const double ez = sEz[cZ + rZ[i]];
+                    const double msk = (cdeg <= rD[i]) ? 1.0 : 0.0;
+                    A[i] = (ex * ey) * (ez * msk);
                 }
-            }
+#pragma unroll
+                for (int i = 0; i < n; ++i) {
+                    if (D == 2) accE[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bE, accE[i], 0, 0, 0);
+                    accO[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bO, accO[i], 0, 0, 0);
+                }
+            };
+            // two operand sets used alternately: the set consumed at step s is
+            // refilled with step s+2, so a load has a full step of work to land
+            fetch(sbeg, cxy0, czd0, e0, o0);
+            fetch(sbeg + 1, cxy1, czd1, e1, o1);
+            int s = sbeg;
+            auto phase = [&](auto nc, int s_end) {
+                for (; s + 1 < s_end; s += 2) {
+                    {
+                        const int a0 = cxy0, b0 = czd0;
+                        const double f0 = e0, g0 = o0;
+                        fetch(s + 2, cxy0, czd0, e0, o0);
+                        step(nc, a0, b0, f0, g0);
+                    }
+                    {
+                        const int a1 = cxy1, b1 = czd1;
+                        const double f1 = e1, g1 = o1;
+                        fetch(s + 3, cxy1, czd1, e1, o1);
+                        step(nc, a1, b1, f1, g1);
+                    }
+                }
+                if (s < s_end) {
+                    const int a0 = cxy0, b0 = czd0;
+                    const double f0 = e0, g0 = o0;
+                    cxy0 = cxy1; czd0 = czd1; e0 = e1; o0 = o1;
+                    fetch(s + 2, cxy1, czd1, e1, o1);
+                    step(nc, a0, b0, f0, g0);
+                    ++s;
+                }
+            };
+            static_assert(MAXS == 3, "phase dispatch below is written for three slots");
+            phase(std::integral_constant<int, 3>{}, ks[2]);
+            phase(std::integral_constant<int, 2>{}, ks[1]);
+            phase(std::integral_constant<int, 1>{}, ks[0]);
         }
     }
     // partial segments: park in LDS, owners add them in a fixed order
@@ -409,6 +445,16 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
             if (kO < n_int) lam[((int64_t)X * Nc + row) * n_int + kO] = accO[i][r];
         }
     }
+}
+
+// Sum the per-share partial locals of a level whose interaction lists were
+// split over several workgroups (fixed order: share 0, 1, ...).
+__global__ void k_sum_parts(double* __restrict__ lam, const double* __restrict__ parts, int nparts, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = lam[i];
+    for (int p = 0; p < nparts; ++p) s += parts[(int64_t)p * n + i];
+    lam[i] = s;
 }
 
 // L2L (transpose of eqs. temp_m2m / st_m2m) from level l-1 into every box of level l.
@@ -810,6 +856,8 @@ struct DevLevel {
     int* m2l_src = nullptr;
     int* m2l_cls = nullptr;
     double* ops = nullptr;
+    double* lam_parts = nullptr;  // extra shares of a split interaction list
+    int nsplit = 1;
     int* off3 = nullptr;
     int64_t at_off = 0, qt_off = -1, qx_off = -1, e1_off = 0, cab_off = 0;
     int n_off = 0, R = 0;
@@ -843,6 +891,7 @@ struct pfmm_tree {
     int* tile_ks = nullptr;       // K-steps per 16-row tile
     int mfma_slots = 0;           // 0: matrix-core M2L not used
     int n_partial = 0;            // split-K partial segments
+    size_t m2l_shm = 0;           // dynamic LDS of the matrix-core M2L
     CoefMaps cm{};
     std::vector<DevLevel> lv;
     bool low_leaves = false;      // leaves at levels < 2 (no far field)
@@ -1110,9 +1159,11 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         // a wave's segments must be sorted by end (descending) for the phase loop; empty slots end at start
         int slots = ok ? kM2LSlots : 0;
         if (P.m_t > 15 || P.m_x > 15) slots = 0;
-        const size_t shm = (size_t)3 * (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1) * sizeof(double) +
-                           (size_t)2 * P.Nc * sizeof(int);
-        if (shm > 65536 || redtile.size() * 8 * 64 * sizeof(double) > shm) slots = 0;
+        const size_t shm = std::max((size_t)3 * (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1) * sizeof(double) +
+                                        (size_t)2 * P.Nc * sizeof(int),
+                                    redtile.size() * 8 * 64 * sizeof(double));
+        if (shm > 65536) slots = 0;
+        t->m2l_shm = shm;
         t->mfma_slots = slots;
         if (slots) {
             for (int wv = 0; wv < kM2LWaves; ++wv)
@@ -1146,6 +1197,15 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         PF_TRY(upload(t, &D.off3, FL.off3.data(), FL.off3.size()));
         PF_TRY(dalloc(t, &D.mu, (size_t)D.nx * P.Nc * D.n_int));
         PF_TRY(dalloc(t, &D.lam, (size_t)D.nx * P.Nc * D.n_int));
+        {
+            // enough workgroups to fill the chip several times: split source lists otherwise
+            int dev = 0, ncu = 256;
+            if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+            const int64_t wg = (int64_t)D.nx * ((D.n_int + 63) / 64) * (D.n_int > 32 ? 2 : 1);
+            D.nsplit = 1;
+            while (D.nsplit < 4 && wg * D.nsplit < 4 * ncu) D.nsplit *= 2;
+            if (D.nsplit > 1) PF_TRY(dalloc(t, &D.lam_parts, (size_t)(D.nsplit - 1) * D.nx * P.Nc * D.n_int));
+        }
         PF_TRY(upload(t, &D.leaf_xs, FL.leaf_xs.data(), FL.leaf_xs.size()));
         PF_TRY(upload(t, &D.ax_off, FL.ax_off.data(), FL.ax_off.size()));
         PF_TRY(upload(t, &D.tb, L.tb.data(), L.tb.size()));
@@ -1270,15 +1330,19 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         for (int l = 2; l <= P.depth; ++l) {
             DevLevel& D = t->lv[l];
             if (t->mfma_slots) {
-                const int nt1 = P.m_t + 1, nx1 = P.m_x + 1;
-                const size_t shm = (size_t)3 * nt1 * nt1 * nx1 * nx1 * sizeof(double) + (size_t)2 * P.Nc * sizeof(int);
-                dim3 grid(D.nx, (D.n_int + 63) / 64, D.n_int > 32 ? 2 : 1);
+                const size_t shm = t->m2l_shm;
+                const int halves = D.n_int > 32 ? 2 : 1;
+                dim3 grid(D.nx, (D.n_int + 63) / 64, halves * D.nsplit);
                 dim3 block(64 * kM2LWaves);
-#define M2L_MFMA(S) hipLaunchKernelGGL(k_m2l_mfma<S>, grid, block, shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src,      \
-                                       D.m2l_cls, D.off3, t->E1 + D.e1_off, t->Cab + D.cab_off, t->packinfo,      \
-                                       t->tile_ks, t->slot_tile, t->n_partial, P.Nc, D.n_int, P.m_t, P.m_x, D.R)
-                M2L_MFMA(kM2LSlots);
-#undef M2L_MFMA
+                // share 0 writes lambda, share p >= 1 writes lam_parts + (p - 1) * (slots * Nc * n_int)
+                const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
+                hipLaunchKernelGGL(k_m2l_mfma<kM2LSlots>, grid, block, shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src,
+                                   D.m2l_cls, D.off3, t->E1 + D.e1_off, t->Cab + D.cab_off, t->packinfo, t->tile_ks,
+                                   t->slot_tile, t->n_partial, P.Nc, D.n_int, P.m_t, P.m_x, D.R, D.nsplit, halves,
+                                   D.lam_parts);
+                if (D.nsplit > 1)
+                    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam,
+                                       D.lam_parts, D.nsplit - 1, nl);
             } else {
                 dim3 grid(D.nx, (D.n_int + kWave - 1) / kWave, t->F.n_chunks);
                 hipLaunchKernelGGL(k_m2l, grid, dim3(kWave), 0, st, D.mu, D.lam, D.ops, D.m2l_ptr, D.m2l_src,
@@ -1319,7 +1383,7 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
     return PFMM_OK;
 }
 
-void fill_stats(const Plan& P, uint64_t bytes, pfmm_stats* out) {
+void fill_stats(const Plan& P, uint64_t bytes, pfmm_stats* out, int m2l_mfma) {
     out->depth = P.depth;
     out->n_levels_far = P.depth >= 2 ? P.depth - 1 : 0;
     out->boxes = P.n_boxes;
@@ -1329,6 +1393,7 @@ void fill_stats(const Plan& P, uint64_t bytes, pfmm_stats* out) {
     out->near_row_groups = (int64_t)P.rows.size();
     out->distinct_integrals = P.distinct;
     out->device_bytes = bytes;
+    out->m2l_matrix_cores = m2l_mfma;
 }
 
 }  // namespace
@@ -1367,7 +1432,7 @@ pfmm_status pfmm_plan_stats(const double* vertices, int64_t n_vertices, const in
         if (s != PFMM_OK) return fail(s, msg);
         FarTables F;
         build_far_tables(P, F);
-        fill_stats(P, estimate_bytes(P, F, prm.operators), out);
+        fill_stats(P, estimate_bytes(P, F, prm.operators), out, -1);
     } catch (const std::bad_alloc&) {
         return fail(PFMM_ENOMEM, "host allocation failed while planning");
     } catch (const std::exception& e) {
@@ -1435,7 +1500,7 @@ pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void*
 
 pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out) {
     if (!t || !out) return fail(PFMM_EINVAL, "NULL argument");
-    fill_stats(t->P, t->bytes, out);
+    fill_stats(t->P, t->bytes, out, t->mfma_slots > 0 ? 1 : 0);
     return PFMM_OK;
 }
 

@@ -37,7 +37,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("n_levels_far", ctypes.c_int32), ("boxes", ctypes.c_int64),
                 ("leaves", ctypes.c_int64), ("near_entries", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
                 ("near_row_groups", ctypes.c_int64), ("distinct_integrals", ctypes.c_int64),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("m2l_matrix_cores", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -72,3 +72,32 @@ def test_deterministic_and_errors():
     with pytest.raises(ValueError):
         tree.apply_V(x[:-1])
     tree.close()
+
+
+@pytest.mark.parametrize("kind", ["V", "K"])
+def test_c1_mesh_degree6_matrix_cores(kind):
+    """Degrees 6/6 on the 192 x 16 mesh: exercises the FP64 matrix-core M2L
+    (split-K segments, split interaction lists) against the oracle."""
+    print(f"[parity] c1 m=6 kind={kind}", flush=True)
+    v, t, tn, w = problem(4, 16, seed=5)
+    tree = P.Tree(v, t, tn, P.default_params(m_t=6, m_x=6), device=0)
+    assert tree.stats()["m2l_matrix_cores"] == 1
+    x = torch.from_numpy(w).to("cuda:0")
+    g = (tree.apply_V(x) if kind == "V" else tree.apply_K(x)).cpu().numpy()
+    tree.close()
+    r = reference(v, t, tn, w, kind, m_t=6, m_x=6)
+    _check(g, r)
+
+
+def test_vector_unit_m2l_above_matrix_core_limits():
+    """Degrees 7/7 exceed the LDS budget of the matrix-core M2L; the vector-unit
+    M2L with explicit operators must give the same product as the oracle."""
+    print("[parity] m=7 vector-unit M2L", flush=True)
+    v, t, tn, w = problem(2, 8, seed=9)
+    prm = dict(m_t=7, m_x=7, n_max=8, n_tr=-1)
+    tree = P.Tree(v, t, tn, P.default_params(**prm), device=0)
+    assert tree.stats()["m2l_matrix_cores"] == 0
+    x = torch.from_numpy(w).to("cuda:0")
+    g = tree.apply_V(x).cpu().numpy()
+    tree.close()
+    _check(g, reference(v, t, tn, w, "V", **prm))
