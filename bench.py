@@ -24,39 +24,103 @@ METRIC = "space-time DOF matvec/s of pFMM V_h at 1e-6 rel err; GMRES solve time 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 
+# HBM bytes per apply from rocprofv3 FETCH_SIZE / WRITE_SIZE runs on the
+# 3072 x 256, m = 6 workload, scaled by the same counters on a plain 1 GiB
+# device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid only for the
+# kernel source they were taken on; any change to it reports null.
+TRAFFIC = {
+    "source_sha256_prefix": "79434b790ab7c4d9",
+    "config": 2,
+    "k_near_apply": 55682184181.0,
+    "k_m2l_mfma": 52984278396.0,
+}
+
+
+def measured_traffic(kernel, cfg):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2106_15911_amd", "csrc", "pfmm.hip")
+    with open(src, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    if sha != TRAFFIC["source_sha256_prefix"] or cfg != TRAFFIC["config"]:
+        return None
+    return TRAFFIC.get(kernel)
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, rows, w):
-    """The CPU oracle on a bounded sample: full upward pass plus `rows` rows."""
+def cpu_baseline(cfg, w, per_level=12, leaves=12, seed=123):
+    """The CPU oracle's full V_h apply, timed on a bounded sample and scaled.
+
+    The oracle's apply is a loop over boxes: moments of every box (timed in
+    full), then per level the M2L and L2L of each box, then per leaf the L2T
+    and the nearfield blocks.  A random sample of boxes per level and of
+    leaves is timed and scaled by the number of boxes.
+    """
     import numpy as np
     from oracle.fmm import FMMOracle
     from oracle.tree import Tree
     from workloads import config_problem
     v, t, tn, c, _ = config_problem(cfg)
+    rng = np.random.default_rng(seed)
     t0 = time.perf_counter()
     tr = Tree(v, t, tn, 1.0, c["n_max"], c["c_st"], c["n_tr"])
     o = FMMOracle(tr, c["m_t"], c["m_x"], "V")
     mu = o.moments(w)
     t_up = time.perf_counter() - t0
-    rng = np.random.default_rng(123)
-    sample = rng.choice(len(w), rows, replace=False)
+    est, timed, n_far = t_up, t_up, 0
+    for l in range(2, tr.depth + 1):
+        boxes = tr.levels[l]
+        pick = rng.choice(len(boxes), min(per_level, len(boxes)), replace=False)
+        t0 = time.perf_counter()
+        for i in pick:
+            Z = boxes[int(i)]
+            lam_ = o.m2l(Z, mu)
+            if l >= 3:
+                lam_ = lam_ + o.l2l(Z, Z.parent, np.zeros_like(lam_))
+        dt = time.perf_counter() - t0
+        timed += dt
+        n_far += len(pick)
+        est += dt * len(boxes) / len(pick)
+    pick = rng.choice(len(tr.leaves), leaves, replace=False)
+    memo = {}
     t0 = time.perf_counter()
-    vals, _ = o.apply_rows(w, sample, mu)
-    t_rows = time.perf_counter() - t0
+    for i in pick:
+        Z = tr.leaves[int(i)]
+        rows = tr.elements(Z)
+        f = o.l2t(Z, np.zeros((c["m_t"] + 1, o.Nk))).ravel()
+        for S in tr.nearfield(Z, memo):
+            f = f + o.near_block(Z, S) @ w[tr.elements(S)]
+    dt = time.perf_counter() - t0
+    timed += dt
+    est += dt * len(tr.leaves) / leaves
     N = len(w)
-    est = t_up + t_rows * N / rows
     try:
         from threadpoolctl import threadpool_info
         blas = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
         blas = 1
     return {"value": N / est, "unit": "DOF-matvec/s", "cores": int(blas), "kind": "oracle",
-            "sample": (f"tree + upward pass ({t_up:.1f} s) + {rows} random rows of V_h w "
-                       f"({t_rows:.1f} s), extrapolated to all {N} rows"),
-            "host_cpus": os.cpu_count()}, sample, vals
+            "sample": (f"oracle V_h apply on {N} DOFs: tree + all moments ({t_up:.1f} s) in full; M2L+L2L of "
+                       f"{n_far} sampled boxes (up to {per_level} per level) and L2T+nearfield of {leaves} "
+                       f"sampled leaves ({timed - t_up:.1f} s), scaled by box counts; estimated full apply "
+                       f"{est:.0f} s"),
+            "timed_s": timed, "host_cpus": os.cpu_count()}
+
+
+def oracle_rows(cfg, w, rows, seed=123):
+    """Sampled rows of the oracle product for an accuracy check of the timed result."""
+    import numpy as np
+    from oracle.fmm import FMMOracle
+    from oracle.tree import Tree
+    from workloads import config_problem
+    v, t, tn, c, _ = config_problem(cfg)
+    tr = Tree(v, t, tn, 1.0, c["n_max"], c["c_st"], c["n_tr"])
+    o = FMMOracle(tr, c["m_t"], c["m_x"], "V")
+    sample = np.random.default_rng(seed).choice(len(w), rows, replace=False)
+    vals, _ = o.apply_rows(w, sample)
+    return sample, vals
 
 
 def main():
@@ -66,12 +130,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=4)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--check-rows", type=int, default=0, help="compare this many sampled rows with the oracle")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the time-slice distribution across GPUs is described in DESIGN.md)", file=sys.stderr)
+              "(distributing time slices over GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -91,6 +156,15 @@ def main():
     t_build = time.perf_counter() - t0
     st = tree.stats()
     log(f"[bench] built config {args.config}: {st} in {t_build:.2f} s")
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {8 * n} bytes read, {8 * n} bytes written")
+        del a, b
     x = torch.from_numpy(w).to(dev)
     f = torch.empty_like(x)
     for _ in range(args.warmup):
@@ -119,27 +193,31 @@ def main():
     if near_ms >= m2l_ms:
         achieved = near_bytes / (near_ms * 1e-3) / 1e9
         roof = {"kernel": "k_near_apply", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_near_apply", args.config),
                 "launch_ms": near_ms, "algorithmic_bytes": near_bytes}
     else:
         achieved = m2l_flop / (m2l_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_m2l (all levels)", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS, "traffic": None,
+        roof = {"kernel": "k_m2l_mfma (all levels)" if st["m2l_matrix_cores"] == 1 else "k_m2l (all levels)",
+                "bound": "mfma" if st["m2l_matrix_cores"] == 1 else "alu", "achieved": achieved, "peak": FP64_PEAK_TFS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS,
+                "traffic": measured_traffic("k_m2l_mfma", args.config) if st["m2l_matrix_cores"] == 1 else None,
                 "launch_ms": m2l_ms, "algorithmic_flop": m2l_flop}
-    other = {"nearfield": {"ms": near_ms, "GB/s": near_bytes / (near_ms * 1e-3) / 1e9},
+    roof["traffic_note"] = "HBM bytes per apply, all launches of the kernel (rocprofv3 counters, copy-calibrated)"
+    other = {"nearfield": {"ms": near_ms, "GB/s": near_bytes / (near_ms * 1e-3) / 1e9,
+                           "traffic": measured_traffic("k_near_apply", args.config)},
              "m2l": {"ms": m2l_ms, "TFLOP/s": m2l_flop / (m2l_ms * 1e-3) / 1e12}}
 
     check = None
-    cpu = None
-    if not args.no_cpu_baseline or args.check_rows:
-        rows = max(args.cpu_rows, args.check_rows)
-        cpu, sample, vals = cpu_baseline(args.config, rows, w)
+    if args.check_rows:
+        sample, vals = oracle_rows(args.config, w, args.check_rows)
         fg = f.cpu().numpy()
         err = float(np.abs(fg[sample] - vals).max() / np.abs(vals).max())
-        check = {"rows": int(rows), "max_rel_err_vs_oracle": err}
+        check = {"rows": int(args.check_rows), "max_rel_err_vs_oracle": err}
         log(f"[bench] oracle rows check: {check}")
-        if args.no_cpu_baseline:
-            cpu = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.config, w)
+        log(f"[bench] cpu baseline: {cpu}")
 
     out = {
         "metric": METRIC,

@@ -1,0 +1,71 @@
+"""Dirichlet data of the paper's model problem, projected onto p0 x p0.
+
+Section 5 (eq. dirdata) prescribes u(x, t) = G(x - y*, t) on the lateral
+boundary, the heat fundamental solution with a source point y* outside the
+domain.  A source time t* shifts it to G(x - y*, t - t*).  The system of
+Section 2 needs the L2 projection g_h of u; in the p0 x p0 setting that is
+the element mean over every space-time element sigma = gamma x (t_{j-1}, t_j).
+
+The means are computed with a collapsed tensor Gauss-Legendre rule on each
+triangle (q x q points) times q_t Gauss-Legendre points per step.  This is
+input preparation (a datum and its projection), not part of the FMM.
+
+The manufactured Neumann datum alpha du/dn (the exact solution w of the
+boundary integral equation when u(., 0) = 0 inside the domain) is projected
+the same way, for convergence tests.
+"""
+import numpy as np
+
+
+def _heat(r2, s, alpha):
+    """G for squared distance r2 and time lag s (0 where s <= 0)."""
+    s = np.asarray(s, dtype=np.float64)
+    out = np.zeros(np.broadcast(r2, s).shape)
+    pos = np.broadcast_to(s > 0, out.shape)
+    sp = np.where(s > 0, s, 1.0)
+    val = (4.0 * np.pi * alpha * sp) ** -1.5 * np.exp(-r2 / (4.0 * alpha * sp))
+    out[pos] = np.broadcast_to(val, out.shape)[pos]
+    return out
+
+
+def _points(verts, tris, time_nodes, q, q_t):
+    """Quadrature points and weights (normalised to element means)."""
+    g, gw = np.polynomial.legendre.leggauss(q)
+    g, gw = 0.5 * (g + 1.0), 0.5 * gw
+    # collapsed rule on the unit triangle: (s, t s), s, t in (0, 1), Jacobian s
+    s = np.repeat(g, q)
+    t = np.tile(g, q)
+    w_tri = np.repeat(gw, q) * np.tile(gw, q) * s * 2.0      # sums to 1
+    P = verts[tris]                                           # (E_x, 3, 3)
+    X = (P[:, None, 0] + s[None, :, None] * (P[:, None, 1] - P[:, None, 0])
+         + (s * t)[None, :, None] * (P[:, None, 2] - P[:, None, 1]))
+    gt, gtw = np.polynomial.legendre.leggauss(q_t)
+    gt, gtw = 0.5 * (gt + 1.0), 0.5 * gtw
+    t0, t1 = time_nodes[:-1], time_nodes[1:]
+    T = t0[:, None] + (t1 - t0)[:, None] * gt[None, :]       # (E_t, q_t)
+    return X, w_tri, T, gtw
+
+
+def _normals(verts, tris):
+    P = verts[tris]
+    n = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+    return n / np.linalg.norm(n, axis=1)[:, None]
+
+
+def project_source_datum(verts, tris, time_nodes, y_star, t_star=0.0, alpha=1.0, q=6, q_t=6):
+    """Element means of G(x - y*, t - t*) (natural time-major order, length E_t E_x)."""
+    X, w_tri, T, gtw = _points(verts, tris, time_nodes, q, q_t)
+    r2 = ((X - np.asarray(y_star, dtype=np.float64)) ** 2).sum(-1)          # (E_x, nq)
+    vals = _heat(r2[None, :, :, None], (T - t_star)[:, None, None, :], alpha)  # (E_t, E_x, nq, q_t)
+    return np.einsum("txqs,q,s->tx", vals, w_tri, gtw).ravel()
+
+
+def project_source_flux(verts, tris, time_nodes, y_star, t_star=0.0, alpha=1.0, q=6, q_t=6):
+    """Element means of alpha dG(x - y*, t - t*)/dn_x = -(x - y*).n / (2 (t - t*)) G."""
+    X, w_tri, T, gtw = _points(verts, tris, time_nodes, q, q_t)
+    d = X - np.asarray(y_star, dtype=np.float64)
+    r2 = (d ** 2).sum(-1)
+    dn = np.einsum("xqk,xk->xq", d, _normals(verts, tris))
+    s = (T - t_star)[:, None, None, :]
+    vals = _heat(r2[None, :, :, None], s, alpha) * (-dn[None, :, :, None]) / (2.0 * np.where(s > 0, s, 1.0))
+    return np.einsum("txqs,q,s->tx", vals, w_tri, gtw).ravel()
