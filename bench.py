@@ -123,6 +123,64 @@ def oracle_rows(cfg, w, rows, seed=123):
     return sample, vals
 
 
+def solve_bench(args):
+    """Dirichlet solve on the 12,288-triangle x 512-step cube: plain FP64 GMRES to 1e-8.
+
+    The right-hand side (1/2 M_h + K_h) g is formed on a tree holding only
+    K_h, which is then released; the solve runs on a tree holding only V_h
+    (the two stored nearfields do not fit 288 GB together at this size).
+    """
+    import numpy as np
+    import torch
+    import paper_2106_15911_amd as P
+    from workloads import config_problem
+    from workloads.dirichlet import project_source_datum
+    v, t, tn, c, _ = config_problem(args.config)
+    N = len(t) * (len(tn) - 1)
+    t0 = time.perf_counter()
+    g = project_source_datum(v, t, tn, (2.5, 0.0, 0.0), -0.1, 1.0)
+    t_g = time.perf_counter() - t0
+    log(f"[solve] datum projected in {t_g:.1f} s")
+    kw = dict(m_t=c["m_t"], m_x=c["m_x"], n_max=c["n_max"], c_st=c["c_st"], n_tr=c["n_tr"])
+    dev = torch.device("cuda:0")
+    gd = torch.from_numpy(g).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tk = P.Tree(v, t, tn, P.default_params(operators=2, **kw), device=0)
+    torch.cuda.synchronize()
+    t_bk = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b = tk.dirichlet_rhs(gd)
+    torch.cuda.synchronize()
+    t_rhs = time.perf_counter() - t0
+    tk.close()
+    t0 = time.perf_counter()
+    tv = P.Tree(v, t, tn, P.default_params(operators=1, **kw), device=0)
+    torch.cuda.synchronize()
+    t_bv = time.perf_counter() - t0
+    st = tv.stats()
+    log(f"[solve] K tree {t_bk:.2f} s, rhs {t_rhs * 1e3:.1f} ms, V tree {t_bv:.2f} s: {st}")
+    w, info = tv.solve_V(b, rtol=args.rtol, max_iter=args.max_iter)
+    torch.cuda.synchronize()
+    tv.close()
+    log(f"[solve] {info['iters']} iterations, {info['seconds']:.3f} s, true residual {info['true_rel_residual']:.3e}")
+    out = {
+        "metric": "GMRES time to relative residual 1e-8, plain FP64 (pFMM V_h, no preconditioner)",
+        "value": info["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+        "iterations": info["iters"], "ms_per_iteration": 1e3 * info["seconds"] / max(info["iters"], 1),
+        "converged": info["converged"], "rel_residual": info["rel_residual"],
+        "true_rel_residual": info["true_rel_residual"], "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"Dirichlet solve V_h w = (1/2 M_h + K_h) g, cube [-1,1]^3 {c['n']}x{c['n']} "
+                                f"squares/face ({len(t)} triangles) x {c['n_steps']} steps on [0,1], g = p0 "
+                                f"projection of G(x - (2.5,0,0), t + 0.1), alpha=1, m_t=m_x={c['m_t']}, "
+                                f"n_max={c['n_max']}, c_st={c['c_st']}, n_tr={c['n_tr']}"),
+                   "dofs": N},
+        "build_K_s": t_bk, "rhs_ms": 1e3 * t_rhs, "build_V_s": t_bv, "datum_s": t_g,
+        "history": info["history"], "tree": st,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,11 +191,20 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--check-rows", type=int, default=0, help="compare this many sampled rows with the oracle")
+    ap.add_argument("--solve", action="store_true",
+                    help="instead of the apply benchmark: Dirichlet solve on the 12,288 x 512 cube (config 5)")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--max-iter", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(distributing time slices over GPUs is not built)", file=sys.stderr)
         sys.exit(2)
+    if args.solve:
+        if args.config == 2:
+            args.config = 5
+        solve_bench(args)
+        return
 
     import numpy as np
     import torch

@@ -157,6 +157,68 @@ pfmm_status pfmm_plan_stats(const double* vertices, int64_t n_vertices,
 pfmm_status pfmm_profile_enable(pfmm_tree* t, int32_t enable);
 pfmm_status pfmm_profile_read(pfmm_tree* t, double* ms, int64_t* counts, int32_t* n_stages);
 
+/*
+ * Dirichlet solve (Section 2, system 02:linear:system; Section 5 solves it
+ * with GMRES without preconditioner to a relative precision of 1e-8).
+ */
+typedef struct {
+    double  rtol;            /* stop when the GMRES residual estimate
+                                ||b - V_h w_k||_2 / ||b||_2 <= rtol.              default 1e-8 */
+    int32_t max_iter;        /* Krylov dimension; no restart, 1..100000.         default 200  */
+    int32_t reserved;
+} pfmm_solve_opts;
+
+typedef struct {
+    int32_t iters;               /* GMRES iterations (V_h applies in the Arnoldi loop)         */
+    int32_t converged;           /* 1 if the estimate reached rtol                             */
+    double  rel_residual;        /* GMRES estimate at exit                                     */
+    double  true_rel_residual;   /* ||b - V_h w||_2 / ||b||_2, recomputed with one more apply  */
+    double  seconds;             /* wall time of the call                                      */
+    double* history;             /* optional caller-owned HOST array receiving the estimate
+                                    before iteration 1 (= 1) and after every iteration; NULL = none */
+    int32_t history_cap;         /* entries available in history                              */
+    int32_t history_len;         /* entries written                                            */
+} pfmm_solve_info;
+
+/* Fill *out with the defaults above.  Returns PFMM_EINVAL on NULL. */
+pfmm_status pfmm_default_solve_opts(pfmm_solve_opts* out);
+
+/*
+ * Solve V_h w = b by GMRES from w_0 = 0 (no restart, FP64 Arnoldi with
+ * classical Gram-Schmidt applied twice, Givens rotations).  b_dev and w_dev
+ * are device arrays of n_steps * n_triangles doubles in the natural order and
+ * must not alias.  o = NULL takes the defaults; info may be NULL.
+ * Synchronous: returns after the solve has finished on `stream`.  Allocates
+ * (max_iter + 1) Krylov vectors for the duration of the call and frees them.
+ * Errors: PFMM_EINVAL (NULL, bad options, V not built), PFMM_ENOMEM (workspace
+ * larger than free device memory), PFMM_ENONFINITE (b or an Arnoldi value not
+ * finite), PFMM_ENOTCONV (max_iter reached; w_dev then holds the last
+ * iterate and info is filled), PFMM_EDEVICE.
+ */
+pfmm_status pfmm_solve_V(pfmm_tree* t, const double* b_dev, double* w_dev, const pfmm_solve_opts* o,
+                         pfmm_solve_info* info, void* stream);
+
+/*
+ * b = (1/2 M_h + K_h) g, the right-hand side of the Dirichlet system, for the
+ * projected datum g (device, natural order; M_h is the diagonal p0 x p0 mass
+ * matrix |gamma_k| h_t).  Needs K_h built; asynchronous on `stream` like an
+ * apply; g_dev and b_dev must not alias.  With it a caller can form b on a
+ * tree holding only K_h, release it, and solve on a tree holding only V_h
+ * (for problems whose two nearfields do not fit the device together).
+ * Errors: PFMM_EINVAL (NULL, K not built), PFMM_EDEVICE.
+ */
+pfmm_status pfmm_dirichlet_rhs(pfmm_tree* t, const double* g_dev, double* b_dev, void* stream);
+
+/*
+ * Solve the Dirichlet problem V_h w = (1/2 M_h + K_h) g for the projected
+ * datum g (device, natural order, the p0 coefficients of the Dirichlet data;
+ * M_h is the diagonal p0 x p0 mass matrix |gamma_k| h_t).  Needs both V_h and
+ * K_h built.  Same conventions and errors as pfmm_solve_V; one more
+ * right-hand-side vector is allocated for the call.
+ */
+pfmm_status pfmm_solve_dirichlet(pfmm_tree* t, const double* g_dev, double* w_dev, const pfmm_solve_opts* o,
+                                 pfmm_solve_info* info, void* stream);
+
 /* Release every host and device resource of the tree.  NULL is a no-op. */
 void pfmm_destroy(pfmm_tree* t);
 

@@ -1,10 +1,11 @@
-"""MI355X space-time FMM for the heat equation (single- and double-layer apply).
+"""MI355X space-time FMM for the heat equation (single- and double-layer apply,
+Dirichlet solve).
 
 The compute path lives in the HIP library ``libpfmm.so`` (see include/pfmm.h);
 this package only loads it and marshals arguments.
 """
-from .pfmm import (PfmmError, Params, Tree, default_params, plan_stats, lib_path, load_library,
-                   STATUS_NAMES, PROFILE_STAGES)
+from .pfmm import (PfmmError, Params, SolveOpts, SolveInfo, Tree, default_params, plan_stats, lib_path,
+                   load_library, STATUS_NAMES, PROFILE_STAGES)
 
-__all__ = ["PfmmError", "Params", "Tree", "default_params", "plan_stats", "lib_path", "load_library",
-           "STATUS_NAMES", "PROFILE_STAGES"]
+__all__ = ["PfmmError", "Params", "SolveOpts", "SolveInfo", "Tree", "default_params", "plan_stats", "lib_path",
+           "load_library", "STATUS_NAMES", "PROFILE_STAGES"]

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpfmm.so")
-SOURCES = ["plan.cpp", "tables.cpp", "pfmm.hip"]
+SOURCES = ["plan.cpp", "tables.cpp", "pfmm.hip", "solve.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -19,16 +19,21 @@ FLAGS = [
 
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
+    objs, cmds = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
-        cmd = [hipcc] + FLAGS + ["-c", "-x", "hip", path, "-o", obj, "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([hipcc] + FLAGS + ["-c", "-x", "hip", path, "-o", obj, "-I", os.path.join(ROOT, "include"),
+                                       "-I", CSRC])
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=min(len(cmds), 4)) as ex:
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+        for f in [ex.submit(subprocess.run, cmd, check=True) for cmd in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     if verbose:

@@ -20,6 +20,7 @@
 #include <string>
 #include <vector>
 
+#include "internal.hpp"
 #include "near_kernels.hpp"
 #include "pfmm.h"
 #include "plan.hpp"
@@ -255,6 +256,7 @@ __global__ void __launch_bounds__(64) k_m2l(const double* __restrict__ mu, doubl
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kM2LWaves = 16;   // waves per workgroup (one interval half)
+constexpr int kXcds = 8;        // accelerator complex dies of an MI355X (one L2 each)
 constexpr int kM2LSlots = 3;    // accumulator slots (row-tile segments) per wave
 
 // Work split of one (X, interval half) output block.  Each 16-row tile's
@@ -268,26 +270,38 @@ constexpr int kM2LSlots = 3;    // accumulator slots (row-tile segments) per wav
 template <int MAXS>
 __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
     const double* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
-    const int* __restrict__ cls, const int* __restrict__ off3, const double* __restrict__ E1,
-    const double* __restrict__ Cab, const int* __restrict__ packinfo, const int* __restrict__ wave_meta,
+    const int* __restrict__ cls, const int* __restrict__ off3, const double* __restrict__ E1s, int TSp,
+    const int* __restrict__ packinfo, const int* __restrict__ wave_meta,
     const int* __restrict__ seg, int n_partial, int Nc, int n_int, int mt, int mx, int R, int nsplit,
     int halves, double* __restrict__ lam_parts) {
     extern __shared__ double smem[];
     const int nt1 = mt + 1, nx1 = mx + 1;
     const int nx2 = nx1 * nx1;
-    const int TS = nt1 * nt1 * nx2;
-    double* sEx = smem;
-    double* sEy = smem + TS;
-    double* sEz = smem + 2 * TS;
-    int* sCol = (int*)(smem + 3 * TS);           // per coefficient: table column offsets (x | y<<16), (z | deg<<16)
+    // two buffers of the three 1D tables of one (source, Delta) phase: [buf][x | y | z][TSp]
+    int* sCol = (int*)(smem + 6 * TSp);          // per coefficient: table column offsets (x | y<<16), (z | deg<<16)
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int half = blockIdx.z % halves;
-    const int split = blockIdx.z / halves;     // which share of the source list this workgroup takes
-    const int X = blockIdx.x;
+    // Workgroups are dealt to the 8 XCDs round-robin by linear id.  Remap so
+    // that each XCD walks a contiguous range of target slots (Morton order):
+    // concurrently running neighbours share most of their interaction lists,
+    // so the source moments they stream stay in that XCD's L2.
+    int bx, by, bz;
+    {
+        const int nxg = gridDim.x, nyg = gridDim.y;
+        const int total = nxg * nyg * gridDim.z;
+        const int lin = blockIdx.x + nxg * (blockIdx.y + nyg * blockIdx.z);
+        const int per = total / kXcds;
+        const int lm = lin < per * kXcds ? (lin % kXcds) * per + lin / kXcds : lin;
+        bx = lm % nxg;
+        by = (lm / nxg) % nyg;
+        bz = lm / (nxg * nyg);
+    }
+    const int half = bz % halves;
+    const int split = bz / halves;             // which share of the source list this workgroup takes
+    const int X = bx;
     if (split > 0) lam = lam_parts + (int64_t)(split - 1) * ((int64_t)gridDim.x * Nc * n_int);
     const int lr = lane & 15, lq = lane >> 4;
-    const int kE = blockIdx.y * 64 + 32 * half + 2 * lr;
+    const int kE = by * 64 + 32 * half + 2 * lr;
     const int kO = kE + 1;
     for (int c = threadIdx.x; c < Nc; c += blockDim.x) {
         const int ci = packinfo[c];
@@ -321,24 +335,36 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
     const int sb = ptr[X], se = ptr[X + 1];
     const int s_lo = sb + (int)(((int64_t)(se - sb) * split) / nsplit);
     const int s_hi = sb + (int)(((int64_t)(se - sb) * (split + 1)) / nsplit);
-    for (int si = s_lo; si < s_hi; ++si) {
-        const int Y = src[si];
+    // Phase p = (source s_lo + p/2, Delta = 2 + p%2).  Its tables are copied
+    // global -> LDS asynchronously (no registers) one phase ahead, into the
+    // buffer the previous phase has released; each wave copies 1 KB pieces.
+    const int n_phase = 2 * (s_hi - s_lo);
+    const int pieces = TSp / 128;                    // 1 KB pieces per table
+    auto stage = [&](int p) {
+        const int si = s_lo + (p >> 1), D = 2 + (p & 1);
         const int c3 = cls[si];
+        double* dst = smem + (p & 1) * 3 * TSp;
+        for (int c = w; c < 3 * pieces; c += kM2LWaves) {
+            const int tb = c / pieces, pc = c - tb * pieces;
+            const int o = off3[3 * c3 + tb] + R;
+            const double* g = E1s + (((int64_t)(D - 2) * nR + o) * 2 + (tb == 0 ? 0 : 1)) * TSp + pc * 128 + 2 * lane;
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                             (void __attribute__((address_space(3)))*)(dst + tb * TSp + pc * 128),
+                                             16, 0, 0);
+        }
+    };
+    if (n_phase > 0) stage(0);
+    for (int p = 0; p < n_phase; ++p) {
+        const int si = s_lo + (p >> 1), D = 2 + (p & 1);
+        const int Y = src[si];
         const double* muY = mu + (int64_t)Y * Nc * n_int;
-        for (int D = 2; D <= 3; ++D) {
-            __syncthreads();
-            {
-                const double* ex = E1 + ((int64_t)(D - 2) * nR + off3[3 * c3] + R) * TS;
-                const double* ey = E1 + ((int64_t)(D - 2) * nR + off3[3 * c3 + 1] + R) * TS;
-                const double* ez = E1 + ((int64_t)(D - 2) * nR + off3[3 * c3 + 2] + R) * TS;
-                const double* cab = Cab + (int64_t)(D - 2) * nt1 * nt1;
-                for (int e = threadIdx.x; e < TS; e += blockDim.x) {
-                    sEx[e] = cab[e / nx2] * ex[e];
-                    sEy[e] = ey[e];
-                    sEz[e] = ez[e];
-                }
-            }
-            __syncthreads();
+        const double* sEx = smem + (p & 1) * 3 * TSp;
+        const double* sEy = sEx + TSp;
+        const double* sEz = sEx + 2 * TSp;
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's pieces of phase p have landed in LDS
+        __syncthreads();                 // ... everyone's; and phase p-1 is done with the other buffer
+        if (p + 1 < n_phase) stage(p + 1);
+        {
             const bool vE = (D == 2) && (kE < n_int) && (kE >= D);
             const bool vO = (kO < n_int) && (kO >= D);
             if (D == 3 && !__any(vO)) continue;
@@ -810,10 +836,23 @@ __global__ void __launch_bounds__(256) k_near_apply(const double* __restrict__ B
                 const int64_t total = (int64_t)ns * S;
                 int jt = j0, i = cs;
                 while (i >= S) { i -= S; ++jt; }
-                for (int64_t c = cs; c < total; c += cpi) {
-                    acc = fma(blk[(colbase + c) * nX + r], wd[(int64_t)jt * L.E_x + pos[i]], acc);
-                    i += cpi;
-                    while (i >= S) { i -= S; ++jt; }
+                // four columns per trip with independent loads; the block stream
+                // is read once (non-temporal), the densities stay in L2
+                for (int64_t c = cs; c < total; c += 4 * cpi) {
+                    double bv[4], xv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t cc = c + u * cpi;
+                        const bool ok = cc < total;
+                        const int64_t ce = ok ? cc : cs;
+                        bv[u] = __builtin_nontemporal_load(&blk[(colbase + ce) * nX + r]);
+                        xv[u] = wd[(int64_t)(ok ? jt : j0) * L.E_x + pos[ok ? i : 0]];
+                        bv[u] = ok ? bv[u] : 0.0;
+                        i += cpi;
+                        while (i >= S) { i -= S; ++jt; }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc = fma(bv[u], xv[u], acc);
                 }
                 colbase += total;
             }
@@ -859,7 +898,7 @@ struct DevLevel {
     double* lam_parts = nullptr;  // extra shares of a split interaction list
     int nsplit = 1;
     int* off3 = nullptr;
-    int64_t at_off = 0, qt_off = -1, qx_off = -1, e1_off = 0, cab_off = 0;
+    int64_t at_off = 0, qt_off = -1, qx_off = -1, e1_off = 0, cab_off = 0, e1s_off = 0;
     int n_off = 0, R = 0;
 };
 
@@ -881,11 +920,14 @@ struct pfmm_tree {
     int* inv_sigma = nullptr;
     double* wd = nullptr;
     double* fd = nullptr;
+    double* mass = nullptr;       // |gamma_k| h per triangle (natural order)
     double *At = nullptr, *Ax = nullptr, *AxK = nullptr, *qt = nullptr, *qx = nullptr;
     int* chunk_cols = nullptr;
     int64_t* chunk_off = nullptr;
     double* E1 = nullptr;
     double* Cab = nullptr;
+    double* E1s = nullptr;        // matrix-core M2L: staged tables [level][Delta][offset][x (C_ab folded in) | y,z][TSp]
+    int TSp = 0;                  // padded table length (multiple of 128 doubles)
     int* packinfo = nullptr;      // per coefficient: a | k1<<4 | k2<<8 | k3<<12 | deg<<16
     int* slot_tile = nullptr;     // [groups][mfma_slots] row tiles per wave group (-1 = none)
     int* tile_ks = nullptr;       // K-steps per 16-row tile
@@ -962,7 +1004,7 @@ uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask) {
     int nop = ((ops_mask & PFMM_OP_V) ? 1 : 0) + ((ops_mask & PFMM_OP_K) ? 1 : 0);
     b += (uint64_t)nop * ((uint64_t)P.near_entries * 8 + (uint64_t)P.table_size * 8);
     b += P.umap.size() * 4 + P.set_pos.size() * 4 + P.upos.size() * 4;
-    b += (F.At.size() + F.Ax.size() + F.AxK.size() + F.qt.size() + F.qx.size() + F.E1.size()) * 8;
+    b += (F.At.size() + F.Ax.size() + F.AxK.size() + F.qt.size() + F.qx.size() + 4 * F.E1.size()) * 8;
     b += P.rows.size() * 16;
     return b;
 }
@@ -1059,6 +1101,11 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
     PF_TRY(upload(t, &t->inv_sigma, P.inv_sigma.data(), P.inv_sigma.size()));
     PF_TRY(dalloc(t, &t->wd, (size_t)N));
     PF_TRY(dalloc(t, &t->fd, (size_t)N));
+    {
+        std::vector<double> m(P.E_x);
+        for (int i = 0; i < P.E_x; ++i) m[i] = P.area[i] * P.h;
+        PF_TRY(upload(t, &t->mass, m.data(), m.size()));
+    }
     // coefficient maps
     {
         const int nx1 = P.m_x + 1;
@@ -1103,55 +1150,74 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             ks[tt] = (cols + 3) / 4;
             total += ks[tt];
         }
-        // find the smallest block length T whose split fits kM2LWaves waves x kM2LSlots slots
-        std::vector<std::array<int, 3>> best;   // per wave later
+        // Split-K plan of one output block (all row tiles, one interval half).
+        // For a block length T every tile's K-range is cut at multiples of T;
+        // segments with the same start share the moment operands, so they are
+        // grouped three at a time (sorted by length, so a group's lengths are
+        // close) into waves.  Waves are then dealt to the 4 SIMDs of the CU
+        // (wave w runs on SIMD w % 4) by longest-processing-time on their
+        // slot-steps.  T minimises (busiest SIMD's slot-steps + longest wave),
+        // i.e. MFMA balance plus the dependent chain of the slowest wave.
         std::vector<int> wmeta, segtab, redtile;
         bool ok = false;
-        for (int T = (int)((total + kM2LWaves - 1) / kM2LWaves); T <= 4096 && !ok; ++T) {
-            // segments per K-block b: [b*T, min((b+1)*T, ks))
-            int nblk = 0;
-            for (int tt = 0; tt < ntile; ++tt) nblk = std::max(nblk, (ks[tt] + T - 1) / T);
-            std::vector<std::vector<std::array<int, 2>>> blk(nblk);   // (tile, end)
-            for (int tt = 0; tt < ntile; ++tt)
-                for (int b = 0; b * T < ks[tt]; ++b) blk[b].push_back({tt, std::min((b + 1) * T, ks[tt])});
-            // waves per block: LPT with at most kM2LSlots segments and load <= T
-            std::vector<int> meta;
-            std::vector<std::vector<std::array<int, 2>>> waves;
-            bool fit = true;
-            for (int b = 0; b < nblk && fit; ++b) {
-                auto& sg = blk[b];
-                std::stable_sort(sg.begin(), sg.end(), [](const std::array<int, 2>& x, const std::array<int, 2>& y) { return x[1] > y[1]; });
-                std::vector<std::vector<std::array<int, 2>>> wv;
-                std::vector<int> load;
-                for (auto& g : sg) {
-                    const int len = g[1] - b * T;
-                    int pick = -1;
-                    for (size_t i = 0; i < wv.size(); ++i)
-                        if ((int)wv[i].size() < kM2LSlots && load[i] + len <= T && (pick < 0 || load[i] < load[pick])) pick = (int)i;
-                    if (pick < 0) { wv.push_back({}); load.push_back(0); pick = (int)wv.size() - 1; }
-                    wv[pick].push_back(g);
-                    load[pick] += len;
+        {
+            struct Seg { int tile, start, end; };
+            int best_cost = INT32_MAX;
+            std::vector<std::vector<Seg>> best_waves;
+            int maxks = 0;
+            for (int k : ks) maxks = std::max(maxks, k);
+            for (int T = 1; T <= maxks; ++T) {
+                int nblk = (maxks + T - 1) / T;
+                std::vector<std::vector<Seg>> waves;
+                for (int b = 0; b < nblk; ++b) {
+                    std::vector<Seg> sg;
+                    for (int tt = 0; tt < ntile; ++tt)
+                        if (ks[tt] > b * T) sg.push_back({tt, b * T, std::min((b + 1) * T, ks[tt])});
+                    std::stable_sort(sg.begin(), sg.end(), [](const Seg& x, const Seg& y) { return x.end > y.end; });
+                    for (size_t i = 0; i < sg.size(); i += kM2LSlots) {
+                        std::vector<Seg> wv(sg.begin() + i, sg.begin() + std::min(sg.size(), i + kM2LSlots));
+                        waves.push_back(wv);
+                    }
                 }
-                for (auto& x : wv) { waves.push_back(x); meta.push_back(b * T); }
-                if ((int)waves.size() > kM2LWaves) fit = false;
+                if ((int)waves.size() > kM2LWaves) continue;
+                // LPT over SIMDs, at most kM2LWaves / 4 waves each
+                std::vector<int> order(waves.size());
+                for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+                auto load = [&](int i) { int l = 0; for (auto& g : waves[i]) l += g.end - g.start; return l; };
+                std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return load(x) > load(y); });
+                int simd_load[4] = {0, 0, 0, 0}, simd_n[4] = {0, 0, 0, 0};
+                std::vector<std::vector<Seg>> placed(kM2LWaves);
+                int longest = 0;
+                for (int i : order) {
+                    int pick = -1;
+                    for (int q = 0; q < 4; ++q)
+                        if (simd_n[q] < kM2LWaves / 4 && (pick < 0 || simd_load[q] < simd_load[pick])) pick = q;
+                    placed[simd_n[pick] * 4 + pick] = waves[i];
+                    simd_n[pick] += 1;
+                    simd_load[pick] += load(i);
+                    longest = std::max(longest, waves[i][0].end - waves[i][0].start);
+                }
+                const int cost = *std::max_element(simd_load, simd_load + 4) + longest;
+                if (cost < best_cost) { best_cost = cost; best_waves = placed; }
             }
-            if (!fit) continue;
-            ok = true;
-            // tables: per wave (start, count); per slot (tile, end, partial index)
-            wmeta.assign(2 * kM2LWaves, 0);
-            segtab.assign((size_t)kM2LWaves * kM2LSlots * 3, -1);
-            for (int wv = 0; wv < kM2LWaves; ++wv) {
-                wmeta[2 * wv] = wv < (int)waves.size() ? meta[wv] : 0;
-                wmeta[2 * wv + 1] = wv < (int)waves.size() ? (int)waves[wv].size() : 0;
-                for (int i = 0; i < kM2LSlots; ++i) {
-                    int* e = &segtab[((size_t)wv * kM2LSlots + i) * 3];
-                    if (wv < (int)waves.size() && i < (int)waves[wv].size()) {
-                        e[0] = waves[wv][i][0];
-                        e[1] = waves[wv][i][1];
-                        e[2] = -1;
-                        if (meta[wv] > 0) { e[2] = (int)redtile.size(); redtile.push_back(e[0]); }
-                    } else {
-                        e[0] = -1; e[1] = meta[wv < (int)waves.size() ? wv : 0] * 0; e[2] = -1;
+            if (!best_waves.empty()) {
+                ok = true;
+                wmeta.assign(2 * kM2LWaves, 0);
+                segtab.assign((size_t)kM2LWaves * kM2LSlots * 3, -1);
+                for (int wv = 0; wv < kM2LWaves; ++wv) {
+                    const auto& g = best_waves[wv];
+                    wmeta[2 * wv] = g.empty() ? 0 : g[0].start;
+                    wmeta[2 * wv + 1] = (int)g.size();
+                    for (int i = 0; i < kM2LSlots; ++i) {
+                        int* e = &segtab[((size_t)wv * kM2LSlots + i) * 3];
+                        if (i < (int)g.size()) {
+                            e[0] = g[i].tile;
+                            e[1] = g[i].end;
+                            e[2] = -1;
+                            if (g[i].start > 0) { e[2] = (int)redtile.size(); redtile.push_back(e[0]); }
+                        } else {
+                            e[0] = -1; e[1] = 0; e[2] = -1;
+                        }
                     }
                 }
             }
@@ -1159,10 +1225,17 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         // a wave's segments must be sorted by end (descending) for the phase loop; empty slots end at start
         int slots = ok ? kM2LSlots : 0;
         if (P.m_t > 15 || P.m_x > 15) slots = 0;
-        const size_t shm = std::max((size_t)3 * (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1) * sizeof(double) +
-                                        (size_t)2 * P.Nc * sizeof(int),
+        const int TS = (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1);
+        t->TSp = (TS + 127) / 128 * 128;
+        const size_t shm = std::max((size_t)6 * t->TSp * sizeof(double) + (size_t)2 * P.Nc * sizeof(int),
                                     redtile.size() * 8 * 64 * sizeof(double));
-        if (shm > 65536) slots = 0;
+        int dev = 0, lds_max = 65536;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (shm > (size_t)lds_max) slots = 0;
+        if (slots && shm > 65536)
+            HIP_TRY(hipFuncSetAttribute((const void*)k_m2l_mfma<kM2LSlots>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
         t->m2l_shm = shm;
         t->mfma_slots = slots;
         if (slots) {
@@ -1179,6 +1252,31 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             PF_TRY(upload(t, &t->tile_ks, wmeta.data(), wmeta.size()));
         }
     }
+    // staged 1D tables of the matrix-core M2L: per (level, Delta, offset) the
+    // x table with C_ab folded in and the plain table for y and z, each padded
+    // to TSp doubles so that 1 KB pieces can be copied straight into LDS
+    std::vector<int64_t> e1s_off(P.depth + 1, 0);
+    if (t->mfma_slots) {
+        const int nt1 = P.m_t + 1, nx1 = P.m_x + 1, TS = nt1 * nt1 * nx1 * nx1, TSp = t->TSp;
+        std::vector<double> E1s;
+        for (int l = 2; l <= P.depth; ++l) {
+            const FarLevel& FL = F.lv[l];
+            const int nR = 2 * FL.R + 1;
+            e1s_off[l] = (int64_t)E1s.size();
+            E1s.resize(E1s.size() + (size_t)2 * nR * 2 * TSp, 0.0);
+            for (int D = 0; D < 2; ++D)
+                for (int oi = 0; oi < nR; ++oi) {
+                    const double* e = &F.E1[FL.e1_off + ((size_t)D * nR + oi) * TS];
+                    double* x = &E1s[e1s_off[l] + (((size_t)D * nR + oi) * 2 + 0) * TSp];
+                    double* yz = x + TSp;
+                    for (int i = 0; i < TS; ++i) {
+                        x[i] = F.Cab[FL.cab_off + (size_t)D * nt1 * nt1 + i / (nx1 * nx1)] * e[i];
+                        yz[i] = e[i];
+                    }
+                }
+        }
+        PF_TRY(upload(t, &t->E1s, E1s.data(), E1s.size()));
+    }
     // levels
     t->lv.assign(P.depth + 1, DevLevel());
     for (int l = 0; l < 2 && l <= P.depth; ++l) {
@@ -1193,7 +1291,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         D.l = l; D.nx = L.nx(); D.n_int = L.n_int; D.steps = FL.steps;
         D.n_leafx = (int)FL.leaf_xs.size();
         D.at_off = FL.at_off; D.qt_off = FL.qt_off; D.qx_off = FL.qx_off; D.n_off = FL.n_off;
-        D.e1_off = FL.e1_off; D.cab_off = FL.cab_off; D.R = FL.R;
+        D.e1_off = FL.e1_off; D.cab_off = FL.cab_off; D.R = FL.R; D.e1s_off = e1s_off[l];
         PF_TRY(upload(t, &D.off3, FL.off3.data(), FL.off3.size()));
         PF_TRY(dalloc(t, &D.mu, (size_t)D.nx * P.Nc * D.n_int));
         PF_TRY(dalloc(t, &D.lam, (size_t)D.nx * P.Nc * D.n_int));
@@ -1337,7 +1435,7 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
                 // share 0 writes lambda, share p >= 1 writes lam_parts + (p - 1) * (slots * Nc * n_int)
                 const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
                 hipLaunchKernelGGL(k_m2l_mfma<kM2LSlots>, grid, block, shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src,
-                                   D.m2l_cls, D.off3, t->E1 + D.e1_off, t->Cab + D.cab_off, t->packinfo, t->tile_ks,
+                                   D.m2l_cls, D.off3, t->E1s + D.e1s_off, t->TSp, t->packinfo, t->tile_ks,
                                    t->slot_tile, t->n_partial, P.Nc, D.n_int, P.m_t, P.m_x, D.R, D.nsplit, halves,
                                    D.lam_parts);
                 if (D.nsplit > 1)
@@ -1397,6 +1495,20 @@ void fill_stats(const Plan& P, uint64_t bytes, pfmm_stats* out, int m2l_mfma) {
 }
 
 }  // namespace
+
+// ====================================================================== internal accessors
+
+namespace pfmm {
+
+pfmm_status set_error(pfmm_status s, const std::string& msg) { return fail(s, msg); }
+int tree_device(const pfmm_tree* t) { return t->device; }
+int64_t tree_dofs(const pfmm_tree* t) { return (int64_t)t->P.E_t * t->P.E_x; }
+int64_t tree_triangles(const pfmm_tree* t) { return t->P.E_x; }
+bool tree_has(const pfmm_tree* t, int op) { return op == PFMM_OP_V ? t->hasV : (op == PFMM_OP_K ? t->hasK : false); }
+const double* tree_mass(const pfmm_tree* t) { return t->mass; }
+pfmm_status tree_apply(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st) { return apply(t, K, x, y, st); }
+
+}  // namespace pfmm
 
 // ====================================================================== C ABI
 

@@ -44,6 +44,17 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
+                ("history_len", ctypes.c_int32)]
+
+
 def lib_path():
     return os.path.join(_HERE, "libpfmm.so")
 
@@ -68,6 +79,10 @@ def load_library():
         "pfmm_plan_stats": ([dp, I64, ip, I64, dp, I64, P(Params), P(Stats)], I32),
         "pfmm_profile_enable": ([VP, I32], I32),
         "pfmm_profile_read": ([VP, dp, P(I64), P(I32)], I32),
+        "pfmm_default_solve_opts": ([P(SolveOpts)], I32),
+        "pfmm_solve_V": ([VP, VP, VP, P(SolveOpts), P(SolveInfo), VP], I32),
+        "pfmm_solve_dirichlet": ([VP, VP, VP, P(SolveOpts), P(SolveInfo), VP], I32),
+        "pfmm_dirichlet_rhs": ([VP, VP, VP, VP], I32),
         "pfmm_destroy": ([VP], None),
         "pfmm_last_error": ([], ctypes.c_char_p),
     }
@@ -151,6 +166,41 @@ class Tree:
 
     def apply_K(self, u, out=None, stream=None):
         return self._apply(self.lib.pfmm_apply_K, u, out, stream)
+
+    def _solve(self, fn, rhs, out, rtol, max_iter, stream, raise_on_notconv):
+        import torch
+        if rhs.dtype != torch.float64 or rhs.device != self.device or rhs.numel() != self.n_dofs:
+            raise ValueError(f"expected a float64 tensor of {self.n_dofs} entries on {self.device}")
+        rhs = rhs.contiguous()
+        if out is None:
+            out = torch.empty_like(rhs)
+        o = SolveOpts()
+        _check(self.lib.pfmm_default_solve_opts(ctypes.byref(o)))
+        o.rtol, o.max_iter = rtol, max_iter
+        hist = (ctypes.c_double * (max_iter + 1))()
+        info = SolveInfo()
+        info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        info.history_cap = max_iter + 1
+        st = fn(self.handle, ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctypes.byref(o),
+                ctypes.byref(info), _stream_ptr(stream))
+        d = {"iters": info.iters, "converged": bool(info.converged), "rel_residual": info.rel_residual,
+             "true_rel_residual": info.true_rel_residual, "seconds": info.seconds,
+             "history": list(hist[:info.history_len])}
+        if st != 0 and not (st == -4 and not raise_on_notconv):
+            _check(st)
+        return out, d
+
+    def solve_V(self, b, out=None, rtol=1e-8, max_iter=200, stream=None, raise_on_notconv=True):
+        """GMRES solve of V_h w = b (device tensors, natural order); returns (w, info)."""
+        return self._solve(self.lib.pfmm_solve_V, b, out, rtol, max_iter, stream, raise_on_notconv)
+
+    def dirichlet_rhs(self, g, out=None, stream=None):
+        """(1/2 M_h + K_h) g on the device (needs K_h)."""
+        return self._apply(self.lib.pfmm_dirichlet_rhs, g, out, stream)
+
+    def solve_dirichlet(self, g, out=None, rtol=1e-8, max_iter=200, stream=None, raise_on_notconv=True):
+        """GMRES solve of V_h w = (1/2 M_h + K_h) g; returns (w, info)."""
+        return self._solve(self.lib.pfmm_solve_dirichlet, g, out, rtol, max_iter, stream, raise_on_notconv)
 
     def stats(self):
         st = Stats()

@@ -90,3 +90,14 @@ def test_error_codes():
     with pytest.raises(P.PfmmError) as e:
         P.plan_stats(v4, t4, uniform_time_nodes(20))     # 20 steps: level 3 intervals of 2 and 3 steps
     assert e.value.status == -6
+
+
+def test_solve_entry_points_validate_without_gpu():
+    lib = P.load_library()
+    o = P.SolveOpts()
+    assert lib.pfmm_default_solve_opts(o) == 0 and o.rtol == 1e-8 and o.max_iter == 200
+    assert lib.pfmm_default_solve_opts(None) == -1
+    info = P.SolveInfo()
+    for fn in (lib.pfmm_solve_V, lib.pfmm_solve_dirichlet):
+        assert fn(None, None, None, None, None, None) == -1
+        assert b"NULL" in lib.pfmm_last_error()

@@ -46,26 +46,38 @@ def _points(verts, tris, time_nodes, q, q_t):
     return X, w_tri, T, gtw
 
 
+def _time_chunks(n_steps, per_step, cap=8_000_000):
+    """Step ranges holding at most `cap` quadrature values each."""
+    step = max(1, cap // max(per_step, 1))
+    return [(j, min(j + step, n_steps)) for j in range(0, n_steps, step)]
+
+
 def _normals(verts, tris):
     P = verts[tris]
     n = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
     return n / np.linalg.norm(n, axis=1)[:, None]
 
 
-def project_source_datum(verts, tris, time_nodes, y_star, t_star=0.0, alpha=1.0, q=6, q_t=6):
+def project_source_datum(verts, tris, time_nodes, y_star, t_star=0.0, alpha=1.0, q=4, q_t=4):
     """Element means of G(x - y*, t - t*) (natural time-major order, length E_t E_x)."""
     X, w_tri, T, gtw = _points(verts, tris, time_nodes, q, q_t)
     r2 = ((X - np.asarray(y_star, dtype=np.float64)) ** 2).sum(-1)          # (E_x, nq)
-    vals = _heat(r2[None, :, :, None], (T - t_star)[:, None, None, :], alpha)  # (E_t, E_x, nq, q_t)
-    return np.einsum("txqs,q,s->tx", vals, w_tri, gtw).ravel()
+    out = np.empty((len(T), len(tris)))
+    for j0, j1 in _time_chunks(len(T), r2.size * q_t):
+        vals = _heat(r2[None, :, :, None], (T[j0:j1] - t_star)[:, None, None, :], alpha)
+        out[j0:j1] = vals.reshape(j1 - j0, len(tris), -1) @ np.kron(w_tri, gtw)
+    return out.ravel()
 
 
-def project_source_flux(verts, tris, time_nodes, y_star, t_star=0.0, alpha=1.0, q=6, q_t=6):
+def project_source_flux(verts, tris, time_nodes, y_star, t_star=0.0, alpha=1.0, q=4, q_t=4):
     """Element means of alpha dG(x - y*, t - t*)/dn_x = -(x - y*).n / (2 (t - t*)) G."""
     X, w_tri, T, gtw = _points(verts, tris, time_nodes, q, q_t)
     d = X - np.asarray(y_star, dtype=np.float64)
     r2 = (d ** 2).sum(-1)
     dn = np.einsum("xqk,xk->xq", d, _normals(verts, tris))
-    s = (T - t_star)[:, None, None, :]
-    vals = _heat(r2[None, :, :, None], s, alpha) * (-dn[None, :, :, None]) / (2.0 * np.where(s > 0, s, 1.0))
-    return np.einsum("txqs,q,s->tx", vals, w_tri, gtw).ravel()
+    out = np.empty((len(T), len(tris)))
+    for j0, j1 in _time_chunks(len(T), r2.size * q_t):
+        s = (T[j0:j1] - t_star)[:, None, None, :]
+        vals = _heat(r2[None, :, :, None], s, alpha) * (-dn[None, :, :, None]) / (2.0 * np.where(s > 0, s, 1.0))
+        out[j0:j1] = vals.reshape(j1 - j0, len(tris), -1) @ np.kron(w_tri, gtw)
+    return out.ravel()
