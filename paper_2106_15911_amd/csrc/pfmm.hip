@@ -473,6 +473,273 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
     }
 }
 
+// M2L on FP64 matrix cores, wide form for levels with >= 64 intervals.
+//
+// The rows of eq. m2l (16-row tiles of the staircase) are partitioned into
+// row groups; a workgroup of WAVES waves owns one target slot X, one row
+// group and NB blocks of 32 consecutive intervals.  An operator element a
+// wave generates from the 1D tables then feeds 2 NB matrix-core products
+// (even and odd intervals of every block) for Delta = 2 and NB for
+// Delta = 3, instead of 2 and 1 in k_m2l_mfma, so generating the operator
+// costs 2 NB times fewer vector instructions per product.  Within a group
+// the tiles' K-ranges are cut into segments (up to MAXS per wave, sharing
+// their first K-step) as in k_m2l_mfma; partial segments are added to their
+// tile's first segment through LDS, one interval block at a time.
+//
+// Per group g the host table plan[g * plan_stride ...] holds
+//   [0, 2 W)                  wave w: (first K-step, number of segments)
+//   [2 W, 2 W + 3 W MAXS)     wave w, slot i: (tile, end K-step, partial index or -1)
+//   [2 W + 3 W MAXS]          number of partial segments n_p
+//   [.. + 1, .. + 1 + n_p)    the tile of every partial segment
+// with W = WAVES.  A wave's slots are sorted by end; every end but the
+// largest lies an even number of K-steps after the wave's first K-step (a
+// tile's last segment may be extended by one K-step whose columns are all
+// beyond the tile's degree limit), so the two operand sets below alternate
+// without copies.  Source moments are read through a buffer descriptor
+// spanning the source slot's moments: prefetches beyond a segment (and
+// padding columns) return zero without touching other memory.
+template <int NB, int MAXS, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
+    const double* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
+    const int* __restrict__ cls, const int* __restrict__ off3, const double* __restrict__ E1s, int TSp,
+    const int* __restrict__ packinfo, const int* __restrict__ plan, int plan_stride, int Nc, int n_int, int mt,
+    int mx, int R, int nsplit, int ncb, double* __restrict__ lam_parts) {
+    static_assert(MAXS >= 1 && MAXS <= 2, "phase dispatch below is written for one or two slots");
+    extern __shared__ double smem[];
+    const int nt1 = mt + 1, nx1 = mx + 1;
+    const int nx2 = nx1 * nx1;
+    const int Nc4 = (Nc + 3) & ~3;
+    // two buffers of the three 1D tables of one (source, Delta) phase: [buf][x | y | z][TSp];
+    // then per coefficient column (padded): byte offsets of its x, y, z table
+    // columns and its degree (255 for padding columns)
+    int4* sCol = (int4*)(smem + 6 * TSp);
+    const int lane = threadIdx.x % kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // Workgroups are dealt to the 8 XCDs round-robin by linear id; remap so
+    // that each XCD walks a contiguous range of (row group, target slot):
+    // the groups of one slot and neighbouring slots read the same moments.
+    int g, X, bz;
+    {
+        const int ng = gridDim.x, nxs = gridDim.y;
+        const int total = ng * nxs * gridDim.z;
+        const int lin = blockIdx.x + ng * (blockIdx.y + nxs * blockIdx.z);
+        const int per = total / kXcds;
+        const int lm = lin < per * kXcds ? (lin % kXcds) * per + lin / kXcds : lin;
+        g = lm % ng;
+        X = (lm / ng) % nxs;
+        bz = lm / (ng * nxs);
+    }
+    const int cb = bz % ncb;
+    const int split = bz / ncb;                // which share of the source list this workgroup takes
+    if (split > 0) lam = lam_parts + (int64_t)(split - 1) * ((int64_t)gridDim.y * Nc * n_int);
+    const int* gp = plan + (int64_t)g * plan_stride;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int k0 = cb * (32 * NB) + 2 * lr;    // even target interval of block 0
+    for (int c = threadIdx.x; c < Nc4 + 16; c += blockDim.x) {
+        int4 v = {0, 0, 0, 255};
+        if (c < Nc) {
+            const int ci = packinfo[c];
+            const int cbase = (ci & 15) * nt1 * nx2;
+            v.x = 8 * (cbase + ((ci >> 4) & 15) * nx1);
+            v.y = 8 * (cbase + ((ci >> 8) & 15) * nx1);
+            v.z = 8 * (cbase + ((ci >> 12) & 15) * nx1);
+            v.w = (ci >> 16) & 255;
+        }
+        sCol[c] = v;
+    }
+    const int sbeg = __builtin_amdgcn_readfirstlane(gp[2 * w]);
+    int tiles[MAXS], ks[MAXS], part[MAXS], rX[MAXS], rY[MAXS], rZ[MAXS], rD[MAXS];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        const int* e = gp + 2 * WAVES + (w * MAXS + i) * 3;
+        tiles[i] = __builtin_amdgcn_readfirstlane(e[0]);
+        ks[i] = __builtin_amdgcn_readfirstlane(e[1]);   // segment end (exclusive, absolute)
+        part[i] = __builtin_amdgcn_readfirstlane(e[2]);
+        const int row = 16 * (tiles[i] >= 0 ? tiles[i] : 0) + lr;
+        const bool rv = tiles[i] >= 0 && row < Nc;
+        const int ri = rv ? packinfo[row] : 0;
+        const int b = ri & 15;
+        rX[i] = 8 * (b * nx2 + ((ri >> 4) & 15));
+        rY[i] = 8 * (b * nx2 + ((ri >> 8) & 15) + TSp);
+        rZ[i] = 8 * (b * nx2 + ((ri >> 12) & 15) + 2 * TSp);
+        rD[i] = mx - (rv ? ((ri >> 16) & 255) : 255);   // largest column degree this row accepts
+    }
+    d4_t accE[MAXS][NB], accO[MAXS][NB];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            accE[i][nb] = d4_t{0.0, 0.0, 0.0, 0.0};
+            accO[i][nb] = d4_t{0.0, 0.0, 0.0, 0.0};
+        }
+    const int nR = 2 * R + 1;
+    const int sb = ptr[X], se = ptr[X + 1];
+    const int s_lo = sb + (int)(((int64_t)(se - sb) * split) / nsplit);
+    const int s_hi = sb + (int)(((int64_t)(se - sb) * (split + 1)) / nsplit);
+    const int n_phase = 2 * (s_hi - s_lo);
+    const int pieces = TSp / 128;                    // 1 KB pieces per table
+    auto stage = [&](int p) {
+        const int si = s_lo + (p >> 1), D = 2 + (p & 1);
+        const int c3 = cls[si];
+        double* dst = smem + (p & 1) * 3 * TSp;
+        for (int c = w; c < 3 * pieces; c += WAVES) {
+            const int tb = c / pieces, pc = c - tb * pieces;
+            const int o = off3[3 * c3 + tb] + R;
+            const double* gsrc = E1s + (((int64_t)(D - 2) * nR + o) * 2 + (tb == 0 ? 0 : 1)) * TSp + pc * 128 + 2 * lane;
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)gsrc,
+                                             (void __attribute__((address_space(3)))*)(dst + tb * TSp + pc * 128),
+                                             16, 0, 0);
+        }
+    };
+    // Lane (lr, lq) of K-step s reads, for every block nb, the pair
+    // mu[Y][c][k - 2], mu[Y][c][k - 1] with c = 4 s + lq and k = its even
+    // target interval: the Delta = 2 sources of the even and odd targets, and
+    // (first value) the Delta = 3 source of the odd target.  Block nb is
+    // 256 bytes further.  Targets k < 2 have no sources: their results are
+    // written as zero at the end.  The descriptor starts two values before the
+    // slot (mu has two leading guard values), so every offset is >= 0; reads
+    // past the slot's last coefficient are out of its range and return zero.
+    const int vbase = ((4 * sbeg + lq) * n_int + k0) * 8;   // byte offset of mu[Y][c][k - 2] from the descriptor base
+    const int bstep = 4 * n_int * 8;                        // bytes between consecutive K-steps
+    const int slot_bytes = (Nc * n_int + 2) * 8;
+    const char* lds = (const char*)smem;
+    if (n_phase > 0) stage(0);
+    for (int p = 0; p < n_phase; ++p) {
+        const int si = s_lo + (p >> 1);
+        const int Y = src[si];
+        const int boff = (p & 1) * 3 * TSp * 8;        // byte offset of this phase's table buffer
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(mu + (int64_t)Y * Nc * n_int - 2), (short)0, slot_bytes, 0x00020000);
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's pieces of phase p have landed in LDS
+        __syncthreads();                 // ... everyone's; and phase p-1 is done with the other buffer
+        if (p + 1 < n_phase) stage(p + 1);
+        int pX[MAXS], pY[MAXS], pZ[MAXS];
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            pX[i] = boff + rX[i];
+            pY[i] = boff + rY[i];
+            pZ[i] = boff + rZ[i];
+        }
+        auto run = [&](auto dc) {
+            constexpr int D = decltype(dc)::value;
+            // Delta = 2 uses both values of the pair, Delta = 3 only the first
+            using BT = std::conditional_t<D == 2, double2, double>;
+            auto load = [&](BT* bv, int s) {
+                const int vo = vbase + (s - sbeg) * bstep;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    if constexpr (D == 2)
+                        bv[nb] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + nb * 256, 0, 0));
+                    else
+                        bv[nb] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo + nb * 256, 0, 0));
+                }
+            };
+            // one K-step with n active slots
+            auto step = [&](auto nc, int4 col, const BT* bv) {
+                constexpr int n = decltype(nc)::value;
+                double A[n];
+#pragma unroll
+                for (int i = 0; i < n; ++i) {
+                    const double ex = *(const double*)(lds + (pX[i] + col.x));
+                    const double ey = *(const double*)(lds + (pY[i] + col.y));
+                    const double ez = *(const double*)(lds + (pZ[i] + col.z));
+                    const double msk = (col.w <= rD[i]) ? 1.0 : 0.0;
+                    A[i] = (ex * ey) * (ez * msk);
+                }
+#pragma unroll
+                for (int i = 0; i < n; ++i)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        if constexpr (D == 2) {
+                            accE[i][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bv[nb].x, accE[i][nb], 0, 0, 0);
+                            accO[i][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bv[nb].y, accO[i][nb], 0, 0, 0);
+                        } else {
+                            accO[i][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bv[nb], accO[i][nb], 0, 0, 0);
+                        }
+                    }
+            };
+            // two operand sets used alternately; the set consumed at step s is
+            // refilled with step s + 2 right after its products are issued
+            int s = sbeg;
+            int4 cA = sCol[4 * s + lq], cB = sCol[4 * s + 4 + lq];
+            BT bA[NB], bB[NB];
+            load(bA, s);
+            load(bB, s + 1);
+            auto phase = [&](auto nc, int s_end) {
+                for (; s + 1 < s_end; s += 2) {
+                    step(nc, cA, bA);
+                    cA = sCol[4 * s + 8 + lq];
+                    load(bA, s + 2);
+                    step(nc, cB, bB);
+                    cB = sCol[4 * s + 12 + lq];
+                    load(bB, s + 3);
+                }
+            };
+            if constexpr (MAXS == 2) phase(std::integral_constant<int, 2>{}, ks[1]);
+            phase(std::integral_constant<int, 1>{}, ks[0]);
+            if (s < ks[0]) {   // odd final step
+                if (MAXS == 2 && s < ks[MAXS - 1]) step(std::integral_constant<int, MAXS>{}, cA, bA);
+                else step(std::integral_constant<int, 1>{}, cA, bA);
+            }
+        };
+        if ((p & 1) == 0) run(std::integral_constant<int, 2>{});
+        else run(std::integral_constant<int, 3>{});
+    }
+    // partial segments: one interval block at a time, park in LDS and let the
+    // owners of the tiles' first segments add them in a fixed order
+    const int n_partial = gp[2 * WAVES + 3 * WAVES * MAXS];
+    const int* ptile = gp + 2 * WAVES + 3 * WAVES * MAXS + 1;
+    double* red = smem;   // [n_partial][8][64]
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            if (tiles[i] >= 0 && part[i] >= 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    red[((int64_t)part[i] * 8 + r) * kWave + lane] = accE[i][nb][r];
+                    red[((int64_t)part[i] * 8 + 4 + r) * kWave + lane] = accO[i][nb][r];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            if (tiles[i] < 0 || part[i] >= 0) continue;
+            for (int q = 0; q < n_partial; ++q) {
+                if (ptile[q] != tiles[i]) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    accE[i][nb][r] += red[((int64_t)q * 8 + r) * kWave + lane];
+                    accO[i][nb][r] += red[((int64_t)q * 8 + 4 + r) * kWave + lane];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        if (tiles[i] < 0 || part[i] >= 0) continue;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int kE = k0 + 32 * nb, kO = kE + 1;
+            const bool has = kE >= 2;   // targets 0 and 1 have no interaction list in time
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * tiles[i] + lq + 4 * r;
+                if (row >= Nc) continue;
+                double* out = lam + ((int64_t)X * Nc + row) * n_int;
+                out[kE] = has ? accE[i][nb][r] : 0.0;
+                out[kO] = has ? accO[i][nb][r] : 0.0;
+            }
+        }
+    }
+}
+
+// wide M2L variants: [0] two interval blocks, [1] four interval blocks
+constexpr int kWideMaxs[2] = {2, 2};
+constexpr int kWideWaves[2] = {16, 8};
+
 // Sum the per-share partial locals of a level whose interaction lists were
 // split over several workgroups (fixed order: share 0, 1, ...).
 __global__ void k_sum_parts(double* __restrict__ lam, const double* __restrict__ parts, int nparts, int64_t n) {
@@ -897,6 +1164,8 @@ struct DevLevel {
     double* ops = nullptr;
     double* lam_parts = nullptr;  // extra shares of a split interaction list
     int nsplit = 1;
+    int m2l_nb = 0;               // wide M2L interval blocks per workgroup (2 or 4); 0: k_m2l_mfma / k_m2l
+    int ncb = 1;                  // wide M2L: workgroup column blocks of 32 m2l_nb intervals
     int* off3 = nullptr;
     int64_t at_off = 0, qt_off = -1, qx_off = -1, e1_off = 0, cab_off = 0, e1s_off = 0;
     int n_off = 0, R = 0;
@@ -934,6 +1203,8 @@ struct pfmm_tree {
     int mfma_slots = 0;           // 0: matrix-core M2L not used
     int n_partial = 0;            // split-K partial segments
     size_t m2l_shm = 0;           // dynamic LDS of the matrix-core M2L
+    // wide matrix-core M2L: [0] two interval blocks / two slots, [1] four blocks / one slot
+    struct Wide { int* plan = nullptr; int G = 0, stride = 0; size_t shm = 0; bool ok = false; } wide[2];
     CoefMaps cm{};
     std::vector<DevLevel> lv;
     bool low_leaves = false;      // leaves at levels < 2 (no far field)
@@ -1091,6 +1362,124 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
         HIP_TRY(hipGetLastError());
     }
     return PFMM_OK;
+}
+
+// Split-K plan of one row group of the wide matrix-core M2L.  For an even
+// block length T every tile's K-range is cut at multiples of T; segments with
+// the same start share their moment operands and are grouped (by descending
+// end) up to maxs per wave; waves go to the 4 SIMDs of the CU (wave w runs on
+// SIMD w % 4) by longest-processing-time on their slot-steps.  T minimises
+// the busiest SIMD's slot-steps plus the longest wave (its dependent chain).
+struct WideSeg { int tile, start, end; };
+
+bool plan_row_group(const std::vector<int>& tiles, const std::vector<int>& ks, int maxs, int waves_max,
+                    std::vector<std::vector<WideSeg>>& best, int& best_cost) {
+    best_cost = INT32_MAX;
+    best.clear();
+    int maxks = 0;
+    for (int tt : tiles) maxks = std::max(maxks, ks[tt]);
+    for (int T = 2; T <= maxks + 1; T += 2) {
+        const int nblk = (maxks + T - 1) / T;
+        std::vector<std::vector<WideSeg>> waves;
+        for (int b = 0; b < nblk; ++b) {
+            std::vector<WideSeg> sg;
+            for (int tt : tiles)
+                if (ks[tt] > b * T) sg.push_back({tt, b * T, std::min((b + 1) * T, ks[tt])});
+            std::stable_sort(sg.begin(), sg.end(), [](const WideSeg& x, const WideSeg& y) { return x.end > y.end; });
+            for (size_t i = 0; i < sg.size(); i += maxs)
+                waves.emplace_back(sg.begin() + i, sg.begin() + std::min(sg.size(), i + (size_t)maxs));
+        }
+        if ((int)waves.size() > waves_max) continue;
+        // every end but a wave's largest must lie an even number of K-steps
+        // after its start: only a tile's last segment can be odd, and one more
+        // K-step there only meets columns beyond the tile's degree limit
+        for (auto& wv : waves)
+            for (size_t i = 1; i < wv.size(); ++i)
+                if (wv[i].end < wv[0].end && ((wv[i].end - wv[i].start) & 1)) wv[i].end += 1;
+        auto load = [&](int i) { int l = 0; for (auto& s : waves[i]) l += s.end - s.start; return l; };
+        std::vector<int> order(waves.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return load(x) > load(y); });
+        int simd_load[4] = {0, 0, 0, 0}, simd_n[4] = {0, 0, 0, 0};
+        std::vector<std::vector<WideSeg>> placed(waves_max);
+        int longest = 0;
+        for (int i : order) {
+            int pick = -1;
+            for (int q = 0; q < 4; ++q)
+                if (simd_n[q] < waves_max / 4 && (pick < 0 || simd_load[q] < simd_load[pick])) pick = q;
+            placed[simd_n[pick] * 4 + pick] = waves[i];
+            simd_n[pick] += 1;
+            simd_load[pick] += load(i);
+            longest = std::max(longest, waves[i][0].end - waves[i][0].start);
+        }
+        const int cost = *std::max_element(simd_load, simd_load + 4) + longest;
+        if (cost < best_cost) { best_cost = cost; best = placed; }
+    }
+    return !best.empty();
+}
+
+// Row groups of the wide M2L with `waves` waves of maxs slots: tiles are
+// dealt to G groups by longest-processing-time on their K-lengths, every
+// group gets a split-K plan, and G minimises the summed group costs plus a
+// fixed per-workgroup overhead.  Fills the per-group tables of k_m2l_wide.
+bool plan_wide(const std::vector<int>& ks, int maxs, int waves, std::vector<int>& tab, int& G_out, int& stride,
+               int& max_partial) {
+    const int ntile = (int)ks.size();
+    stride = 2 * waves + 4 * waves * maxs + 1;
+    int best_total = INT32_MAX;
+    std::vector<std::vector<std::vector<WideSeg>>> best_groups;
+    const int gmin = std::max(1, (ntile + waves * maxs - 1) / (waves * maxs));
+    for (int G = gmin; G <= 12; ++G) {
+        std::vector<int> order(ntile);
+        for (int i = 0; i < ntile; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ks[a] > ks[b]; });
+        std::vector<std::vector<int>> gt(G);
+        std::vector<int> tot(G, 0);
+        for (int tt : order) {
+            const int q = (int)(std::min_element(tot.begin(), tot.end()) - tot.begin());
+            gt[q].push_back(tt);
+            tot[q] += ks[tt];
+        }
+        int total = 0;
+        bool ok = true;
+        std::vector<std::vector<std::vector<WideSeg>>> groups(G);
+        for (int q = 0; q < G && ok; ++q) {
+            int c = 0;
+            if (gt[q].empty() || !plan_row_group(gt[q], ks, maxs, waves, groups[q], c)) ok = false;
+            total += c + 8;
+        }
+        if (ok && total < best_total) { best_total = total; best_groups = groups; }
+    }
+    if (best_groups.empty()) return false;
+    const int G = (int)best_groups.size();
+    tab.assign((size_t)G * stride, -1);
+    max_partial = 0;
+    for (int q = 0; q < G; ++q) {
+        int* gp = &tab[(size_t)q * stride];
+        std::vector<int> red;
+        for (int wv = 0; wv < waves; ++wv) {
+            const auto& g = best_groups[q][wv];
+            const int start = g.empty() ? 0 : g[0].start;
+            gp[2 * wv] = start;
+            gp[2 * wv + 1] = (int)g.size();
+            for (int i = 0; i < maxs; ++i) {
+                int* e = gp + 2 * waves + (wv * maxs + i) * 3;
+                if (i < (int)g.size()) {
+                    e[0] = g[i].tile;
+                    e[1] = g[i].end;
+                    e[2] = -1;
+                    if (g[i].start > 0) { e[2] = (int)red.size(); red.push_back(g[i].tile); }
+                } else {
+                    e[0] = -1; e[1] = start; e[2] = -1;   // empty slot: ends where the wave starts
+                }
+            }
+        }
+        gp[2 * waves + 3 * waves * maxs] = (int)red.size();
+        for (size_t i = 0; i < red.size(); ++i) gp[2 * waves + 3 * waves * maxs + 1 + i] = red[i];
+        max_partial = std::max(max_partial, (int)red.size());
+    }
+    G_out = G;
+    return true;
 }
 
 pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
@@ -1252,6 +1641,32 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             PF_TRY(upload(t, &t->tile_ks, wmeta.data(), wmeta.size()));
         }
     }
+    // wide matrix-core M2L: row groups for two and four interval blocks
+    if (t->mfma_slots) {
+        const int Nc = P.Nc, ntile = (Nc + 15) / 16;
+        std::vector<int> ks(ntile);
+        for (int tt = 0; tt < ntile; ++tt)
+            ks[tt] = ((P.m_t + 1) * binom(P.m_x - P.coef_deg[16 * tt] + 3, 3) + 3) / 4;
+        int dev = 0, lds_max = 65536;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        const int Nc4 = (Nc + 3) & ~3;
+        for (int v = 0; v < 2; ++v) {
+            auto& W = t->wide[v];
+            const int maxs = kWideMaxs[v], waves = kWideWaves[v];
+            std::vector<int> tab;
+            int maxp = 0;
+            if (!plan_wide(ks, maxs, waves, tab, W.G, W.stride, maxp)) continue;
+            W.shm = std::max((size_t)6 * t->TSp * sizeof(double) + (size_t)(Nc4 + 16) * 4 * sizeof(int),
+                             (size_t)maxp * 8 * 64 * sizeof(double));
+            if (W.shm > (size_t)lds_max) continue;
+            const void* fn = v == 0 ? (const void*)k_m2l_wide<2, kWideMaxs[0], kWideWaves[0]>
+                                    : (const void*)k_m2l_wide<4, kWideMaxs[1], kWideWaves[1]>;
+            if (W.shm > 65536) HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.shm));
+            PF_TRY(upload(t, &W.plan, tab.data(), tab.size()));
+            W.ok = true;
+        }
+    }
     // staged 1D tables of the matrix-core M2L: per (level, Delta, offset) the
     // x table with C_ab folded in and the plain table for y and z, each padded
     // to TSp doubles so that 1 KB pieces can be copied straight into LDS
@@ -1293,13 +1708,26 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         D.at_off = FL.at_off; D.qt_off = FL.qt_off; D.qx_off = FL.qx_off; D.n_off = FL.n_off;
         D.e1_off = FL.e1_off; D.cab_off = FL.cab_off; D.R = FL.R; D.e1s_off = e1s_off[l];
         PF_TRY(upload(t, &D.off3, FL.off3.data(), FL.off3.size()));
-        PF_TRY(dalloc(t, &D.mu, (size_t)D.nx * P.Nc * D.n_int));
+        // Two leading guard values (the wide M2L reads mu[-2], mu[-1] for target
+        // interval 0, whose result it discards).  Zeroed once, so that every
+        // moment a matrix-core M2L may multiply by a zero operator entry
+        // (padding columns) is finite.
+        PF_TRY(dalloc(t, &D.mu, (size_t)D.nx * P.Nc * D.n_int + 2));
+        HIP_TRY(hipMemset(D.mu, 0, ((size_t)D.nx * P.Nc * D.n_int + 2) * sizeof(double)));
+        D.mu += 2;
         PF_TRY(dalloc(t, &D.lam, (size_t)D.nx * P.Nc * D.n_int));
         {
             // enough workgroups to fill the chip several times: split source lists otherwise
             int dev = 0, ncu = 256;
             if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-            const int64_t wg = (int64_t)D.nx * ((D.n_int + 63) / 64) * (D.n_int > 32 ? 2 : 1);
+            int64_t wg = (int64_t)D.nx * ((D.n_int + 63) / 64) * (D.n_int > 32 ? 2 : 1);
+            D.m2l_nb = 0;
+            if (t->mfma_slots && D.n_int % 128 == 0 && t->wide[1].ok) D.m2l_nb = 4;
+            else if (t->mfma_slots && D.n_int % 64 == 0 && t->wide[0].ok) D.m2l_nb = 2;
+            if (D.m2l_nb) {
+                D.ncb = D.n_int / (32 * D.m2l_nb);
+                wg = (int64_t)D.nx * t->wide[D.m2l_nb == 4 ? 1 : 0].G * D.ncb;
+            }
             D.nsplit = 1;
             while (D.nsplit < 4 && wg * D.nsplit < 4 * ncu) D.nsplit *= 2;
             if (D.nsplit > 1) PF_TRY(dalloc(t, &D.lam_parts, (size_t)(D.nsplit - 1) * D.nx * P.Nc * D.n_int));
@@ -1427,7 +1855,24 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         prof_begin(t, 3, st, ev);
         for (int l = 2; l <= P.depth; ++l) {
             DevLevel& D = t->lv[l];
-            if (t->mfma_slots) {
+            if (D.m2l_nb) {
+                const auto& W = t->wide[D.m2l_nb == 4 ? 1 : 0];
+                dim3 grid(W.G, D.nx, D.ncb * D.nsplit);
+                const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
+                if (D.m2l_nb == 4)
+                    hipLaunchKernelGGL((k_m2l_wide<4, kWideMaxs[1], kWideWaves[1]>), grid, dim3(64 * kWideWaves[1]),
+                                       W.shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3,
+                                       t->E1s + D.e1s_off, t->TSp, t->packinfo, W.plan, W.stride, P.Nc, D.n_int,
+                                       P.m_t, P.m_x, D.R, D.nsplit, D.ncb, D.lam_parts);
+                else
+                    hipLaunchKernelGGL((k_m2l_wide<2, kWideMaxs[0], kWideWaves[0]>), grid, dim3(64 * kWideWaves[0]),
+                                       W.shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3,
+                                       t->E1s + D.e1s_off, t->TSp, t->packinfo, W.plan, W.stride, P.Nc, D.n_int,
+                                       P.m_t, P.m_x, D.R, D.nsplit, D.ncb, D.lam_parts);
+                if (D.nsplit > 1)
+                    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam,
+                                       D.lam_parts, D.nsplit - 1, nl);
+            } else if (t->mfma_slots) {
                 const size_t shm = t->m2l_shm;
                 const int halves = D.n_int > 32 ? 2 : 1;
                 dim3 grid(D.nx, (D.n_int + 63) / 64, halves * D.nsplit);
