@@ -504,7 +504,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     const int* __restrict__ cls, const int* __restrict__ off3, const double* __restrict__ E1s, int TSp,
     const int* __restrict__ packinfo, const int* __restrict__ plan, int plan_stride, int Nc, int n_int, int mt,
     int mx, int R, int nsplit, int ncb, double* __restrict__ lam_parts) {
-    static_assert(MAXS >= 1 && MAXS <= 2, "phase dispatch below is written for one or two slots");
+    static_assert(MAXS >= 1 && MAXS <= 4, "phase dispatch below is written for one to four slots");
     extern __shared__ double smem[];
     const int nt1 = mt + 1, nx1 = mx + 1;
     const int nx2 = nx1 * nx1;
@@ -675,11 +675,18 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
                     load(bB, s + 3);
                 }
             };
-            if constexpr (MAXS == 2) phase(std::integral_constant<int, 2>{}, ks[1]);
+            if constexpr (MAXS >= 4) phase(std::integral_constant<int, 4>{}, ks[3]);
+            if constexpr (MAXS >= 3) phase(std::integral_constant<int, 3>{}, ks[2]);
+            if constexpr (MAXS >= 2) phase(std::integral_constant<int, 2>{}, ks[1]);
             phase(std::integral_constant<int, 1>{}, ks[0]);
-            if (s < ks[0]) {   // odd final step
-                if (MAXS == 2 && s < ks[MAXS - 1]) step(std::integral_constant<int, MAXS>{}, cA, bA);
-                else step(std::integral_constant<int, 1>{}, cA, bA);
+            if (s < ks[0]) {   // odd final step of the slots that end last
+                int na = 1;
+#pragma unroll
+                for (int i = 1; i < MAXS; ++i) na += ks[i] > s ? 1 : 0;
+                if (na == 1) step(std::integral_constant<int, 1>{}, cA, bA);
+                if constexpr (MAXS >= 2) if (na == 2) step(std::integral_constant<int, 2>{}, cA, bA);
+                if constexpr (MAXS >= 3) if (na == 3) step(std::integral_constant<int, 3>{}, cA, bA);
+                if constexpr (MAXS >= 4) if (na == 4) step(std::integral_constant<int, 4>{}, cA, bA);
             }
         };
         if ((p & 1) == 0) run(std::integral_constant<int, 2>{});
@@ -736,9 +743,26 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     }
 }
 
-// wide M2L variants: [0] two interval blocks, [1] four interval blocks
-constexpr int kWideMaxs[2] = {2, 2};
-constexpr int kWideWaves[2] = {16, 8};
+// wide M2L variants (interval blocks, slots per wave, waves per workgroup):
+// [0] for levels with 32 intervals, [1] with a multiple of 64, [2] of 128
+constexpr int kWideNB[3] = {1, 2, 4};
+constexpr int kWideMaxs[3] = {2, 1, 2};
+constexpr int kWideWaves[3] = {16, 16, 8};
+constexpr bool kWideUseNB1 = true;   // levels with 32 intervals: wide form instead of k_m2l_mfma
+
+template <int V>
+const void* wide_fn() {
+    return (const void*)k_m2l_wide<kWideNB[V], kWideMaxs[V], kWideWaves[V]>;
+}
+
+template <int V>
+void launch_wide(dim3 grid, size_t shm, hipStream_t st, const double* mu, double* lam, const int* ptr, const int* src,
+                 const int* cls, const int* off3, const double* E1s, int TSp, const int* packinfo, const int* plan,
+                 int plan_stride, int Nc, int n_int, int mt, int mx, int R, int nsplit, int ncb, double* lam_parts) {
+    hipLaunchKernelGGL((k_m2l_wide<kWideNB[V], kWideMaxs[V], kWideWaves[V]>), grid, dim3(64 * kWideWaves[V]), shm, st,
+                       mu, lam, ptr, src, cls, off3, E1s, TSp, packinfo, plan, plan_stride, Nc, n_int, mt, mx, R,
+                       nsplit, ncb, lam_parts);
+}
 
 // Sum the per-share partial locals of a level whose interaction lists were
 // split over several workgroups (fixed order: share 0, 1, ...).
@@ -1204,7 +1228,7 @@ struct pfmm_tree {
     int n_partial = 0;            // split-K partial segments
     size_t m2l_shm = 0;           // dynamic LDS of the matrix-core M2L
     // wide matrix-core M2L: [0] two interval blocks / two slots, [1] four blocks / one slot
-    struct Wide { int* plan = nullptr; int G = 0, stride = 0; size_t shm = 0; bool ok = false; } wide[2];
+    struct Wide { int* plan = nullptr; int G = 0, stride = 0; size_t shm = 0; bool ok = false; } wide[3];
     CoefMaps cm{};
     std::vector<DevLevel> lv;
     bool low_leaves = false;      // leaves at levels < 2 (no far field)
@@ -1651,7 +1675,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         const int Nc4 = (Nc + 3) & ~3;
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < 3; ++v) {
             auto& W = t->wide[v];
             const int maxs = kWideMaxs[v], waves = kWideWaves[v];
             std::vector<int> tab;
@@ -1660,8 +1684,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             W.shm = std::max((size_t)6 * t->TSp * sizeof(double) + (size_t)(Nc4 + 16) * 4 * sizeof(int),
                              (size_t)maxp * 8 * 64 * sizeof(double));
             if (W.shm > (size_t)lds_max) continue;
-            const void* fn = v == 0 ? (const void*)k_m2l_wide<2, kWideMaxs[0], kWideWaves[0]>
-                                    : (const void*)k_m2l_wide<4, kWideMaxs[1], kWideWaves[1]>;
+            const void* fn = v == 0 ? wide_fn<0>() : (v == 1 ? wide_fn<1>() : wide_fn<2>());
             if (W.shm > 65536) HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.shm));
             PF_TRY(upload(t, &W.plan, tab.data(), tab.size()));
             W.ok = true;
@@ -1722,11 +1745,15 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
             int64_t wg = (int64_t)D.nx * ((D.n_int + 63) / 64) * (D.n_int > 32 ? 2 : 1);
             D.m2l_nb = 0;
-            if (t->mfma_slots && D.n_int % 128 == 0 && t->wide[1].ok) D.m2l_nb = 4;
-            else if (t->mfma_slots && D.n_int % 64 == 0 && t->wide[0].ok) D.m2l_nb = 2;
+            if (t->mfma_slots) {
+                for (int v = 2; v >= 0 && !D.m2l_nb; --v)
+                    if (t->wide[v].ok && D.n_int % (32 * kWideNB[v]) == 0 && (v > 0 || kWideUseNB1))
+                        D.m2l_nb = kWideNB[v];
+            }
             if (D.m2l_nb) {
+                const int v = D.m2l_nb == 4 ? 2 : (D.m2l_nb == 2 ? 1 : 0);
                 D.ncb = D.n_int / (32 * D.m2l_nb);
-                wg = (int64_t)D.nx * t->wide[D.m2l_nb == 4 ? 1 : 0].G * D.ncb;
+                wg = (int64_t)D.nx * t->wide[v].G * D.ncb;
             }
             D.nsplit = 1;
             while (D.nsplit < 4 && wg * D.nsplit < 4 * ncu) D.nsplit *= 2;
@@ -1856,19 +1883,14 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         for (int l = 2; l <= P.depth; ++l) {
             DevLevel& D = t->lv[l];
             if (D.m2l_nb) {
-                const auto& W = t->wide[D.m2l_nb == 4 ? 1 : 0];
+                const int v = D.m2l_nb == 4 ? 2 : (D.m2l_nb == 2 ? 1 : 0);
+                const auto& W = t->wide[v];
                 dim3 grid(W.G, D.nx, D.ncb * D.nsplit);
                 const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
-                if (D.m2l_nb == 4)
-                    hipLaunchKernelGGL((k_m2l_wide<4, kWideMaxs[1], kWideWaves[1]>), grid, dim3(64 * kWideWaves[1]),
-                                       W.shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3,
-                                       t->E1s + D.e1s_off, t->TSp, t->packinfo, W.plan, W.stride, P.Nc, D.n_int,
-                                       P.m_t, P.m_x, D.R, D.nsplit, D.ncb, D.lam_parts);
-                else
-                    hipLaunchKernelGGL((k_m2l_wide<2, kWideMaxs[0], kWideWaves[0]>), grid, dim3(64 * kWideWaves[0]),
-                                       W.shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3,
-                                       t->E1s + D.e1s_off, t->TSp, t->packinfo, W.plan, W.stride, P.Nc, D.n_int,
-                                       P.m_t, P.m_x, D.R, D.nsplit, D.ncb, D.lam_parts);
+                auto* launch = v == 2 ? launch_wide<2> : (v == 1 ? launch_wide<1> : launch_wide<0>);
+                launch(grid, W.shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3, t->E1s + D.e1s_off,
+                       t->TSp, t->packinfo, W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, D.nsplit, D.ncb,
+                       D.lam_parts);
                 if (D.nsplit > 1)
                     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam,
                                        D.lam_parts, D.nsplit - 1, nl);
