@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 METRIC = "space-time DOF matvec/s of pFMM V_h at 1e-6 rel err; GMRES solve time vs plain"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3     # dense FP32 matrix-core peak
 
 # HBM bytes per apply from rocprofv3 FETCH_SIZE / WRITE_SIZE runs on the
 # 3072 x 256, m = 6 workload, scaled by the same counters on a plain 1 GiB
@@ -187,6 +188,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="farfield precision: fp64, or fp32 (M2L with FP32 inputs and accumulation; "
+                         "the error against the FP64 apply on the same tree is measured and reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
@@ -213,8 +217,10 @@ def main():
 
     v, t, tn, c, w = config_problem(args.config)
     N = len(w)
+    mixed = args.precision == "fp32"
+    # the tree holds both farfield paths; the timed one is selected with set_precision
     prm = P.default_params(m_t=c["m_t"], m_x=c["m_x"], n_max=c["n_max"], c_st=c["c_st"], n_tr=c["n_tr"],
-                           operators=1)
+                           operators=1, precision=P.MIXED_FP32)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     t0 = time.perf_counter()
@@ -233,22 +239,43 @@ def main():
         log(f"[bench] copy calibration: {8 * n} bytes read, {8 * n} bytes written")
         del a, b
     x = torch.from_numpy(w).to(dev)
-    f = torch.empty_like(x)
-    for _ in range(args.warmup):
-        tree.apply_V(x, out=f, stream=stream)
-    torch.cuda.synchronize()
-    # timed region
-    tree.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        tree.apply_V(x, out=f, stream=stream)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = tree.profile_read()
-    tree.profile_enable(False)
-    ms_per_step = 1e3 * dt / args.steps
-    log(f"[bench] {args.steps} applies: {ms_per_step:.3f} ms/apply; stages {prof}")
+
+    def timed(precision, steps, warmup):
+        """warmup untimed applies, then `steps` applies bracketed by device synchronisation"""
+        tree.set_precision(precision)
+        out = torch.empty_like(x)
+        for _ in range(warmup):
+            tree.apply_V(x, out=out, stream=stream)
+        torch.cuda.synchronize()
+        tree.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            tree.apply_V(x, out=out, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pr = tree.profile_read()
+        tree.profile_enable(False)
+        return out, 1e3 * dt / steps, pr
+
+    # timed region: the selected precision
+    f, ms_per_step, prof = timed(P.MIXED_FP32 if mixed else P.FP64, args.steps, args.warmup)
+    log(f"[bench] {args.steps} applies ({args.precision}): {ms_per_step:.3f} ms/apply; stages {prof}")
+    # the other precision on the same tree, and the measured error of the mixed mode
+    import numpy as np
+    g, ms_other, prof_other = timed(P.FP64 if mixed else P.MIXED_FP32, max(3, args.steps // 2), 1)
+    fm, fd = (f, g) if mixed else (g, f)
+    fm, fd = fm.cpu().numpy(), fd.cpu().numpy()
+    mixed_err = {"rel_2norm_vs_fp64": float(np.linalg.norm(fm - fd) / np.linalg.norm(fd)),
+                 "rel_max_vs_fp64": float(np.abs(fm - fd).max() / np.abs(fd).max())}
+    other = "fp64" if mixed else "fp32"
+    log(f"[bench] {other}: {ms_other:.3f} ms/apply; mixed vs FP64 on the same tree: {mixed_err}")
+    other_precision = {"precision": other, "ms_per_step": ms_other, "value": N / (ms_other * 1e-3),
+                       "m2l_ms": prof_other["m2l"][0] / max(prof_other["m2l"][1], 1),
+                       "mixed_error": mixed_err,
+                       "note": ("fp32: M2L with FP32 moments/operator entries and FP32 matrix-core accumulation, "
+                                "everything else FP64")}
+    tree.set_precision(P.MIXED_FP32 if mixed else P.FP64)
 
     # roofline of the dominant kernel
     near_ms = prof["nearfield"][0] / max(prof["nearfield"][1], 1)
@@ -264,10 +291,13 @@ def main():
                 "launch_ms": near_ms, "algorithmic_bytes": near_bytes}
     else:
         achieved = m2l_flop / (m2l_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_m2l_mfma (all levels)" if st["m2l_matrix_cores"] == 1 else "k_m2l (all levels)",
-                "bound": "mfma" if st["m2l_matrix_cores"] == 1 else "alu", "achieved": achieved, "peak": FP64_PEAK_TFS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS,
-                "traffic": measured_traffic("k_m2l_mfma", args.config) if st["m2l_matrix_cores"] == 1 else None,
+        peak = FP32_PEAK_TFS if mixed else FP64_PEAK_TFS
+        roof = {"kernel": ("M2L stage: k_m2l_wide + k_m2l_mfma (all levels)" if st["m2l_matrix_cores"] == 1
+                           else "k_m2l (all levels)"),
+                "bound": "mfma" if st["m2l_matrix_cores"] == 1 else "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": (measured_traffic("m2l", args.config)
+                            if st["m2l_matrix_cores"] == 1 and not mixed else None),
                 "launch_ms": m2l_ms, "algorithmic_flop": m2l_flop}
     roof["traffic_note"] = "HBM bytes per apply, all launches of the kernel (rocprofv3 counters, copy-calibrated)"
     other = {"nearfield": {"ms": near_ms, "GB/s": near_bytes / (near_ms * 1e-3) / 1e9,
@@ -297,12 +327,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 M2L + f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": (f"V_h apply, cube [-1,1]^3 {c['n']}x{c['n']} squares/face ({len(t)} triangles) x "
                                 f"{c['n_steps']} uniform steps on [0,1], alpha=1, m_t={c['m_t']}, m_x={c['m_x']}, "
-                                f"n_max={c['n_max']}, c_st={c['c_st']}, n_tr={c['n_tr']}, FP64"),
-                   "dofs": N, "parallelism": "single GPU"},
+                                f"n_max={c['n_max']}, c_st={c['c_st']}, n_tr={c['n_tr']}, "
+                                + ("M2L in FP32 (inputs and accumulation), rest FP64" if mixed else "FP64")),
+                   "dofs": N, "parallelism": "single GPU", "precision": args.precision},
+        "mixed_error": mixed_err if mixed else None,
+        "other_precision": other_precision,
         "roofline": roof,
         "other_kernels": other,
         "stages_ms_per_apply": {k: (vv[0] / max(vv[1], 1)) for k, vv in prof.items()},

@@ -51,7 +51,12 @@ typedef enum {
 } pfmm_status;
 
 typedef enum {
-    PFMM_FP64 = 0            /* farfield and nearfield in FP64                 */
+    PFMM_FP64 = 0,           /* farfield and nearfield in FP64                 */
+    PFMM_MIXED_FP32 = 1      /* M2L (eq. m2l) with FP32 moments and operator
+                                entries on FP32 matrix cores with FP32
+                                accumulation, on every level with >= 32 time
+                                intervals; nearfield, S2M, M2M, L2L, L2T, the
+                                locals and the final sum stay FP64           */
 } pfmm_precision;
 
 /* which operators pfmm_build_tree assembles (bit mask) */
@@ -68,7 +73,8 @@ typedef struct {
     int32_t  n_tr;           /* spatial cut, grid distance (eq. 03:Iarea); -1 none. default 5   */
     int32_t  q_reg;          /* Gauss points per direction, regular panel pairs.   default 4   */
     int32_t  q_sing;         /* Gauss points per direction, touching panel pairs.  default 5   */
-    int32_t  precision;      /* pfmm_precision.                                    default FP64 */
+    int32_t  precision;      /* pfmm_precision of the applies; a MIXED tree also
+                                keeps the FP64 path (pfmm_set_precision).     default FP64 */
     int32_t  operators;      /* PFMM_OP_V | PFMM_OP_K.                             default both */
     int32_t  check_finite;   /* 1: reject non-finite mesh/time input.              default 1   */
     int32_t  reserved;
@@ -132,6 +138,17 @@ pfmm_status pfmm_apply_V(pfmm_tree* t, const double* w_dev, double* f_dev, void*
 
 /* f = K_h u, same conventions as pfmm_apply_V (K must have been built). */
 pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void* stream);
+
+/*
+ * Select the farfield precision of the following applies of t (and of the
+ * solves, which call the same apply).  PFMM_FP64 is always available;
+ * PFMM_MIXED_FP32 needs a tree built with precision PFMM_MIXED_FP32 (which
+ * holds FP32 copies of the moments and tables in addition to the FP64 data).
+ * Not stream-ordered: call it between applies, not while one is being
+ * enqueued.  Errors: PFMM_EINVAL (NULL tree, unknown precision, FP32 data
+ * not built).
+ */
+pfmm_status pfmm_set_precision(pfmm_tree* t, int32_t precision);
 
 /* Counts and sizes of a built tree. */
 pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out);

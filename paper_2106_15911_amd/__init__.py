@@ -5,7 +5,7 @@ The compute path lives in the HIP library ``libpfmm.so`` (see include/pfmm.h);
 this package only loads it and marshals arguments.
 """
 from .pfmm import (PfmmError, Params, SolveOpts, SolveInfo, Tree, default_params, plan_stats, lib_path,
-                   load_library, STATUS_NAMES, PROFILE_STAGES)
+                   load_library, STATUS_NAMES, PROFILE_STAGES, FP64, MIXED_FP32)
 
 __all__ = ["PfmmError", "Params", "SolveOpts", "SolveInfo", "Tree", "default_params", "plan_stats", "lib_path",
-           "load_library", "STATUS_NAMES", "PROFILE_STAGES"]
+           "load_library", "STATUS_NAMES", "PROFILE_STAGES", "FP64", "MIXED_FP32"]

@@ -254,6 +254,7 @@ __global__ void __launch_bounds__(64) k_m2l(const double* __restrict__ mu, doubl
 // MFMA register layout (checked on gfx950): A[i][k] lane i+16k, B[k][j]
 // lane j+16k, D[i][j] lane j+16(i%4), register i/4.
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kM2LWaves = 16;   // waves per workgroup (one interval half)
 constexpr int kXcds = 8;        // accelerator complex dies of an MI355X (one L2 each)
@@ -473,7 +474,9 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
     }
 }
 
-// M2L on FP64 matrix cores, wide form for levels with >= 64 intervals.
+// M2L on matrix cores, wide form for levels with >= 32 intervals, in FP64
+// (T = double, v_mfma_f64_16x16x4f64) or with FP32 moments and operator
+// tables and FP32 accumulation (T = float, v_mfma_f32_16x16x4f32).
 //
 // The rows of eq. m2l (16-row tiles of the staircase) are partitioned into
 // row groups; a workgroup of WAVES waves owns one target slot X, one row
@@ -498,13 +501,34 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
 // without copies.  Source moments are read through a buffer descriptor
 // spanning the source slot's moments: prefetches beyond a segment (and
 // padding columns) return zero without touching other memory.
-template <int NB, int MAXS, int WAVES>
+template <class T> struct M2LTraits;
+template <> struct M2LTraits<double> {
+    using acc_t = d4_t;
+    static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // D[i][j] of a 16x16 tile: lane j + 16 (i % 4), register i / 4
+    static __device__ __forceinline__ int row(int lq, int r) { return lq + 4 * r; }
+};
+template <> struct M2LTraits<float> {
+    using acc_t = f4_t;
+    static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // D[i][j] of a 16x16 tile: lane j + 16 (i / 4), register i % 4
+    static __device__ __forceinline__ int row(int lq, int r) { return 4 * lq + r; }
+};
+
+template <class T, int NB, int MAXS, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
-    const double* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
-    const int* __restrict__ cls, const int* __restrict__ off3, const double* __restrict__ E1s, int TSp,
+    const T* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
+    const int* __restrict__ cls, const int* __restrict__ off3, const T* __restrict__ E1s, int TSp,
     const int* __restrict__ packinfo, const int* __restrict__ plan, int plan_stride, int Nc, int n_int, int mt,
     int mx, int R, int nsplit, int ncb, double* __restrict__ lam_parts) {
     static_assert(MAXS >= 1 && MAXS <= 4, "phase dispatch below is written for one to four slots");
+    using Tr = M2LTraits<T>;
+    using acc_t = typename Tr::acc_t;
+    constexpr int ES = sizeof(T);              // bytes per table entry / moment
     extern __shared__ double smem[];
     const int nt1 = mt + 1, nx1 = mx + 1;
     const int nx2 = nx1 * nx1;
@@ -512,7 +536,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     // two buffers of the three 1D tables of one (source, Delta) phase: [buf][x | y | z][TSp];
     // then per coefficient column (padded): byte offsets of its x, y, z table
     // columns and its degree (255 for padding columns)
-    int4* sCol = (int4*)(smem + 6 * TSp);
+    int4* sCol = (int4*)((char*)smem + 6 * TSp * ES);
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     // Workgroups are dealt to the 8 XCDs round-robin by linear id; remap so
@@ -540,9 +564,9 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
         if (c < Nc) {
             const int ci = packinfo[c];
             const int cbase = (ci & 15) * nt1 * nx2;
-            v.x = 8 * (cbase + ((ci >> 4) & 15) * nx1);
-            v.y = 8 * (cbase + ((ci >> 8) & 15) * nx1);
-            v.z = 8 * (cbase + ((ci >> 12) & 15) * nx1);
+            v.x = ES * (cbase + ((ci >> 4) & 15) * nx1);
+            v.y = ES * (cbase + ((ci >> 8) & 15) * nx1);
+            v.z = ES * (cbase + ((ci >> 12) & 15) * nx1);
             v.w = (ci >> 16) & 255;
         }
         sCol[c] = v;
@@ -559,35 +583,36 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
         const bool rv = tiles[i] >= 0 && row < Nc;
         const int ri = rv ? packinfo[row] : 0;
         const int b = ri & 15;
-        rX[i] = 8 * (b * nx2 + ((ri >> 4) & 15));
-        rY[i] = 8 * (b * nx2 + ((ri >> 8) & 15) + TSp);
-        rZ[i] = 8 * (b * nx2 + ((ri >> 12) & 15) + 2 * TSp);
+        rX[i] = ES * (b * nx2 + ((ri >> 4) & 15));
+        rY[i] = ES * (b * nx2 + ((ri >> 8) & 15) + TSp);
+        rZ[i] = ES * (b * nx2 + ((ri >> 12) & 15) + 2 * TSp);
         rD[i] = mx - (rv ? ((ri >> 16) & 255) : 255);   // largest column degree this row accepts
     }
-    d4_t accE[MAXS][NB], accO[MAXS][NB];
+    acc_t accE[MAXS][NB], accO[MAXS][NB];
 #pragma unroll
     for (int i = 0; i < MAXS; ++i)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            accE[i][nb] = d4_t{0.0, 0.0, 0.0, 0.0};
-            accO[i][nb] = d4_t{0.0, 0.0, 0.0, 0.0};
+            accE[i][nb] = acc_t{0, 0, 0, 0};
+            accO[i][nb] = acc_t{0, 0, 0, 0};
         }
     const int nR = 2 * R + 1;
     const int sb = ptr[X], se = ptr[X + 1];
     const int s_lo = sb + (int)(((int64_t)(se - sb) * split) / nsplit);
     const int s_hi = sb + (int)(((int64_t)(se - sb) * (split + 1)) / nsplit);
     const int n_phase = 2 * (s_hi - s_lo);
-    const int pieces = TSp / 128;                    // 1 KB pieces per table
+    const int pieces = TSp * ES / 1024;              // 1 KB pieces per table
     auto stage = [&](int p) {
         const int si = s_lo + (p >> 1), D = 2 + (p & 1);
         const int c3 = cls[si];
-        double* dst = smem + (p & 1) * 3 * TSp;
+        char* dst = (char*)smem + (p & 1) * 3 * TSp * ES;
         for (int c = w; c < 3 * pieces; c += WAVES) {
             const int tb = c / pieces, pc = c - tb * pieces;
             const int o = off3[3 * c3 + tb] + R;
-            const double* gsrc = E1s + (((int64_t)(D - 2) * nR + o) * 2 + (tb == 0 ? 0 : 1)) * TSp + pc * 128 + 2 * lane;
+            const char* gsrc = (const char*)(E1s + (((int64_t)(D - 2) * nR + o) * 2 + (tb == 0 ? 0 : 1)) * TSp) +
+                               pc * 1024 + 16 * lane;
             __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)gsrc,
-                                             (void __attribute__((address_space(3)))*)(dst + tb * TSp + pc * 128),
+                                             (void __attribute__((address_space(3)))*)(dst + tb * TSp * ES + pc * 1024),
                                              16, 0, 0);
         }
     };
@@ -595,19 +620,19 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     // mu[Y][c][k - 2], mu[Y][c][k - 1] with c = 4 s + lq and k = its even
     // target interval: the Delta = 2 sources of the even and odd targets, and
     // (first value) the Delta = 3 source of the odd target.  Block nb is
-    // 256 bytes further.  Targets k < 2 have no sources: their results are
+    // 32 values further.  Targets k < 2 have no sources: their results are
     // written as zero at the end.  The descriptor starts two values before the
     // slot (mu has two leading guard values), so every offset is >= 0; reads
     // past the slot's last coefficient are out of its range and return zero.
-    const int vbase = ((4 * sbeg + lq) * n_int + k0) * 8;   // byte offset of mu[Y][c][k - 2] from the descriptor base
-    const int bstep = 4 * n_int * 8;                        // bytes between consecutive K-steps
-    const int slot_bytes = (Nc * n_int + 2) * 8;
+    const int vbase = ((4 * sbeg + lq) * n_int + k0) * ES;   // byte offset of mu[Y][c][k - 2] from the descriptor base
+    const int bstep = 4 * n_int * ES;                        // bytes between consecutive K-steps
+    const int slot_bytes = (Nc * n_int + 2) * ES;
     const char* lds = (const char*)smem;
     if (n_phase > 0) stage(0);
     for (int p = 0; p < n_phase; ++p) {
         const int si = s_lo + (p >> 1);
         const int Y = src[si];
-        const int boff = (p & 1) * 3 * TSp * 8;        // byte offset of this phase's table buffer
+        const int boff = (p & 1) * 3 * TSp * ES;       // byte offset of this phase's table buffer
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void*)(mu + (int64_t)Y * Nc * n_int - 2), (short)0, slot_bytes, 0x00020000);
         __builtin_amdgcn_s_waitcnt(0);   // this wave's pieces of phase p have landed in LDS
@@ -623,27 +648,31 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
         auto run = [&](auto dc) {
             constexpr int D = decltype(dc)::value;
             // Delta = 2 uses both values of the pair, Delta = 3 only the first
-            using BT = std::conditional_t<D == 2, double2, double>;
+            using T2 = std::conditional_t<sizeof(T) == 8, double2, float2>;
+            using BT = std::conditional_t<D == 2, T2, T>;
             auto load = [&](BT* bv, int s) {
                 const int vo = vbase + (s - sbeg) * bstep;
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    if constexpr (D == 2)
-                        bv[nb] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + nb * 256, 0, 0));
+                    const int off = vo + nb * 32 * ES;
+                    if constexpr (D == 2 && ES == 8)
+                        bv[nb] = __builtin_bit_cast(BT, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+                    else if constexpr (D == 2 || ES == 8)
+                        bv[nb] = __builtin_bit_cast(BT, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
                     else
-                        bv[nb] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo + nb * 256, 0, 0));
+                        bv[nb] = __builtin_bit_cast(BT, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
                 }
             };
             // one K-step with n active slots
             auto step = [&](auto nc, int4 col, const BT* bv) {
                 constexpr int n = decltype(nc)::value;
-                double A[n];
+                T A[n];
 #pragma unroll
                 for (int i = 0; i < n; ++i) {
-                    const double ex = *(const double*)(lds + (pX[i] + col.x));
-                    const double ey = *(const double*)(lds + (pY[i] + col.y));
-                    const double ez = *(const double*)(lds + (pZ[i] + col.z));
-                    const double msk = (col.w <= rD[i]) ? 1.0 : 0.0;
+                    const T ex = *(const T*)(lds + (pX[i] + col.x));
+                    const T ey = *(const T*)(lds + (pY[i] + col.y));
+                    const T ez = *(const T*)(lds + (pZ[i] + col.z));
+                    const T msk = (col.w <= rD[i]) ? T(1) : T(0);
                     A[i] = (ex * ey) * (ez * msk);
                 }
 #pragma unroll
@@ -651,10 +680,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) {
                         if constexpr (D == 2) {
-                            accE[i][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bv[nb].x, accE[i][nb], 0, 0, 0);
-                            accO[i][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bv[nb].y, accO[i][nb], 0, 0, 0);
+                            accE[i][nb] = Tr::mfma(A[i], bv[nb].x, accE[i][nb]);
+                            accO[i][nb] = Tr::mfma(A[i], bv[nb].y, accO[i][nb]);
                         } else {
-                            accO[i][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bv[nb], accO[i][nb], 0, 0, 0);
+                            accO[i][nb] = Tr::mfma(A[i], bv[nb], accO[i][nb]);
                         }
                     }
             };
@@ -696,7 +725,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     // owners of the tiles' first segments add them in a fixed order
     const int n_partial = gp[2 * WAVES + 3 * WAVES * MAXS];
     const int* ptile = gp + 2 * WAVES + 3 * WAVES * MAXS + 1;
-    double* red = smem;   // [n_partial][8][64]
+    T* red = (T*)smem;   // [n_partial][8][64]
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         __syncthreads();
@@ -733,11 +762,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
             const bool has = kE >= 2;   // targets 0 and 1 have no interaction list in time
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = 16 * tiles[i] + lq + 4 * r;
+                const int row = 16 * tiles[i] + Tr::row(lq, r);
                 if (row >= Nc) continue;
                 double* out = lam + ((int64_t)X * Nc + row) * n_int;
-                out[kE] = has ? accE[i][nb][r] : 0.0;
-                out[kO] = has ? accO[i][nb][r] : 0.0;
+                out[kE] = has ? (double)accE[i][nb][r] : 0.0;
+                out[kO] = has ? (double)accO[i][nb][r] : 0.0;
             }
         }
     }
@@ -745,23 +774,48 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
 
 // wide M2L variants (interval blocks, slots per wave, waves per workgroup):
 // [0] for levels with 32 intervals, [1] with a multiple of 64, [2] of 128
+// [precision: 0 FP64, 1 FP32][variant]
 constexpr int kWideNB[3] = {1, 2, 4};
-constexpr int kWideMaxs[3] = {2, 1, 2};
-constexpr int kWideWaves[3] = {16, 16, 8};
+constexpr int kWideMaxs[2][3] = {{2, 1, 2}, {2, 2, 2}};
+constexpr int kWideWaves[2][3] = {{16, 16, 8}, {16, 16, 8}};
 constexpr bool kWideUseNB1 = true;   // levels with 32 intervals: wide form instead of k_m2l_mfma
 
-template <int V>
+template <int Q, int V>
+using WideT = std::conditional_t<Q == 0, double, float>;
+
+template <int Q, int V>
 const void* wide_fn() {
-    return (const void*)k_m2l_wide<kWideNB[V], kWideMaxs[V], kWideWaves[V]>;
+    return (const void*)k_m2l_wide<WideT<Q, V>, kWideNB[V], kWideMaxs[Q][V], kWideWaves[Q][V]>;
 }
 
-template <int V>
-void launch_wide(dim3 grid, size_t shm, hipStream_t st, const double* mu, double* lam, const int* ptr, const int* src,
-                 const int* cls, const int* off3, const double* E1s, int TSp, const int* packinfo, const int* plan,
+const void* wide_fn(int q, int v) {
+    if (q == 0) return v == 0 ? wide_fn<0, 0>() : (v == 1 ? wide_fn<0, 1>() : wide_fn<0, 2>());
+    return v == 0 ? wide_fn<1, 0>() : (v == 1 ? wide_fn<1, 1>() : wide_fn<1, 2>());
+}
+
+template <int Q, int V>
+void launch_wide(dim3 grid, size_t shm, hipStream_t st, const void* mu, double* lam, const int* ptr, const int* src,
+                 const int* cls, const int* off3, const void* E1s, int TSp, const int* packinfo, const int* plan,
                  int plan_stride, int Nc, int n_int, int mt, int mx, int R, int nsplit, int ncb, double* lam_parts) {
-    hipLaunchKernelGGL((k_m2l_wide<kWideNB[V], kWideMaxs[V], kWideWaves[V]>), grid, dim3(64 * kWideWaves[V]), shm, st,
-                       mu, lam, ptr, src, cls, off3, E1s, TSp, packinfo, plan, plan_stride, Nc, n_int, mt, mx, R,
-                       nsplit, ncb, lam_parts);
+    using T = WideT<Q, V>;
+    hipLaunchKernelGGL((k_m2l_wide<T, kWideNB[V], kWideMaxs[Q][V], kWideWaves[Q][V]>), grid,
+                       dim3(64 * kWideWaves[Q][V]), shm, st, (const T*)mu, lam, ptr, src, cls, off3, (const T*)E1s,
+                       TSp, packinfo, plan, plan_stride, Nc, n_int, mt, mx, R, nsplit, ncb, lam_parts);
+}
+
+using WideLaunch = void (*)(dim3, size_t, hipStream_t, const void*, double*, const int*, const int*, const int*,
+                            const int*, const void*, int, const int*, const int*, int, int, int, int, int, int, int,
+                            int, double*);
+
+WideLaunch wide_launcher(int q, int v) {
+    if (q == 0) return v == 0 ? launch_wide<0, 0> : (v == 1 ? launch_wide<0, 1> : launch_wide<0, 2>);
+    return v == 0 ? launch_wide<1, 0> : (v == 1 ? launch_wide<1, 1> : launch_wide<1, 2>);
+}
+
+// FP32 copy of a level's moments for the mixed-precision M2L.
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
 }
 
 // Sum the per-share partial locals of a level whose interaction lists were
@@ -1188,8 +1242,10 @@ struct DevLevel {
     double* ops = nullptr;
     double* lam_parts = nullptr;  // extra shares of a split interaction list
     int nsplit = 1;
-    int m2l_nb = 0;               // wide M2L interval blocks per workgroup (2 or 4); 0: k_m2l_mfma / k_m2l
-    int ncb = 1;                  // wide M2L: workgroup column blocks of 32 m2l_nb intervals
+    int nsplit_q[2] = {1, 1};     // per precision (0 FP64, 1 FP32): interaction-list shares
+    int m2l_nb[2] = {0, 0};       // per precision: wide M2L interval blocks per workgroup; 0: k_m2l_mfma / k_m2l
+    int ncb[2] = {1, 1};          // per precision: wide M2L column blocks of 32 m2l_nb intervals
+    float* mu32 = nullptr;        // FP32 moments (mixed mode), same layout as mu
     int* off3 = nullptr;
     int64_t at_off = 0, qt_off = -1, qx_off = -1, e1_off = 0, cab_off = 0, e1s_off = 0;
     int n_off = 0, R = 0;
@@ -1228,7 +1284,11 @@ struct pfmm_tree {
     int n_partial = 0;            // split-K partial segments
     size_t m2l_shm = 0;           // dynamic LDS of the matrix-core M2L
     // wide matrix-core M2L: [0] two interval blocks / two slots, [1] four blocks / one slot
-    struct Wide { int* plan = nullptr; int G = 0, stride = 0; size_t shm = 0; bool ok = false; } wide[3];
+    struct Wide { int* plan = nullptr; int G = 0, stride = 0; size_t shm = 0; bool ok = false; } wide[2][3];
+    int prec = PFMM_FP64;         // farfield precision of the next applies
+    bool has_f32 = false;         // FP32 moments and tables allocated (tree built in a mixed mode)
+    float* E1s32 = nullptr;       // FP32 copy of E1s with rows of TSf entries
+    int TSf = 0;                  // FP32 table length (multiple of 256 floats)
     CoefMaps cm{};
     std::vector<DevLevel> lv;
     bool low_leaves = false;      // leaves at levels < 2 (no far field)
@@ -1287,13 +1347,14 @@ int dmax_class(int dmax) {
 }
 
 // Device memory the build will need (bytes), computed before allocating.
-uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask) {
+uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask, int precision) {
     uint64_t b = 0;
     const uint64_t N = (uint64_t)P.E_t * P.E_x;
     b += 2 * N * 8;                                   // w, f in tree order
     for (int l = 2; l <= P.depth; ++l) {
         const FarLevel& L = F.lv[l];
         b += 2ull * L.nx * P.Nc * L.n_int * 8;        // mu, lambda
+        if (precision == PFMM_MIXED_FP32) b += (uint64_t)L.nx * P.Nc * L.n_int * 4;   // FP32 moments
         b += (uint64_t)L.n_off * 2 * F.op_size * 8;   // explicit M2L operators (upper bound: fallback path)
     }
     int nop = ((ops_mask & PFMM_OP_V) ? 1 : 0) + ((ops_mask & PFMM_OP_K) ? 1 : 0);
@@ -1675,20 +1736,24 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         const int Nc4 = (Nc + 3) & ~3;
-        for (int v = 0; v < 3; ++v) {
-            auto& W = t->wide[v];
-            const int maxs = kWideMaxs[v], waves = kWideWaves[v];
-            std::vector<int> tab;
-            int maxp = 0;
-            if (!plan_wide(ks, maxs, waves, tab, W.G, W.stride, maxp)) continue;
-            W.shm = std::max((size_t)6 * t->TSp * sizeof(double) + (size_t)(Nc4 + 16) * 4 * sizeof(int),
-                             (size_t)maxp * 8 * 64 * sizeof(double));
-            if (W.shm > (size_t)lds_max) continue;
-            const void* fn = v == 0 ? wide_fn<0>() : (v == 1 ? wide_fn<1>() : wide_fn<2>());
-            if (W.shm > 65536) HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.shm));
-            PF_TRY(upload(t, &W.plan, tab.data(), tab.size()));
-            W.ok = true;
-        }
+        const int TS = (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1);
+        t->TSf = (TS + 255) / 256 * 256;
+        for (int q = 0; q < (t->has_f32 ? 2 : 1); ++q)
+            for (int v = 0; v < 3; ++v) {
+                auto& W = t->wide[q][v];
+                const int maxs = kWideMaxs[q][v], waves = kWideWaves[q][v];
+                const size_t es = q == 0 ? sizeof(double) : sizeof(float);
+                const int tsp = q == 0 ? t->TSp : t->TSf;
+                std::vector<int> tab;
+                int maxp = 0;
+                if (!plan_wide(ks, maxs, waves, tab, W.G, W.stride, maxp)) continue;
+                W.shm = std::max((size_t)6 * tsp * es + (size_t)(Nc4 + 16) * 4 * sizeof(int), (size_t)maxp * 8 * 64 * es);
+                if (W.shm > (size_t)lds_max) continue;
+                if (W.shm > 65536)
+                    HIP_TRY(hipFuncSetAttribute(wide_fn(q, v), hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.shm));
+                PF_TRY(upload(t, &W.plan, tab.data(), tab.size()));
+                W.ok = true;
+            }
     }
     // staged 1D tables of the matrix-core M2L: per (level, Delta, offset) the
     // x table with C_ab folded in and the plain table for y and z, each padded
@@ -1714,6 +1779,14 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
                 }
         }
         PF_TRY(upload(t, &t->E1s, E1s.data(), E1s.size()));
+        if (t->has_f32) {
+            // the same tables in FP32 with rows of TSf entries (offsets scale by TSf / TSp)
+            const int TSf = t->TSf;
+            std::vector<float> E1f(E1s.size() / TSp * TSf, 0.f);
+            for (size_t r = 0; r < E1s.size() / TSp; ++r)
+                for (int i = 0; i < TSp; ++i) E1f[r * TSf + i] = (float)E1s[r * TSp + i];
+            PF_TRY(upload(t, &t->E1s32, E1f.data(), E1f.size()));
+        }
     }
     // levels
     t->lv.assign(P.depth + 1, DevLevel());
@@ -1743,21 +1816,31 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             // enough workgroups to fill the chip several times: split source lists otherwise
             int dev = 0, ncu = 256;
             if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-            int64_t wg = (int64_t)D.nx * ((D.n_int + 63) / 64) * (D.n_int > 32 ? 2 : 1);
-            D.m2l_nb = 0;
-            if (t->mfma_slots) {
-                for (int v = 2; v >= 0 && !D.m2l_nb; --v)
-                    if (t->wide[v].ok && D.n_int % (32 * kWideNB[v]) == 0 && (v > 0 || kWideUseNB1))
-                        D.m2l_nb = kWideNB[v];
+            int nsplit_max = 1;
+            for (int q = 0; q < 2; ++q) {
+                int64_t wg = (int64_t)D.nx * ((D.n_int + 63) / 64) * (D.n_int > 32 ? 2 : 1);
+                D.m2l_nb[q] = 0;
+                if (t->mfma_slots && (q == 0 || t->has_f32)) {
+                    for (int v = 2; v >= 0 && !D.m2l_nb[q]; --v)
+                        if (t->wide[q][v].ok && D.n_int % (32 * kWideNB[v]) == 0 && (v > 0 || kWideUseNB1))
+                            D.m2l_nb[q] = kWideNB[v];
+                }
+                if (D.m2l_nb[q]) {
+                    const int v = D.m2l_nb[q] == 4 ? 2 : (D.m2l_nb[q] == 2 ? 1 : 0);
+                    D.ncb[q] = D.n_int / (32 * D.m2l_nb[q]);
+                    wg = (int64_t)D.nx * t->wide[q][v].G * D.ncb[q];
+                }
+                D.nsplit_q[q] = 1;
+                while (D.nsplit_q[q] < 4 && wg * D.nsplit_q[q] < 4 * ncu) D.nsplit_q[q] *= 2;
+                nsplit_max = std::max(nsplit_max, D.nsplit_q[q]);
             }
-            if (D.m2l_nb) {
-                const int v = D.m2l_nb == 4 ? 2 : (D.m2l_nb == 2 ? 1 : 0);
-                D.ncb = D.n_int / (32 * D.m2l_nb);
-                wg = (int64_t)D.nx * t->wide[v].G * D.ncb;
+            D.nsplit = D.nsplit_q[0];
+            if (nsplit_max > 1) PF_TRY(dalloc(t, &D.lam_parts, (size_t)(nsplit_max - 1) * D.nx * P.Nc * D.n_int));
+            if (t->has_f32 && D.m2l_nb[1]) {
+                PF_TRY(dalloc(t, &D.mu32, (size_t)D.nx * P.Nc * D.n_int + 2));
+                HIP_TRY(hipMemset(D.mu32, 0, ((size_t)D.nx * P.Nc * D.n_int + 2) * sizeof(float)));
+                D.mu32 += 2;
             }
-            D.nsplit = 1;
-            while (D.nsplit < 4 && wg * D.nsplit < 4 * ncu) D.nsplit *= 2;
-            if (D.nsplit > 1) PF_TRY(dalloc(t, &D.lam_parts, (size_t)(D.nsplit - 1) * D.nx * P.Nc * D.n_int));
         }
         PF_TRY(upload(t, &D.leaf_xs, FL.leaf_xs.data(), FL.leaf_xs.size()));
         PF_TRY(upload(t, &D.ax_off, FL.ax_off.data(), FL.ax_off.size()));
@@ -1882,18 +1965,28 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         prof_begin(t, 3, st, ev);
         for (int l = 2; l <= P.depth; ++l) {
             DevLevel& D = t->lv[l];
-            if (D.m2l_nb) {
-                const int v = D.m2l_nb == 4 ? 2 : (D.m2l_nb == 2 ? 1 : 0);
-                const auto& W = t->wide[v];
-                dim3 grid(W.G, D.nx, D.ncb * D.nsplit);
+            const int q = (t->prec == PFMM_MIXED_FP32 && D.m2l_nb[1]) ? 1 : 0;
+            if (D.m2l_nb[q]) {
+                const int v = D.m2l_nb[q] == 4 ? 2 : (D.m2l_nb[q] == 2 ? 1 : 0);
+                const auto& W = t->wide[q][v];
+                const int nsplit = D.nsplit_q[q];
+                dim3 grid(W.G, D.nx, D.ncb[q] * nsplit);
                 const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
-                auto* launch = v == 2 ? launch_wide<2> : (v == 1 ? launch_wide<1> : launch_wide<0>);
-                launch(grid, W.shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3, t->E1s + D.e1s_off,
-                       t->TSp, t->packinfo, W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, D.nsplit, D.ncb,
-                       D.lam_parts);
-                if (D.nsplit > 1)
+                const void* m = D.mu;
+                const void* e1 = t->E1s + D.e1s_off;
+                int tsp = t->TSp;
+                if (q == 1) {
+                    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl);
+                    m = D.mu32;
+                    e1 = t->E1s32 + D.e1s_off / t->TSp * t->TSf;
+                    tsp = t->TSf;
+                }
+                wide_launcher(q, v)(grid, W.shm, st, m, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3, e1, tsp,
+                                    t->packinfo, W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, nsplit, D.ncb[q],
+                                    D.lam_parts);
+                if (nsplit > 1)
                     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam,
-                                       D.lam_parts, D.nsplit - 1, nl);
+                                       D.lam_parts, nsplit - 1, nl);
             } else if (t->mfma_slots) {
                 const size_t shm = t->m2l_shm;
                 const int halves = D.n_int > 32 ? 2 : 1;
@@ -2011,7 +2104,7 @@ pfmm_status pfmm_plan_stats(const double* vertices, int64_t n_vertices, const in
         if (s != PFMM_OK) return fail(s, msg);
         FarTables F;
         build_far_tables(P, F);
-        fill_stats(P, estimate_bytes(P, F, prm.operators), out, -1);
+        fill_stats(P, estimate_bytes(P, F, prm.operators, prm.precision), out, -1);
     } catch (const std::bad_alloc&) {
         return fail(PFMM_ENOMEM, "host allocation failed while planning");
     } catch (const std::exception& e) {
@@ -2047,13 +2140,15 @@ pfmm_status pfmm_build_tree(const double* vertices, int64_t n_vertices, const in
         return fail(PFMM_ENOMEM, "host allocation failed while planning");
     }
     if (t->P.Nc > 2048) return fail(PFMM_EUNSUPPORTED, "(m_t+1) * C(m_x+3,3) must be <= 2048");
-    const uint64_t need = estimate_bytes(t->P, t->F, prm.operators);
+    const uint64_t need = estimate_bytes(t->P, t->F, prm.operators, prm.precision);
     size_t fr = 0, tot = 0;
     HIP_TRY(hipMemGetInfo(&fr, &tot));
     const uint64_t budget = prm.device_mem_budget ? prm.device_mem_budget : (uint64_t)(0.9 * (double)fr);
     if (need > budget)
         return fail(PFMM_ENOMEM, "tree needs " + std::to_string(need) + " device bytes, budget " + std::to_string(budget));
     hipStream_t st = as_stream(stream);
+    t->prec = prm.precision;
+    t->has_f32 = prm.precision == PFMM_MIXED_FP32;
     pfmm_status s = setup_device(t.get(), st, prm.operators);
     if (s != PFMM_OK) {
         pfmm_destroy(t.release());
@@ -2075,6 +2170,17 @@ pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void*
     if (!t->hasK) return fail(PFMM_EINVAL, "K_h was not built for this tree");
     if (hipSetDevice(t->device) != hipSuccess) return fail(PFMM_EDEVICE, "hipSetDevice failed");
     return apply(t, true, u_dev, f_dev, as_stream(stream));
+}
+
+pfmm_status pfmm_set_precision(pfmm_tree* t, int32_t precision) {
+    if (!t) return fail(PFMM_EINVAL, "NULL tree");
+    if (precision == PFMM_FP64) { t->prec = PFMM_FP64; return PFMM_OK; }
+    if (precision == PFMM_MIXED_FP32) {
+        if (!t->has_f32) return fail(PFMM_EINVAL, "tree was not built with precision PFMM_MIXED_FP32");
+        t->prec = PFMM_MIXED_FP32;
+        return PFMM_OK;
+    }
+    return fail(PFMM_EINVAL, "unknown precision");
 }
 
 pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out) {

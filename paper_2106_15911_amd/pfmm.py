@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_ENOMEM", -3: "PFMM_ED
                 -4: "PFMM_ENOTCONV", -5: "PFMM_ENONFINITE", -6: "PFMM_EUNSUPPORTED"}
 PROFILE_STAGES = ["permute", "s2m", "m2m", "m2l", "l2l", "l2t", "nearfield", "unpermute"]
 OP_V, OP_K = 1, 2
+FP64, MIXED_FP32 = 0, 1
 
 
 class PfmmError(RuntimeError):
@@ -78,6 +79,7 @@ def load_library():
         "pfmm_tree_stats": ([VP, P(Stats)], I32),
         "pfmm_plan_stats": ([dp, I64, ip, I64, dp, I64, P(Params), P(Stats)], I32),
         "pfmm_profile_enable": ([VP, I32], I32),
+        "pfmm_set_precision": ([VP, I32], I32),
         "pfmm_profile_read": ([VP, dp, P(I64), P(I32)], I32),
         "pfmm_default_solve_opts": ([P(SolveOpts)], I32),
         "pfmm_solve_V": ([VP, VP, VP, P(SolveOpts), P(SolveInfo), VP], I32),
@@ -206,6 +208,10 @@ class Tree:
         st = Stats()
         _check(self.lib.pfmm_tree_stats(self.handle, ctypes.byref(st)))
         return st.as_dict()
+
+    def set_precision(self, precision):
+        """Farfield precision of the following applies: FP64 or MIXED_FP32 (tree built in MIXED_FP32)."""
+        _check(self.lib.pfmm_set_precision(self.handle, int(precision)))
 
     def profile_enable(self, on=True):
         _check(self.lib.pfmm_profile_enable(self.handle, 1 if on else 0))
