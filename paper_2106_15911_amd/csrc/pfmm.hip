@@ -113,59 +113,6 @@ __global__ void k_s2m(const double* __restrict__ wd, double* __restrict__ mu,
     }
 }
 
-// M2M (eqs. temp_m2m, st_m2m) from level l+1 into the non-leaf boxes of level l.
-// qt: child level table [n_int_c][a_c][a_p]; qx: child slot tables [3][kappa][nu].
-__global__ void k_m2m(const double* __restrict__ mu_c, double* __restrict__ mu_p,
-                      const int* __restrict__ par_xs, const int* __restrict__ ch_ptr, const int* __restrict__ ch,
-                      const double* __restrict__ qt, const double* __restrict__ qx, CoefMaps cm,
-                      int n_int_p, int n_int_c) {
-    extern __shared__ double sm[];
-    double* sc = sm;                 // child moments, Nc
-    double* st = sm + cm.Nc;         // temporally transformed, Nc
-    double* so = sm + 2 * cm.Nc;     // parent moments being accumulated, Nc
-    const int pi = blockIdx.x / n_int_p, k = blockIdx.x % n_int_p;
-    const int xs = par_xs[pi];
-    const int nt1 = cm.mt + 1, nx1 = cm.mx + 1;
-    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) so[c] = 0.0;
-    for (int ci = ch_ptr[xs]; ci < ch_ptr[xs + 1]; ++ci) {
-        const int xc = ch[ci];
-        const double* Q = qx + (int64_t)xc * 3 * nx1 * nx1;
-        for (int b = 0; b < 2; ++b) {
-            const int kc = 2 * k + b;
-            __syncthreads();
-            for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) sc[c] = mu_c[((int64_t)xc * cm.Nc + c) * n_int_c + kc];
-            __syncthreads();
-            const double* q = qt + (int64_t)kc * nt1 * nt1;
-            for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
-                const int ap = cm.coef_a[c], kp = cm.coef_kpos[c];
-                double s = 0.0;
-                for (int ac = 0; ac < nt1; ++ac) s += q[ac * nt1 + ap] * sc[cm.cidx[ac * cm.Nk + kp]];
-                st[c] = s;
-            }
-            __syncthreads();
-            for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
-                const int ap = cm.coef_a[c];
-                const int n1 = cm.coef_k[3 * c], n2 = cm.coef_k[3 * c + 1], n3 = cm.coef_k[3 * c + 2];
-                double s = 0.0;
-                for (int k1 = 0; k1 <= n1; ++k1) {
-                    const double q1 = Q[k1 * nx1 + n1];
-                    for (int k2 = 0; k2 <= n2; ++k2) {
-                        const double q12 = q1 * Q[nx1 * nx1 + k2 * nx1 + n2];
-                        for (int k3 = 0; k3 <= n3; ++k3) {
-                            const int kp = cm.kposmap[(k1 * nx1 + k2) * nx1 + k3];
-                            s += q12 * Q[2 * nx1 * nx1 + k3 * nx1 + n3] * st[cm.cidx[ap * cm.Nk + kp]];
-                        }
-                    }
-                }
-                so[c] += s;
-            }
-        }
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x)
-        mu_p[((int64_t)xs * cm.Nc + c) * n_int_p + k] = so[c];
-}
-
 // M2L operator generation: op[(class, Delta)][chunk][c_in][r] =
 //   C_ab prod_j E_{kappa_j, nu_j}(r_j, d_ab)  if |kappa| + |nu| <= m_x  (eq. exp_coeffs_3d)
 __global__ void k_m2l_opgen(double* __restrict__ ops, const double* __restrict__ E1, const double* __restrict__ Cab,
@@ -828,38 +775,164 @@ __global__ void k_sum_parts(double* __restrict__ lam, const double* __restrict__
     lam[i] = s;
 }
 
-// L2L (transpose of eqs. temp_m2m / st_m2m) from level l-1 into every box of level l.
-__global__ void k_l2l(const double* __restrict__ lam_p, double* __restrict__ lam_c, const int* __restrict__ parent,
-                      const double* __restrict__ qt, const double* __restrict__ qx, CoefMaps cm,
-                      int n_int_c, int n_int_p) {
-    extern __shared__ double sm[];
-    double* sp = sm;             // parent locals
-    double* ss = sm + cm.Nc;     // spatially transformed
-    const int xs = blockIdx.x / n_int_c, k = blockIdx.x % n_int_c;
-    const int ps = parent[xs], kp = k >> 1;
-    const int nt1 = cm.mt + 1, nx1 = cm.mx + 1;
-    const double* Q = qx + (int64_t)xs * 3 * nx1 * nx1;
-    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) sp[c] = lam_p[((int64_t)ps * cm.Nc + c) * n_int_p + kp];
-    __syncthreads();
-    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
-        const int bp = cm.coef_a[c], deg = cm.coef_deg[c];
-        const int n1 = cm.coef_k[3 * c], n2 = cm.coef_k[3 * c + 1], n3 = cm.coef_k[3 * c + 2];
-        const int nd = pfmm_binom3(cm.mx - deg);
-        double s = 0.0;
-        for (int di = 0; di < nd; ++di) {
-            const int p1 = n1 + cm.kidx[3 * di], p2 = n2 + cm.kidx[3 * di + 1], p3 = n3 + cm.kidx[3 * di + 2];
-            const double q = Q[n1 * nx1 + p1] * Q[nx1 * nx1 + n2 * nx1 + p2] * Q[2 * nx1 * nx1 + n3 * nx1 + p3];
-            s += q * sp[cm.cidx[bp * cm.Nk + cm.kposmap[(p1 * nx1 + p2) * nx1 + p3]]];
+// Index data of the separable re-expansions, shared by k_m2m_sep and
+// k_l2l_sep.  Inside a block, moments and locals are held as [a][p][kk]:
+// time index a, position p of the spatial multi-index in the degree-sorted
+// list (kidx), interval kk of the block innermost.  ax[(j * Nk + p) * (m_x+1) + t]
+// is the position of multi-index p with its component j replaced by t, or -1
+// when that exceeds the total degree m_x.
+constexpr int kMaxT = 17;   // time nodes per interval at the largest Lagrange degree (16)
+
+struct SepMaps {
+    const int* coef_a;      // Nc: time index of coefficient c
+    const int* coef_kpos;   // Nc: spatial position of coefficient c
+    const int* cidx;        // (m_t+1) x Nk -> coefficient index
+    const int* kidx;        // Nk x 3 multi-indices
+    const int* ax;          // 3 x Nk x (m_x+1)
+    int Nc, Nk, mt, mx;
+};
+
+// One 1D re-expansion pass along axis j over a [nt1][Nk][KI] block.
+// Forward (M2M): out[a][p] = sum_{t <= n_j(p)} Q_j[t][n_j(p)] in[a][p with n_j = t].
+// Transposed (L2L): out[a][p] = sum_{t >= n_j(p)} Q_j[n_j(p)][t] in[a][p with n_j = t].
+template <bool TRANSPOSED, bool ACCUMULATE>
+__device__ __forceinline__ void sep_pass(const double* __restrict__ in, double* __restrict__ out,
+                                         const double* __restrict__ Qj, const int* __restrict__ axj,
+                                         const int* __restrict__ kid, int j, int nt1, int Nk, int nx1, int KI,
+                                         int nk) {
+    const int total = nt1 * Nk * KI;
+    for (int o = threadIdx.x; o < total; o += blockDim.x) {
+        const int kk = o % KI;
+        if (kk >= nk) continue;
+        const int ap = o / KI;            // a * Nk + p
+        const int pp = ap % Nk, a = ap / Nk;
+        const int n = kid[3 * pp + j];
+        const int* src = axj + pp * nx1;
+        const double* row = in + (int64_t)a * Nk * KI + kk;
+        double acc = 0.0;
+        if (!TRANSPOSED) {
+            for (int t = 0; t <= n; ++t) acc += Qj[t * nx1 + n] * row[src[t] * KI];
+        } else {
+            for (int t = n; t < nx1; ++t) {
+                const int q = src[t];
+                if (q < 0) break;
+                acc += Qj[n * nx1 + t] * row[q * KI];
+            }
         }
-        ss[c] = s;
+        if (ACCUMULATE) out[o] += acc; else out[o] = acc;
+    }
+}
+
+// M2M (eqs. temp_m2m, st_m2m) from level l+1 into the boxes of level l that
+// have children.  Block = (parent slot, KI parent intervals).  Per child:
+// the temporal re-expansion of the child's two intervals per parent interval
+// (read straight from HBM, intervals contiguous), then the spatial
+// re-expansion as three 1D passes in LDS, accumulated over the children.
+__global__ void __launch_bounds__(256) k_m2m_sep(const double* __restrict__ mu_c, double* __restrict__ mu_p,
+                                                 const int* __restrict__ par_xs, const int* __restrict__ ch_ptr,
+                                                 const int* __restrict__ ch, const double* __restrict__ qt,
+                                                 const double* __restrict__ qx, SepMaps m, int n_int_p, int n_int_c,
+                                                 int KI) {
+    extern __shared__ double sm[];
+    const int nt1 = m.mt + 1, nx1 = m.mx + 1, Nk = m.Nk, Nc = m.Nc;
+    const int blk = Nc * KI;
+    double* T = sm;                    // [nt1][Nk][KI]
+    double* U = T + blk;
+    double* Acc = U + blk;
+    double* sq = Acc + blk;            // Q of the current child: 3 x nx1 x nx1
+    double* sqt = sq + 3 * nx1 * nx1;  // q_t of the block's child intervals: [2 KI][nt1][nt1]
+    const SepMaps& L = m;
+    const int xs = par_xs[blockIdx.x];
+    const int k0 = blockIdx.y * KI;
+    const int nk = min(KI, n_int_p - k0);
+    for (int i = threadIdx.x; i < blk; i += blockDim.x) Acc[i] = 0.0;
+    for (int i = threadIdx.x; i < 2 * nk * nt1 * nt1; i += blockDim.x)
+        sqt[i] = qt[(int64_t)2 * k0 * nt1 * nt1 + i];
+    for (int ci = ch_ptr[xs]; ci < ch_ptr[xs + 1]; ++ci) {
+        const int xc = ch[ci];
+        __syncthreads();   // previous child's last pass is done with T, U and sq
+        for (int i = threadIdx.x; i < 3 * nx1 * nx1; i += blockDim.x) sq[i] = qx[(int64_t)xc * 3 * nx1 * nx1 + i];
+        // temporal: T[ap][p][kk] = sum_{b, ac} q_t[2kk+b][ac][ap] mu_c[(ac, p)][2(k0+kk)+b]
+        for (int it = threadIdx.x; it < Nk * KI; it += blockDim.x) {
+            const int kk = it % KI, pp = it / KI;
+            if (kk >= nk) continue;
+            double acc[kMaxT];
+#pragma unroll
+            for (int a = 0; a < kMaxT; ++a) acc[a] = 0.0;
+            for (int ac = 0; ac < nt1; ++ac) {
+                const double* src = mu_c + ((int64_t)xc * Nc + m.cidx[ac * Nk + pp]) * n_int_c + 2 * (k0 + kk);
+                const double v0 = src[0], v1 = src[1];
+                const double* q0 = sqt + ((2 * kk) * nt1 + ac) * nt1;
+                const double* q1 = q0 + nt1 * nt1;
+#pragma unroll
+                for (int ap = 0; ap < kMaxT; ++ap)
+                    if (ap < nt1) acc[ap] += q0[ap] * v0 + q1[ap] * v1;
+            }
+#pragma unroll
+            for (int ap = 0; ap < kMaxT; ++ap)
+                if (ap < nt1) T[((int64_t)ap * Nk + pp) * KI + kk] = acc[ap];
+        }
+        __syncthreads();
+        sep_pass<false, false>(T, U, sq, L.ax, L.kidx, 0, nt1, Nk, nx1, KI, nk);
+        __syncthreads();
+        sep_pass<false, false>(U, T, sq + nx1 * nx1, L.ax + Nk * nx1, L.kidx, 1, nt1, Nk, nx1, KI, nk);
+        __syncthreads();
+        sep_pass<false, true>(T, Acc, sq + 2 * nx1 * nx1, L.ax + 2 * Nk * nx1, L.kidx, 2, nt1, Nk, nx1, KI, nk);
     }
     __syncthreads();
-    const double* q = qt + (int64_t)k * nt1 * nt1;
-    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
-        const int bc = cm.coef_a[c], kp2 = cm.coef_kpos[c];
-        double s = 0.0;
-        for (int bp = 0; bp < nt1; ++bp) s += q[bc * nt1 + bp] * ss[cm.cidx[bp * cm.Nk + kp2]];
-        lam_c[((int64_t)xs * cm.Nc + c) * n_int_c + k] += s;
+    for (int o = threadIdx.x; o < blk; o += blockDim.x) {
+        const int kk = o % KI, c = o / KI;
+        if (kk >= nk) continue;
+        mu_p[((int64_t)xs * Nc + c) * n_int_p + k0 + kk] = Acc[((int64_t)m.coef_a[c] * Nk + m.coef_kpos[c]) * KI + kk];
+    }
+}
+
+// L2L (transposes of eqs. temp_m2m / st_m2m) from level l-1 into every box
+// of level l.  Block = (child slot, 2 KI child intervals): the parent's
+// locals of KI intervals are re-expanded in space by three transposed 1D
+// passes in LDS, then in time into the child's intervals (added to the
+// child's M2L result; intervals contiguous).
+__global__ void __launch_bounds__(256) k_l2l_sep(const double* __restrict__ lam_p, double* __restrict__ lam_c,
+                                                 const int* __restrict__ parent, const double* __restrict__ qt,
+                                                 const double* __restrict__ qx, SepMaps m, int n_int_c, int n_int_p,
+                                                 int KI) {
+    extern __shared__ double sm[];
+    const int nt1 = m.mt + 1, nx1 = m.mx + 1, Nk = m.Nk, Nc = m.Nc;
+    const int blk = Nc * KI;
+    double* T = sm;                    // [nt1][Nk][KI] (parent intervals)
+    double* U = T + blk;
+    double* sq = U + blk;
+    double* sqt = sq + 3 * nx1 * nx1;  // q_t of the block's child intervals: [2 KI][nt1][nt1]
+    const SepMaps& L = m;
+    const int xs = blockIdx.x, ps = parent[xs];
+    const int kp0 = blockIdx.y * KI;               // first parent interval
+    const int nk = min(KI, n_int_p - kp0);
+    for (int i = threadIdx.x; i < 3 * nx1 * nx1; i += blockDim.x) sq[i] = qx[(int64_t)xs * 3 * nx1 * nx1 + i];
+    for (int i = threadIdx.x; i < 2 * nk * nt1 * nt1; i += blockDim.x)
+        sqt[i] = qt[(int64_t)2 * kp0 * nt1 * nt1 + i];
+    for (int o = threadIdx.x; o < blk; o += blockDim.x) {
+        const int kk = o % KI, c = o / KI;
+        if (kk >= nk) continue;
+        T[((int64_t)m.coef_a[c] * Nk + m.coef_kpos[c]) * KI + kk] = lam_p[((int64_t)ps * Nc + c) * n_int_p + kp0 + kk];
+    }
+    __syncthreads();
+    sep_pass<true, false>(T, U, sq, L.ax, L.kidx, 0, nt1, Nk, nx1, KI, nk);
+    __syncthreads();
+    sep_pass<true, false>(U, T, sq + nx1 * nx1, L.ax + Nk * nx1, L.kidx, 1, nt1, Nk, nx1, KI, nk);
+    __syncthreads();
+    sep_pass<true, false>(T, U, sq + 2 * nx1 * nx1, L.ax + 2 * Nk * nx1, L.kidx, 2, nt1, Nk, nx1, KI, nk);
+    __syncthreads();
+    // temporal: lam_c[(bc, p)][kc] += sum_bp q_t[kc][bc][bp] U[bp][p][kc/2 - kp0]
+    const int KC = 2 * KI;
+    for (int o = threadIdx.x; o < Nc * KC; o += blockDim.x) {
+        const int kc = o % KC, c = o / KC;
+        if (kc >= 2 * nk) continue;
+        const int bc = m.coef_a[c], pp = m.coef_kpos[c];
+        const double* q = sqt + (kc * nt1 + bc) * nt1;
+        const double* u = U + (int64_t)pp * KI + kc / 2;
+        double acc = 0.0;
+        for (int bp = 0; bp < nt1; ++bp) acc += q[bp] * u[(int64_t)bp * Nk * KI];
+        lam_c[((int64_t)xs * Nc + c) * n_int_c + 2 * kp0 + kc] += acc;
     }
 }
 
@@ -1290,6 +1363,8 @@ struct pfmm_tree {
     float* E1s32 = nullptr;       // FP32 copy of E1s with rows of TSf entries
     int TSf = 0;                  // FP32 table length (multiple of 256 floats)
     CoefMaps cm{};
+    SepMaps sm{};
+    int ki_m2m = 0, ki_l2l = 0;   // intervals per block of k_m2m_sep / k_l2l_sep
     std::vector<DevLevel> lv;
     bool low_leaves = false;      // leaves at levels < 2 (no far field)
     NearLayout nl{};
@@ -1598,6 +1673,29 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         PF_TRY(upload(t, &kpm, kposmap.data(), kposmap.size()));
         PF_TRY(upload(t, &ci, cidx.data(), cidx.size()));
         t->cm = CoefMaps{a, deg, k3, kp, ki, kpm, ci, P.Nc, P.Nk, P.m_t, P.m_x};
+        // separable re-expansions: position of multi-index p with component j set to t
+        std::vector<int> ax((size_t)3 * P.Nk * nx1, -1);
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < P.Nk; ++i) {
+                int k[3] = {P.kidx_k[3 * i], P.kidx_k[3 * i + 1], P.kidx_k[3 * i + 2]};
+                for (int tt = 0; tt < nx1; ++tt) {
+                    k[j] = tt;
+                    if (k[0] + k[1] + k[2] <= P.m_x)
+                        ax[((size_t)j * P.Nk + i) * nx1 + tt] = kposmap[(k[0] * nx1 + k[1]) * nx1 + k[2]];
+                }
+            }
+        int* axd;
+        PF_TRY(upload(t, &axd, ax.data(), ax.size()));
+        t->sm = SepMaps{a, kp, ci, ki, axd, P.Nc, P.Nk, P.m_t, P.m_x};
+        // intervals per block of k_m2m_sep / k_l2l_sep: the largest of 4, 2, 1 whose LDS fits 64 KB
+        const size_t tabs = (size_t)(3 * nx1 * nx1) * sizeof(double);
+        const int nt1 = P.m_t + 1;
+        t->ki_m2m = t->ki_l2l = 0;
+        for (int KI = 4; KI >= 1 && !t->ki_m2m; KI /= 2)
+            if ((3 * (size_t)P.Nc * KI + 2 * KI * nt1 * nt1) * sizeof(double) + tabs <= 65536) t->ki_m2m = KI;
+        for (int KI = 4; KI >= 1 && !t->ki_l2l; KI /= 2)
+            if ((2 * (size_t)P.Nc * KI + 2 * KI * nt1 * nt1) * sizeof(double) + tabs <= 65536) t->ki_l2l = KI;
+        if (!t->ki_m2m || !t->ki_l2l) return fail(PFMM_EUNSUPPORTED, "expansion degrees too large for the re-expansion kernels");
     }
     PF_TRY(upload(t, &t->At, F.At.data(), F.At.size()));
     PF_TRY(upload(t, &t->Ax, F.Ax.data(), F.Ax.size()));
@@ -1957,8 +2055,11 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
             DevLevel& D = t->lv[l];
             DevLevel& C = t->lv[l + 1];
             if (D.n_par == 0) continue;
-            hipLaunchKernelGGL(k_m2m, dim3(D.n_par * D.n_int), dim3(256), 3 * P.Nc * sizeof(double), st, C.mu, D.mu,
-                               D.par_xs, D.ch_ptr, D.ch, t->qt + C.qt_off, t->qx + C.qx_off, cm, D.n_int, C.n_int);
+            const int KI = t->ki_m2m, nt1 = P.m_t + 1, nx1 = P.m_x + 1;
+            const size_t shm = (3 * (size_t)P.Nc * KI + 3 * nx1 * nx1 + 2 * KI * nt1 * nt1) * sizeof(double);
+            hipLaunchKernelGGL(k_m2m_sep, dim3(D.n_par, (D.n_int + KI - 1) / KI), dim3(256), shm, st, C.mu, D.mu,
+                               D.par_xs, D.ch_ptr, D.ch, t->qt + C.qt_off, t->qx + C.qx_off, t->sm, D.n_int, C.n_int,
+                               KI);
         }
         prof_end(t, st, ev);
         // M2L, levels 2 .. p
@@ -2013,8 +2114,10 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         for (int l = 3; l <= P.depth; ++l) {
             DevLevel& D = t->lv[l];
             DevLevel& Pp = t->lv[l - 1];
-            hipLaunchKernelGGL(k_l2l, dim3(D.nx * D.n_int), dim3(256), 2 * P.Nc * sizeof(double), st, Pp.lam, D.lam,
-                               D.parent, t->qt + D.qt_off, t->qx + D.qx_off, cm, D.n_int, Pp.n_int);
+            const int KI = t->ki_l2l, nt1 = P.m_t + 1, nx1 = P.m_x + 1;
+            const size_t shm = (2 * (size_t)P.Nc * KI + 3 * nx1 * nx1 + 2 * KI * nt1 * nt1) * sizeof(double);
+            hipLaunchKernelGGL(k_l2l_sep, dim3(D.nx, (Pp.n_int + KI - 1) / KI), dim3(256), shm, st, Pp.lam, D.lam,
+                               D.parent, t->qt + D.qt_off, t->qx + D.qx_off, t->sm, D.n_int, Pp.n_int, KI);
         }
         prof_end(t, st, ev);
         // L2T
