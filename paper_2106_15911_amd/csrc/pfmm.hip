@@ -47,8 +47,6 @@ pfmm_status fail(pfmm_status s, const std::string& m) {
 constexpr int kChunk = 32;          // M2L output rows per wave
 constexpr int kWave = 64;
 
-// number of multi-indices in N^3 with total degree <= n
-__device__ __forceinline__ int pfmm_binom3(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
 
 // ------------------------------------------------------------------ permutations
 
@@ -87,31 +85,6 @@ struct CoefMaps {
     const int* cidx;        // (m_t+1) x Nk -> coefficient index
     int Nc, Nk, mt, mx;
 };
-
-// S2M (eq. s2m): mu[a, kappa] = sum_{elements} w A_t[j][a] A_x[r][kappa].
-__global__ void k_s2m(const double* __restrict__ wd, double* __restrict__ mu,
-                      const int* __restrict__ leaf_xs, const int64_t* __restrict__ ax_off,
-                      const int* __restrict__ tb, const int* __restrict__ te,
-                      const double* __restrict__ At, const double* __restrict__ Ax, CoefMaps cm,
-                      int n_int, int steps, int E_x) {
-    const int li = blockIdx.x / n_int, k = blockIdx.x % n_int;
-    const int xs = leaf_xs[li];
-    const int t0 = tb[xs], nX = te[xs] - t0;
-    const int s0 = k * steps;
-    const double* A = Ax + ax_off[li];
-    const double* T = At + (int64_t)k * steps * (cm.mt + 1);
-    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) {
-        const int a = cm.coef_a[c], kp = cm.coef_kpos[c];
-        double acc = 0.0;
-        for (int j = 0; j < steps; ++j) {
-            const double* wrow = wd + (int64_t)(s0 + j) * E_x + t0;
-            double sp = 0.0;
-            for (int r = 0; r < nX; ++r) sp += wrow[r] * A[(int64_t)r * cm.Nk + kp];
-            acc += T[j * (cm.mt + 1) + a] * sp;
-        }
-        mu[((int64_t)xs * cm.Nc + c) * n_int + k] = acc;
-    }
-}
 
 // M2L operator generation: op[(class, Delta)][chunk][c_in][r] =
 //   C_ab prod_j E_{kappa_j, nu_j}(r_j, d_ab)  if |kappa| + |nu| <= m_x  (eq. exp_coeffs_3d)
@@ -936,30 +909,97 @@ __global__ void __launch_bounds__(256) k_l2l_sep(const double* __restrict__ lam_
     }
 }
 
-// L2T (eq. l2t): f at the elements of a leaf (overwrites f).
-__global__ void k_l2t(const double* __restrict__ lam, double* __restrict__ fd,
-                      const int* __restrict__ leaf_xs, const int64_t* __restrict__ ax_off,
-                      const int* __restrict__ tb, const int* __restrict__ te,
-                      const double* __restrict__ At, const double* __restrict__ Ax, CoefMaps cm,
-                      int n_int, int steps, int E_x) {
+// S2M (eq. s2m) by leaf blocks: block = (leaf, KI intervals).  The time
+// integrals are applied first, W[a][r][kk] = sum_j A_t[j][a] w[j][r] (the
+// densities of the leaf's triangles are contiguous in tree order), then the
+// space integrals, mu[(a, p)][kk] = sum_r W[a][r][kk] A_x[r][p], written with
+// the intervals contiguous.  A_x of the leaf's spatial box is staged in LDS.
+__global__ void __launch_bounds__(256) k_s2m_blk(const double* __restrict__ wd, double* __restrict__ mu,
+                                                 const int* __restrict__ leaf_xs, const int64_t* __restrict__ ax_off,
+                                                 const int* __restrict__ tb, const int* __restrict__ te,
+                                                 const double* __restrict__ At, const double* __restrict__ Ax,
+                                                 SepMaps m, int n_int, int steps, int E_x, int KI, int stageA) {
     extern __shared__ double sm[];
-    const int li = blockIdx.x / n_int, k = blockIdx.x % n_int;
-    const int xs = leaf_xs[li];
+    const int nt1 = m.mt + 1, Nk = m.Nk, Nc = m.Nc;
+    const int li = blockIdx.x, xs = leaf_xs[li];
     const int t0 = tb[xs], nX = te[xs] - t0;
-    for (int c = threadIdx.x; c < cm.Nc; c += blockDim.x) sm[c] = lam[((int64_t)xs * cm.Nc + c) * n_int + k];
-    __syncthreads();
+    const int k0 = blockIdx.y * KI, nk = min(KI, n_int - k0);
     const double* A = Ax + ax_off[li];
-    const double* T = At + (int64_t)k * steps * (cm.mt + 1);
-    const int nt1 = cm.mt + 1;
-    for (int e = threadIdx.x; e < steps * nX; e += blockDim.x) {
-        const int j = e / nX, r = e % nX;
+    double* W = sm;                                     // [nt1][nX][KI]
+    double* sAl = W + nt1 * nX * KI;                    // [nX][Nk] when staged
+    if (stageA)
+        for (int i = threadIdx.x; i < nX * Nk; i += blockDim.x) sAl[i] = A[i];
+    const double* sA = stageA ? sAl : A;
+    for (int o = threadIdx.x; o < nt1 * nX * KI; o += blockDim.x) {
+        const int r = o % nX, rest = o / nX;
+        const int kk = rest % KI, a = rest / KI;
         double acc = 0.0;
-        for (int b = 0; b < nt1; ++b) {
-            double sp = 0.0;
-            for (int kp = 0; kp < cm.Nk; ++kp) sp += sm[cm.cidx[b * cm.Nk + kp]] * A[(int64_t)r * cm.Nk + kp];
-            acc += T[j * nt1 + b] * sp;
+        if (kk < nk) {
+            const int k = k0 + kk;
+            const double* T = At + (int64_t)k * steps * nt1 + a;
+            const double* wr = wd + (int64_t)k * steps * E_x + t0 + r;
+            for (int j = 0; j < steps; ++j) acc += T[j * nt1] * wr[(int64_t)j * E_x];
         }
-        fd[(int64_t)(k * steps + j) * E_x + t0 + r] = acc;
+        W[((int64_t)a * nX + r) * KI + kk] = acc;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < Nc * KI; o += blockDim.x) {
+        const int kk = o % KI, c = o / KI;
+        if (kk >= nk) continue;
+        const int a = m.coef_a[c], pp = m.coef_kpos[c];
+        const double* wv = W + (int64_t)a * nX * KI + kk;
+        double acc = 0.0;
+        for (int r = 0; r < nX; ++r) acc += wv[r * KI] * sA[r * Nk + pp];
+        mu[((int64_t)xs * Nc + c) * n_int + k0 + kk] = acc;
+    }
+}
+
+// L2T (eq. l2t) by leaf blocks: block = (leaf, KI intervals).  The leaf's
+// locals of KI intervals are loaded with the intervals contiguous, the space
+// basis is applied first, U[a][r][kk] = sum_p lambda[(a, p)][kk] A_x[r][p],
+// then the time basis, f[j][r] = sum_a A_t[j][a] U[a][r][kk] (overwrites f,
+// triangles contiguous).
+__global__ void __launch_bounds__(256) k_l2t_blk(const double* __restrict__ lam, double* __restrict__ fd,
+                                                 const int* __restrict__ leaf_xs, const int64_t* __restrict__ ax_off,
+                                                 const int* __restrict__ tb, const int* __restrict__ te,
+                                                 const double* __restrict__ At, const double* __restrict__ Ax,
+                                                 SepMaps m, int n_int, int steps, int E_x, int KI, int stageA) {
+    extern __shared__ double sm[];
+    const int nt1 = m.mt + 1, Nk = m.Nk, Nc = m.Nc;
+    const int li = blockIdx.x, xs = leaf_xs[li];
+    const int t0 = tb[xs], nX = te[xs] - t0;
+    const int k0 = blockIdx.y * KI, nk = min(KI, n_int - k0);
+    const double* A = Ax + ax_off[li];
+    double* L = sm;                                     // [nt1][Nk][KI]
+    double* U = L + Nc * KI;                            // [nt1][nX][KI]
+    double* sAl = U + nt1 * nX * KI;                    // [nX][Nk] when staged
+    if (stageA)
+        for (int i = threadIdx.x; i < nX * Nk; i += blockDim.x) sAl[i] = A[i];
+    const double* sA = stageA ? sAl : A;
+    for (int o = threadIdx.x; o < Nc * KI; o += blockDim.x) {
+        const int kk = o % KI, c = o / KI;
+        L[((int64_t)m.coef_a[c] * Nk + m.coef_kpos[c]) * KI + kk] =
+            kk < nk ? lam[((int64_t)xs * Nc + c) * n_int + k0 + kk] : 0.0;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < nt1 * nX * KI; o += blockDim.x) {
+        const int kk = o % KI, rest = o / KI;
+        const int r = rest % nX, a = rest / nX;
+        const double* lv = L + (int64_t)a * Nk * KI + kk;
+        const double* ar = sA + r * Nk;
+        double acc = 0.0;
+        for (int pp = 0; pp < Nk; ++pp) acc += lv[pp * KI] * ar[pp];
+        U[((int64_t)a * nX + r) * KI + kk] = acc;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < nk * steps * nX; o += blockDim.x) {
+        const int r = o % nX, rest = o / nX;
+        const int j = rest % steps, kk = rest / steps;
+        const int k = k0 + kk;
+        const double* T = At + ((int64_t)k * steps + j) * nt1;
+        double acc = 0.0;
+        for (int a = 0; a < nt1; ++a) acc += T[a] * U[((int64_t)a * nX + r) * KI + kk];
+        fd[((int64_t)k * steps + j) * E_x + t0 + r] = acc;
     }
 }
 
@@ -1365,6 +1405,8 @@ struct pfmm_tree {
     CoefMaps cm{};
     SepMaps sm{};
     int ki_m2m = 0, ki_l2l = 0;   // intervals per block of k_m2m_sep / k_l2l_sep
+    int ki_s2m = 0, ki_l2t = 0;   // intervals per block of k_s2m_blk / k_l2t_blk
+    int stage_s2m = 0, stage_l2t = 0;   // A_x staged in LDS
     std::vector<DevLevel> lv;
     bool low_leaves = false;      // leaves at levels < 2 (no far field)
     NearLayout nl{};
@@ -1696,6 +1738,22 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         for (int KI = 4; KI >= 1 && !t->ki_l2l; KI /= 2)
             if ((2 * (size_t)P.Nc * KI + 2 * KI * nt1 * nt1) * sizeof(double) + tabs <= 65536) t->ki_l2l = KI;
         if (!t->ki_m2m || !t->ki_l2l) return fail(PFMM_EUNSUPPORTED, "expansion degrees too large for the re-expansion kernels");
+        // S2M / L2T leaf blocks (leaves hold at most 64 triangles): stage A_x in
+        // LDS when it fits, with the largest of 4, 2, 1 intervals per block
+        for (int stage = 1; stage >= 0 && !t->ki_s2m; --stage)
+            for (int KI = 4; KI >= 1 && !t->ki_s2m; KI /= 2)
+                if (((size_t)nt1 * 64 * KI + (stage ? 64 * (size_t)P.Nk : 0)) * sizeof(double) <= 65536) {
+                    t->ki_s2m = KI;
+                    t->stage_s2m = stage;
+                }
+        for (int stage = 1; stage >= 0 && !t->ki_l2t; --stage)
+            for (int KI = 4; KI >= 1 && !t->ki_l2t; KI /= 2)
+                if (((size_t)P.Nc * KI + (size_t)nt1 * 64 * KI + (stage ? 64 * (size_t)P.Nk : 0)) * sizeof(double) <=
+                    65536) {
+                    t->ki_l2t = KI;
+                    t->stage_l2t = stage;
+                }
+        if (!t->ki_s2m || !t->ki_l2t) return fail(PFMM_EUNSUPPORTED, "expansion degrees too large for the S2M/L2T kernels");
     }
     PF_TRY(upload(t, &t->At, F.At.data(), F.At.size()));
     PF_TRY(upload(t, &t->Ax, F.Ax.data(), F.Ax.size()));
@@ -2032,7 +2090,6 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
     Plan& P = t->P;
     const int64_t N = (int64_t)P.E_t * P.E_x;
     const unsigned nb = (unsigned)((N + 255) / 256);
-    const CoefMaps& cm = t->cm;
     int ev;
     prof_begin(t, 0, st, ev);
     hipLaunchKernelGGL(k_permute_in, dim3(nb), dim3(256), 0, st, w, t->wd, t->inv_sigma, P.E_x, N);
@@ -2045,8 +2102,11 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         for (int l = 2; l <= P.depth; ++l) {
             DevLevel& D = t->lv[l];
             if (D.n_leafx == 0) continue;
-            hipLaunchKernelGGL(k_s2m, dim3(D.n_leafx * D.n_int), dim3(256), 0, st, t->wd, D.mu, D.leaf_xs, D.ax_off,
-                               D.tb, D.te, t->At + D.at_off, K ? t->AxK : t->Ax, cm, D.n_int, D.steps, P.E_x);
+            const int KI = t->ki_s2m, nt1 = P.m_t + 1;
+            const size_t shm = ((size_t)nt1 * 64 * KI + (t->stage_s2m ? 64 * (size_t)P.Nk : 0)) * sizeof(double);
+            hipLaunchKernelGGL(k_s2m_blk, dim3(D.n_leafx, (D.n_int + KI - 1) / KI), dim3(256), shm, st, t->wd, D.mu,
+                               D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, K ? t->AxK : t->Ax, t->sm, D.n_int,
+                               D.steps, P.E_x, KI, t->stage_s2m);
         }
         prof_end(t, st, ev);
         // M2M, levels p-1 .. 2
@@ -2125,8 +2185,12 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         for (int l = 2; l <= P.depth; ++l) {
             DevLevel& D = t->lv[l];
             if (D.n_leafx == 0) continue;
-            hipLaunchKernelGGL(k_l2t, dim3(D.n_leafx * D.n_int), dim3(256), P.Nc * sizeof(double), st, D.lam, t->fd,
-                               D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, t->Ax, cm, D.n_int, D.steps, P.E_x);
+            const int KI = t->ki_l2t, nt1 = P.m_t + 1;
+            const size_t shm = ((size_t)P.Nc * KI + (size_t)nt1 * 64 * KI + (t->stage_l2t ? 64 * (size_t)P.Nk : 0)) *
+                               sizeof(double);
+            hipLaunchKernelGGL(k_l2t_blk, dim3(D.n_leafx, (D.n_int + KI - 1) / KI), dim3(256), shm, st, D.lam, t->fd,
+                               D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, t->Ax, t->sm, D.n_int, D.steps,
+                               P.E_x, KI, t->stage_l2t);
         }
         prof_end(t, st, ev);
     }
