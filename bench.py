@@ -26,25 +26,26 @@ FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3     # dense FP32 matrix-core peak
 
 # HBM bytes per apply from rocprofv3 FETCH_SIZE / WRITE_SIZE runs on the
-# 3072 x 256, m = 6 workload, scaled by the same counters on a plain 1 GiB
-# device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid only for the
-# kernel source they were taken on; any change to it reports null.
+# 3072 x 256, m = 6 workload (FP64 farfield), scaled by the same counters on a
+# plain 1 GiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Each entry
+# is valid only for the kernel source file it was taken on (sha256 prefix);
+# any change to that file reports null.
 TRAFFIC = {
-    "source_sha256_prefix": "79434b790ab7c4d9",
-    "config": 2,
-    "k_near_apply": 55682184181.0,
-    "k_m2l_mfma": 52984278396.0,
+    "m2l": {"file": "m2l_kernels.hpp", "sha256_prefix": "6ae8f2192373c762", "config": 2, "precision": "fp64",
+            "bytes": 96714070016.0},
+    "k_near_apply": {"file": "near_apply.hpp", "sha256_prefix": "6cc3b5fbcdf24a39", "config": 2,
+                     "bytes": 54271281152.0},
 }
 
 
-def measured_traffic(kernel, cfg):
+def measured_traffic(kernel, cfg, precision="fp64"):
     import hashlib
-    src = os.path.join(ROOT, "paper_2106_15911_amd", "csrc", "pfmm.hip")
-    with open(src, "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
-    if sha != TRAFFIC["source_sha256_prefix"] or cfg != TRAFFIC["config"]:
+    e = TRAFFIC.get(kernel)
+    if e is None or e["bytes"] is None or e["config"] != cfg or e.get("precision", precision) != precision:
         return None
-    return TRAFFIC.get(kernel)
+    with open(os.path.join(ROOT, "paper_2106_15911_amd", "csrc", e["file"]), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    return e["bytes"] if sha == e["sha256_prefix"] else None
 
 
 def log(*a):
@@ -296,8 +297,8 @@ def main():
                            else "k_m2l (all levels)"),
                 "bound": "mfma" if st["m2l_matrix_cores"] == 1 else "alu", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": (measured_traffic("m2l", args.config)
-                            if st["m2l_matrix_cores"] == 1 and not mixed else None),
+                "traffic": (measured_traffic("m2l", args.config, args.precision)
+                            if st["m2l_matrix_cores"] == 1 else None),
                 "launch_ms": m2l_ms, "algorithmic_flop": m2l_flop}
     roof["traffic_note"] = "HBM bytes per apply, all launches of the kernel (rocprofv3 counters, copy-calibrated)"
     other = {"nearfield": {"ms": near_ms, "GB/s": near_bytes / (near_ms * 1e-3) / 1e9,

@@ -1,0 +1,595 @@
+// Matrix-core M2L kernels of the space-time FMM (eq. m2l with the
+// coefficients of eqs. exp_coeffs_3d / exp_coeffs_1d) and their launch
+// helpers.  Included by pfmm.hip inside its anonymous namespace; relies on
+// kWave and the HIP runtime declared there.
+#pragma once
+
+// M2L on FP64 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// A workgroup owns the locals of one target slot X for 64 consecutive
+// intervals k0..k0+63 (all rows of eq. m2l).  Waves 0-3 take intervals
+// k0..k0+31, waves 4-7 take k0+32..k0+63; within a half, the 16 even and the
+// 16 odd intervals form two 16-column MFMA tiles, so the second source
+// interval of odd targets (Delta = 3) costs no wasted columns.  The output
+// rows (coefficient order: degree, time index, multi-index) are cut into
+// 16-row tiles; tile t only needs the first tile_ks[t] 4-column K-steps
+// (|kappa + nu| <= m_x), and the tiles are spread over the 4 waves of a
+// half by their K-step counts (slot_tile, computed on the host).
+// Operator tiles are generated on the fly from the 1D coefficient tables of
+// eq. exp_coeffs_1d held in LDS: A = C_ab E_x E_y E_z.
+// MFMA register layout (checked on gfx950): A[i][k] lane i+16k, B[k][j]
+// lane j+16k, D[i][j] lane j+16(i%4), register i/4.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kM2LWaves = 16;   // waves per workgroup (one interval half)
+constexpr int kXcds = 8;        // accelerator complex dies of an MI355X (one L2 each)
+constexpr int kM2LSlots = 3;    // accumulator slots (row-tile segments) per wave
+
+// Work split of one (X, interval half) output block.  Each 16-row tile's
+// K-range (its staircase length) is cut at multiples of a target length;
+// every wave owns up to kM2LSlots segments that start at the same K-step
+// (so they share the moment operands), sorted by length.  Segments after the
+// first of a tile are partial sums, added to the first segment through LDS
+// at the end.  wave_meta[w] = (K-step start, number of segments);
+// seg[w][i] = (tile, length, partial index or -1); red_slot gives, for each
+// partial segment, the owner wave and slot that adds it.
+template <int MAXS>
+__global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
+    const double* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
+    const int* __restrict__ cls, const int* __restrict__ off3, const double* __restrict__ E1s, int TSp,
+    const int* __restrict__ packinfo, const int* __restrict__ wave_meta,
+    const int* __restrict__ seg, int n_partial, int Nc, int n_int, int mt, int mx, int R, int nsplit,
+    int halves, double* __restrict__ lam_parts) {
+    extern __shared__ double smem[];
+    const int nt1 = mt + 1, nx1 = mx + 1;
+    const int nx2 = nx1 * nx1;
+    // two buffers of the three 1D tables of one (source, Delta) phase: [buf][x | y | z][TSp]
+    int* sCol = (int*)(smem + 6 * TSp);          // per coefficient: table column offsets (x | y<<16), (z | deg<<16)
+    const int lane = threadIdx.x % kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // Workgroups are dealt to the 8 XCDs round-robin by linear id.  Remap so
+    // that each XCD walks a contiguous range of target slots (Morton order):
+    // concurrently running neighbours share most of their interaction lists,
+    // so the source moments they stream stay in that XCD's L2.
+    int bx, by, bz;
+    {
+        const int nxg = gridDim.x, nyg = gridDim.y;
+        const int total = nxg * nyg * gridDim.z;
+        const int lin = blockIdx.x + nxg * (blockIdx.y + nyg * blockIdx.z);
+        const int per = total / kXcds;
+        const int lm = lin < per * kXcds ? (lin % kXcds) * per + lin / kXcds : lin;
+        bx = lm % nxg;
+        by = (lm / nxg) % nyg;
+        bz = lm / (nxg * nyg);
+    }
+    const int half = bz % halves;
+    const int split = bz / halves;             // which share of the source list this workgroup takes
+    const int X = bx;
+    if (split > 0) lam = lam_parts + (int64_t)(split - 1) * ((int64_t)gridDim.x * Nc * n_int);
+    const int lr = lane & 15, lq = lane >> 4;
+    const int kE = by * 64 + 32 * half + 2 * lr;
+    const int kO = kE + 1;
+    for (int c = threadIdx.x; c < Nc; c += blockDim.x) {
+        const int ci = packinfo[c];
+        const int cb = (ci & 15) * nt1 * nx2;
+        sCol[2 * c] = (cb + ((ci >> 4) & 15) * nx1) | ((cb + ((ci >> 8) & 15) * nx1) << 16);
+        sCol[2 * c + 1] = (cb + ((ci >> 12) & 15) * nx1) | (((ci >> 16) & 255) << 16);
+    }
+    const int sbeg = __builtin_amdgcn_readfirstlane(wave_meta[2 * w]);
+    int tiles[MAXS], ks[MAXS], part[MAXS], rX[MAXS], rY[MAXS], rZ[MAXS], rD[MAXS];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        tiles[i] = __builtin_amdgcn_readfirstlane(seg[(w * MAXS + i) * 3]);
+        ks[i] = __builtin_amdgcn_readfirstlane(seg[(w * MAXS + i) * 3 + 1]);   // segment end (exclusive, absolute)
+        part[i] = __builtin_amdgcn_readfirstlane(seg[(w * MAXS + i) * 3 + 2]);
+        const int row = 16 * (tiles[i] >= 0 ? tiles[i] : 0) + lr;
+        const bool rv = tiles[i] >= 0 && row < Nc;
+        const int ri = rv ? packinfo[row] : 0;
+        const int b = ri & 15;
+        rX[i] = b * nx2 + ((ri >> 4) & 15);
+        rY[i] = b * nx2 + ((ri >> 8) & 15);
+        rZ[i] = b * nx2 + ((ri >> 12) & 15);
+        rD[i] = mx - (rv ? ((ri >> 16) & 255) : 255);   // largest column degree this row accepts
+    }
+    d4_t accE[MAXS], accO[MAXS];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        accE[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+        accO[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+    }
+    const int nR = 2 * R + 1;
+    const int sb = ptr[X], se = ptr[X + 1];
+    const int s_lo = sb + (int)(((int64_t)(se - sb) * split) / nsplit);
+    const int s_hi = sb + (int)(((int64_t)(se - sb) * (split + 1)) / nsplit);
+    // Phase p = (source s_lo + p/2, Delta = 2 + p%2).  Its tables are copied
+    // global -> LDS asynchronously (no registers) one phase ahead, into the
+    // buffer the previous phase has released; each wave copies 1 KB pieces.
+    const int n_phase = 2 * (s_hi - s_lo);
+    const int pieces = TSp / 128;                    // 1 KB pieces per table
+    auto stage = [&](int p) {
+        const int si = s_lo + (p >> 1), D = 2 + (p & 1);
+        const int c3 = cls[si];
+        double* dst = smem + (p & 1) * 3 * TSp;
+        for (int c = w; c < 3 * pieces; c += kM2LWaves) {
+            const int tb = c / pieces, pc = c - tb * pieces;
+            const int o = off3[3 * c3 + tb] + R;
+            const double* g = E1s + (((int64_t)(D - 2) * nR + o) * 2 + (tb == 0 ? 0 : 1)) * TSp + pc * 128 + 2 * lane;
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                             (void __attribute__((address_space(3)))*)(dst + tb * TSp + pc * 128),
+                                             16, 0, 0);
+        }
+    };
+    if (n_phase > 0) stage(0);
+    for (int p = 0; p < n_phase; ++p) {
+        const int si = s_lo + (p >> 1), D = 2 + (p & 1);
+        const int Y = src[si];
+        const double* muY = mu + (int64_t)Y * Nc * n_int;
+        const double* sEx = smem + (p & 1) * 3 * TSp;
+        const double* sEy = sEx + TSp;
+        const double* sEz = sEx + 2 * TSp;
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's pieces of phase p have landed in LDS
+        __syncthreads();                 // ... everyone's; and phase p-1 is done with the other buffer
+        if (p + 1 < n_phase) stage(p + 1);
+        {
+            const bool vE = (D == 2) && (kE < n_int) && (kE >= D);
+            const bool vO = (kO < n_int) && (kO >= D);
+            if (D == 3 && !__any(vO)) continue;
+            const int64_t oE = vE ? (kE - D) : 0, oO = vO ? (kO - D) : 0;
+            const double mE = vE ? 1.0 : 0.0, mO = vO ? 1.0 : 0.0;
+            int cxy0, czd0, cxy1, czd1;
+            double e0, o0, e1, o1;
+            auto fetch = [&](int step, int& cxy, int& czd, double& e, double& o) {
+                const int cn = 4 * step + lq;
+                const bool ok = cn < Nc;
+                const int cc = ok ? cn : 0;
+                cxy = sCol[2 * cc];
+                czd = ok ? sCol[2 * cc + 1] : (sCol[2 * cc + 1] | (255 << 16));
+                e = muY[(int64_t)cc * n_int + oE];
+                o = muY[(int64_t)cc * n_int + oO];
+            };
+            // one K-step with n active slots, operands taken from (cxy, czd, e, o)
+            auto step = [&](auto nc, int cxy, int czd, double e, double o) {
+                constexpr int n = decltype(nc)::value;
+                const int cdeg = czd >> 16;
+                const double bE = e * mE, bO = o * mO;
+                const int cX = cxy & 0xffff, cY = cxy >> 16, cZ = czd & 0xffff;
+                double A[n];
+#pragma unroll
+                for (int i = 0; i < n; ++i) {
+                    const double ex = sEx[cX + rX[i]];
+                    const double ey = sEy[cY + rY[i]];
+                    const double ez = sEz[cZ + rZ[i]];
+                    const double msk = (cdeg <= rD[i]) ? 1.0 : 0.0;
+                    A[i] = (ex * ey) * (ez * msk);
+                }
+#pragma unroll
+                for (int i = 0; i < n; ++i) {
+                    if (D == 2) accE[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bE, accE[i], 0, 0, 0);
+                    accO[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[i], bO, accO[i], 0, 0, 0);
+                }
+            };
+            // two operand sets used alternately: the set consumed at step s is
+            // refilled with step s+2, so a load has a full step of work to land
+            fetch(sbeg, cxy0, czd0, e0, o0);
+            fetch(sbeg + 1, cxy1, czd1, e1, o1);
+            int s = sbeg;
+            auto phase = [&](auto nc, int s_end) {
+                for (; s + 1 < s_end; s += 2) {
+                    {
+                        const int a0 = cxy0, b0 = czd0;
+                        const double f0 = e0, g0 = o0;
+                        fetch(s + 2, cxy0, czd0, e0, o0);
+                        step(nc, a0, b0, f0, g0);
+                    }
+                    {
+                        const int a1 = cxy1, b1 = czd1;
+                        const double f1 = e1, g1 = o1;
+                        fetch(s + 3, cxy1, czd1, e1, o1);
+                        step(nc, a1, b1, f1, g1);
+                    }
+                }
+                if (s < s_end) {
+                    const int a0 = cxy0, b0 = czd0;
+                    const double f0 = e0, g0 = o0;
+                    cxy0 = cxy1; czd0 = czd1; e0 = e1; o0 = o1;
+                    fetch(s + 2, cxy1, czd1, e1, o1);
+                    step(nc, a0, b0, f0, g0);
+                    ++s;
+                }
+            };
+            static_assert(MAXS == 3, "phase dispatch below is written for three slots");
+            phase(std::integral_constant<int, 3>{}, ks[2]);
+            phase(std::integral_constant<int, 2>{}, ks[1]);
+            phase(std::integral_constant<int, 1>{}, ks[0]);
+        }
+    }
+    // partial segments: park in LDS, owners add them in a fixed order
+    __syncthreads();
+    double* red = smem;   // [n_partial][8][64]
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        if (tiles[i] >= 0 && part[i] >= 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                red[((int64_t)part[i] * 8 + r) * kWave + lane] = accE[i][r];
+                red[((int64_t)part[i] * 8 + 4 + r) * kWave + lane] = accO[i][r];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        if (tiles[i] < 0 || part[i] >= 0) continue;
+        // add every partial segment of this tile (they follow in seg order)
+        for (int q = 0; q < n_partial; ++q) {
+            if (seg[(kM2LWaves * MAXS) * 3 + q] != tiles[i]) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                accE[i][r] += red[((int64_t)q * 8 + r) * kWave + lane];
+                accO[i][r] += red[((int64_t)q * 8 + 4 + r) * kWave + lane];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * tiles[i] + lq + 4 * r;
+            if (row >= Nc) continue;
+            if (kE < n_int) lam[((int64_t)X * Nc + row) * n_int + kE] = accE[i][r];
+            if (kO < n_int) lam[((int64_t)X * Nc + row) * n_int + kO] = accO[i][r];
+        }
+    }
+}
+
+// M2L on matrix cores, wide form for levels with >= 32 intervals, in FP64
+// (T = double, v_mfma_f64_16x16x4f64) or with FP32 moments and operator
+// tables and FP32 accumulation (T = float, v_mfma_f32_16x16x4f32).
+//
+// The rows of eq. m2l (16-row tiles of the staircase) are partitioned into
+// row groups; a workgroup of WAVES waves owns one target slot X, one row
+// group and NB blocks of 32 consecutive intervals.  An operator element a
+// wave generates from the 1D tables then feeds 2 NB matrix-core products
+// (even and odd intervals of every block) for Delta = 2 and NB for
+// Delta = 3, instead of 2 and 1 in k_m2l_mfma, so generating the operator
+// costs 2 NB times fewer vector instructions per product.  Within a group
+// the tiles' K-ranges are cut into segments (up to MAXS per wave, sharing
+// their first K-step) as in k_m2l_mfma; partial segments are added to their
+// tile's first segment through LDS, one interval block at a time.
+//
+// Per group g the host table plan[g * plan_stride ...] holds
+//   [0, 2 W)                  wave w: (first K-step, number of segments)
+//   [2 W, 2 W + 3 W MAXS)     wave w, slot i: (tile, end K-step, partial index or -1)
+//   [2 W + 3 W MAXS]          number of partial segments n_p
+//   [.. + 1, .. + 1 + n_p)    the tile of every partial segment
+// with W = WAVES.  A wave's slots are sorted by end; every end but the
+// largest lies an even number of K-steps after the wave's first K-step (a
+// tile's last segment may be extended by one K-step whose columns are all
+// beyond the tile's degree limit), so the two operand sets below alternate
+// without copies.  Source moments are read through a buffer descriptor
+// spanning the source slot's moments: prefetches beyond a segment (and
+// padding columns) return zero without touching other memory.
+template <class T> struct M2LTraits;
+template <> struct M2LTraits<double> {
+    using acc_t = d4_t;
+    static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // D[i][j] of a 16x16 tile: lane j + 16 (i % 4), register i / 4
+    static __device__ __forceinline__ int row(int lq, int r) { return lq + 4 * r; }
+};
+template <> struct M2LTraits<float> {
+    using acc_t = f4_t;
+    static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // D[i][j] of a 16x16 tile: lane j + 16 (i / 4), register i % 4
+    static __device__ __forceinline__ int row(int lq, int r) { return 4 * lq + r; }
+};
+
+template <class T, int NB, int MAXS, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
+    const T* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
+    const int* __restrict__ cls, const int* __restrict__ off3, const T* __restrict__ E1s, int TSp,
+    const int* __restrict__ packinfo, const int* __restrict__ plan, int plan_stride, int Nc, int n_int, int mt,
+    int mx, int R, int nsplit, int ncb, double* __restrict__ lam_parts) {
+    static_assert(MAXS >= 1 && MAXS <= 4, "phase dispatch below is written for one to four slots");
+    using Tr = M2LTraits<T>;
+    using acc_t = typename Tr::acc_t;
+    constexpr int ES = sizeof(T);              // bytes per table entry / moment
+    extern __shared__ double smem[];
+    const int nt1 = mt + 1, nx1 = mx + 1;
+    const int nx2 = nx1 * nx1;
+    const int Nc4 = (Nc + 3) & ~3;
+    // two buffers of the three 1D tables of one (source, Delta) phase: [buf][x | y | z][TSp];
+    // then per coefficient column (padded): byte offsets of its x, y, z table
+    // columns and its degree (255 for padding columns)
+    int4* sCol = (int4*)((char*)smem + 6 * TSp * ES);
+    const int lane = threadIdx.x % kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // Workgroups are dealt to the 8 XCDs round-robin by linear id; remap so
+    // that each XCD walks a contiguous range of (row group, target slot):
+    // the groups of one slot and neighbouring slots read the same moments.
+    int g, X, bz;
+    {
+        const int ng = gridDim.x, nxs = gridDim.y;
+        const int total = ng * nxs * gridDim.z;
+        const int lin = blockIdx.x + ng * (blockIdx.y + nxs * blockIdx.z);
+        const int per = total / kXcds;
+        const int lm = lin < per * kXcds ? (lin % kXcds) * per + lin / kXcds : lin;
+        g = lm % ng;
+        X = (lm / ng) % nxs;
+        bz = lm / (ng * nxs);
+    }
+    const int cb = bz % ncb;
+    const int split = bz / ncb;                // which share of the source list this workgroup takes
+    if (split > 0) lam = lam_parts + (int64_t)(split - 1) * ((int64_t)gridDim.y * Nc * n_int);
+    const int* gp = plan + (int64_t)g * plan_stride;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int k0 = cb * (32 * NB) + 2 * lr;    // even target interval of block 0
+    for (int c = threadIdx.x; c < Nc4 + 16; c += blockDim.x) {
+        int4 v = {0, 0, 0, 255};
+        if (c < Nc) {
+            const int ci = packinfo[c];
+            const int cbase = (ci & 15) * nt1 * nx2;
+            v.x = ES * (cbase + ((ci >> 4) & 15) * nx1);
+            v.y = ES * (cbase + ((ci >> 8) & 15) * nx1);
+            v.z = ES * (cbase + ((ci >> 12) & 15) * nx1);
+            v.w = (ci >> 16) & 255;
+        }
+        sCol[c] = v;
+    }
+    const int sbeg = __builtin_amdgcn_readfirstlane(gp[2 * w]);
+    int tiles[MAXS], ks[MAXS], part[MAXS], rX[MAXS], rY[MAXS], rZ[MAXS], rD[MAXS];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        const int* e = gp + 2 * WAVES + (w * MAXS + i) * 3;
+        tiles[i] = __builtin_amdgcn_readfirstlane(e[0]);
+        ks[i] = __builtin_amdgcn_readfirstlane(e[1]);   // segment end (exclusive, absolute)
+        part[i] = __builtin_amdgcn_readfirstlane(e[2]);
+        const int row = 16 * (tiles[i] >= 0 ? tiles[i] : 0) + lr;
+        const bool rv = tiles[i] >= 0 && row < Nc;
+        const int ri = rv ? packinfo[row] : 0;
+        const int b = ri & 15;
+        rX[i] = ES * (b * nx2 + ((ri >> 4) & 15));
+        rY[i] = ES * (b * nx2 + ((ri >> 8) & 15) + TSp);
+        rZ[i] = ES * (b * nx2 + ((ri >> 12) & 15) + 2 * TSp);
+        rD[i] = mx - (rv ? ((ri >> 16) & 255) : 255);   // largest column degree this row accepts
+    }
+    acc_t accE[MAXS][NB], accO[MAXS][NB];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            accE[i][nb] = acc_t{0, 0, 0, 0};
+            accO[i][nb] = acc_t{0, 0, 0, 0};
+        }
+    const int nR = 2 * R + 1;
+    const int sb = ptr[X], se = ptr[X + 1];
+    const int s_lo = sb + (int)(((int64_t)(se - sb) * split) / nsplit);
+    const int s_hi = sb + (int)(((int64_t)(se - sb) * (split + 1)) / nsplit);
+    const int n_phase = 2 * (s_hi - s_lo);
+    const int pieces = TSp * ES / 1024;              // 1 KB pieces per table
+    auto stage = [&](int p) {
+        const int si = s_lo + (p >> 1), D = 2 + (p & 1);
+        const int c3 = cls[si];
+        char* dst = (char*)smem + (p & 1) * 3 * TSp * ES;
+        for (int c = w; c < 3 * pieces; c += WAVES) {
+            const int tb = c / pieces, pc = c - tb * pieces;
+            const int o = off3[3 * c3 + tb] + R;
+            const char* gsrc = (const char*)(E1s + (((int64_t)(D - 2) * nR + o) * 2 + (tb == 0 ? 0 : 1)) * TSp) +
+                               pc * 1024 + 16 * lane;
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)gsrc,
+                                             (void __attribute__((address_space(3)))*)(dst + tb * TSp * ES + pc * 1024),
+                                             16, 0, 0);
+        }
+    };
+    // Lane (lr, lq) of K-step s reads, for every block nb, the pair
+    // mu[Y][c][k - 2], mu[Y][c][k - 1] with c = 4 s + lq and k = its even
+    // target interval: the Delta = 2 sources of the even and odd targets, and
+    // (first value) the Delta = 3 source of the odd target.  Block nb is
+    // 32 values further.  Targets k < 2 have no sources: their results are
+    // written as zero at the end.  The descriptor starts two values before the
+    // slot (mu has two leading guard values), so every offset is >= 0; reads
+    // past the slot's last coefficient are out of its range and return zero.
+    const int vbase = ((4 * sbeg + lq) * n_int + k0) * ES;   // byte offset of mu[Y][c][k - 2] from the descriptor base
+    const int bstep = 4 * n_int * ES;                        // bytes between consecutive K-steps
+    const int slot_bytes = (Nc * n_int + 2) * ES;
+    const char* lds = (const char*)smem;
+    if (n_phase > 0) stage(0);
+    for (int p = 0; p < n_phase; ++p) {
+        const int si = s_lo + (p >> 1);
+        const int Y = src[si];
+        const int boff = (p & 1) * 3 * TSp * ES;       // byte offset of this phase's table buffer
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(mu + (int64_t)Y * Nc * n_int - 2), (short)0, slot_bytes, 0x00020000);
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's pieces of phase p have landed in LDS
+        __syncthreads();                 // ... everyone's; and phase p-1 is done with the other buffer
+        if (p + 1 < n_phase) stage(p + 1);
+        int pX[MAXS], pY[MAXS], pZ[MAXS];
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            pX[i] = boff + rX[i];
+            pY[i] = boff + rY[i];
+            pZ[i] = boff + rZ[i];
+        }
+        auto run = [&](auto dc) {
+            constexpr int D = decltype(dc)::value;
+            // Delta = 2 uses both values of the pair, Delta = 3 only the first
+            using T2 = std::conditional_t<sizeof(T) == 8, double2, float2>;
+            using BT = std::conditional_t<D == 2, T2, T>;
+            auto load = [&](BT* bv, int s) {
+                const int vo = vbase + (s - sbeg) * bstep;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int off = vo + nb * 32 * ES;
+                    if constexpr (D == 2 && ES == 8)
+                        bv[nb] = __builtin_bit_cast(BT, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+                    else if constexpr (D == 2 || ES == 8)
+                        bv[nb] = __builtin_bit_cast(BT, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+                    else
+                        bv[nb] = __builtin_bit_cast(BT, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                }
+            };
+            // one K-step with n active slots
+            auto step = [&](auto nc, int4 col, const BT* bv) {
+                constexpr int n = decltype(nc)::value;
+                T A[n];
+#pragma unroll
+                for (int i = 0; i < n; ++i) {
+                    const T ex = *(const T*)(lds + (pX[i] + col.x));
+                    const T ey = *(const T*)(lds + (pY[i] + col.y));
+                    const T ez = *(const T*)(lds + (pZ[i] + col.z));
+                    const T msk = (col.w <= rD[i]) ? T(1) : T(0);
+                    A[i] = (ex * ey) * (ez * msk);
+                }
+#pragma unroll
+                for (int i = 0; i < n; ++i)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        if constexpr (D == 2) {
+                            accE[i][nb] = Tr::mfma(A[i], bv[nb].x, accE[i][nb]);
+                            accO[i][nb] = Tr::mfma(A[i], bv[nb].y, accO[i][nb]);
+                        } else {
+                            accO[i][nb] = Tr::mfma(A[i], bv[nb], accO[i][nb]);
+                        }
+                    }
+            };
+            // two operand sets used alternately; the set consumed at step s is
+            // refilled with step s + 2 right after its products are issued
+            int s = sbeg;
+            int4 cA = sCol[4 * s + lq], cB = sCol[4 * s + 4 + lq];
+            BT bA[NB], bB[NB];
+            load(bA, s);
+            load(bB, s + 1);
+            auto phase = [&](auto nc, int s_end) {
+                for (; s + 1 < s_end; s += 2) {
+                    step(nc, cA, bA);
+                    cA = sCol[4 * s + 8 + lq];
+                    load(bA, s + 2);
+                    step(nc, cB, bB);
+                    cB = sCol[4 * s + 12 + lq];
+                    load(bB, s + 3);
+                }
+            };
+            if constexpr (MAXS >= 4) phase(std::integral_constant<int, 4>{}, ks[3]);
+            if constexpr (MAXS >= 3) phase(std::integral_constant<int, 3>{}, ks[2]);
+            if constexpr (MAXS >= 2) phase(std::integral_constant<int, 2>{}, ks[1]);
+            phase(std::integral_constant<int, 1>{}, ks[0]);
+            if (s < ks[0]) {   // odd final step of the slots that end last
+                int na = 1;
+#pragma unroll
+                for (int i = 1; i < MAXS; ++i) na += ks[i] > s ? 1 : 0;
+                if (na == 1) step(std::integral_constant<int, 1>{}, cA, bA);
+                if constexpr (MAXS >= 2) if (na == 2) step(std::integral_constant<int, 2>{}, cA, bA);
+                if constexpr (MAXS >= 3) if (na == 3) step(std::integral_constant<int, 3>{}, cA, bA);
+                if constexpr (MAXS >= 4) if (na == 4) step(std::integral_constant<int, 4>{}, cA, bA);
+            }
+        };
+        if ((p & 1) == 0) run(std::integral_constant<int, 2>{});
+        else run(std::integral_constant<int, 3>{});
+    }
+    // partial segments: one interval block at a time, park in LDS and let the
+    // owners of the tiles' first segments add them in a fixed order
+    const int n_partial = gp[2 * WAVES + 3 * WAVES * MAXS];
+    const int* ptile = gp + 2 * WAVES + 3 * WAVES * MAXS + 1;
+    T* red = (T*)smem;   // [n_partial][8][64]
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            if (tiles[i] >= 0 && part[i] >= 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    red[((int64_t)part[i] * 8 + r) * kWave + lane] = accE[i][nb][r];
+                    red[((int64_t)part[i] * 8 + 4 + r) * kWave + lane] = accO[i][nb][r];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            if (tiles[i] < 0 || part[i] >= 0) continue;
+            for (int q = 0; q < n_partial; ++q) {
+                if (ptile[q] != tiles[i]) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    accE[i][nb][r] += red[((int64_t)q * 8 + r) * kWave + lane];
+                    accO[i][nb][r] += red[((int64_t)q * 8 + 4 + r) * kWave + lane];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        if (tiles[i] < 0 || part[i] >= 0) continue;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int kE = k0 + 32 * nb, kO = kE + 1;
+            const bool has = kE >= 2;   // targets 0 and 1 have no interaction list in time
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * tiles[i] + Tr::row(lq, r);
+                if (row >= Nc) continue;
+                double* out = lam + ((int64_t)X * Nc + row) * n_int;
+                out[kE] = has ? (double)accE[i][nb][r] : 0.0;
+                out[kO] = has ? (double)accO[i][nb][r] : 0.0;
+            }
+        }
+    }
+}
+
+// wide M2L variants (interval blocks, slots per wave, waves per workgroup):
+// [0] for levels with 32 intervals, [1] with a multiple of 64, [2] of 128
+// [precision: 0 FP64, 1 FP32][variant]
+constexpr int kWideNB[3] = {1, 2, 4};
+constexpr int kWideMaxs[2][3] = {{2, 1, 2}, {2, 2, 2}};
+constexpr int kWideWaves[2][3] = {{16, 16, 8}, {16, 16, 8}};
+constexpr bool kWideUseNB1 = true;   // levels with 32 intervals: wide form instead of k_m2l_mfma
+
+template <int Q, int V>
+using WideT = std::conditional_t<Q == 0, double, float>;
+
+template <int Q, int V>
+const void* wide_fn() {
+    return (const void*)k_m2l_wide<WideT<Q, V>, kWideNB[V], kWideMaxs[Q][V], kWideWaves[Q][V]>;
+}
+
+const void* wide_fn(int q, int v) {
+    if (q == 0) return v == 0 ? wide_fn<0, 0>() : (v == 1 ? wide_fn<0, 1>() : wide_fn<0, 2>());
+    return v == 0 ? wide_fn<1, 0>() : (v == 1 ? wide_fn<1, 1>() : wide_fn<1, 2>());
+}
+
+template <int Q, int V>
+void launch_wide(dim3 grid, size_t shm, hipStream_t st, const void* mu, double* lam, const int* ptr, const int* src,
+                 const int* cls, const int* off3, const void* E1s, int TSp, const int* packinfo, const int* plan,
+                 int plan_stride, int Nc, int n_int, int mt, int mx, int R, int nsplit, int ncb, double* lam_parts) {
+    using T = WideT<Q, V>;
+    hipLaunchKernelGGL((k_m2l_wide<T, kWideNB[V], kWideMaxs[Q][V], kWideWaves[Q][V]>), grid,
+                       dim3(64 * kWideWaves[Q][V]), shm, st, (const T*)mu, lam, ptr, src, cls, off3, (const T*)E1s,
+                       TSp, packinfo, plan, plan_stride, Nc, n_int, mt, mx, R, nsplit, ncb, lam_parts);
+}
+
+using WideLaunch = void (*)(dim3, size_t, hipStream_t, const void*, double*, const int*, const int*, const int*,
+                            const int*, const void*, int, const int*, const int*, int, int, int, int, int, int, int,
+                            int, double*);
+
+WideLaunch wide_launcher(int q, int v) {
+    if (q == 0) return v == 0 ? launch_wide<0, 0> : (v == 1 ? launch_wide<0, 1> : launch_wide<0, 2>);
+    return v == 0 ? launch_wide<1, 0> : (v == 1 ? launch_wide<1, 1> : launch_wide<1, 2>);
+}
+
+// FP32 copy of a level's moments for the mixed-precision M2L.
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+// Sum the per-share partial locals of a level whose interaction lists were
+// split over several workgroups (fixed order: share 0, 1, ...).
+__global__ void k_sum_parts(double* __restrict__ lam, const double* __restrict__ parts, int nparts, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = lam[i];
+    for (int p = 0; p < nparts; ++p) s += parts[(int64_t)p * n + i];
+    lam[i] = s;
+}
