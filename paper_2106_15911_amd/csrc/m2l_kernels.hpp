@@ -246,14 +246,25 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
 //
 // The rows of eq. m2l (16-row tiles of the staircase) are partitioned into
 // row groups; a workgroup of WAVES waves owns one target slot X, one row
-// group and NB blocks of 32 consecutive intervals.  An operator element a
-// wave generates from the 1D tables then feeds 2 NB matrix-core products
-// (even and odd intervals of every block) for Delta = 2 and NB for
-// Delta = 3, instead of 2 and 1 in k_m2l_mfma, so generating the operator
-// costs 2 NB times fewer vector instructions per product.  Within a group
-// the tiles' K-ranges are cut into segments (up to MAXS per wave, sharing
-// their first K-step) as in k_m2l_mfma; partial segments are added to their
-// tile's first segment through LDS, one interval block at a time.
+// group and NB blocks of 32 consecutive intervals.  It walks X's interaction
+// list one source slot Y at a time; both time offsets of the source
+// (Delta = 2 for every target interval, Delta = 3 for the odd ones) are
+// applied in the same phase, so each source moment is read once per
+// workgroup.  An operator element a wave generates from the 1D tables feeds
+// 2 NB products (Delta = 2, even and odd intervals of every block) or NB
+// products (Delta = 3, odd intervals).  Within a group the tiles' K-ranges
+// are cut into segments (up to MAXS per wave, sharing their first K-step);
+// partial segments are added to their tile's first segment through LDS, one
+// interval block at a time.
+//
+// The 1D coefficient tables E_{kappa,nu}(r, d_ab) (eq. exp_coeffs_1d) of a
+// (level, Delta, offset) are stored compactly: for every time pair (a, b) the
+// entries with kappa + nu <= m_x, kappa-major, so that entry (a, b, kappa,
+// nu) sits at (a (m_t+1) + b) BS + T(kappa) + nu with BS = (m_x+1)(m_x+2)/2
+// and T(kappa) = kappa (m_x+1) - kappa (kappa-1)/2: a column part plus a row
+// part.  Entries with kappa + nu > m_x are never used unmasked (their total
+// degree exceeds m_x); reading them stays inside the padded table.  The x
+// table has C_ab folded in.
 //
 // Per group g the host table plan[g * plan_stride ...] holds
 //   [0, 2 W)                  wave w: (first K-step, number of segments)
@@ -270,39 +281,49 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
 template <class T> struct M2LTraits;
 template <> struct M2LTraits<double> {
     using acc_t = d4_t;
+    using pair_t = double2;
     static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     // D[i][j] of a 16x16 tile: lane j + 16 (i % 4), register i / 4
     static __device__ __forceinline__ int row(int lq, int r) { return lq + 4 * r; }
+    static __device__ __forceinline__ pair_t load_pair(__amdgpu_buffer_rsrc_t rs, int off) {
+        return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    }
 };
 template <> struct M2LTraits<float> {
     using acc_t = f4_t;
+    using pair_t = float2;
     static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     // D[i][j] of a 16x16 tile: lane j + 16 (i / 4), register i % 4
     static __device__ __forceinline__ int row(int lq, int r) { return 4 * lq + r; }
+    static __device__ __forceinline__ pair_t load_pair(__amdgpu_buffer_rsrc_t rs, int off) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    }
 };
 
 template <class T, int NB, int MAXS, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     const T* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
-    const int* __restrict__ cls, const int* __restrict__ off3, const T* __restrict__ E1s, int TSp,
+    const int* __restrict__ cls, const int* __restrict__ off3, const T* __restrict__ E1c, int TSp,
     const int* __restrict__ packinfo, const int* __restrict__ plan, int plan_stride, int Nc, int n_int, int mt,
     int mx, int R, int nsplit, int ncb, double* __restrict__ lam_parts) {
     static_assert(MAXS >= 1 && MAXS <= 4, "phase dispatch below is written for one to four slots");
     using Tr = M2LTraits<T>;
     using acc_t = typename Tr::acc_t;
+    using pair_t = typename Tr::pair_t;
     constexpr int ES = sizeof(T);              // bytes per table entry / moment
     extern __shared__ double smem[];
     const int nt1 = mt + 1, nx1 = mx + 1;
-    const int nx2 = nx1 * nx1;
+    const int BS = nx1 * (nx1 + 1) / 2;        // compact entries per time pair (a, b)
     const int Nc4 = (Nc + 3) & ~3;
-    // two buffers of the three 1D tables of one (source, Delta) phase: [buf][x | y | z][TSp];
-    // then per coefficient column (padded): byte offsets of its x, y, z table
-    // columns and its degree (255 for padding columns)
-    int4* sCol = (int4*)((char*)smem + 6 * TSp * ES);
+    // two buffers of the six 1D tables of one source phase:
+    // [buf][Delta 2: x | y | z, Delta 3: x | y | z][TSp]; then per coefficient
+    // column (padded): byte offsets of its x, y, z table columns and its
+    // degree (255 for padding columns)
+    int4* sCol = (int4*)((char*)smem + 12 * TSp * ES);
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     // Workgroups are dealt to the 8 XCDs round-robin by linear id; remap so
@@ -325,14 +346,15 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     const int* gp = plan + (int64_t)g * plan_stride;
     const int lr = lane & 15, lq = lane >> 4;
     const int k0 = cb * (32 * NB) + 2 * lr;    // even target interval of block 0
+    auto tri = [&](int k) { return k * nx1 - (k * (k - 1)) / 2; };
     for (int c = threadIdx.x; c < Nc4 + 16; c += blockDim.x) {
         int4 v = {0, 0, 0, 255};
         if (c < Nc) {
             const int ci = packinfo[c];
-            const int cbase = (ci & 15) * nt1 * nx2;
-            v.x = ES * (cbase + ((ci >> 4) & 15) * nx1);
-            v.y = ES * (cbase + ((ci >> 8) & 15) * nx1);
-            v.z = ES * (cbase + ((ci >> 12) & 15) * nx1);
+            const int cbase = (ci & 15) * nt1 * BS;
+            v.x = ES * (cbase + tri((ci >> 4) & 15));
+            v.y = ES * (cbase + tri((ci >> 8) & 15));
+            v.z = ES * (cbase + tri((ci >> 12) & 15));
             v.w = (ci >> 16) & 255;
         }
         sCol[c] = v;
@@ -349,9 +371,9 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
         const bool rv = tiles[i] >= 0 && row < Nc;
         const int ri = rv ? packinfo[row] : 0;
         const int b = ri & 15;
-        rX[i] = ES * (b * nx2 + ((ri >> 4) & 15));
-        rY[i] = ES * (b * nx2 + ((ri >> 8) & 15) + TSp);
-        rZ[i] = ES * (b * nx2 + ((ri >> 12) & 15) + 2 * TSp);
+        rX[i] = ES * (b * BS + ((ri >> 4) & 15));
+        rY[i] = ES * (b * BS + ((ri >> 8) & 15) + TSp);
+        rZ[i] = ES * (b * BS + ((ri >> 12) & 15) + 2 * TSp);
         rD[i] = mx - (rv ? ((ri >> 16) & 255) : 255);   // largest column degree this row accepts
     }
     acc_t accE[MAXS][NB], accO[MAXS][NB];
@@ -366,16 +388,16 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     const int sb = ptr[X], se = ptr[X + 1];
     const int s_lo = sb + (int)(((int64_t)(se - sb) * split) / nsplit);
     const int s_hi = sb + (int)(((int64_t)(se - sb) * (split + 1)) / nsplit);
-    const int n_phase = 2 * (s_hi - s_lo);
+    const int n_phase = s_hi - s_lo;
     const int pieces = TSp * ES / 1024;              // 1 KB pieces per table
     auto stage = [&](int p) {
-        const int si = s_lo + (p >> 1), D = 2 + (p & 1);
-        const int c3 = cls[si];
-        char* dst = (char*)smem + (p & 1) * 3 * TSp * ES;
-        for (int c = w; c < 3 * pieces; c += WAVES) {
-            const int tb = c / pieces, pc = c - tb * pieces;
-            const int o = off3[3 * c3 + tb] + R;
-            const char* gsrc = (const char*)(E1s + (((int64_t)(D - 2) * nR + o) * 2 + (tb == 0 ? 0 : 1)) * TSp) +
+        const int c3 = cls[s_lo + p];
+        char* dst = (char*)smem + (p & 1) * 6 * TSp * ES;
+        for (int c = w; c < 6 * pieces; c += WAVES) {
+            const int tb = c / pieces, pc = c - tb * pieces;   // tb = 3 (Delta - 2) + axis
+            const int D = tb / 3, axis = tb - 3 * D;
+            const int o = off3[3 * c3 + axis] + R;
+            const char* gsrc = (const char*)(E1c + (((int64_t)D * nR + o) * 2 + (axis == 0 ? 0 : 1)) * TSp) +
                                pc * 1024 + 16 * lane;
             __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)gsrc,
                                              (void __attribute__((address_space(3)))*)(dst + tb * TSp * ES + pc * 1024),
@@ -394,11 +416,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     const int bstep = 4 * n_int * ES;                        // bytes between consecutive K-steps
     const int slot_bytes = (Nc * n_int + 2) * ES;
     const char* lds = (const char*)smem;
+    const int d3 = 3 * TSp * ES;                             // Delta = 3 tables follow the Delta = 2 ones
     if (n_phase > 0) stage(0);
     for (int p = 0; p < n_phase; ++p) {
-        const int si = s_lo + (p >> 1);
-        const int Y = src[si];
-        const int boff = (p & 1) * 3 * TSp * ES;       // byte offset of this phase's table buffer
+        const int Y = src[s_lo + p];
+        const int boff = (p & 1) * 6 * TSp * ES;       // byte offset of this phase's table buffer
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void*)(mu + (int64_t)Y * Nc * n_int - 2), (short)0, slot_bytes, 0x00020000);
         __builtin_amdgcn_s_waitcnt(0);   // this wave's pieces of phase p have landed in LDS
@@ -411,81 +433,66 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
             pY[i] = boff + rY[i];
             pZ[i] = boff + rZ[i];
         }
-        auto run = [&](auto dc) {
-            constexpr int D = decltype(dc)::value;
-            // Delta = 2 uses both values of the pair, Delta = 3 only the first
-            using T2 = std::conditional_t<sizeof(T) == 8, double2, float2>;
-            using BT = std::conditional_t<D == 2, T2, T>;
-            auto load = [&](BT* bv, int s) {
-                const int vo = vbase + (s - sbeg) * bstep;
+        auto load = [&](pair_t* bv, int s) {
+            const int vo = vbase + (s - sbeg) * bstep;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) bv[nb] = Tr::load_pair(rs, vo + nb * 32 * ES);
+        };
+        // one K-step with n active slots
+        auto step = [&](auto nc, int4 col, const pair_t* bv) {
+            constexpr int n = decltype(nc)::value;
+            T A2[n], A3[n];
+#pragma unroll
+            for (int i = 0; i < n; ++i) {
+                const T msk = (col.w <= rD[i]) ? T(1) : T(0);
+                const T x2 = *(const T*)(lds + (pX[i] + col.x));
+                const T y2 = *(const T*)(lds + (pY[i] + col.y));
+                const T z2 = *(const T*)(lds + (pZ[i] + col.z));
+                const T x3 = *(const T*)(lds + (pX[i] + d3 + col.x));
+                const T y3 = *(const T*)(lds + (pY[i] + d3 + col.y));
+                const T z3 = *(const T*)(lds + (pZ[i] + d3 + col.z));
+                A2[i] = (x2 * y2) * (z2 * msk);
+                A3[i] = (x3 * y3) * (z3 * msk);
+            }
+#pragma unroll
+            for (int i = 0; i < n; ++i)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const int off = vo + nb * 32 * ES;
-                    if constexpr (D == 2 && ES == 8)
-                        bv[nb] = __builtin_bit_cast(BT, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-                    else if constexpr (D == 2 || ES == 8)
-                        bv[nb] = __builtin_bit_cast(BT, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
-                    else
-                        bv[nb] = __builtin_bit_cast(BT, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                    accE[i][nb] = Tr::mfma(A2[i], bv[nb].x, accE[i][nb]);
+                    accO[i][nb] = Tr::mfma(A2[i], bv[nb].y, accO[i][nb]);
+                    accO[i][nb] = Tr::mfma(A3[i], bv[nb].x, accO[i][nb]);
                 }
-            };
-            // one K-step with n active slots
-            auto step = [&](auto nc, int4 col, const BT* bv) {
-                constexpr int n = decltype(nc)::value;
-                T A[n];
-#pragma unroll
-                for (int i = 0; i < n; ++i) {
-                    const T ex = *(const T*)(lds + (pX[i] + col.x));
-                    const T ey = *(const T*)(lds + (pY[i] + col.y));
-                    const T ez = *(const T*)(lds + (pZ[i] + col.z));
-                    const T msk = (col.w <= rD[i]) ? T(1) : T(0);
-                    A[i] = (ex * ey) * (ez * msk);
-                }
-#pragma unroll
-                for (int i = 0; i < n; ++i)
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        if constexpr (D == 2) {
-                            accE[i][nb] = Tr::mfma(A[i], bv[nb].x, accE[i][nb]);
-                            accO[i][nb] = Tr::mfma(A[i], bv[nb].y, accO[i][nb]);
-                        } else {
-                            accO[i][nb] = Tr::mfma(A[i], bv[nb], accO[i][nb]);
-                        }
-                    }
-            };
-            // two operand sets used alternately; the set consumed at step s is
-            // refilled with step s + 2 right after its products are issued
-            int s = sbeg;
-            int4 cA = sCol[4 * s + lq], cB = sCol[4 * s + 4 + lq];
-            BT bA[NB], bB[NB];
-            load(bA, s);
-            load(bB, s + 1);
-            auto phase = [&](auto nc, int s_end) {
-                for (; s + 1 < s_end; s += 2) {
-                    step(nc, cA, bA);
-                    cA = sCol[4 * s + 8 + lq];
-                    load(bA, s + 2);
-                    step(nc, cB, bB);
-                    cB = sCol[4 * s + 12 + lq];
-                    load(bB, s + 3);
-                }
-            };
-            if constexpr (MAXS >= 4) phase(std::integral_constant<int, 4>{}, ks[3]);
-            if constexpr (MAXS >= 3) phase(std::integral_constant<int, 3>{}, ks[2]);
-            if constexpr (MAXS >= 2) phase(std::integral_constant<int, 2>{}, ks[1]);
-            phase(std::integral_constant<int, 1>{}, ks[0]);
-            if (s < ks[0]) {   // odd final step of the slots that end last
-                int na = 1;
-#pragma unroll
-                for (int i = 1; i < MAXS; ++i) na += ks[i] > s ? 1 : 0;
-                if (na == 1) step(std::integral_constant<int, 1>{}, cA, bA);
-                if constexpr (MAXS >= 2) if (na == 2) step(std::integral_constant<int, 2>{}, cA, bA);
-                if constexpr (MAXS >= 3) if (na == 3) step(std::integral_constant<int, 3>{}, cA, bA);
-                if constexpr (MAXS >= 4) if (na == 4) step(std::integral_constant<int, 4>{}, cA, bA);
+        };
+        // two operand sets used alternately; the set consumed at step s is
+        // refilled with step s + 2 right after its products are issued
+        int s = sbeg;
+        int4 cA = sCol[4 * s + lq], cB = sCol[4 * s + 4 + lq];
+        pair_t bA[NB], bB[NB];
+        load(bA, s);
+        load(bB, s + 1);
+        auto phase = [&](auto nc, int s_end) {
+            for (; s + 1 < s_end; s += 2) {
+                step(nc, cA, bA);
+                cA = sCol[4 * s + 8 + lq];
+                load(bA, s + 2);
+                step(nc, cB, bB);
+                cB = sCol[4 * s + 12 + lq];
+                load(bB, s + 3);
             }
         };
-        if ((p & 1) == 0) run(std::integral_constant<int, 2>{});
-        else run(std::integral_constant<int, 3>{});
+        if constexpr (MAXS >= 4) phase(std::integral_constant<int, 4>{}, ks[3]);
+        if constexpr (MAXS >= 3) phase(std::integral_constant<int, 3>{}, ks[2]);
+        if constexpr (MAXS >= 2) phase(std::integral_constant<int, 2>{}, ks[1]);
+        phase(std::integral_constant<int, 1>{}, ks[0]);
+        if (s < ks[0]) {   // odd final step of the slots that end last
+            int na = 1;
+#pragma unroll
+            for (int i = 1; i < MAXS; ++i) na += ks[i] > s ? 1 : 0;
+            if (na == 1) step(std::integral_constant<int, 1>{}, cA, bA);
+            if constexpr (MAXS >= 2) if (na == 2) step(std::integral_constant<int, 2>{}, cA, bA);
+            if constexpr (MAXS >= 3) if (na == 3) step(std::integral_constant<int, 3>{}, cA, bA);
+            if constexpr (MAXS >= 4) if (na == 4) step(std::integral_constant<int, 4>{}, cA, bA);
+        }
     }
     // partial segments: one interval block at a time, park in LDS and let the
     // owners of the tiles' first segments add them in a fixed order

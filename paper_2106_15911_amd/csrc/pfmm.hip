@@ -755,8 +755,11 @@ struct pfmm_tree {
     struct Wide { int* plan = nullptr; int G = 0, stride = 0; size_t shm = 0; bool ok = false; } wide[2][3];
     int prec = PFMM_FP64;         // farfield precision of the next applies
     bool has_f32 = false;         // FP32 moments and tables allocated (tree built in a mixed mode)
-    float* E1s32 = nullptr;       // FP32 copy of E1s with rows of TSf entries
-    int TSf = 0;                  // FP32 table length (multiple of 256 floats)
+    // wide M2L: compact 1D tables (entries with kappa + nu <= m_x per time pair),
+    // rows [level][Delta][offset][x (C_ab folded in) | y,z] of TSc64 doubles / TSc32 floats
+    double* E1c = nullptr;
+    float* E1c32 = nullptr;
+    int TSc64 = 0, TSc32 = 0;
     CoefMaps cm{};
     SepMaps sm{};
     int ki_m2m = 0, ki_l2l = 0;   // intervals per block of k_m2m_sep / k_l2l_sep
@@ -1247,18 +1250,21 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         const int Nc4 = (Nc + 3) & ~3;
-        const int TS = (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1);
-        t->TSf = (TS + 255) / 256 * 256;
+        // compact table length: (m_t+1)^2 time pairs of (m_x+1)(m_x+2)/2 entries,
+        // plus m_x entries read (masked) past the last pair
+        const int TSc = (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 2) / 2 + P.m_x;
+        t->TSc64 = (TSc + 127) / 128 * 128;
+        t->TSc32 = (TSc + 255) / 256 * 256;
         for (int q = 0; q < (t->has_f32 ? 2 : 1); ++q)
             for (int v = 0; v < 3; ++v) {
                 auto& W = t->wide[q][v];
                 const int maxs = kWideMaxs[q][v], waves = kWideWaves[q][v];
                 const size_t es = q == 0 ? sizeof(double) : sizeof(float);
-                const int tsp = q == 0 ? t->TSp : t->TSf;
+                const int tsp = q == 0 ? t->TSc64 : t->TSc32;
                 std::vector<int> tab;
                 int maxp = 0;
                 if (!plan_wide(ks, maxs, waves, tab, W.G, W.stride, maxp)) continue;
-                W.shm = std::max((size_t)6 * tsp * es + (size_t)(Nc4 + 16) * 4 * sizeof(int), (size_t)maxp * 8 * 64 * es);
+                W.shm = std::max((size_t)12 * tsp * es + (size_t)(Nc4 + 16) * 4 * sizeof(int), (size_t)maxp * 8 * 64 * es);
                 if (W.shm > (size_t)lds_max) continue;
                 if (W.shm > 65536)
                     HIP_TRY(hipFuncSetAttribute(wide_fn(q, v), hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.shm));
@@ -1290,13 +1296,23 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
                 }
         }
         PF_TRY(upload(t, &t->E1s, E1s.data(), E1s.size()));
+        // compact rows of the wide M2L: entry (a, b, kappa, nu) with kappa + nu <= m_x
+        // at (a (m_t+1) + b) BS + T(kappa) + nu, T(kappa) = kappa (m_x+1) - kappa (kappa-1) / 2
+        const int BS = nx1 * (nx1 + 1) / 2;
+        const size_t nrows = E1s.size() / TSp;
+        std::vector<double> E1c(nrows * t->TSc64, 0.0);
+        for (size_t r = 0; r < nrows; ++r)
+            for (int ab = 0; ab < nt1 * nt1; ++ab)
+                for (int k = 0; k < nx1; ++k)
+                    for (int n = 0; n + k < nx1; ++n)
+                        E1c[r * t->TSc64 + (size_t)ab * BS + (k * nx1 - k * (k - 1) / 2) + n] =
+                            E1s[r * TSp + (size_t)ab * nx1 * nx1 + k * nx1 + n];
+        PF_TRY(upload(t, &t->E1c, E1c.data(), E1c.size()));
         if (t->has_f32) {
-            // the same tables in FP32 with rows of TSf entries (offsets scale by TSf / TSp)
-            const int TSf = t->TSf;
-            std::vector<float> E1f(E1s.size() / TSp * TSf, 0.f);
-            for (size_t r = 0; r < E1s.size() / TSp; ++r)
-                for (int i = 0; i < TSp; ++i) E1f[r * TSf + i] = (float)E1s[r * TSp + i];
-            PF_TRY(upload(t, &t->E1s32, E1f.data(), E1f.size()));
+            std::vector<float> E1f(nrows * t->TSc32, 0.f);
+            for (size_t r = 0; r < nrows; ++r)
+                for (int i = 0; i < t->TSc64 && i < t->TSc32; ++i) E1f[r * t->TSc32 + i] = (float)E1c[r * t->TSc64 + i];
+            PF_TRY(upload(t, &t->E1c32, E1f.data(), E1f.size()));
         }
     }
     // levels
@@ -1488,14 +1504,15 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
                 const int nsplit = D.nsplit_q[q];
                 dim3 grid(W.G, D.nx, D.ncb[q] * nsplit);
                 const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
+                const int64_t row0 = D.e1s_off / t->TSp;   // first table row of the level
                 const void* m = D.mu;
-                const void* e1 = t->E1s + D.e1s_off;
-                int tsp = t->TSp;
+                const void* e1 = t->E1c + row0 * t->TSc64;
+                int tsp = t->TSc64;
                 if (q == 1) {
                     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl);
                     m = D.mu32;
-                    e1 = t->E1s32 + D.e1s_off / t->TSp * t->TSf;
-                    tsp = t->TSf;
+                    e1 = t->E1c32 + row0 * t->TSc32;
+                    tsp = t->TSc32;
                 }
                 wide_launcher(q, v)(grid, W.shm, st, m, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3, e1, tsp,
                                     t->packinfo, W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, nsplit, D.ncb[q],
