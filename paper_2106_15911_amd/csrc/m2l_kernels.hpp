@@ -549,8 +549,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
 // [0] for levels with 32 intervals, [1] with a multiple of 64, [2] of 128
 // [precision: 0 FP64, 1 FP32][variant]
 constexpr int kWideNB[3] = {1, 2, 4};
-constexpr int kWideMaxs[2][3] = {{2, 1, 2}, {2, 2, 2}};
-constexpr int kWideWaves[2][3] = {{16, 16, 8}, {16, 16, 8}};
+constexpr int kWideMaxs[2][3] = {{2, 2, 1}, {2, 2, 2}};
+constexpr int kWideWaves[2][3] = {{16, 16, 16}, {16, 16, 16}};
 constexpr bool kWideUseNB1 = true;   // levels with 32 intervals: wide form instead of k_m2l_mfma
 
 template <int Q, int V>

@@ -978,38 +978,50 @@ bool plan_row_group(const std::vector<int>& tiles, const std::vector<int>& ks, i
     return !best.empty();
 }
 
-// Row groups of the wide M2L with `waves` waves of maxs slots: tiles are
-// dealt to G groups by longest-processing-time on their K-lengths, every
-// group gets a split-K plan, and G minimises the summed group costs plus a
-// fixed per-workgroup overhead.  Fills the per-group tables of k_m2l_wide.
+// Row groups of the wide M2L with `waves` waves of maxs slots.  Tiles are
+// dealt to G groups either by longest-processing-time on their K-lengths or
+// as contiguous runs of the length-sorted tiles (so that few groups contain
+// the long low-degree tiles); every group gets a split-K plan.  The choice
+// minimises, summed over groups, max(plan cost, half the group's longest
+// K-range) plus a fixed per-workgroup overhead: a workgroup streams the
+// source moments of its longest K-range once per source, which bounds it
+// from below when the moment stream, not the matrix cores, is the limit.
+// Fills the per-group tables of k_m2l_wide.
 bool plan_wide(const std::vector<int>& ks, int maxs, int waves, std::vector<int>& tab, int& G_out, int& stride,
                int& max_partial) {
     const int ntile = (int)ks.size();
     stride = 2 * waves + 4 * waves * maxs + 1;
-    int best_total = INT32_MAX;
+    double best_total = 1e300;
     std::vector<std::vector<std::vector<WideSeg>>> best_groups;
     const int gmin = std::max(1, (ntile + waves * maxs - 1) / (waves * maxs));
-    for (int G = gmin; G <= 12; ++G) {
-        std::vector<int> order(ntile);
-        for (int i = 0; i < ntile; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ks[a] > ks[b]; });
-        std::vector<std::vector<int>> gt(G);
-        std::vector<int> tot(G, 0);
-        for (int tt : order) {
-            const int q = (int)(std::min_element(tot.begin(), tot.end()) - tot.begin());
-            gt[q].push_back(tt);
-            tot[q] += ks[tt];
+    std::vector<int> order(ntile);
+    for (int i = 0; i < ntile; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ks[a] > ks[b]; });
+    int ktot = 0;
+    for (int k : ks) ktot += k;
+    for (int mode = 0; mode < 2; ++mode)
+        for (int G = gmin; G <= 12; ++G) {
+            std::vector<std::vector<int>> gt(G);
+            std::vector<int> tot(G, 0);
+            int q = 0;
+            for (int tt : order) {
+                if (mode == 0) q = (int)(std::min_element(tot.begin(), tot.end()) - tot.begin());
+                else if (tot[q] * G >= ktot && q < G - 1) ++q;
+                gt[q].push_back(tt);
+                tot[q] += ks[tt];
+            }
+            double total = 0;
+            bool ok = true;
+            std::vector<std::vector<std::vector<WideSeg>>> groups(G);
+            for (int g = 0; g < G && ok; ++g) {
+                int c = 0;
+                if (gt[g].empty() || !plan_row_group(gt[g], ks, maxs, waves, groups[g], c)) { ok = false; break; }
+                int mk = 0;
+                for (int tt : gt[g]) mk = std::max(mk, ks[tt]);
+                total += std::max((double)c, 0.5 * mk) + 8;
+            }
+            if (ok && total < best_total) { best_total = total; best_groups = groups; }
         }
-        int total = 0;
-        bool ok = true;
-        std::vector<std::vector<std::vector<WideSeg>>> groups(G);
-        for (int q = 0; q < G && ok; ++q) {
-            int c = 0;
-            if (gt[q].empty() || !plan_row_group(gt[q], ks, maxs, waves, groups[q], c)) ok = false;
-            total += c + 8;
-        }
-        if (ok && total < best_total) { best_total = total; best_groups = groups; }
-    }
     if (best_groups.empty()) return false;
     const int G = (int)best_groups.size();
     tab.assign((size_t)G * stride, -1);
