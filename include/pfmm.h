@@ -59,6 +59,16 @@ typedef enum {
                                 locals and the final sum stay FP64           */
 } pfmm_precision;
 
+/* how the nearfield blocks (Section 3.4, eq. eval_sl_nf_block) are applied */
+typedef enum {
+    PFMM_NF_STORED = 0,      /* causal blocks assembled once and streamed from
+                                device memory at every apply                  */
+    PFMM_NF_TOEPLITZ = 1     /* uniform steps make a block entry depend on the
+                                triangles and the step difference only: keep
+                                the distinct values per (leaf spatial box, d)
+                                and read them at every apply (no block storage) */
+} pfmm_nearfield_mode;
+
 /* which operators pfmm_build_tree assembles (bit mask) */
 enum { PFMM_OP_V = 1, PFMM_OP_K = 2 };
 
@@ -77,7 +87,7 @@ typedef struct {
                                 keeps the FP64 path (pfmm_set_precision).     default FP64 */
     int32_t  operators;      /* PFMM_OP_V | PFMM_OP_K.                             default both */
     int32_t  check_finite;   /* 1: reject non-finite mesh/time input.              default 1   */
-    int32_t  reserved;
+    int32_t  nearfield_mode; /* pfmm_nearfield_mode.                               default STORED */
     uint64_t device_mem_budget; /* bytes the tree may allocate; 0 = 90% of free memory */
 } pfmm_params;
 

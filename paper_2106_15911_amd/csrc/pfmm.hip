@@ -18,6 +18,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "internal.hpp"
@@ -462,7 +463,7 @@ __global__ void k_near_regular(double* __restrict__ table, const GroupDev* __res
     const int nX = gr.te - gr.tb;
     const int64_t idx = blk_base[blockIdx.x] + threadIdx.x;
     if (idx >= (int64_t)nX * gr.usize) return;
-    const int r = (int)(idx / gr.usize), u = (int)(idx % gr.usize);
+    const int r = (int)(idx % nX), u = (int)(idx / nX);
     const int kx = G.inv_sigma[gr.tb + r];
     const int jx = G.inv_sigma[upos[gr.uoff + u]];
     double acc[DMAX + 1];
@@ -492,7 +493,7 @@ __global__ void k_near_regular(double* __restrict__ table, const GroupDev* __res
             }
     }
     double* out = table + gr.toff;
-    for (int d = 0; d <= gr.dmax && d <= DMAX; ++d) out[((int64_t)d * nX + r) * gr.usize + u] = acc[d];
+    for (int d = 0; d <= gr.dmax && d <= DMAX; ++d) out[((int64_t)d * gr.usize + u) * nX + r] = acc[d];
 }
 
 struct TouchDev { int group, r, u, nshared; };
@@ -618,7 +619,7 @@ __global__ void k_near_singular(double* __restrict__ table, const GroupDev* __re
         }
     }
     double* out = table + gr.toff;
-    for (int d = 0; d <= dlast && d <= DMAX; ++d) out[((int64_t)d * nX + tp.r) * gr.usize + tp.u] = acc[d];
+    for (int d = 0; d <= dlast && d <= DMAX; ++d) out[((int64_t)d * gr.usize + tp.u) * nX + tp.r] = acc[d];
 }
 
 struct NearLayout {
@@ -641,7 +642,7 @@ struct NearLayout {
 };
 
 // Expand the distinct-integral table into the causal block storage:
-// B[boff + c * nX + r] = T[d = kt - jt][r][u(y)].  One wave per row group.
+// B[boff + c * nX + r] = T[d = kt - jt][u(y)][r].  One wave per row group.
 __global__ void __launch_bounds__(256) k_near_expand(double* __restrict__ B, const double* __restrict__ table,
                                                      const GroupDev* __restrict__ groups, const int* __restrict__ umap,
                                                      NearLayout L) {
@@ -669,7 +670,7 @@ __global__ void __launch_bounds__(256) k_near_expand(double* __restrict__ B, con
         while (i >= S) { i -= S; ++jt; }
         for (int64_t c = cs; c < total; c += cpi) {
             const int d = kt - jt;
-            out[(colbase + c) * nX + r] = T[((int64_t)d * nX + r) * gr.usize + um[pos[i]]];
+            out[(colbase + c) * nX + r] = T[((int64_t)d * gr.usize + um[pos[i]]) * nX + r];
             i += cpi;
             while (i >= S) { i -= S; ++jt; }
         }
@@ -772,6 +773,9 @@ struct pfmm_tree {
     int* umap = nullptr;
     NearOp opV, opK;
     bool hasV = false, hasK = false;
+    int nf_mode = PFMM_NF_STORED;
+    int64_t* ru_off = nullptr;    // Toeplitz nearfield: per leaf rectangle, offset into ru
+    int* ru = nullptr;            // table columns u of the rectangles' source triangles
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev;   // pairs per stage
@@ -822,7 +826,7 @@ int dmax_class(int dmax) {
 }
 
 // Device memory the build will need (bytes), computed before allocating.
-uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask, int precision) {
+uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask, int precision, int nf_mode) {
     uint64_t b = 0;
     const uint64_t N = (uint64_t)P.E_t * P.E_x;
     b += 2 * N * 8;                                   // w, f in tree order
@@ -833,7 +837,8 @@ uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask, int pre
         b += (uint64_t)L.n_off * 2 * F.op_size * 8;   // explicit M2L operators (upper bound: fallback path)
     }
     int nop = ((ops_mask & PFMM_OP_V) ? 1 : 0) + ((ops_mask & PFMM_OP_K) ? 1 : 0);
-    b += (uint64_t)nop * ((uint64_t)P.near_entries * 8 + (uint64_t)P.table_size * 8);
+    b += (uint64_t)nop * ((nf_mode == PFMM_NF_STORED ? (uint64_t)P.near_entries * 8 : 0) + (uint64_t)P.table_size * 8);
+    if (nf_mode == PFMM_NF_TOEPLITZ) b += P.rects.size() * 8 + P.set_pos.size() * 4;
     b += P.umap.size() * 4 + P.set_pos.size() * 4 + P.upos.size() * 4;
     b += (F.At.size() + F.Ax.size() + F.AxK.size() + F.qt.size() + F.qx.size() + 4 * F.E1.size()) * 8;
     b += P.rows.size() * 16;
@@ -844,8 +849,9 @@ hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
     Plan& P = t->P;
+    const bool stored = t->nf_mode == PFMM_NF_STORED;
     PF_TRY(dalloc(t, &op.table, (size_t)P.table_size));
-    PF_TRY(dalloc(t, &op.B, (size_t)P.near_entries));
+    if (stored) PF_TRY(dalloc(t, &op.B, (size_t)P.near_entries));
     // quadrature rules
     QuadRules Q{};
     std::vector<double> g, w;
@@ -916,7 +922,7 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
 #undef LAUNCH_SING
     // expand into the causal blocks
     const int64_t nrg = (int64_t)P.rows.size();
-    if (nrg > 0) {
+    if (stored && nrg > 0) {
         hipLaunchKernelGGL(k_near_expand, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, op.B, op.table, t->groups,
                            t->umap, t->nl);
         HIP_TRY(hipGetLastError());
@@ -1445,6 +1451,28 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         }
         PF_TRY(upload(t, &t->groups, gd.data(), gd.size()));
         PF_TRY(upload(t, &t->umap, P.umap.data(), P.umap.size()));
+        if (t->nf_mode == PFMM_NF_TOEPLITZ) {
+            // per leaf rectangle: the table column u of every source triangle
+            // (one list per distinct (group, set) pair)
+            std::vector<int64_t> roff(P.rects.size(), 0);
+            std::vector<int> ru;
+            std::map<std::pair<int, int>, int64_t> seen;
+            for (const LeafRec& R : P.leaves)
+                for (int q = R.rect0; q < R.rect1; ++q) {
+                    const int set = P.rects[q].set;
+                    auto key = std::make_pair(R.group, set);
+                    auto it = seen.find(key);
+                    if (it == seen.end()) {
+                        it = seen.emplace(key, (int64_t)ru.size()).first;
+                        const AsmGroup& A = P.groups[R.group];
+                        for (int i = 0; i < P.set_size[set]; ++i)
+                            ru.push_back(P.umap[A.mapoff + P.set_pos[P.set_off[set] + i]]);
+                    }
+                    roff[q] = it->second;
+                }
+            PF_TRY(upload(t, &t->ru_off, roff.data(), roff.size()));
+            PF_TRY(upload(t, &t->ru, ru.data(), ru.size()));
+        }
     }
     if (ops_mask & PFMM_OP_V) { PF_TRY(assemble_near(t, false, t->opV, st)); t->hasV = true; }
     if (ops_mask & PFMM_OP_K) { PF_TRY(assemble_near(t, true, t->opK, st)); t->hasK = true; }
@@ -1581,7 +1609,10 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
     // nearfield
     prof_begin(t, 6, st, ev);
     const int64_t nrg = (int64_t)P.rows.size();
-    if (nrg > 0)
+    if (nrg > 0 && t->nf_mode == PFMM_NF_TOEPLITZ)
+        hipLaunchKernelGGL(k_near_toep, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st,
+                           K ? t->opK.table : t->opV.table, t->groups, t->ru_off, t->ru, t->wd, t->fd, t->nl);
+    else if (nrg > 0)
         hipLaunchKernelGGL(k_near_apply, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, K ? t->opK.B : t->opV.B,
                            t->wd, t->fd, t->nl);
     prof_end(t, st, ev);
@@ -1655,7 +1686,7 @@ pfmm_status pfmm_plan_stats(const double* vertices, int64_t n_vertices, const in
         if (s != PFMM_OK) return fail(s, msg);
         FarTables F;
         build_far_tables(P, F);
-        fill_stats(P, estimate_bytes(P, F, prm.operators, prm.precision), out, -1);
+        fill_stats(P, estimate_bytes(P, F, prm.operators, prm.precision, prm.nearfield_mode), out, -1);
     } catch (const std::bad_alloc&) {
         return fail(PFMM_ENOMEM, "host allocation failed while planning");
     } catch (const std::exception& e) {
@@ -1691,7 +1722,7 @@ pfmm_status pfmm_build_tree(const double* vertices, int64_t n_vertices, const in
         return fail(PFMM_ENOMEM, "host allocation failed while planning");
     }
     if (t->P.Nc > 2048) return fail(PFMM_EUNSUPPORTED, "(m_t+1) * C(m_x+3,3) must be <= 2048");
-    const uint64_t need = estimate_bytes(t->P, t->F, prm.operators, prm.precision);
+    const uint64_t need = estimate_bytes(t->P, t->F, prm.operators, prm.precision, prm.nearfield_mode);
     size_t fr = 0, tot = 0;
     HIP_TRY(hipMemGetInfo(&fr, &tot));
     const uint64_t budget = prm.device_mem_budget ? prm.device_mem_budget : (uint64_t)(0.9 * (double)fr);
@@ -1700,6 +1731,7 @@ pfmm_status pfmm_build_tree(const double* vertices, int64_t n_vertices, const in
     hipStream_t st = as_stream(stream);
     t->prec = prm.precision;
     t->has_f32 = prm.precision == PFMM_MIXED_FP32;
+    t->nf_mode = prm.nearfield_mode;
     pfmm_status s = setup_device(t.get(), st, prm.operators);
     if (s != PFMM_OK) {
         pfmm_destroy(t.release());

@@ -58,7 +58,7 @@ struct AsmGroup {
     int dmax;           // largest time offset needed
     int64_t uoff;       // offset into upos (source positions, sorted)
     int usize;
-    int64_t toff;       // offset of the table [d][r][u]
+    int64_t toff;       // offset of the table [d][u][r] (rows innermost)
     int64_t mapoff;     // offset of the position -> u map (size E_x)
 };
 

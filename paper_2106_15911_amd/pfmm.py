@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_ENOMEM", -3: "PFMM_ED
 PROFILE_STAGES = ["permute", "s2m", "m2m", "m2l", "l2l", "l2t", "nearfield", "unpermute"]
 OP_V, OP_K = 1, 2
 FP64, MIXED_FP32 = 0, 1
+NF_STORED, NF_TOEPLITZ = 0, 1
 
 
 class PfmmError(RuntimeError):
@@ -30,7 +31,7 @@ class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("m_t", ctypes.c_int32), ("m_x", ctypes.c_int32),
                 ("n_max", ctypes.c_int32), ("c_st", ctypes.c_double), ("n_tr", ctypes.c_int32),
                 ("q_reg", ctypes.c_int32), ("q_sing", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("operators", ctypes.c_int32), ("check_finite", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("operators", ctypes.c_int32), ("check_finite", ctypes.c_int32), ("nearfield_mode", ctypes.c_int32),
                 ("device_mem_budget", ctypes.c_uint64)]
 
 
