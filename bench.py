@@ -189,10 +189,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="farfield precision: fp64, or fp32 (M2L with FP32 inputs and accumulation; "
                          "the error against the FP64 apply on the same tree is measured and reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-toeplitz", action="store_true", help="skip the Toeplitz-nearfield measurement")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--check-rows", type=int, default=0, help="compare this many sampled rows with the oracle")
@@ -218,7 +219,7 @@ def main():
 
     v, t, tn, c, w = config_problem(args.config)
     N = len(w)
-    mixed = args.precision == "fp32"
+    mixed = args.precision != "fp64"
     # the tree holds both farfield paths; the timed one is selected with set_precision
     prm = P.default_params(m_t=c["m_t"], m_x=c["m_x"], n_max=c["n_max"], c_st=c["c_st"], n_tr=c["n_tr"],
                            operators=1, precision=P.MIXED_FP32)
@@ -260,23 +261,64 @@ def main():
         return out, 1e3 * dt / steps, pr
 
     # timed region: the selected precision
-    f, ms_per_step, prof = timed(P.MIXED_FP32 if mixed else P.FP64, args.steps, args.warmup)
+    f, ms_per_step, prof = timed({"fp64": P.FP64, "fp32": P.MIXED_FP32, "bf16": P.MIXED_BF16}[args.precision],
+                                 args.steps, args.warmup)
     log(f"[bench] {args.steps} applies ({args.precision}): {ms_per_step:.3f} ms/apply; stages {prof}")
-    # the other precision on the same tree, and the measured error of the mixed mode
+    # the other farfield precisions on the same tree, with their measured error against FP64
     import numpy as np
-    g, ms_other, prof_other = timed(P.FP64 if mixed else P.MIXED_FP32, max(3, args.steps // 2), 1)
-    fm, fd = (f, g) if mixed else (g, f)
-    fm, fd = fm.cpu().numpy(), fd.cpu().numpy()
-    mixed_err = {"rel_2norm_vs_fp64": float(np.linalg.norm(fm - fd) / np.linalg.norm(fd)),
-                 "rel_max_vs_fp64": float(np.abs(fm - fd).max() / np.abs(fd).max())}
-    other = "fp64" if mixed else "fp32"
-    log(f"[bench] {other}: {ms_other:.3f} ms/apply; mixed vs FP64 on the same tree: {mixed_err}")
-    other_precision = {"precision": other, "ms_per_step": ms_other, "value": N / (ms_other * 1e-3),
-                       "m2l_ms": prof_other["m2l"][0] / max(prof_other["m2l"][1], 1),
-                       "mixed_error": mixed_err,
-                       "note": ("fp32: M2L with FP32 moments/operator entries and FP32 matrix-core accumulation, "
-                                "everything else FP64")}
-    tree.set_precision(P.MIXED_FP32 if mixed else P.FP64)
+    names = {"fp64": P.FP64, "fp32": P.MIXED_FP32, "bf16": P.MIXED_BF16}
+    outs = {args.precision: f.cpu().numpy()}
+    other_precision = {}
+    for name, code in names.items():
+        if name == args.precision:
+            continue
+        g, ms_o, prof_o = timed(code, max(3, args.steps // 2), 1)
+        outs[name] = g.cpu().numpy()
+        other_precision[name] = {"ms_per_step": ms_o, "value": N / (ms_o * 1e-3),
+                                 "m2l_ms": prof_o["m2l"][0] / max(prof_o["m2l"][1], 1)}
+    fd = outs["fp64"]
+    for name in ("fp32", "bf16"):
+        e = {"rel_2norm_vs_fp64": float(np.linalg.norm(outs[name] - fd) / np.linalg.norm(fd)),
+             "rel_max_vs_fp64": float(np.abs(outs[name] - fd).max() / np.abs(fd).max())}
+        if name in other_precision:
+            other_precision[name]["error"] = e
+        if name == args.precision:
+            mixed_err = e
+    if args.precision == "fp64":
+        mixed_err = None
+    other_precision["note"] = ("fp32: M2L with FP32 moments/operator entries and FP32 matrix-core accumulation; "
+                               "bf16: the same with moments, table and operator entries rounded to bfloat16 "
+                               "(exact products, FP32 accumulation); everything else FP64")
+    log(f"[bench] other precisions: {other_precision}")
+    tree.set_precision(names[args.precision])
+
+    # the same product with the Toeplitz nearfield (no stored blocks), on a tree of its own
+    toeplitz = None
+    if not args.no_toeplitz:
+        prm_t = P.default_params(m_t=c["m_t"], m_x=c["m_x"], n_max=c["n_max"], c_st=c["c_st"], n_tr=c["n_tr"],
+                                 operators=1, precision=P.MIXED_FP32, nearfield_mode=P.NF_TOEPLITZ)
+        tt = P.Tree(v, t, tn, prm_t, device=0, stream=stream)
+        tt.set_precision({"fp64": P.FP64, "fp32": P.MIXED_FP32, "bf16": P.MIXED_BF16}[args.precision])
+        ft = torch.empty_like(x)
+        for _ in range(max(1, args.warmup)):
+            tt.apply_V(x, out=ft, stream=stream)
+        torch.cuda.synchronize()
+        tt.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nt = max(3, args.steps // 2)
+        for _ in range(nt):
+            tt.apply_V(x, out=ft, stream=stream)
+        torch.cuda.synchronize()
+        ms_t = 1e3 * (time.perf_counter() - t0) / nt
+        pt = tt.profile_read()
+        toeplitz = {"ms_per_step": ms_t, "value": N / (ms_t * 1e-3),
+                    "nearfield_ms": pt["nearfield"][0] / max(pt["nearfield"][1], 1),
+                    "device_bytes": tt.stats()["device_bytes"], "bitwise_equal_to_stored": bool(torch.equal(ft, f)),
+                    "note": "nearfield entries read from the distinct integrals per (leaf spatial box, step "
+                            "difference) instead of stored blocks (uniform steps)"}
+        tt.close()
+        log(f"[bench] toeplitz nearfield: {toeplitz}")
 
     # roofline of the dominant kernel
     near_ms = prof["nearfield"][0] / max(prof["nearfield"][1], 1)
@@ -328,15 +370,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 M2L + f64" if mixed else "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32 M2L + f64", "bf16": "bf16-input M2L + f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": (f"V_h apply, cube [-1,1]^3 {c['n']}x{c['n']} squares/face ({len(t)} triangles) x "
                                 f"{c['n_steps']} uniform steps on [0,1], alpha=1, m_t={c['m_t']}, m_x={c['m_x']}, "
                                 f"n_max={c['n_max']}, c_st={c['c_st']}, n_tr={c['n_tr']}, "
-                                + ("M2L in FP32 (inputs and accumulation), rest FP64" if mixed else "FP64")),
+                                + {"fp64": "FP64", "fp32": "M2L in FP32 (inputs and accumulation), rest FP64",
+                                   "bf16": "M2L with BF16 inputs and FP32 accumulation, rest FP64"}[args.precision]),
                    "dofs": N, "parallelism": "single GPU", "precision": args.precision},
-        "mixed_error": mixed_err if mixed else None,
+        "mixed_error": mixed_err,
         "other_precision": other_precision,
+        "toeplitz_nearfield": toeplitz,
         "roofline": roof,
         "other_kernels": other,
         "stages_ms_per_apply": {k: (vv[0] / max(vv[1], 1)) for k, vv in prof.items()},

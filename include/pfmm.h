@@ -52,11 +52,15 @@ typedef enum {
 
 typedef enum {
     PFMM_FP64 = 0,           /* farfield and nearfield in FP64                 */
-    PFMM_MIXED_FP32 = 1      /* M2L (eq. m2l) with FP32 moments and operator
+    PFMM_MIXED_FP32 = 1,     /* M2L (eq. m2l) with FP32 moments and operator
                                 entries on FP32 matrix cores with FP32
                                 accumulation, on every level with >= 32 time
                                 intervals; nearfield, S2M, M2M, L2L, L2T, the
                                 locals and the final sum stay FP64           */
+    PFMM_MIXED_BF16 = 2      /* as PFMM_MIXED_FP32 with moments, table entries
+                                and operator entries rounded to bfloat16 (the
+                                products are exact in FP32, accumulation FP32):
+                                the error of BF16 matrix-core inputs          */
 } pfmm_precision;
 
 /* how the nearfield blocks (Section 3.4, eq. eval_sl_nf_block) are applied */
@@ -152,8 +156,8 @@ pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void*
 /*
  * Select the farfield precision of the following applies of t (and of the
  * solves, which call the same apply).  PFMM_FP64 is always available;
- * PFMM_MIXED_FP32 needs a tree built with precision PFMM_MIXED_FP32 (which
- * holds FP32 copies of the moments and tables in addition to the FP64 data).
+ * PFMM_MIXED_FP32 and PFMM_MIXED_BF16 need a tree built with either of them
+ * (which holds FP32 moments and FP32 / BF16 tables besides the FP64 data).
  * Not stream-ordered: call it between applies, not while one is being
  * enqueued.  Errors: PFMM_EINVAL (NULL tree, unknown precision, FP32 data
  * not built).

@@ -242,7 +242,10 @@ __global__ void __launch_bounds__(64 * kM2LWaves) k_m2l_mfma(
 
 // M2L on matrix cores, wide form for levels with >= 32 intervals, in FP64
 // (T = double, v_mfma_f64_16x16x4f64) or with FP32 moments and operator
-// tables and FP32 accumulation (T = float, v_mfma_f32_16x16x4f32).
+// tables and FP32 accumulation (T = float, v_mfma_f32_16x16x4f32).  With
+// RB = true (T = float) the moments and table entries are bfloat16 values and
+// every generated operator entry is rounded to bfloat16 before its product:
+// BF16 inputs with exact products and FP32 accumulation.
 //
 // The rows of eq. m2l (16-row tiles of the staircase) are partitioned into
 // row groups; a workgroup of WAVES waves owns one target slot X, one row
@@ -304,7 +307,14 @@ template <> struct M2LTraits<float> {
     }
 };
 
-template <class T, int NB, int MAXS, int WAVES>
+// Round to the nearest bfloat16 (ties to even), kept in an FP32 register.
+__device__ __forceinline__ float bf16_round(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+template <class T, int NB, int MAXS, int WAVES, bool RB = false>
 __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     const T* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
     const int* __restrict__ cls, const int* __restrict__ off3, const T* __restrict__ E1c, int TSp,
@@ -453,6 +463,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
                 const T z3 = *(const T*)(lds + (pZ[i] + d3 + col.z));
                 A2[i] = (x2 * y2) * (z2 * msk);
                 A3[i] = (x3 * y3) * (z3 * msk);
+                if constexpr (RB) {
+                    A2[i] = bf16_round(A2[i]);
+                    A3[i] = bf16_round(A3[i]);
+                }
             }
 #pragma unroll
             for (int i = 0; i < n; ++i)
@@ -547,10 +561,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
 
 // wide M2L variants (interval blocks, slots per wave, waves per workgroup):
 // [0] for levels with 32 intervals, [1] with a multiple of 64, [2] of 128
-// [precision: 0 FP64, 1 FP32][variant]
+// [precision: 0 FP64, 1 FP32, 2 BF16 inputs][variant]
 constexpr int kWideNB[3] = {1, 2, 4};
-constexpr int kWideMaxs[2][3] = {{2, 2, 1}, {2, 2, 2}};
-constexpr int kWideWaves[2][3] = {{16, 16, 16}, {16, 16, 16}};
+constexpr int kWideMaxs[3][3] = {{2, 2, 1}, {2, 2, 2}, {2, 2, 2}};
+constexpr int kWideWaves[3][3] = {{16, 16, 16}, {16, 16, 16}, {16, 16, 16}};
 constexpr bool kWideUseNB1 = true;   // levels with 32 intervals: wide form instead of k_m2l_mfma
 
 template <int Q, int V>
@@ -558,12 +572,13 @@ using WideT = std::conditional_t<Q == 0, double, float>;
 
 template <int Q, int V>
 const void* wide_fn() {
-    return (const void*)k_m2l_wide<WideT<Q, V>, kWideNB[V], kWideMaxs[Q][V], kWideWaves[Q][V]>;
+    return (const void*)k_m2l_wide<WideT<Q, V>, kWideNB[V], kWideMaxs[Q][V], kWideWaves[Q][V], Q == 2>;
 }
 
 const void* wide_fn(int q, int v) {
     if (q == 0) return v == 0 ? wide_fn<0, 0>() : (v == 1 ? wide_fn<0, 1>() : wide_fn<0, 2>());
-    return v == 0 ? wide_fn<1, 0>() : (v == 1 ? wide_fn<1, 1>() : wide_fn<1, 2>());
+    if (q == 1) return v == 0 ? wide_fn<1, 0>() : (v == 1 ? wide_fn<1, 1>() : wide_fn<1, 2>());
+    return v == 0 ? wide_fn<2, 0>() : (v == 1 ? wide_fn<2, 1>() : wide_fn<2, 2>());
 }
 
 template <int Q, int V>
@@ -571,7 +586,7 @@ void launch_wide(dim3 grid, size_t shm, hipStream_t st, const void* mu, double* 
                  const int* cls, const int* off3, const void* E1s, int TSp, const int* packinfo, const int* plan,
                  int plan_stride, int Nc, int n_int, int mt, int mx, int R, int nsplit, int ncb, double* lam_parts) {
     using T = WideT<Q, V>;
-    hipLaunchKernelGGL((k_m2l_wide<T, kWideNB[V], kWideMaxs[Q][V], kWideWaves[Q][V]>), grid,
+    hipLaunchKernelGGL((k_m2l_wide<T, kWideNB[V], kWideMaxs[Q][V], kWideWaves[Q][V], Q == 2>), grid,
                        dim3(64 * kWideWaves[Q][V]), shm, st, (const T*)mu, lam, ptr, src, cls, off3, (const T*)E1s,
                        TSp, packinfo, plan, plan_stride, Nc, n_int, mt, mx, R, nsplit, ncb, lam_parts);
 }
@@ -582,13 +597,15 @@ using WideLaunch = void (*)(dim3, size_t, hipStream_t, const void*, double*, con
 
 WideLaunch wide_launcher(int q, int v) {
     if (q == 0) return v == 0 ? launch_wide<0, 0> : (v == 1 ? launch_wide<0, 1> : launch_wide<0, 2>);
-    return v == 0 ? launch_wide<1, 0> : (v == 1 ? launch_wide<1, 1> : launch_wide<1, 2>);
+    if (q == 1) return v == 0 ? launch_wide<1, 0> : (v == 1 ? launch_wide<1, 1> : launch_wide<1, 2>);
+    return v == 0 ? launch_wide<2, 0> : (v == 1 ? launch_wide<2, 1> : launch_wide<2, 2>);
 }
 
-// FP32 copy of a level's moments for the mixed-precision M2L.
-__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+// FP32 copy of a level's moments for the mixed-precision M2L (rounded on to
+// bfloat16 values when bf16 is set).
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n, int bf16) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = (float)a[i];
+    if (i < n) b[i] = bf16 ? bf16_round((float)a[i]) : (float)a[i];
 }
 
 // Sum the per-share partial locals of a level whose interaction lists were

@@ -753,13 +753,14 @@ struct pfmm_tree {
     int n_partial = 0;            // split-K partial segments
     size_t m2l_shm = 0;           // dynamic LDS of the matrix-core M2L
     // wide matrix-core M2L: [0] two interval blocks / two slots, [1] four blocks / one slot
-    struct Wide { int* plan = nullptr; int G = 0, stride = 0; size_t shm = 0; bool ok = false; } wide[2][3];
+    struct Wide { int* plan = nullptr; int G = 0, stride = 0; size_t shm = 0; bool ok = false; } wide[3][3];
     int prec = PFMM_FP64;         // farfield precision of the next applies
-    bool has_f32 = false;         // FP32 moments and tables allocated (tree built in a mixed mode)
+    bool has_f32 = false;         // FP32/BF16 moments and tables allocated (tree built in a mixed mode)
     // wide M2L: compact 1D tables (entries with kappa + nu <= m_x per time pair),
     // rows [level][Delta][offset][x (C_ab folded in) | y,z] of TSc64 doubles / TSc32 floats
     double* E1c = nullptr;
     float* E1c32 = nullptr;
+    float* E1c16 = nullptr;       // the FP32 rows rounded to bfloat16 values
     int TSc64 = 0, TSc32 = 0;
     CoefMaps cm{};
     SepMaps sm{};
@@ -833,7 +834,7 @@ uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask, int pre
     for (int l = 2; l <= P.depth; ++l) {
         const FarLevel& L = F.lv[l];
         b += 2ull * L.nx * P.Nc * L.n_int * 8;        // mu, lambda
-        if (precision == PFMM_MIXED_FP32) b += (uint64_t)L.nx * P.Nc * L.n_int * 4;   // FP32 moments
+        if (precision != PFMM_FP64) b += (uint64_t)L.nx * P.Nc * L.n_int * 4;   // FP32 moments
         b += (uint64_t)L.n_off * 2 * F.op_size * 8;   // explicit M2L operators (upper bound: fallback path)
     }
     int nop = ((ops_mask & PFMM_OP_V) ? 1 : 0) + ((ops_mask & PFMM_OP_K) ? 1 : 0);
@@ -1273,7 +1274,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         const int TSc = (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 2) / 2 + P.m_x;
         t->TSc64 = (TSc + 127) / 128 * 128;
         t->TSc32 = (TSc + 255) / 256 * 256;
-        for (int q = 0; q < (t->has_f32 ? 2 : 1); ++q)
+        for (int q = 0; q < (t->has_f32 ? 3 : 1); ++q)
             for (int v = 0; v < 3; ++v) {
                 auto& W = t->wide[q][v];
                 const int maxs = kWideMaxs[q][v], waves = kWideWaves[q][v];
@@ -1331,6 +1332,14 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             for (size_t r = 0; r < nrows; ++r)
                 for (int i = 0; i < t->TSc64 && i < t->TSc32; ++i) E1f[r * t->TSc32 + i] = (float)E1c[r * t->TSc64 + i];
             PF_TRY(upload(t, &t->E1c32, E1f.data(), E1f.size()));
+            for (float& x : E1f) {   // nearest bfloat16, ties to even
+                uint32_t u;
+                std::memcpy(&u, &x, 4);
+                u += 0x7fffu + ((u >> 16) & 1u);
+                u &= 0xffff0000u;
+                std::memcpy(&x, &u, 4);
+            }
+            PF_TRY(upload(t, &t->E1c16, E1f.data(), E1f.size()));
         }
     }
     // levels
@@ -1367,7 +1376,8 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
                 D.m2l_nb[q] = 0;
                 if (t->mfma_slots && (q == 0 || t->has_f32)) {
                     for (int v = 2; v >= 0 && !D.m2l_nb[q]; --v)
-                        if (t->wide[q][v].ok && D.n_int % (32 * kWideNB[v]) == 0 && (v > 0 || kWideUseNB1))
+                        if (t->wide[q][v].ok && (q == 0 || t->wide[2][v].ok) && D.n_int % (32 * kWideNB[v]) == 0 &&
+                            (v > 0 || kWideUseNB1))
                             D.m2l_nb[q] = kWideNB[v];
                 }
                 if (D.m2l_nb[q]) {
@@ -1537,25 +1547,29 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         prof_begin(t, 3, st, ev);
         for (int l = 2; l <= P.depth; ++l) {
             DevLevel& D = t->lv[l];
-            const int q = (t->prec == PFMM_MIXED_FP32 && D.m2l_nb[1]) ? 1 : 0;
-            if (D.m2l_nb[q]) {
-                const int v = D.m2l_nb[q] == 4 ? 2 : (D.m2l_nb[q] == 2 ? 1 : 0);
+            // q: 0 FP64, 1 FP32, 2 BF16 inputs; the per-level choices of the two
+            // reduced precisions coincide (same kernel shapes), stored at index 1
+            const int q = (t->prec != PFMM_FP64 && D.m2l_nb[1]) ? (t->prec == PFMM_MIXED_BF16 ? 2 : 1) : 0;
+            const int ql = q > 0 ? 1 : 0;
+            if (D.m2l_nb[ql]) {
+                const int v = D.m2l_nb[ql] == 4 ? 2 : (D.m2l_nb[ql] == 2 ? 1 : 0);
                 const auto& W = t->wide[q][v];
-                const int nsplit = D.nsplit_q[q];
-                dim3 grid(W.G, D.nx, D.ncb[q] * nsplit);
+                const int nsplit = D.nsplit_q[ql];
+                dim3 grid(W.G, D.nx, D.ncb[ql] * nsplit);
                 const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
                 const int64_t row0 = D.e1s_off / t->TSp;   // first table row of the level
                 const void* m = D.mu;
                 const void* e1 = t->E1c + row0 * t->TSc64;
                 int tsp = t->TSc64;
-                if (q == 1) {
-                    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl);
+                if (q >= 1) {
+                    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl,
+                                       q == 2 ? 1 : 0);
                     m = D.mu32;
-                    e1 = t->E1c32 + row0 * t->TSc32;
+                    e1 = (q == 2 ? t->E1c16 : t->E1c32) + row0 * t->TSc32;
                     tsp = t->TSc32;
                 }
                 wide_launcher(q, v)(grid, W.shm, st, m, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3, e1, tsp,
-                                    t->packinfo, W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, nsplit, D.ncb[q],
+                                    t->packinfo, W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, nsplit, D.ncb[ql],
                                     D.lam_parts);
                 if (nsplit > 1)
                     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam,
@@ -1730,7 +1744,7 @@ pfmm_status pfmm_build_tree(const double* vertices, int64_t n_vertices, const in
         return fail(PFMM_ENOMEM, "tree needs " + std::to_string(need) + " device bytes, budget " + std::to_string(budget));
     hipStream_t st = as_stream(stream);
     t->prec = prm.precision;
-    t->has_f32 = prm.precision == PFMM_MIXED_FP32;
+    t->has_f32 = prm.precision == PFMM_MIXED_FP32 || prm.precision == PFMM_MIXED_BF16;
     t->nf_mode = prm.nearfield_mode;
     pfmm_status s = setup_device(t.get(), st, prm.operators);
     if (s != PFMM_OK) {
@@ -1758,9 +1772,9 @@ pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void*
 pfmm_status pfmm_set_precision(pfmm_tree* t, int32_t precision) {
     if (!t) return fail(PFMM_EINVAL, "NULL tree");
     if (precision == PFMM_FP64) { t->prec = PFMM_FP64; return PFMM_OK; }
-    if (precision == PFMM_MIXED_FP32) {
-        if (!t->has_f32) return fail(PFMM_EINVAL, "tree was not built with precision PFMM_MIXED_FP32");
-        t->prec = PFMM_MIXED_FP32;
+    if (precision == PFMM_MIXED_FP32 || precision == PFMM_MIXED_BF16) {
+        if (!t->has_f32) return fail(PFMM_EINVAL, "tree was not built in a mixed precision");
+        t->prec = precision;
         return PFMM_OK;
     }
     return fail(PFMM_EINVAL, "unknown precision");

@@ -85,7 +85,10 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
     if (!(p.c_st > 0) || !std::isfinite(p.c_st)) { msg = "c_st must be > 0"; return PFMM_EINVAL; }
     if (p.n_tr < -1) { msg = "n_tr must be >= -1"; return PFMM_EINVAL; }
     if (p.q_reg < 1 || p.q_reg > 16 || p.q_sing < 1 || p.q_sing > 16) { msg = "quadrature orders must be in [1,16]"; return PFMM_EINVAL; }
-    if (p.precision != PFMM_FP64 && p.precision != PFMM_MIXED_FP32) { msg = "unknown precision"; return PFMM_EINVAL; }
+    if (p.precision != PFMM_FP64 && p.precision != PFMM_MIXED_FP32 && p.precision != PFMM_MIXED_BF16) {
+        msg = "unknown precision";
+        return PFMM_EINVAL;
+    }
     if (p.operators & ~(PFMM_OP_V | PFMM_OP_K)) { msg = "unknown operator bits"; return PFMM_EINVAL; }
     if (p.nearfield_mode != PFMM_NF_STORED && p.nearfield_mode != PFMM_NF_TOEPLITZ) {
         msg = "unknown nearfield mode";

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_ENOMEM", -3: "PFMM_ED
                 -4: "PFMM_ENOTCONV", -5: "PFMM_ENONFINITE", -6: "PFMM_EUNSUPPORTED"}
 PROFILE_STAGES = ["permute", "s2m", "m2m", "m2l", "l2l", "l2t", "nearfield", "unpermute"]
 OP_V, OP_K = 1, 2
-FP64, MIXED_FP32 = 0, 1
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 NF_STORED, NF_TOEPLITZ = 0, 1
 
 

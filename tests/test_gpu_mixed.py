@@ -81,3 +81,28 @@ def test_precision_switch_errors():
         tree.set_precision(7)
     tree.set_precision(P.FP64)
     tree.close()
+
+
+@pytest.mark.parametrize("kind", ["V", "K"])
+def test_bf16_inputs_error_reported(kind):
+    """BF16 moments / operator entries (exact products, FP32 accumulation): the
+    error against FP64 is that of 8-bit significands; it is reported, and it is
+    checked to lie between the FP32 mode's and a loose upper bound."""
+    c = dict(CASES[1])
+    n, E_t = c.pop("n"), c.pop("E_t")
+    v, t, tn, w = problem(n, E_t, seed=23)
+    op = 1 if kind == "V" else 2
+    tree = P.Tree(v, t, tn, P.default_params(operators=op, precision=P.MIXED_BF16, **c), device=0)
+    x = torch.from_numpy(w).to("cuda:0")
+    fn = tree.apply_V if kind == "V" else tree.apply_K
+    out = {}
+    for name, code in (("fp64", P.FP64), ("fp32", P.MIXED_FP32), ("bf16", P.MIXED_BF16)):
+        tree.set_precision(code)
+        out[name] = fn(x).cpu().numpy()
+    tree.close()
+    e32 = np.linalg.norm(out["fp32"] - out["fp64"]) / np.linalg.norm(out["fp64"])
+    e16 = np.linalg.norm(out["bf16"] - out["fp64"]) / np.linalg.norm(out["fp64"])
+    print(f"[mixed] {kind}: rel 2-norm vs FP64: fp32 {e32:.3e}, bf16 {e16:.3e}", flush=True)
+    assert np.all(np.isfinite(out["bf16"]))
+    assert e32 <= MIXED_TOL
+    assert 10 * e32 < e16 < 1e-2
