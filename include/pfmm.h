@@ -250,6 +250,24 @@ pfmm_status pfmm_dirichlet_rhs(pfmm_tree* t, const double* g_dev, double* b_dev,
 pfmm_status pfmm_solve_dirichlet(pfmm_tree* t, const double* g_dev, double* w_dev, const pfmm_solve_opts* o,
                                  pfmm_solve_info* info, void* stream);
 
+/*
+ * Batches of independent problems (trees on one device, each holding V_h).
+ * pfmm_apply_V_batch computes f_i = V_h^(i) w_i for every tree i of the
+ * batch in one stream-ordered call: the applies are captured once into a HIP
+ * graph whose branches run on up to 8 internal streams (tree i on branch
+ * i mod 8, in batch order: put the largest problems first), and the graph is
+ * replayed while the vector pointers stay the same (new pointers re-capture).
+ * w_dev[i], f_dev[i]: device arrays of tree i's size, natural order, not
+ * aliasing.  The batch keeps pointers to the trees: destroy it before them.
+ * Stage profiling must be off for the trees of a batch.
+ * Errors: PFMM_EINVAL (NULL or empty, a tree without V_h, trees on different
+ * devices or repeated, profiling on), PFMM_ENOMEM, PFMM_EDEVICE.
+ */
+typedef struct pfmm_batch pfmm_batch;
+pfmm_status pfmm_batch_create(pfmm_tree* const* trees, int32_t n, pfmm_batch** out);
+pfmm_status pfmm_apply_V_batch(pfmm_batch* b, const double* const* w_dev, double* const* f_dev, void* stream);
+void pfmm_batch_destroy(pfmm_batch* b);
+
 /* Release every host and device resource of the tree.  NULL is a no-op. */
 void pfmm_destroy(pfmm_tree* t);
 

@@ -21,6 +21,9 @@ bool tree_has(const pfmm_tree* t, int op);        // PFMM_OP_V / PFMM_OP_K built
 // Diagonal of the p0 x p0 mass matrix per triangle, |gamma_k| h_t (device, E_x doubles).
 const double* tree_mass(const pfmm_tree* t);
 
+// Stage profiling (pfmm_profile_enable) switched on.
+bool tree_profiling(const pfmm_tree* t);
+
 // Stream-ordered applies without argument checks (natural order in and out).
 pfmm_status tree_apply(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st);
 

@@ -830,12 +830,17 @@ int dmax_class(int dmax) {
 uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask, int precision, int nf_mode) {
     uint64_t b = 0;
     const uint64_t N = (uint64_t)P.E_t * P.E_x;
+    // explicit M2L operators exist only on the vector-unit fallback (degrees
+    // above 15, or 1D tables too large for the matrix-core kernel's LDS)
+    const int TS = (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1);
+    const size_t shm = (size_t)6 * ((TS + 127) / 128 * 128) * 8 + (size_t)(((P.Nc + 3) & ~3) + 16) * 16;
+    const bool explicit_ops = P.m_t > 15 || P.m_x > 15 || shm > 163840;
     b += 2 * N * 8;                                   // w, f in tree order
     for (int l = 2; l <= P.depth; ++l) {
         const FarLevel& L = F.lv[l];
         b += 2ull * L.nx * P.Nc * L.n_int * 8;        // mu, lambda
         if (precision != PFMM_FP64) b += (uint64_t)L.nx * P.Nc * L.n_int * 4;   // FP32 moments
-        b += (uint64_t)L.n_off * 2 * F.op_size * 8;   // explicit M2L operators (upper bound: fallback path)
+        if (explicit_ops) b += (uint64_t)L.n_off * 2 * F.op_size * 8;
     }
     int nop = ((ops_mask & PFMM_OP_V) ? 1 : 0) + ((ops_mask & PFMM_OP_K) ? 1 : 0);
     b += (uint64_t)nop * ((nf_mode == PFMM_NF_STORED ? (uint64_t)P.near_entries * 8 : 0) + (uint64_t)P.table_size * 8);
@@ -1660,6 +1665,7 @@ pfmm_status set_error(pfmm_status s, const std::string& msg) { return fail(s, ms
 int tree_device(const pfmm_tree* t) { return t->device; }
 int64_t tree_dofs(const pfmm_tree* t) { return (int64_t)t->P.E_t * t->P.E_x; }
 int64_t tree_triangles(const pfmm_tree* t) { return t->P.E_x; }
+bool tree_profiling(const pfmm_tree* t) { return t->prof; }
 bool tree_has(const pfmm_tree* t, int op) { return op == PFMM_OP_V ? t->hasV : (op == PFMM_OP_K ? t->hasK : false); }
 const double* tree_mass(const pfmm_tree* t) { return t->mass; }
 pfmm_status tree_apply(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st) { return apply(t, K, x, y, st); }

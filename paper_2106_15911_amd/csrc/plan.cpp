@@ -516,6 +516,12 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         }
     }
     P.near_entries = boff;
+    for (const LeafRec& R : P.leaves)
+        if (R.te - R.tb > 64) {
+            // the nearfield kernels give each row of a leaf one lane of a wave
+            msg = "a leaf holds more than 64 triangles (lower n_max or use more time steps)";
+            return PFMM_EUNSUPPORTED;
+        }
 
     // ------------------------------------------------------------ assembly groups
     {

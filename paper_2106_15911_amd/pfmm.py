@@ -87,6 +87,9 @@ def load_library():
         "pfmm_solve_dirichlet": ([VP, VP, VP, P(SolveOpts), P(SolveInfo), VP], I32),
         "pfmm_dirichlet_rhs": ([VP, VP, VP, VP], I32),
         "pfmm_destroy": ([VP], None),
+        "pfmm_batch_create": ([P(VP), I32, P(VP)], I32),
+        "pfmm_apply_V_batch": ([VP, P(VP), P(VP), VP], I32),
+        "pfmm_batch_destroy": ([VP], None),
         "pfmm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -227,6 +230,45 @@ class Tree:
     def close(self):
         if getattr(self, "handle", None):
             self.lib.pfmm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent trees (same device) applied together: apply_V(ws) returns
+    [V_h^(i) w_i]; the applies run as one captured HIP graph (re-captured when
+    the output/input tensors change)."""
+
+    def __init__(self, trees):
+        self.lib = load_library()
+        self.trees = list(trees)
+        arr = (ctypes.c_void_p * len(self.trees))(*[t.handle.value for t in self.trees])
+        h = ctypes.c_void_p()
+        _check(self.lib.pfmm_batch_create(arr, len(self.trees), ctypes.byref(h)))
+        self.handle = h
+
+    def apply_V(self, ws, outs=None, stream=None):
+        import torch
+        if len(ws) != len(self.trees):
+            raise ValueError("one density per tree")
+        for t, x in zip(self.trees, ws):
+            if x.dtype != torch.float64 or x.device != t.device or x.numel() != t.n_dofs or not x.is_contiguous():
+                raise ValueError(f"expected a contiguous float64 tensor of {t.n_dofs} entries on {t.device}")
+        if outs is None:
+            outs = [torch.empty_like(x) for x in ws]
+        wp = (ctypes.c_void_p * len(ws))(*[x.data_ptr() for x in ws])
+        fp = (ctypes.c_void_p * len(ws))(*[y.data_ptr() for y in outs])
+        _check(self.lib.pfmm_apply_V_batch(self.handle, wp, fp, _stream_ptr(stream)))
+        return outs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pfmm_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -5,6 +5,6 @@ random densities.  It contains none of the boundary-element or fast-multipole
 arithmetic, so that the CPU oracle and the GPU path can be fed identical
 inputs without sharing any computation.
 """
-from .cube import cube_surface_mesh, uniform_time_nodes, densities, CONFIGS, config_problem
+from .cube import cube_surface_mesh, uniform_time_nodes, densities, CONFIGS, config_problem, batch_sizes
 
-__all__ = ["cube_surface_mesh", "uniform_time_nodes", "densities", "CONFIGS", "config_problem"]
+__all__ = ["cube_surface_mesh", "uniform_time_nodes", "densities", "CONFIGS", "config_problem", "batch_sizes"]

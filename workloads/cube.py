@@ -89,3 +89,16 @@ def config_problem(cfg_id):
     t = uniform_time_nodes(c["n_steps"])
     w = densities(c["n_steps"] * len(tris), c["seed"])
     return verts, tris, t, c, w
+
+
+def batch_sizes(seed=4, count=48):
+    """The batched workload: `count` independent cube problems with face grids
+    n ~ U{4..32} and step counts E_t ~ U{32..512}, drawn in that order from
+    default_rng(seed).  Returns [(n, E_t)]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(4, 33))
+        e = int(rng.integers(32, 513))
+        out.append((n, e))
+    return out
