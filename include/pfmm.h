@@ -209,6 +209,8 @@ typedef struct {
                                     before iteration 1 (= 1) and after every iteration; NULL = none */
     int32_t history_cap;         /* entries available in history                              */
     int32_t history_len;         /* entries written                                            */
+    int32_t outer;               /* pfmm_solve_V_precond: refinement steps (FP64 residuals)    */
+    int32_t precond_fallback;    /* pfmm_solve_V_precond: 1 if it fell back to plain GMRES     */
 } pfmm_solve_info;
 
 /* Fill *out with the defaults above.  Returns PFMM_EINVAL on NULL. */
@@ -267,6 +269,64 @@ typedef struct pfmm_batch pfmm_batch;
 pfmm_status pfmm_batch_create(pfmm_tree* const* trees, int32_t n, pfmm_batch** out);
 pfmm_status pfmm_apply_V_batch(pfmm_batch* b, const double* const* w_dev, double* const* f_dev, void* stream);
 void pfmm_batch_destroy(pfmm_batch* b);
+
+/*
+ * Learned temporal-block preconditioner (not part of the paper, whose GMRES
+ * is unpreconditioned).  A small FP32 perceptron N (3 x features -> hidden
+ * -> hidden -> 1, tanh, no biases) maps the local space-time neighbourhood
+ * of a residual r to the correction z(j, k) = s N(x): with u = r / (D s)
+ * (D the diagonal of V_h, s the root mean square of r / D), for each lag
+ * f < features the inputs are u(step j - f, k), the mean of u(j - f, .)
+ * over the 3 edge neighbours of triangle k and its mean over their own
+ * neighbours other than k.  The weights are independent of the mesh, so a
+ * preconditioner trained on one tree can be applied on another.
+ *
+ * pfmm_precond_create: random (Glorot-uniform, seeded) weights on a device;
+ *   features (time lags) 1..32, hidden 1..256.
+ * pfmm_precond_train: runs a plain FP64 GMRES solve of V_h x = b on tree t
+ *   to 1e-10, takes x_k at n_snap iterations spread over the solve and
+ *   n_snap of its Krylov basis vectors v_j, forms the pairs
+ *   (r = V_h e, e) for e = x* - x_k and e = v_j, and fits N to them (mean squared error of
+ *   the pairs normalised by their r, Adam, `steps` minibatches of `batch`
+ *   samples, learning rate lr, seeded sampling).  Synchronous; allocates its
+ *   workspace for the call.  final_loss (may be NULL) gets the last batch's
+ *   loss.
+ * pfmm_precond_apply: z = s N(x(v)) for one vector v on tree t (device,
+ *   natural order, v and z distinct); synchronous on `stream`.
+ * pfmm_precond_save / _load: a small binary file of the weights: four int32
+ *   (0x4d4c5031, version 3, features, hidden), then W1 (3 features x hidden,
+ *   row-major, input index 3 f + ring), W2 (hidden x hidden, row-major, input
+ *   first) and w3 (hidden), all FP32 little-endian.
+ * Errors: PFMM_EINVAL, PFMM_ENOMEM, PFMM_EDEVICE, PFMM_ENOTCONV (training
+ *   solve did not converge).
+ */
+typedef struct pfmm_precond pfmm_precond;
+pfmm_status pfmm_precond_create(int32_t device, int32_t features, int32_t hidden, uint64_t seed, pfmm_precond** out);
+pfmm_status pfmm_precond_train(pfmm_precond* pc, pfmm_tree* t, const double* b_dev, int32_t n_snap, int32_t steps,
+                               int32_t batch, float lr, uint64_t seed, float* final_loss, void* stream);
+pfmm_status pfmm_precond_apply(const pfmm_precond* pc, pfmm_tree* t, const double* v_dev, double* z_dev,
+                               void* stream);
+pfmm_status pfmm_precond_save(const pfmm_precond* pc, const char* path);
+pfmm_status pfmm_precond_load(const char* path, int32_t device, pfmm_precond** out);
+void pfmm_precond_destroy(pfmm_precond* pc);
+
+/*
+ * Solve V_h w = b by iterative refinement in FP64 around flexible GMRES
+ * (right preconditioning with pc, or none when pc is NULL), the inner
+ * products applied in the farfield precision `inner_precision`
+ * (pfmm_precision; the reduced ones need a mixed tree).  Every refinement
+ * step computes the true residual b - V_h w with the FP64 apply; the solve
+ * stops when its norm relative to ||b|| reaches o->rtol, and it is judged by
+ * that FP64 residual only.  Each inner solve stops at a relative reduction
+ * of 1e-4 (or max_iter inner iterations).  If a refinement step fails to
+ * halve the FP64 residual, the solve falls back to plain FP64 GMRES from the
+ * current iterate (info->precond_fallback = 1).  info->iters counts all
+ * inner iterations (V_h applies), info->outer the refinement steps.  The
+ * tree's precision setting is restored on return.  Workspace: about
+ * 2 (max_iter + 1) vectors for the call.  Errors as pfmm_solve_V.
+ */
+pfmm_status pfmm_solve_V_precond(pfmm_tree* t, const pfmm_precond* pc, int32_t inner_precision, const double* b_dev,
+                                 double* w_dev, const pfmm_solve_opts* o, pfmm_solve_info* info, void* stream);
 
 /* Release every host and device resource of the tree.  NULL is a no-op. */
 void pfmm_destroy(pfmm_tree* t);

@@ -4,10 +4,10 @@ Dirichlet solve).
 The compute path lives in the HIP library ``libpfmm.so`` (see include/pfmm.h);
 this package only loads it and marshals arguments.
 """
-from .pfmm import (PfmmError, Params, SolveOpts, SolveInfo, Tree, Batch, default_params, plan_stats, lib_path,
+from .pfmm import (PfmmError, Params, SolveOpts, SolveInfo, Tree, Batch, Precond, default_params, plan_stats, lib_path,
                    load_library, STATUS_NAMES, PROFILE_STAGES, FP64, MIXED_FP32, MIXED_BF16, NF_STORED,
                    NF_TOEPLITZ)
 
-__all__ = ["PfmmError", "Params", "SolveOpts", "SolveInfo", "Tree", "Batch", "default_params", "plan_stats", "lib_path",
+__all__ = ["PfmmError", "Params", "SolveOpts", "SolveInfo", "Tree", "Batch", "Precond", "default_params", "plan_stats", "lib_path",
            "load_library", "STATUS_NAMES", "PROFILE_STAGES", "FP64", "MIXED_FP32", "MIXED_BF16", "NF_STORED",
            "NF_TOEPLITZ"]

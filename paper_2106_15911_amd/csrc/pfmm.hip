@@ -680,6 +680,21 @@ __global__ void __launch_bounds__(256) k_near_expand(double* __restrict__ B, con
 
 #include "near_apply.hpp"
 
+// Diagonal entries V_h[(j, k), (j, k)] (d = 0, the triangle with itself) per
+// triangle, natural order: one wave per leaf, lane = row of the leaf.
+__global__ void __launch_bounds__(256) k_near_diag(const double* __restrict__ table, const GroupDev* __restrict__ groups,
+                                                   const int* __restrict__ umap, NearLayout L, int n_leaves,
+                                                   const int* __restrict__ inv_sigma, double* __restrict__ diag) {
+    const int leaf = blockIdx.x * 4 + threadIdx.x / kWave, r = threadIdx.x % kWave;
+    if (leaf >= n_leaves) return;
+    const int nX = L.lf_nx[leaf];
+    if (r >= nX) return;
+    const GroupDev gr = groups[L.lf_group[leaf]];
+    const int pos = L.lf_tb[leaf] + r;
+    const int u = umap[gr.mapoff + pos];
+    if (u >= 0) diag[inv_sigma[pos]] = table[gr.toff + (int64_t)u * nX + r];
+}
+
 
 }  // namespace
 
@@ -735,6 +750,7 @@ struct pfmm_tree {
     uint64_t bytes = 0;
     // device data
     int* sigma = nullptr;
+    int* adj = nullptr;           // E_x x 3 edge neighbours (natural order)
     int* inv_sigma = nullptr;
     double* wd = nullptr;
     double* fd = nullptr;
@@ -1072,6 +1088,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
     const int64_t N = (int64_t)P.E_t * P.E_x;
     PF_TRY(upload(t, &t->sigma, P.sigma.data(), P.sigma.size()));
     PF_TRY(upload(t, &t->inv_sigma, P.inv_sigma.data(), P.inv_sigma.size()));
+    PF_TRY(upload(t, &t->adj, P.adj.data(), P.adj.size()));
     PF_TRY(dalloc(t, &t->wd, (size_t)N));
     PF_TRY(dalloc(t, &t->fd, (size_t)N));
     {
@@ -1666,6 +1683,19 @@ int tree_device(const pfmm_tree* t) { return t->device; }
 int64_t tree_dofs(const pfmm_tree* t) { return (int64_t)t->P.E_t * t->P.E_x; }
 int64_t tree_triangles(const pfmm_tree* t) { return t->P.E_x; }
 bool tree_profiling(const pfmm_tree* t) { return t->prof; }
+int tree_precision(const pfmm_tree* t) { return t->prec; }
+const int* tree_sigma(const pfmm_tree* t) { return t->sigma; }
+const int* tree_inv_sigma(const pfmm_tree* t) { return t->inv_sigma; }
+const int* tree_adjacency(const pfmm_tree* t) { return t->adj; }
+
+pfmm_status tree_near_diag(pfmm_tree* t, double* d_dev, hipStream_t st) {
+    if (!t->hasV) return fail(PFMM_EINVAL, "V_h was not built for this tree");
+    const int nl = (int)t->P.leaves.size();
+    hipLaunchKernelGGL(k_near_diag, dim3((unsigned)((nl + 3) / 4)), dim3(256), 0, st, t->opV.table, t->groups,
+                       t->umap, t->nl, (int)t->P.leaves.size(), t->inv_sigma, d_dev);
+    HIP_TRY(hipGetLastError());
+    return PFMM_OK;
+}
 bool tree_has(const pfmm_tree* t, int op) { return op == PFMM_OP_V ? t->hasV : (op == PFMM_OP_K ? t->hasK : false); }
 const double* tree_mass(const pfmm_tree* t) { return t->mass; }
 pfmm_status tree_apply(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st) { return apply(t, K, x, y, st); }

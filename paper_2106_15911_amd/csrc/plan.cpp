@@ -141,18 +141,23 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
     }
     // closed, consistently oriented surface: every directed edge appears once
     // and its reverse appears once
+    // (the triangle across each edge gives the edge adjacency)
     {
-        std::unordered_map<uint64_t, int> dir;
+        std::unordered_map<uint64_t, int> dir;   // directed edge -> triangle
         dir.reserve(6 * nt);
         for (int i = 0; i < E_x; ++i)
             for (int e = 0; e < 3; ++e) {
                 uint64_t a = (uint32_t)P.tris[3 * i + e], b = (uint32_t)P.tris[3 * i + (e + 1) % 3];
-                if (++dir[(a << 32) | b] > 1) { msg = "mesh is not consistently oriented (repeated directed edge)"; return PFMM_EINVAL; }
+                if (!dir.emplace((a << 32) | b, i).second) { msg = "mesh is not consistently oriented (repeated directed edge)"; return PFMM_EINVAL; }
             }
-        for (auto& kv : dir) {
-            uint64_t a = kv.first >> 32, b = kv.first & 0xffffffffu;
-            if (dir.find((b << 32) | a) == dir.end()) { msg = "mesh is not closed (boundary edge)"; return PFMM_EINVAL; }
-        }
+        P.adj.assign(3 * (size_t)E_x, -1);
+        for (int i = 0; i < E_x; ++i)
+            for (int e = 0; e < 3; ++e) {
+                uint64_t a = (uint32_t)P.tris[3 * i + e], b = (uint32_t)P.tris[3 * i + (e + 1) % 3];
+                auto it = dir.find((b << 32) | a);
+                if (it == dir.end()) { msg = "mesh is not closed (boundary edge)"; return PFMM_EINVAL; }
+                P.adj[3 * i + e] = it->second;
+            }
     }
     double lo[3], hi[3];
     for (int j = 0; j < 3; ++j) { lo[j] = P.verts[j]; hi[j] = P.verts[j]; }

@@ -74,6 +74,7 @@ struct Plan {
     double c_st = 0.9;
     std::vector<double> verts;          // n_vert x 3
     std::vector<int> tris;              // E_x x 3 (natural order)
+    std::vector<int> adj;               // E_x x 3: triangle across edge (v_e, v_{e+1})
     std::vector<double> tnodes;         // E_t + 1
 
     // geometry (natural triangle order)

@@ -12,6 +12,7 @@
 // which reads m+3 doubles per iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -154,8 +155,10 @@ void multidot(Workspace& ws, const double* V, int64_t ld, int ncols, const doubl
     hipLaunchKernelGGL(k_sum_partials, dim3(ncols), dim3(kBlock), 0, st, ws.partial, nb, dst);
 }
 
+// snaps (optional, ascending): iterations k at which x_k = V_k y_k is formed
+// into snap_x + i n (the training pairs of the learned preconditioner).
 pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opts& o, pfmm_solve_info* info,
-                  Workspace& ws, hipStream_t st) {
+                  Workspace& ws, hipStream_t st, const std::vector<int>* snaps = nullptr, double* snap_x = nullptr) {
     const int64_t n = tree_dofs(t);
     const int m = o.max_iter;
     const int64_t ld = n;
@@ -226,6 +229,20 @@ pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opt
         k = j + 1;
         est = std::fabs(e[j + 1]) / beta;
         record(est);
+        if (snaps)
+            for (size_t si = 0; si < snaps->size(); ++si)
+                if ((*snaps)[si] == k) {
+                    std::vector<double> ys(k);
+                    for (int i = k - 1; i >= 0; --i) {
+                        double sum = e[i];
+                        for (int l = i + 1; l < k; ++l) sum -= Hij(i, l) * ys[l];
+                        ys[i] = sum / Hij(i, i);
+                    }
+                    HIP_CHECK(hipMemcpyAsync(ws.coef, ys.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+                    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kBlock), 0, st, ws.basis, ld, k, ws.coef,
+                                       1.0, (const double*)nullptr, snap_x + (int64_t)si * n, n);
+                    HIP_CHECK(hipStreamSynchronize(st));   // ys is released at the end of this block
+                }
         if (est <= o.rtol || hn == 0.0) break;
     }
     // x = V_k y with the triangular solve R y = e
@@ -254,6 +271,190 @@ pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opt
     if (est > o.rtol)
         return set_error(PFMM_ENOTCONV, "GMRES reached max_iter = " + std::to_string(m) +
                                             " with relative residual " + std::to_string(est));
+    return PFMM_OK;
+}
+
+// Flexible GMRES (right preconditioning z_j = M(v_j), Saad 1993) for
+// A d = r with A the tree's apply in its current precision, from d = 0,
+// stopping at a relative reduction inner_rtol or m iterations.  Z and the
+// basis live in ws (allocated by the caller).  iters += iterations done.
+pfmm_status fgmres(pfmm_tree* t, const pfmm_precond* pc, const double* D, const double* r, double* d,
+                   double inner_rtol, int m, Workspace& ws, double* Z, double* part, hipStream_t st, int& iters) {
+    const int64_t n = tree_dofs(t);
+    const int64_t ld = n;
+    const int nb = (int)std::min<int64_t>(kMaxBlocks, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), e(m + 2, 0.0), hbuf(2 * (m + 1) + 1);
+    auto Hij = [&](int i, int j) -> double& { return H[(size_t)j * (m + 1) + i]; };
+    multidot(ws, r, ld, 1, r, n, nb, ws.col, st);
+    HIP_CHECK(hipMemcpyAsync(hbuf.data(), ws.col, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    const double beta = std::sqrt(hbuf[0]);
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, r, d, 0.0, n);
+    if (!(beta > 0.0)) return std::isfinite(beta) ? PFMM_OK : set_error(PFMM_ENONFINITE, "residual not finite");
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, r, ws.basis, 1.0 / beta, n);
+    e[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+        double* vj = ws.basis + (int64_t)j * ld;
+        double* zj = Z + (int64_t)j * ld;
+        double* w = ws.basis + (int64_t)(j + 1) * ld;
+        if (pc)
+            PS_TRY(precond_apply(pc, vj, zj, D, tree_adjacency(t), tree_triangles(t), n, part, st));
+        else hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, vj, zj, 1.0, n);
+        PS_TRY(tree_apply(t, false, zj, w, st));
+        for (int pass = 0; pass < 2; ++pass) {
+            double* h = ws.col + pass * (m + 1);
+            multidot(ws, ws.basis, ld, j + 1, w, n, nb, h, st);
+            hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kBlock), 0, st, ws.basis, ld, j + 1, h, -1.0,
+                               w, w, n);
+        }
+        multidot(ws, w, ld, 1, w, n, nb, ws.col + 2 * (m + 1), st);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipMemcpyAsync(hbuf.data(), ws.col, hbuf.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        for (int i = 0; i <= j; ++i) Hij(i, j) = hbuf[i] + hbuf[(m + 1) + i];
+        const double hn = std::sqrt(hbuf[2 * (m + 1)]);
+        if (!std::isfinite(hn)) return set_error(PFMM_ENONFINITE, "non-finite value in the flexible Arnoldi process");
+        Hij(j + 1, j) = hn;
+        if (hn > 0.0) hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, w, w, 1.0 / hn, n);
+        for (int i = 0; i < j; ++i) {
+            const double a = Hij(i, j), c = Hij(i + 1, j);
+            Hij(i, j) = cs[i] * a + sn[i] * c;
+            Hij(i + 1, j) = -sn[i] * a + cs[i] * c;
+        }
+        const double rr = std::hypot(Hij(j, j), Hij(j + 1, j));
+        if (!(rr > 0.0)) break;   // breakdown: keep what was built
+        cs[j] = Hij(j, j) / rr;
+        sn[j] = Hij(j + 1, j) / rr;
+        Hij(j, j) = rr;
+        Hij(j + 1, j) = 0.0;
+        e[j + 1] = -sn[j] * e[j];
+        e[j] = cs[j] * e[j];
+        k = j + 1;
+        ++iters;
+        if (std::fabs(e[j + 1]) / beta <= inner_rtol || hn == 0.0) break;
+    }
+    std::vector<double> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+        double sum = e[i];
+        for (int l = i + 1; l < k; ++l) sum -= Hij(i, l) * y[l];
+        y[i] = sum / Hij(i, i);
+    }
+    if (k > 0) {
+        HIP_CHECK(hipMemcpyAsync(ws.coef, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kBlock), 0, st, Z, ld, k, ws.coef, 1.0,
+                           (const double*)nullptr, d, n);
+    }
+    HIP_CHECK(hipStreamSynchronize(st));
+    return PFMM_OK;
+}
+
+// ||v||_2 (device vector) on the host, through the multi-dot kernels.
+pfmm_status norm2(Workspace& ws, const double* v, int64_t n, hipStream_t st, double& out) {
+    const int nb = (int)std::min<int64_t>(kMaxBlocks, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
+    multidot(ws, v, n, 1, v, n, nb, ws.col, st);
+    double h = 0.0;
+    HIP_CHECK(hipMemcpyAsync(&h, ws.col, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    out = std::sqrt(h);
+    return PFMM_OK;
+}
+
+// Iterative refinement in FP64 around flexible GMRES (see pfmm_solve_V_precond).
+pfmm_status solve_ir(pfmm_tree* t, const pfmm_precond* pc, int inner_prec, const double* b, double* x,
+                     const pfmm_solve_opts& o, pfmm_solve_info* info, hipStream_t st) {
+    const int64_t n = tree_dofs(t);
+    const int m = o.max_iter;
+    Workspace ws;
+    double *Z, *r, *dvec, *D = nullptr, *part;
+    PS_TRY(ws.alloc(&ws.basis, (size_t)(m + 1) * n));
+    PS_TRY(ws.alloc(&Z, (size_t)m * n));
+    PS_TRY(ws.alloc(&ws.partial, (size_t)kMaxBlocks * (m + 1)));
+    PS_TRY(ws.alloc(&ws.col, (size_t)2 * (m + 1) + 1));
+    PS_TRY(ws.alloc(&ws.coef, (size_t)m + 1));
+    PS_TRY(ws.alloc(&r, (size_t)n));
+    PS_TRY(ws.alloc(&dvec, (size_t)n));
+    PS_TRY(ws.alloc(&part, 1024));
+    if (pc) {
+        PS_TRY(ws.alloc(&D, (size_t)tree_triangles(t)));
+        PS_TRY(tree_near_diag(t, D, st));
+    }
+    if (info) { info->history_len = 0; info->iters = 0; info->outer = 0; info->precond_fallback = 0; }
+    auto record = [&](double v) {
+        if (info && info->history && info->history_len < info->history_cap) info->history[info->history_len++] = v;
+    };
+    double nb_ = 0.0;
+    PS_TRY(norm2(ws, b, n, st, nb_));
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, x, 0.0, n);
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, r, 1.0, n);
+    if (!std::isfinite(nb_)) return set_error(PFMM_ENONFINITE, "right-hand side is not finite");
+    if (!(nb_ > 0.0)) {
+        if (info) { info->converged = 1; info->rel_residual = 0.0; info->true_rel_residual = 0.0; }
+        return PFMM_OK;
+    }
+    const int saved = tree_precision(t);
+    int iters = 0, outer = 0;
+    double res = 1.0, prev = 2.0;
+    pfmm_status status = PFMM_OK;
+    bool fallback = false;
+    while (true) {
+        record(res);
+        if (res <= o.rtol || iters >= m * 20) break;
+        if (res > 0.5 * prev) { fallback = true; break; }
+        prev = res;
+        (void)pfmm_set_precision(t, inner_prec);
+        status = fgmres(t, pc, D, r, dvec, std::max(1e-4, 0.5 * o.rtol / res), m, ws, Z, part, st, iters);
+        (void)pfmm_set_precision(t, PFMM_FP64);
+        if (status != PFMM_OK) break;
+        // x += d; r = b - V_h x (FP64)
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, dvec, dvec, -1.0, n);
+        hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, dvec, x, n);
+        status = tree_apply(t, false, x, r, st);
+        if (status != PFMM_OK) break;
+        hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, r, n);           // r = V x - b
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, r, r, -1.0, n);   // r = b - V x
+        ++outer;
+        double rn = 0.0;
+        status = norm2(ws, r, n, st, rn);
+        if (status != PFMM_OK) break;
+        res = rn / nb_;
+        if (!std::isfinite(res)) { status = set_error(PFMM_ENONFINITE, "non-finite residual"); break; }
+    }
+    (void)pfmm_set_precision(t, saved);
+    if (status != PFMM_OK) return status;
+    if (fallback) {
+        // plain FP64 GMRES on the current residual: x += V_h^{-1} r
+        (void)pfmm_set_precision(t, PFMM_FP64);
+        Workspace w2;
+        pfmm_solve_opts o2 = o;
+        o2.rtol = std::min(1.0, o.rtol / res);
+        pfmm_solve_info i2{};
+        status = gmres(t, r, dvec, o2, &i2, w2, st);
+        (void)pfmm_set_precision(t, saved);
+        if (status != PFMM_OK && status != PFMM_ENOTCONV) return status;
+        iters += i2.iters;
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, dvec, dvec, -1.0, n);
+        hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, dvec, x, n);
+        (void)pfmm_set_precision(t, PFMM_FP64);
+        status = tree_apply(t, false, x, r, st);
+        (void)pfmm_set_precision(t, saved);
+        if (status != PFMM_OK) return status;
+        hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, r, n);
+        double rn = 0.0;
+        PS_TRY(norm2(ws, r, n, st, rn));
+        res = rn / nb_;
+        record(res);
+    }
+    if (info) {
+        info->iters = iters;
+        info->outer = outer;
+        info->precond_fallback = fallback ? 1 : 0;
+        info->rel_residual = res;
+        info->true_rel_residual = res;
+        info->converged = res <= o.rtol ? 1 : 0;
+    }
+    if (res > o.rtol)
+        return set_error(PFMM_ENOTCONV, "preconditioned solve stopped at relative residual " + std::to_string(res));
     return PFMM_OK;
 }
 
@@ -329,6 +530,120 @@ pfmm_status pfmm_solve_V(pfmm_tree* t, const double* b_dev, double* w_dev, const
 pfmm_status pfmm_solve_dirichlet(pfmm_tree* t, const double* g_dev, double* w_dev, const pfmm_solve_opts* o,
                                  pfmm_solve_info* info, void* stream) {
     return solve_common(t, g_dev, w_dev, o, info, stream, true);
+}
+
+pfmm_status pfmm_solve_V_precond(pfmm_tree* t, const pfmm_precond* pc, int32_t inner_precision, const double* b_dev,
+                                 double* w_dev, const pfmm_solve_opts* o, pfmm_solve_info* info, void* stream) {
+    if (!t || !b_dev || !w_dev) return set_error(PFMM_EINVAL, "NULL argument");
+    if (!tree_has(t, PFMM_OP_V)) return set_error(PFMM_EINVAL, "V_h was not built for this tree");
+    pfmm_solve_opts opt;
+    PS_TRY(check_opts(o, opt));
+    if (hipSetDevice(tree_device(t)) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
+    // the inner precision must be available on this tree
+    const int saved = tree_precision(t);
+    PS_TRY(pfmm_set_precision(t, inner_precision));
+    (void)pfmm_set_precision(t, saved);
+    const int64_t n = tree_dofs(t);
+    size_t fr = 0, tot = 0;
+    HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    const uint64_t need = (2 * (uint64_t)opt.max_iter + 4) * n * 8 + (uint64_t)kMaxBlocks * (opt.max_iter + 1) * 8;
+    if (need > fr)
+        return set_error(PFMM_ENOMEM, "solve workspace needs " + std::to_string(need) + " bytes, " +
+                                          std::to_string(fr) + " free (lower max_iter)");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    pfmm_status s = solve_ir(t, pc, inner_precision, b_dev, w_dev, opt, info, st);
+    const hipError_t e = hipStreamSynchronize(st);
+    if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (s == PFMM_OK && e != hipSuccess) return set_error(PFMM_EDEVICE, hipGetErrorString(e));
+    return s;
+}
+
+pfmm_status pfmm_precond_apply(const pfmm_precond* pc, pfmm_tree* t, const double* v_dev, double* z_dev,
+                               void* stream) {
+    if (!pc || !t || !v_dev || !z_dev) return set_error(PFMM_EINVAL, "NULL argument");
+    if (!tree_has(t, PFMM_OP_V)) return set_error(PFMM_EINVAL, "V_h was not built for this tree");
+    if (v_dev == z_dev) return set_error(PFMM_EINVAL, "v and z must not alias");
+    if (hipSetDevice(tree_device(t)) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    Workspace ws;
+    double *D, *part;
+    pfmm_status s = ws.alloc(&D, (size_t)tree_triangles(t));
+    if (s == PFMM_OK) s = ws.alloc(&part, 1024);
+    if (s == PFMM_OK) s = tree_near_diag(t, D, st);
+    if (s == PFMM_OK) s = precond_apply(pc, v_dev, z_dev, D, tree_adjacency(t), tree_triangles(t), tree_dofs(t), part, st);
+    if (s == PFMM_OK && hipStreamSynchronize(st) != hipSuccess) s = set_error(PFMM_EDEVICE, "hipStreamSynchronize failed");
+    return s;
+}
+
+pfmm_status pfmm_precond_train(pfmm_precond* pc, pfmm_tree* t, const double* b_dev, int32_t n_snap, int32_t steps,
+                               int32_t batch, float lr, uint64_t seed, float* final_loss, void* stream) {
+    if (!pc || !t || !b_dev) return set_error(PFMM_EINVAL, "NULL argument");
+    if (!tree_has(t, PFMM_OP_V)) return set_error(PFMM_EINVAL, "V_h was not built for this tree");
+    if (n_snap < 1 || n_snap > 64 || steps < 0 || batch < 1 || batch > (1 << 20) || !(lr > 0.f))
+        return set_error(PFMM_EINVAL, "n_snap in 1..64, steps >= 0, batch in 1..2^20 and lr > 0 required");
+    if (hipSetDevice(tree_device(t)) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
+    const int64_t n = tree_dofs(t);
+    hipStream_t st = (hipStream_t)stream;
+    const int saved = tree_precision(t);
+    (void)pfmm_set_precision(t, PFMM_FP64);
+    // 1. a plain FP64 solve to 1e-10, noting its length
+    pfmm_solve_opts o;
+    pfmm_default_solve_opts(&o);
+    o.rtol = 1e-10;
+    o.max_iter = 400;
+    Workspace ws;
+    double *xs, *snap, *R, *E, *D;
+    pfmm_status s = PFMM_OK;
+    s = ws.alloc(&xs, (size_t)n);
+    pfmm_solve_info i1{};
+    if (s == PFMM_OK) s = gmres(t, b_dev, xs, o, &i1, ws, st);
+    if (s != PFMM_OK) { (void)pfmm_set_precision(t, saved); return s; }
+    if (i1.iters < 2) { (void)pfmm_set_precision(t, saved); return set_error(PFMM_EINVAL, "training solve too short"); }
+    // 2. the same solve again, taking x_k at n_snap iterations spread over it
+    std::vector<int> snaps;
+    for (int i = 0; i < n_snap; ++i) {
+        const int k = std::max(1, (int)((double)(i + 1) * (i1.iters - 1) / (n_snap + 1)));
+        if (snaps.empty() || k > snaps.back()) snaps.push_back(k);
+    }
+    const int ns = (int)snaps.size();
+    const int np = 2 * ns;   // error snapshots, then Krylov basis vectors
+    Workspace ws2;
+    s = ws2.alloc(&snap, (size_t)ns * n);
+    if (s == PFMM_OK) s = ws2.alloc(&R, (size_t)np * n);
+    if (s == PFMM_OK) s = ws2.alloc(&E, (size_t)np * n);
+    // Krylov basis vectors v_j of the first solve (columns 1.. of ws.basis),
+    // spread over it: exact pairs (V_h v_j, v_j) on the space GMRES explores
+    for (int i = 0; i < ns && s == PFMM_OK; ++i) {
+        const int j = 1 + (int)((double)i * std::max(1, i1.iters - 1) / ns);
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, ws.basis + (int64_t)j * n,
+                           E + (int64_t)(ns + i) * n, 1.0, n);
+    }
+    if (s == PFMM_OK) s = ws2.alloc(&D, (size_t)tree_triangles(t));
+    double* xtmp = nullptr;
+    if (s == PFMM_OK) s = ws2.alloc(&xtmp, (size_t)n);
+    pfmm_solve_info i2{};
+    if (s == PFMM_OK) {
+        Workspace ws3;
+        s = gmres(t, b_dev, xtmp, o, &i2, ws3, st, &snaps, snap);
+    }
+    if (s != PFMM_OK) { (void)pfmm_set_precision(t, saved); return s; }
+    // 3. pairs: e = x* - x_k (and the basis vectors above), r = V_h e
+    for (int p = 0; p < np && s == PFMM_OK; ++p) {
+        double* ep = E + (int64_t)p * n;
+        if (p < ns) {
+            hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, xs, ep, 1.0, n);
+            hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, snap + (int64_t)p * n, ep, n);
+        }
+        s = tree_apply(t, false, ep, R + (int64_t)p * n, st);
+    }
+    if (s == PFMM_OK) s = tree_near_diag(t, D, st);
+    (void)pfmm_set_precision(t, saved);
+    if (s != PFMM_OK) return s;
+    // 4. fit
+    s = precond_fit(pc, R, E, np, D, tree_adjacency(t), tree_triangles(t), n, steps, batch, lr, seed, st);
+    if (s == PFMM_OK && final_loss) *final_loss = precond_last_loss(pc);
+    return s;
 }
 
 }  // extern "C"

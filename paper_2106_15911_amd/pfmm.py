@@ -54,7 +54,7 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
-                ("history_len", ctypes.c_int32)]
+                ("history_len", ctypes.c_int32), ("outer", ctypes.c_int32), ("precond_fallback", ctypes.c_int32)]
 
 
 def lib_path():
@@ -90,6 +90,14 @@ def load_library():
         "pfmm_batch_create": ([P(VP), I32, P(VP)], I32),
         "pfmm_apply_V_batch": ([VP, P(VP), P(VP), VP], I32),
         "pfmm_batch_destroy": ([VP], None),
+        "pfmm_precond_create": ([I32, I32, I32, ctypes.c_uint64, P(VP)], I32),
+        "pfmm_precond_train": ([VP, VP, VP, I32, I32, I32, ctypes.c_float, ctypes.c_uint64,
+                                P(ctypes.c_float), VP], I32),
+        "pfmm_precond_apply": ([VP, VP, VP, VP, VP], I32),
+        "pfmm_precond_save": ([VP, ctypes.c_char_p], I32),
+        "pfmm_precond_load": ([ctypes.c_char_p, I32, P(VP)], I32),
+        "pfmm_precond_destroy": ([VP], None),
+        "pfmm_solve_V_precond": ([VP, VP, I32, VP, VP, P(SolveOpts), P(SolveInfo), VP], I32),
         "pfmm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -191,10 +199,20 @@ class Tree:
                 ctypes.byref(info), _stream_ptr(stream))
         d = {"iters": info.iters, "converged": bool(info.converged), "rel_residual": info.rel_residual,
              "true_rel_residual": info.true_rel_residual, "seconds": info.seconds,
-             "history": list(hist[:info.history_len])}
+             "history": list(hist[:info.history_len]), "outer": info.outer,
+             "precond_fallback": bool(info.precond_fallback)}
         if st != 0 and not (st == -4 and not raise_on_notconv):
             _check(st)
         return out, d
+
+    def solve_V_precond(self, b, precond=None, inner_precision=FP64, out=None, rtol=1e-8, max_iter=200, stream=None,
+                        raise_on_notconv=True):
+        """FP64 iterative refinement around flexible GMRES with the learned preconditioner
+        (None: no preconditioner) and inner applies in `inner_precision`; returns (w, info)."""
+        h = precond.handle if precond is not None else None
+        fn = lambda tree, rhs, x, o, info, st: self.lib.pfmm_solve_V_precond(tree, h, int(inner_precision), rhs, x, o,
+                                                                             info, st)
+        return self._solve(fn, b, out, rtol, max_iter, stream, raise_on_notconv)
 
     def solve_V(self, b, out=None, rtol=1e-8, max_iter=200, stream=None, raise_on_notconv=True):
         """GMRES solve of V_h w = b (device tensors, natural order); returns (w, info)."""
@@ -269,6 +287,52 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             self.lib.pfmm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Precond:
+    """The learned temporal-block preconditioner (FP32 perceptron on the GPU)."""
+
+    def __init__(self, device=0, features=8, hidden=256, seed=1, path=None):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        if path is not None:
+            _check(self.lib.pfmm_precond_load(str(path).encode(), device, ctypes.byref(h)))
+        else:
+            _check(self.lib.pfmm_precond_create(device, features, hidden, seed, ctypes.byref(h)))
+        self.handle = h
+
+    def train(self, tree, b, n_snap=8, steps=1500, batch=4096, lr=1e-3, seed=7, stream=None):
+        """Fit on pairs from FP64 GMRES solves of tree's V_h x = b (device tensor); returns the last loss."""
+        loss = ctypes.c_float()
+        _check(self.lib.pfmm_precond_train(self.handle, tree.handle, ctypes.c_void_p(b.data_ptr()), n_snap, steps,
+                                           batch, lr, seed, ctypes.byref(loss), _stream_ptr(stream)))
+        return float(loss.value)
+
+    def apply(self, tree, v, out=None, stream=None):
+        """z = s N(x(v)) on tree's mesh (float64 device tensors in the natural order)."""
+        import torch
+        if v.dtype != torch.float64 or v.device != tree.device or v.numel() != tree.n_dofs:
+            raise ValueError(f"expected a float64 tensor of {tree.n_dofs} entries on {tree.device}")
+        v = v.contiguous()
+        if out is None:
+            out = torch.empty_like(v)
+        _check(self.lib.pfmm_precond_apply(self.handle, tree.handle, ctypes.c_void_p(v.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def save(self, path):
+        _check(self.lib.pfmm_precond_save(self.handle, str(path).encode()))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pfmm_precond_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
