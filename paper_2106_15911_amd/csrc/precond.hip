@@ -40,6 +40,10 @@ struct pfmm_precond {
     float* W1 = nullptr;     // F x H
     float* W2 = nullptr;     // H x H
     float* w3 = nullptr;     // H
+    float* W1p = nullptr;    // packed for inference: F x Hp
+    _Float16* W2t = nullptr; // Hp x Hp (FP16, transposed)
+    float* w3p = nullptr;    // Hp
+    int Hp = 256;            // padded hidden width (64, 128 or 256)
     std::vector<void*> owned;
     float last_loss = 0.f;
 };
@@ -47,7 +51,6 @@ struct pfmm_precond {
 namespace {
 
 constexpr int kT = 256;          // threads per block
-constexpr int kRows = 32;        // rows (DOFs / samples) per inference block
 
 #define HIP_CHECK(expr)                                                                             \
     do {                                                                                            \
@@ -138,51 +141,125 @@ __global__ void __launch_bounds__(kT) k_ssq_final(double* __restrict__ part, int
     if (threadIdx.x == 0) part[0] = sqrt(red[0] / (double)n);   // rms of v / D
 }
 
-// Inference: z(i) = s N(x(i)) for every DOF i (natural order i = j E_x + k).
-// Block = kRows DOFs; the hidden layers live in LDS (the second overwrites
-// the first once every thread has consumed it).
-__global__ void __launch_bounds__(kT) k_mlp_apply(const double* __restrict__ v, const double* __restrict__ D,
-                                                   const double* __restrict__ rms, const float* __restrict__ W1,
-                                                   const float* __restrict__ W2, const float* __restrict__ w3,
-                                                   double* __restrict__ z, int64_t ex, int64_t n, int F, int H,
-                                                   const int* __restrict__ adj) {
+// ---------------------------------------------------------------- inference
+// The hidden width is padded to Hp = 64 NCT (NCT = 1, 2 or 4) with zero
+// weights, which leaves N unchanged (tanh 0 = 0).  Packed operands, rebuilt
+// from the FP32 weights before every application:
+//   W1p [F][Hp]  FP32,
+//   W2t [Hp][Hp] FP16, transposed (output unit first, input unit second),
+//   w3p [Hp]     FP32.
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMR = 64;          // DOFs (rows) per inference block, 4 waves
+
+__global__ void k_pack(const float* __restrict__ W1, const float* __restrict__ W2, const float* __restrict__ w3,
+                       float* __restrict__ W1p, _Float16* __restrict__ W2t, float* __restrict__ w3p, int F, int H,
+                       int Hp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < Hp * Hp) {
+        const int j = i / Hp, a = i % Hp;                 // W2t[j][a] = W2[a][j]
+        W2t[i] = (_Float16)(j < H && a < H ? W2[a * H + j] : 0.f);
+    }
+    if (i < F * Hp) {
+        const int f = i / Hp, h = i % Hp;
+        W1p[i] = h < H ? W1[f * H + h] : 0.f;
+    }
+    if (i < Hp) w3p[i] = i < H ? w3[i] : 0.f;
+}
+
+// tanh x = 1 - 2 / (e^{2x} + 1): exact limits +-1 for large |x|, absolute
+// error a few FP32 ulps of 1
+__device__ __forceinline__ float fast_tanh(float x) { return 1.f - 2.f / (__expf(2.f * x) + 1.f); }
+
+// z(i) = s N(x(i)) for the DOFs i0 .. i0 + kMR - 1 (natural order).
+//  1. features X[kMR][F] (FP32) into LDS;
+//  2. first layer on the vector units in FP32: thread t owns hidden unit
+//     t mod Hp for every (256 / Hp)-th row; tanh, rounded to FP16 into
+//     A[kMR][Hp + 4] (LDS; the 4-element pad spreads the row starts over the
+//     banks);
+//  3. second layer on the matrix cores (v_mfma_f32_16x16x16f16: FP16 inputs,
+//     FP32 accumulation): wave w owns the output units [16 NCT w, 16 NCT (w+1))
+//     for all 64 rows (4 x NCT tiles of 16 x 16);
+//  4. tanh and the output layer in FP32: the 16 lanes that hold one row's
+//     units reduce by shuffles, the 4 waves through LDS.
+template <int NCT>
+__global__ void __launch_bounds__(256) k_mlp_mfma(const double* __restrict__ v, const double* __restrict__ D,
+                                                  const double* __restrict__ rms, const float* __restrict__ W1p,
+                                                  const _Float16* __restrict__ W2t, const float* __restrict__ w3p,
+                                                  double* __restrict__ z, int64_t ex, int64_t n, int F,
+                                                  const int* __restrict__ adj) {
+    constexpr int Hp = 64 * NCT, AS = Hp + 4, RS = 256 / Hp, RPT = kMR / RS;
     extern __shared__ float smf[];
-    float* X = smf;                       // [kRows][F]
-    float* Hs = X + kRows * F;            // [kRows][H]: first, then second hidden layer
-    const int64_t i0 = (int64_t)blockIdx.x * kRows;
+    float* X = smf;                                       // [kMR][F]
+    float* red = X + kMR * F;                             // [4][kMR]
+    _Float16* A = (_Float16*)(red + 4 * kMR);             // [kMR][AS]
+    const int64_t i0 = (int64_t)blockIdx.x * kMR;
     const double s = rms[0];
     const double inv = s > 0.0 ? 1.0 / s : 0.0;
-    for (int e = threadIdx.x; e < kRows * F; e += kT) {
-        const int r = e / F, f = e % F;
+    for (int e = threadIdx.x; e < kMR * F; e += 256) {
+        const int r = e / F, f = e - r * F;
         X[e] = i0 + r < n ? feature(v, D, i0 + r, ex, f, adj, inv) : 0.f;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kRows * H; e += kT) {
-        const int r = e / H, h = e % H;
-        float a = 0.f;
-        for (int f = 0; f < F; ++f) a += X[r * F + f] * W1[f * H + h];
-        Hs[e] = tanhf(a);
+    {
+        const int h = threadIdx.x % Hp, r0 = threadIdx.x / Hp;   // rows r0 + q RS
+        float acc[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) acc[q] = 0.f;
+        for (int f = 0; f < F; ++f) {
+            const float w = W1p[f * Hp + h];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) acc[q] += X[(r0 + q * RS) * F + f] * w;
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) A[(r0 + q * RS) * AS + h] = (_Float16)fast_tanh(acc[q]);
     }
     __syncthreads();
-    // second layer: thread h owns hidden unit h (H <= kT)
-    const int h = threadIdx.x;
-    float a2[kRows];
-    for (int r = 0; r < kRows; ++r) a2[r] = 0.f;
-    if (h < H)
-        for (int a = 0; a < H; ++a) {
-            const float w = W2[a * H + h];
-            for (int r = 0; r < kRows; ++r) a2[r] += Hs[r * H + a] * w;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    f4v_t acc[4][NCT];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = f4v_t{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Hp; k0 += 16) {
+        h4_t b[NCT];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)      // B[k][j] = W2[k][j]: lane j + 16 (k/4), element k % 4
+            b[ct] = *(const h4_t*)(W2t + (int64_t)((wv * NCT + ct) * 16 + li) * Hp + k0 + 4 * lk);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {      // A[i][k]: lane i + 16 (k/4), element k % 4
+            const h4_t a = *(const h4_t*)(A + (rt * 16 + li) * AS + k0 + 4 * lk);
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b[ct], acc[rt][ct], 0, 0, 0);
+        }
+    }
+    // D[i][j]: lane j + 16 (i/4), element i % 4 -> this lane holds rows 4 lk + q of unit li of each tile
+    float p[4][4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float t = 0.f;
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) t += fast_tanh(acc[rt][ct][q]) * w3p[(wv * NCT + ct) * 16 + li];
+            p[rt][q] = t;
+        }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float t = p[rt][q];
+            for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 16);
+            if (li == 0) red[wv * kMR + rt * 16 + 4 * lk + q] = t;
         }
     __syncthreads();
-    if (h < H)
-        for (int r = 0; r < kRows; ++r) Hs[r * H + h] = tanhf(a2[r]);
-    __syncthreads();
-    // output: 8 threads per row, each a strided part of the hidden units
-    const int r = threadIdx.x / 8, part = threadIdx.x % 8;
-    float t = 0.f;
-    for (int h = part; h < H; h += 8) t += Hs[r * H + h] * w3[h];
-    for (int o = 4; o > 0; o >>= 1) t += __shfl_down(t, o, 8);
-    if (part == 0 && i0 + r < n) z[i0 + r] = s * (double)t;
+    if (threadIdx.x < kMR && i0 + threadIdx.x < n) {
+        const int r = threadIdx.x;
+        z[i0 + r] = s * (double)(red[r] + red[kMR + r] + red[2 * kMR + r] + red[3 * kMR + r]);
+    }
 }
 
 // ---------------------------------------------------------------- training
@@ -304,9 +381,21 @@ pfmm_status precond_rms(const double* v, const double* D, int64_t ex, int64_t n,
 pfmm_status precond_apply(const pfmm_precond* pc, const double* v, double* z, const double* D, const int* adj,
                           int64_t ex, int64_t n, double* part, hipStream_t st) {
     if (precond_rms(v, D, ex, n, part, st) != PFMM_OK) return PFMM_EDEVICE;
-    const size_t shm = ((size_t)kRows * pc->F + (size_t)kRows * pc->H) * sizeof(float);
-    hipLaunchKernelGGL(k_mlp_apply, dim3(nblk(n, kRows)), dim3(kT), shm, st, v, D, part, pc->W1, pc->W2, pc->w3, z, ex,
-                       n, pc->F, pc->H, adj);
+    const int Hp = pc->Hp;
+    hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)Hp * std::max(Hp, pc->F))), dim3(kT), 0, st, pc->W1, pc->W2, pc->w3, pc->W1p,
+                       pc->W2t, pc->w3p, pc->F, pc->H, Hp);
+    const size_t shm = (size_t)kMR * pc->F * sizeof(float) + 4 * kMR * sizeof(float) +
+                       (size_t)kMR * (Hp + 4) * sizeof(_Float16);
+    const dim3 g(nblk(n, kMR));
+    if (Hp == 64)
+        hipLaunchKernelGGL(k_mlp_mfma<1>, g, dim3(256), shm, st, v, D, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
+                           pc->F, adj);
+    else if (Hp == 128)
+        hipLaunchKernelGGL(k_mlp_mfma<2>, g, dim3(256), shm, st, v, D, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
+                           pc->F, adj);
+    else
+        hipLaunchKernelGGL(k_mlp_mfma<4>, g, dim3(256), shm, st, v, D, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
+                           pc->F, adj);
     HIP_CHECK(hipGetLastError());
     return PFMM_OK;
 }
@@ -396,9 +485,13 @@ pfmm_status pfmm_precond_create(int32_t device, int32_t features, int32_t hidden
             return set_error(PFMM_EDEVICE, "hipMemcpy failed");
         return PFMM_OK;
     };
+    p->Hp = hidden <= 64 ? 64 : hidden <= 128 ? 128 : 256;
     pfmm_status s = init(&p->W1, p->F, hidden, 1);
     if (s == PFMM_OK) s = init(&p->W2, hidden, hidden, 2);
     if (s == PFMM_OK) s = init(&p->w3, hidden, 1, 3);
+    if (s == PFMM_OK) s = palloc(p->owned, &p->W1p, (size_t)p->F * p->Hp);
+    if (s == PFMM_OK) s = palloc(p->owned, &p->W2t, (size_t)p->Hp * p->Hp);
+    if (s == PFMM_OK) s = palloc(p->owned, &p->w3p, (size_t)p->Hp);
     if (s != PFMM_OK) {
         pfmm_precond_destroy(p);
         return s;

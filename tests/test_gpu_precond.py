@@ -1,5 +1,6 @@
 """Learned temporal-block preconditioner: its inference kernel matches a
-float64 numpy evaluation of the same weights and features (adjacency built
+float64 numpy evaluation of the same weights, features and FP16 rounding
+of the second layer's inputs (adjacency built
 here from the triangle list, the diagonal of V_h from the oracle's panel
 integrals); training on pairs from the
 library's own FP64 GMRES solves lowers the fit loss; FP64 iterative
@@ -54,6 +55,8 @@ def _rings(tris):
 
 
 def _mlp_ref(path, v, tris, D, E_t):
+    """N as the kernel defines it: features and the first layer exact, the
+    second layer's inputs (first-layer activations, W2) rounded to FP16."""
     FT, W1, W2, w3 = _read_weights(path)
     ex = len(tris)
     u = v.reshape(E_t, ex) / D[None, :]
@@ -66,8 +69,23 @@ def _mlp_ref(path, v, tris, D, E_t):
     for f in range(FT):
         for ring, a in enumerate((u, r1, r2)):
             X[f:, :, 3 * f + ring] = a[:E_t - f]
-    z = np.tanh(np.tanh(X @ W1) @ W2) @ w3
-    return s * z.reshape(-1)
+    h1x = np.tanh(X @ W1)
+    h1 = h1x.astype(np.float16).astype(np.float64)
+    W2h = W2.astype(np.float16).astype(np.float64)
+    z = np.tanh(h1 @ W2h) @ w3
+    # The kernel rounds FP32 activations (first layer accumulated in FP32,
+    # tanh through exp: absolute error well below 1e-5) to FP16.  Where the
+    # exact activation lies within 1e-5 of a midpoint between two FP16 values
+    # the kernel may take the other one: one FP16 spacing, which moves z by
+    # at most s |w3| . (spacing |W2h|) per row (|tanh'| <= 1).
+    a = np.abs(h1x)
+    r = a.astype(np.float16)
+    lo = np.where(r.astype(np.float64) > a, np.nextafter(r, np.float16(0)), r)
+    hi = np.nextafter(lo, np.float16(np.inf))
+    lo64, hi64 = lo.astype(np.float64), hi.astype(np.float64)
+    sp = np.where(np.abs(a - 0.5 * (lo64 + hi64)) <= 1e-5, hi64 - lo64, 0.0)
+    bound = s * ((sp @ np.abs(W2h)) @ np.abs(w3))
+    return s * z.reshape(-1), bound.reshape(-1)
 
 
 def test_inference_matches_numpy(tmp_path):
@@ -83,10 +101,15 @@ def test_inference_matches_numpy(tmp_path):
         path = tmp_path / f"pc_{FT}_{H}.bin"
         pc.save(path)
         z = pc.apply(tree, torch.from_numpy(w).to("cuda:0")).cpu().numpy()
-        ref = _mlp_ref(path, w, t, D, E_t)
-        err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
-        print(f"[precond] features {FT} hidden {H}: max error {err:.2e}", flush=True)
-        assert err <= 1e-5
+        ref, bound = _mlp_ref(path, w, t, D, E_t)
+        d = np.abs(z - ref)
+        tol = bound + 1e-5 * np.max(np.abs(ref))
+        zmax = np.max(np.abs(ref))
+        print(f"[precond] features {FT} hidden {H}: max error {np.max(d) / zmax:.2e}, median "
+              f"{np.median(d) / zmax:.2e}, max error / bound {np.max(d / tol):.3f}", flush=True)
+        assert np.all(d <= tol)
+        # rows with no FP16 decision taken differently agree to FP32 rounding
+        assert np.median(d) <= 1e-6 * zmax
         pc.close()
     tree.close()
 
