@@ -323,7 +323,8 @@ void pfmm_precond_destroy(pfmm_precond* pc);
  * current iterate (info->precond_fallback = 1).  info->iters counts all
  * inner iterations (V_h applies), info->outer the refinement steps.  The
  * tree's precision setting is restored on return.  Workspace: about
- * 2 (max_iter + 1) vectors for the call.  Errors as pfmm_solve_V.
+ * 2 (max_iter + 2) vectors for the call, 1.5 more with a preconditioner
+ * (its three FP32 feature fields).  Errors as pfmm_solve_V.
  */
 pfmm_status pfmm_solve_V_precond(pfmm_tree* t, const pfmm_precond* pc, int32_t inner_precision, const double* b_dev,
                                  double* w_dev, const pfmm_solve_opts* o, pfmm_solve_info* info, void* stream);

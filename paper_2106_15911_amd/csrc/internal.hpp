@@ -33,7 +33,8 @@ pfmm_status tree_near_diag(pfmm_tree* t, double* d_dev, hipStream_t st);
 
 // Learned preconditioner (precond.hip): z = s N(x(v)) over a whole vector,
 // and training on pairs (R[p], E[p]) with V_h E[p] = R[p].  part: device
-// scratch of 1024 doubles.
+// scratch of precond_scratch_doubles(n) doubles for precond_apply.
+size_t precond_scratch_doubles(int64_t n);
 pfmm_status precond_apply(const pfmm_precond* pc, const double* v, double* z, const double* D, const int* adj,
                           int64_t ex, int64_t n, double* part, hipStream_t st);
 pfmm_status precond_fit(pfmm_precond* pc, const double* R, const double* E, int npair, const double* D,

@@ -40,7 +40,7 @@ struct pfmm_precond {
     float* W1 = nullptr;     // F x H
     float* W2 = nullptr;     // H x H
     float* w3 = nullptr;     // H
-    float* W1p = nullptr;    // packed for inference: F x Hp
+    float* W1p = nullptr;    // packed for inference: Fp x Hp (Fp = F rounded up to 4)
     _Float16* W2t = nullptr; // Hp x Hp (FP16, transposed)
     float* w3p = nullptr;    // Hp
     int Hp = 256;            // padded hidden width (64, 128 or 256)
@@ -79,14 +79,16 @@ __device__ __host__ inline uint64_t mix64(uint64_t z) {
 
 constexpr int kRings = 3;        // features per time lag: the triangle, first ring, second ring
 
-// Feature f of DOF i (natural order i = j E_x + k) of the residual r, scaled by inv.
-__device__ __forceinline__ float feature(const double* __restrict__ r, const double* __restrict__ D, int64_t i,
-                                         int64_t ex, int f, const int* __restrict__ adj, double inv) {
+// The three normalised fields of a residual r at DOF i (natural order
+// i = j E_x + k), scaled by inv = 1 / s: u(i) = r_i / D_k, the mean of u over
+// the edge neighbours of k and over their neighbours other than k (same
+// step).  Feature 3 f + ring of DOF i is field `ring` at DOF i - f E_x
+// (0 before the first step).
+__device__ __forceinline__ float ring_field(const double* __restrict__ r, const double* __restrict__ D, int64_t i,
+                                            int64_t ex, int ring, const int* __restrict__ adj, double inv) {
     const int64_t j = i / ex;
     const int k = (int)(i - j * ex);
-    const int lag = f / kRings, ring = f - lag * kRings;
-    if (j < lag) return 0.f;
-    const double* rj = r + (j - lag) * ex;
+    const double* rj = r + j * ex;
     double a = 0.0;
     if (ring == 0) {
         a = rj[k] / D[k];
@@ -108,6 +110,17 @@ __device__ __forceinline__ float feature(const double* __restrict__ r, const dou
         a *= c ? 1.0 / c : 0.0;
     }
     return (float)(a * inv);
+}
+
+// U[ring][i] = ring_field(r, i, ring) for every DOF (the inverse rms read from rms[0])
+__global__ void __launch_bounds__(kT) k_rings(const double* __restrict__ r, const double* __restrict__ D,
+                                               const double* __restrict__ rms, const int* __restrict__ adj,
+                                               int64_t ex, int64_t n, float* __restrict__ U) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    const double s = rms[0];
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    for (int ring = 0; ring < kRings; ++ring) U[ring * n + i] = ring_field(r, D, i, ex, ring, adj, inv);
 }
 
 // sum of squares of (v / D) in fixed order: partials per block, then one block
@@ -142,10 +155,11 @@ __global__ void __launch_bounds__(kT) k_ssq_final(double* __restrict__ part, int
 }
 
 // ---------------------------------------------------------------- inference
-// The hidden width is padded to Hp = 64 NCT (NCT = 1, 2 or 4) with zero
-// weights, which leaves N unchanged (tanh 0 = 0).  Packed operands, rebuilt
-// from the FP32 weights before every application:
-//   W1p [F][Hp]  FP32,
+// The hidden width is padded to Hp = 64 NCT (NCT = 1, 2 or 4) and the
+// feature count to Fp = F rounded up to a multiple of 4, with zero weights,
+// which leaves N unchanged (tanh 0 = 0).  Packed operands, rebuilt from the
+// FP32 weights before every application:
+//   W1p [Fp][Hp] FP32,
 //   W2t [Hp][Hp] FP16, transposed (output unit first, input unit second),
 //   w3p [Hp]     FP32.
 typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
@@ -154,70 +168,90 @@ typedef float f4v_t __attribute__((ext_vector_type(4)));
 constexpr int kMR = 64;          // DOFs (rows) per inference block, 4 waves
 
 __global__ void k_pack(const float* __restrict__ W1, const float* __restrict__ W2, const float* __restrict__ w3,
-                       float* __restrict__ W1p, _Float16* __restrict__ W2t, float* __restrict__ w3p, int F, int H,
-                       int Hp) {
+                       float* __restrict__ W1p, _Float16* __restrict__ W2t, float* __restrict__ w3p, int F, int Fp,
+                       int H, int Hp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < Hp * Hp) {
         const int j = i / Hp, a = i % Hp;                 // W2t[j][a] = W2[a][j]
         W2t[i] = (_Float16)(j < H && a < H ? W2[a * H + j] : 0.f);
     }
-    if (i < F * Hp) {
+    if (i < Fp * Hp) {
         const int f = i / Hp, h = i % Hp;
-        W1p[i] = h < H ? W1[f * H + h] : 0.f;
+        W1p[i] = h < H && f < F ? W1[f * H + h] : 0.f;
     }
     if (i < Hp) w3p[i] = i < H ? w3[i] : 0.f;
 }
 
-// tanh x = 1 - 2 / (e^{2x} + 1): exact limits +-1 for large |x|, absolute
-// error a few FP32 ulps of 1
-__device__ __forceinline__ float fast_tanh(float x) { return 1.f - 2.f / (__expf(2.f * x) + 1.f); }
+// tanh x = 1 - 2 / (e^{2x} + 1) with the hardware exponential and
+// reciprocal: exact limits +-1 for large |x| (rcp(inf) = 0), absolute error a
+// few FP32 ulps of 1
+__device__ __forceinline__ float fast_tanh(float x) {
+    return 1.f - 2.f * __builtin_amdgcn_rcpf(__expf(2.f * x) + 1.f);
+}
 
 // z(i) = s N(x(i)) for the DOFs i0 .. i0 + kMR - 1 (natural order).
-//  1. features X[kMR][F] (FP32) into LDS;
-//  2. first layer on the vector units in FP32: thread t owns hidden unit
-//     t mod Hp for every (256 / Hp)-th row; tanh, rounded to FP16 into
-//     A[kMR][Hp + 4] (LDS; the 4-element pad spreads the row starts over the
-//     banks);
+//  1. features X[kMR][Fp + 1] (FP32, read from the ring fields U; the odd
+//     row stride spreads the rows over the LDS banks) into LDS;
+//  2. first layer on the matrix cores in FP32 (v_mfma_f32_16x16x4f32: exact
+//     products, FP32 accumulation); tanh, rounded to FP16 into A[kMR][Hp + 4]
+//     (LDS; the 4-element pad spreads the row starts over the banks);
 //  3. second layer on the matrix cores (v_mfma_f32_16x16x16f16: FP16 inputs,
-//     FP32 accumulation): wave w owns the output units [16 NCT w, 16 NCT (w+1))
-//     for all 64 rows (4 x NCT tiles of 16 x 16);
+//     FP32 accumulation).
+//  In both layers wave w owns the hidden units [16 NCT w, 16 NCT (w+1)) for
+//  all 64 rows (4 x NCT tiles of 16 x 16);
 //  4. tanh and the output layer in FP32: the 16 lanes that hold one row's
 //     units reduce by shuffles, the 4 waves through LDS.
 template <int NCT>
-__global__ void __launch_bounds__(256) k_mlp_mfma(const double* __restrict__ v, const double* __restrict__ D,
-                                                  const double* __restrict__ rms, const float* __restrict__ W1p,
-                                                  const _Float16* __restrict__ W2t, const float* __restrict__ w3p,
-                                                  double* __restrict__ z, int64_t ex, int64_t n, int F,
-                                                  const int* __restrict__ adj) {
-    constexpr int Hp = 64 * NCT, AS = Hp + 4, RS = 256 / Hp, RPT = kMR / RS;
+__global__ void __launch_bounds__(256) k_mlp_mfma(const float* __restrict__ U, const double* __restrict__ rms,
+                                                  const float* __restrict__ W1p, const _Float16* __restrict__ W2t,
+                                                  const float* __restrict__ w3p, double* __restrict__ z, int64_t ex,
+                                                  int64_t n, int F, int Fp) {
+    constexpr int Hp = 64 * NCT, AS = Hp + 4;
+    const int XS = Fp + 1;
     extern __shared__ float smf[];
-    float* X = smf;                                       // [kMR][F]
-    float* red = X + kMR * F;                             // [4][kMR]
+    float* red = smf;                                     // [4][kMR]
     _Float16* A = (_Float16*)(red + 4 * kMR);             // [kMR][AS]
+    float* X = (float*)(A + kMR * AS);                    // [kMR][XS]
     const int64_t i0 = (int64_t)blockIdx.x * kMR;
     const double s = rms[0];
-    const double inv = s > 0.0 ? 1.0 / s : 0.0;
-    for (int e = threadIdx.x; e < kMR * F; e += 256) {
-        const int r = e / F, f = e - r * F;
-        X[e] = i0 + r < n ? feature(v, D, i0 + r, ex, f, adj, inv) : 0.f;
-    }
-    __syncthreads();
-    {
-        const int h = threadIdx.x % Hp, r0 = threadIdx.x / Hp;   // rows r0 + q RS
-        float acc[RPT];
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) acc[q] = 0.f;
-        for (int f = 0; f < F; ++f) {
-            const float w = W1p[f * Hp + h];
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) acc[q] += X[(r0 + q * RS) * F + f] * w;
-        }
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) A[(r0 + q * RS) * AS + h] = (_Float16)fast_tanh(acc[q]);
+    for (int e = threadIdx.x; e < kMR * Fp; e += 256) {  // lanes take consecutive rows: coalesced reads
+        const int f = e / kMR, r = e - f * kMR;
+        const int lag = f / kRings, ring = f - lag * kRings;
+        const int64_t i = i0 + r, q = i - (int64_t)lag * ex;
+        X[r * XS + f] = f < F && i < n && q >= 0 ? U[ring * n + q] : 0.f;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
+    {
+        f4v_t c1[4][NCT];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) c1[rt][ct] = f4v_t{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < Fp; k0 += 4) {
+            float b[NCT];
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)  // B[k][j] = W1[k][j]: lane j + 16 k
+                b[ct] = W1p[(k0 + lk) * Hp + (wv * NCT + ct) * 16 + li];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {  // A[i][k] = X[i][k]: lane i + 16 k
+                const float a = X[(rt * 16 + li) * XS + k0 + lk];
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct)
+                    c1[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ct], c1[rt][ct], 0, 0, 0);
+            }
+        }
+        // D[i][j]: lane j + 16 (i/4), element i % 4
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    A[(rt * 16 + 4 * lk + q) * AS + (wv * NCT + ct) * 16 + li] = (_Float16)fast_tanh(c1[rt][ct][q]);
+    }
+    __syncthreads();
     f4v_t acc[4][NCT];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
@@ -277,7 +311,11 @@ __global__ void __launch_bounds__(kT) k_gather(const double* __restrict__ R, con
     const int64_t i = (int64_t)((h >> 20) % (uint64_t)n);
     const double inv = S[p] > 0.0 ? 1.0 / S[p] : 0.0;
     const double* r = R + (int64_t)p * n;
-    for (int f = 0; f < F; ++f) X[b * F + f] = feature(r, D, i, ex, f, adj, inv);
+    for (int f = 0; f < F; ++f) {
+        const int lag = f / kRings;
+        X[b * F + f] = i - (int64_t)lag * ex >= 0 ? ring_field(r, D, i - (int64_t)lag * ex, ex, f - lag * kRings, adj, inv)
+                                                  : 0.f;
+    }
     T[b] = (float)(E[(int64_t)p * n + i] * inv);
 }
 
@@ -377,25 +415,30 @@ pfmm_status precond_rms(const double* v, const double* D, int64_t ex, int64_t n,
     return PFMM_OK;
 }
 
-// z = s N(x(v)) for the whole vector (natural order); part: scratch of 1024 doubles.
+size_t precond_scratch_doubles(int64_t n) { return 1024 + (size_t)(kRings * n + 1) / 2; }
+
+// z = s N(x(v)) for the whole vector (natural order); part: scratch of
+// precond_scratch_doubles(n) doubles (reduction partials, then the ring fields).
 pfmm_status precond_apply(const pfmm_precond* pc, const double* v, double* z, const double* D, const int* adj,
                           int64_t ex, int64_t n, double* part, hipStream_t st) {
     if (precond_rms(v, D, ex, n, part, st) != PFMM_OK) return PFMM_EDEVICE;
-    const int Hp = pc->Hp;
-    hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)Hp * std::max(Hp, pc->F))), dim3(kT), 0, st, pc->W1, pc->W2, pc->w3, pc->W1p,
-                       pc->W2t, pc->w3p, pc->F, pc->H, Hp);
-    const size_t shm = (size_t)kMR * pc->F * sizeof(float) + 4 * kMR * sizeof(float) +
-                       (size_t)kMR * (Hp + 4) * sizeof(_Float16);
+    float* U = (float*)(part + 1024);
+    hipLaunchKernelGGL(k_rings, dim3(nblk(n)), dim3(kT), 0, st, v, D, part, adj, ex, n, U);
+    const int Hp = pc->Hp, Fp = (pc->F + 3) & ~3;
+    hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)Hp * std::max(Hp, Fp))), dim3(kT), 0, st, pc->W1, pc->W2, pc->w3,
+                       pc->W1p, pc->W2t, pc->w3p, pc->F, Fp, pc->H, Hp);
+    const size_t shm = 4 * kMR * sizeof(float) + (size_t)kMR * (Hp + 4) * sizeof(_Float16) +
+                       (size_t)kMR * (Fp + 1) * sizeof(float);
     const dim3 g(nblk(n, kMR));
     if (Hp == 64)
-        hipLaunchKernelGGL(k_mlp_mfma<1>, g, dim3(256), shm, st, v, D, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
-                           pc->F, adj);
+        hipLaunchKernelGGL(k_mlp_mfma<1>, g, dim3(256), shm, st, U, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
+                           pc->F, Fp);
     else if (Hp == 128)
-        hipLaunchKernelGGL(k_mlp_mfma<2>, g, dim3(256), shm, st, v, D, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
-                           pc->F, adj);
+        hipLaunchKernelGGL(k_mlp_mfma<2>, g, dim3(256), shm, st, U, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
+                           pc->F, Fp);
     else
-        hipLaunchKernelGGL(k_mlp_mfma<4>, g, dim3(256), shm, st, v, D, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
-                           pc->F, adj);
+        hipLaunchKernelGGL(k_mlp_mfma<4>, g, dim3(256), shm, st, U, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
+                           pc->F, Fp);
     HIP_CHECK(hipGetLastError());
     return PFMM_OK;
 }
@@ -489,7 +532,7 @@ pfmm_status pfmm_precond_create(int32_t device, int32_t features, int32_t hidden
     pfmm_status s = init(&p->W1, p->F, hidden, 1);
     if (s == PFMM_OK) s = init(&p->W2, hidden, hidden, 2);
     if (s == PFMM_OK) s = init(&p->w3, hidden, 1, 3);
-    if (s == PFMM_OK) s = palloc(p->owned, &p->W1p, (size_t)p->F * p->Hp);
+    if (s == PFMM_OK) s = palloc(p->owned, &p->W1p, (size_t)((p->F + 3) & ~3) * p->Hp);
     if (s == PFMM_OK) s = palloc(p->owned, &p->W2t, (size_t)p->Hp * p->Hp);
     if (s == PFMM_OK) s = palloc(p->owned, &p->w3p, (size_t)p->Hp);
     if (s != PFMM_OK) {

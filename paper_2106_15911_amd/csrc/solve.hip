@@ -374,7 +374,7 @@ pfmm_status solve_ir(pfmm_tree* t, const pfmm_precond* pc, int inner_prec, const
     PS_TRY(ws.alloc(&ws.coef, (size_t)m + 1));
     PS_TRY(ws.alloc(&r, (size_t)n));
     PS_TRY(ws.alloc(&dvec, (size_t)n));
-    PS_TRY(ws.alloc(&part, 1024));
+    PS_TRY(ws.alloc(&part, pc ? precond_scratch_doubles(n) : 1024));
     if (pc) {
         PS_TRY(ws.alloc(&D, (size_t)tree_triangles(t)));
         PS_TRY(tree_near_diag(t, D, st));
@@ -569,7 +569,7 @@ pfmm_status pfmm_precond_apply(const pfmm_precond* pc, pfmm_tree* t, const doubl
     Workspace ws;
     double *D, *part;
     pfmm_status s = ws.alloc(&D, (size_t)tree_triangles(t));
-    if (s == PFMM_OK) s = ws.alloc(&part, 1024);
+    if (s == PFMM_OK) s = ws.alloc(&part, precond_scratch_doubles(tree_dofs(t)));
     if (s == PFMM_OK) s = tree_near_diag(t, D, st);
     if (s == PFMM_OK) s = precond_apply(pc, v_dev, z_dev, D, tree_adjacency(t), tree_triangles(t), tree_dofs(t), part, st);
     if (s == PFMM_OK && hipStreamSynchronize(st) != hipSuccess) s = set_error(PFMM_EDEVICE, "hipStreamSynchronize failed");
