@@ -1402,13 +1402,26 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
                             (v > 0 || kWideUseNB1))
                             D.m2l_nb[q] = kWideNB[v];
                 }
+                int per_cu = std::max<int>(1, (int)(160 * 1024 / std::max<size_t>(1, t->m2l_shm)));   // resident per CU
                 if (D.m2l_nb[q]) {
                     const int v = D.m2l_nb[q] == 4 ? 2 : (D.m2l_nb[q] == 2 ? 1 : 0);
                     D.ncb[q] = D.n_int / (32 * D.m2l_nb[q]);
                     wg = (int64_t)D.nx * t->wide[q][v].G * D.ncb[q];
+                    per_cu = std::max<int>(1, (int)(160 * 1024 / std::max<size_t>(1, t->wide[q][v].shm)));
                 }
+                // Levels with fewer than 4 workgroups per CU split their source
+                // lists into ns shares (1..4): the share minimising the rounds
+                // of resident workgroups per share, ceil(wg ns / (ncu per_cu)) / ns,
+                // plus 2% per extra partial buffer to sum.
                 D.nsplit_q[q] = 1;
-                while (D.nsplit_q[q] < 4 && wg * D.nsplit_q[q] < 4 * ncu) D.nsplit_q[q] *= 2;
+                if (wg < 4 * ncu) {
+                    double best = 1e30;
+                    for (int ns = 1; ns <= 4; ++ns) {
+                        const int64_t slots = (int64_t)ncu * per_cu;
+                        const double c = (double)((wg * ns + slots - 1) / slots) / ns + 0.02 * (ns - 1);
+                        if (c < best - 1e-9) { best = c; D.nsplit_q[q] = ns; }
+                    }
+                }
                 nsplit_max = std::max(nsplit_max, D.nsplit_q[q]);
             }
             D.nsplit = D.nsplit_q[0];
