@@ -401,21 +401,31 @@ def main():
     x = torch.from_numpy(w).to(dev)
 
     def timed(precision, steps, warmup):
-        """warmup untimed applies, then `steps` applies bracketed by device synchronisation"""
+        """warmup untimed applies, then `steps` applies bracketed by device
+        synchronisation (the nearfield runs beside the farfield chain); then
+        stage times from HIP events on the apply stream over max(3, steps / 4)
+        further applies, whose stages the library runs one after another
+        while timing them"""
         tree.set_precision(precision)
         out = torch.empty_like(x)
         for _ in range(warmup):
             tree.apply_V(x, out=out, stream=stream)
-        torch.cuda.synchronize()
-        tree.profile_enable(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             tree.apply_V(x, out=out, stream=stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        tree.profile_enable(True)
+        n_prof = max(3, steps // 4)
+        t1 = time.perf_counter()
+        for _ in range(n_prof):
+            tree.apply_V(x, out=out, stream=stream)
+        torch.cuda.synchronize()
+        dt_serial = time.perf_counter() - t1
         pr = tree.profile_read()
         tree.profile_enable(False)
+        pr["serial_apply_ms"] = (1e3 * dt_serial / n_prof, 1)
         return out, 1e3 * dt / steps, pr
 
     # timed region: the selected precision
@@ -461,14 +471,16 @@ def main():
         for _ in range(max(1, args.warmup)):
             tt.apply_V(x, out=ft, stream=stream)
         torch.cuda.synchronize()
-        tt.profile_enable(True)
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         nt = max(3, args.steps // 2)
         for _ in range(nt):
             tt.apply_V(x, out=ft, stream=stream)
         torch.cuda.synchronize()
         ms_t = 1e3 * (time.perf_counter() - t0) / nt
+        tt.profile_enable(True)
+        for _ in range(3):
+            tt.apply_V(x, out=ft, stream=stream)
+        torch.cuda.synchronize()
         pt = tt.profile_read()
         toeplitz = {"ms_per_step": ms_t, "value": N / (ms_t * 1e-3),
                     "nearfield_ms": pt["nearfield"][0] / max(pt["nearfield"][1], 1),

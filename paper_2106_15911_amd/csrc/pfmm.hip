@@ -60,13 +60,15 @@ __global__ void k_permute_in(const double* __restrict__ w, double* __restrict__ 
     wd[i] = w[t * E_x + inv_sigma[p]];
 }
 
-__global__ void k_permute_out(const double* __restrict__ fd, double* __restrict__ f,
+// f = far + near, back to the natural order
+__global__ void k_permute_out(const double* __restrict__ fd, const double* __restrict__ fn, double* __restrict__ f,
                               const int* __restrict__ sigma, int E_x, int64_t N) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     int64_t t = i / E_x;
     int k = (int)(i - t * E_x);
-    f[i] = fd[t * E_x + sigma[k]];
+    const int64_t p = t * E_x + sigma[k];
+    f[i] = fd[p] + fn[p];
 }
 
 __global__ void k_fill(double* __restrict__ x, double v, int64_t n) {
@@ -753,7 +755,10 @@ struct pfmm_tree {
     int* adj = nullptr;           // E_x x 3 edge neighbours (natural order)
     int* inv_sigma = nullptr;
     double* wd = nullptr;
-    double* fd = nullptr;
+    double* fd = nullptr;         // farfield result, tree order
+    double* fn = nullptr;         // nearfield result, tree order
+    hipStream_t side = nullptr;   // the nearfield runs here, beside the farfield chain
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double* mass = nullptr;       // |gamma_k| h per triangle (natural order)
     double *At = nullptr, *Ax = nullptr, *AxK = nullptr, *qt = nullptr, *qx = nullptr;
     int* chunk_cols = nullptr;
@@ -851,7 +856,7 @@ uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask, int pre
     const int TS = (P.m_t + 1) * (P.m_t + 1) * (P.m_x + 1) * (P.m_x + 1);
     const size_t shm = (size_t)6 * ((TS + 127) / 128 * 128) * 8 + (size_t)(((P.Nc + 3) & ~3) + 16) * 16;
     const bool explicit_ops = P.m_t > 15 || P.m_x > 15 || shm > 163840;
-    b += 2 * N * 8;                                   // w, f in tree order
+    b += 3 * N * 8;                                   // w, far and near results in tree order
     for (int l = 2; l <= P.depth; ++l) {
         const FarLevel& L = F.lv[l];
         b += 2ull * L.nx * P.Nc * L.n_int * 8;        // mu, lambda
@@ -1091,6 +1096,10 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
     PF_TRY(upload(t, &t->adj, P.adj.data(), P.adj.size()));
     PF_TRY(dalloc(t, &t->wd, (size_t)N));
     PF_TRY(dalloc(t, &t->fd, (size_t)N));
+    PF_TRY(dalloc(t, &t->fn, (size_t)N));
+    HIP_TRY(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming));
     {
         std::vector<double> m(P.E_x);
         for (int i = 0; i < P.E_x; ++i) m[i] = P.area[i] * P.h;
@@ -1550,6 +1559,30 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
     prof_begin(t, 0, st, ev);
     hipLaunchKernelGGL(k_permute_in, dim3(nb), dim3(256), 0, st, w, t->wd, t->inv_sigma, P.E_x, N);
     prof_end(t, st, ev);
+    // The nearfield product needs only the permuted densities: it runs on the
+    // side stream into fn while the farfield chain fills fd, and the two meet
+    // in the final permutation.  With stage timing on, or while st is being
+    // captured into a graph (batched applies, whose branches already run trees
+    // side by side), both run in order on st: same kernels, same results.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cap));
+    const bool fork = !t->prof && cap == hipStreamCaptureStatusNone;
+    auto nearfield = [&](hipStream_t sn) {
+        const int64_t nrg = (int64_t)P.rows.size();
+        hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, sn, t->fn, 0.0, N);
+        if (nrg > 0 && t->nf_mode == PFMM_NF_TOEPLITZ)
+            hipLaunchKernelGGL(k_near_toep, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, sn,
+                               K ? t->opK.table : t->opV.table, t->groups, t->ru_off, t->ru, t->wd, t->fn, t->nl);
+        else if (nrg > 0)
+            hipLaunchKernelGGL(k_near_apply, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, sn,
+                               K ? t->opK.B : t->opV.B, t->wd, t->fn, t->nl);
+    };
+    if (fork) {
+        HIP_TRY(hipEventRecord(t->ev_fork, st));
+        HIP_TRY(hipStreamWaitEvent(t->side, t->ev_fork, 0));
+        nearfield(t->side);
+        HIP_TRY(hipEventRecord(t->ev_join, t->side));
+    }
     if (t->low_leaves || !P.has_far)
         hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, st, t->fd, 0.0, N);
     if (P.has_far) {
@@ -1656,17 +1689,15 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         prof_end(t, st, ev);
     }
     // nearfield
-    prof_begin(t, 6, st, ev);
-    const int64_t nrg = (int64_t)P.rows.size();
-    if (nrg > 0 && t->nf_mode == PFMM_NF_TOEPLITZ)
-        hipLaunchKernelGGL(k_near_toep, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st,
-                           K ? t->opK.table : t->opV.table, t->groups, t->ru_off, t->ru, t->wd, t->fd, t->nl);
-    else if (nrg > 0)
-        hipLaunchKernelGGL(k_near_apply, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, K ? t->opK.B : t->opV.B,
-                           t->wd, t->fd, t->nl);
-    prof_end(t, st, ev);
+    if (fork) {
+        HIP_TRY(hipStreamWaitEvent(st, t->ev_join, 0));
+    } else {
+        prof_begin(t, 6, st, ev);
+        nearfield(st);
+        prof_end(t, st, ev);
+    }
     prof_begin(t, 7, st, ev);
-    hipLaunchKernelGGL(k_permute_out, dim3(nb), dim3(256), 0, st, t->fd, f, t->sigma, P.E_x, N);
+    hipLaunchKernelGGL(k_permute_out, dim3(nb), dim3(256), 0, st, t->fd, t->fn, f, t->sigma, P.E_x, N);
     prof_end(t, st, ev);
     HIP_TRY(hipGetLastError());
     return PFMM_OK;
@@ -1869,6 +1900,12 @@ void pfmm_destroy(pfmm_tree* t) {
     if (!t) return;
     (void)hipSetDevice(t->device);
     for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
+    if (t->side) {
+        (void)hipStreamSynchronize(t->side);
+        (void)hipStreamDestroy(t->side);
+    }
+    for (hipEvent_t e : {t->ev_fork, t->ev_join})
+        if (e) (void)hipEventDestroy(e);
     for (void* p : t->allocs) (void)hipFree(p);
     delete t;
 }
