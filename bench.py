@@ -171,14 +171,22 @@ def solve_bench(args):
     T2 = c2_["n_steps"] * (1.0 / ct["n_steps"]) * (ct["n"] / c2_["n"]) ** 2
     v2, t2, tn2, c2, kw2, b2, _ = _dirichlet_rhs(2, P, torch, nf, T=T2)
     tv2 = P.Tree(v2, t2, tn2, P.default_params(operators=1, **kw2), device=0)
-    pc = P.Precond(device=0, features=args.pc_features, hidden=args.pc_hidden, seed=5)
+    seeds = [5 + i for i in range(max(1, args.pc_seeds))]
+    pcs = []
+    for sd in seeds:
+        pc_i = P.Precond(device=0, features=args.pc_features, hidden=args.pc_hidden, seed=sd)
+        t0 = time.perf_counter()
+        loss_i = pc_i.train(tv2, b2, n_snap=16, steps=args.pc_steps, batch=4096, lr=1e-3)
+        pcs.append((pc_i, loss_i, time.perf_counter() - t0))
+    pc, loss, t_train = pcs[0]
+    stencil = P.Precond(device=0, features=args.pc_features, hidden=0)
     t0 = time.perf_counter()
-    loss = pc.train(tv2, b2, n_snap=16, steps=args.pc_steps, batch=4096, lr=1e-3)
-    t_train = time.perf_counter() - t0
+    loss_st = stencil.train(tv2, b2, n_snap=16, steps=0, batch=4096)
+    t_train_st = time.perf_counter() - t0
     tv2.close()
     del b2
     log(f"[solve] preconditioner trained on {len(t2)} x {len(tn2) - 1} on [0, {T2:g}] in {t_train:.2f} s "
-        f"(loss {loss:.3e})")
+        f"(loss {loss:.3e}); stencil alone {t_train_st:.2f} s (fit residual {loss_st:.3e})")
     # 2. the solves on the large problem
     v, t, tn, c, kw, b, prep = _dirichlet_rhs(args.config, P, torch, nf)
     N = len(t) * (len(tn) - 1)
@@ -194,7 +202,7 @@ def solve_bench(args):
         f"true residual {i0['true_rel_residual']:.3e}")
     runs = {}
     for label, pcx, inner in (("learned_fp64", pc, P.FP64), ("learned_fp32", pc, P.MIXED_FP32),
-                              ("none_fp32", None, P.MIXED_FP32)):
+                              ("stencil_fp32", stencil, P.MIXED_FP32), ("none_fp32", None, P.MIXED_FP32)):
         w, info = tv.solve_V_precond(b, precond=pcx, inner_precision=inner, rtol=args.rtol, max_iter=args.max_iter,
                                      raise_on_notconv=False)
         d = (torch.linalg.norm(w - w0) / torch.linalg.norm(w0)).item()
@@ -205,17 +213,29 @@ def solve_bench(args):
             f"{info['seconds']:.3f} s, true residual {info['true_rel_residual']:.3e}, "
             f"fallback {info['precond_fallback']}, diff to plain {d:.2e}")
         del w
+    # the spread over training seeds (same data, different initial weights and minibatches)
+    seed_runs = []
+    for sd, (pc_i, loss_i, tr_i) in zip(seeds, pcs):
+        _, info = tv.solve_V_precond(b, precond=pc_i, inner_precision=P.MIXED_FP32, rtol=args.rtol,
+                                     max_iter=args.max_iter, raise_on_notconv=False)
+        seed_runs.append(dict(seed=sd, loss=loss_i, iterations=info["iters"], seconds=info["seconds"],
+                              true_rel_residual=info["true_rel_residual"]))
+    log(f"[solve] learned_fp32 over seeds {seeds}: iterations {[r['iterations'] for r in seed_runs]}")
     # one application of the preconditioner (rms, packing, features, MLP), host-timed
     z = torch.empty_like(b)
-    pc.apply(tv, b, out=z)
-    t0 = time.perf_counter()
-    for _ in range(5):
-        pc.apply(tv, b, out=z)
-    t_pc = (time.perf_counter() - t0) / 5
-    log(f"[solve] preconditioner application {t_pc * 1e3:.2f} ms")
+    t_apply = {}
+    for name, pcx in (("learned", pc), ("stencil", stencil)):
+        pcx.apply(tv, b, out=z)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            pcx.apply(tv, b, out=z)
+        t_apply[name] = 1e3 * (time.perf_counter() - t0) / 5
+    log(f"[solve] preconditioner application: {t_apply}")
     del z
     tv.close()
-    pc.close()
+    for pc_i, _, _ in pcs:
+        pc_i.close()
+    stencil.close()
     best = runs["learned_fp32"]
     out = {
         "metric": "Dirichlet GMRES solve time to FP64 relative residual 1e-8 (learned preconditioner, FP32 inner applies)",
@@ -229,14 +249,16 @@ def solve_bench(args):
                                 f"n_max={c['n_max']}, c_st={c['c_st']}, n_tr={c['n_tr']}, "
                                 f"{'Toeplitz' if nf == P.NF_TOEPLITZ else 'stored'} nearfield"),
                    "dofs": N,
-                   "preconditioner": (f"perceptron 3x{args.pc_features} -> {args.pc_hidden} -> {args.pc_hidden} -> 1, "
+                   "preconditioner": (f"least-squares stencil over 3x{args.pc_features} ring features plus a perceptron "
+                                      f"3x{args.pc_features} -> {args.pc_hidden} -> {args.pc_hidden} -> 1 on its residual, "
                                       f"trained on the {len(t2)}-triangle x {len(tn2) - 1}-step Dirichlet problem "
                                       f"on [0, {T2:g}] (h_t / h_x^2 as in the solve) "
                                       f"({args.pc_steps} Adam steps of 4096 samples)")},
         "plain_fp64": dict(seconds=i0["seconds"], iterations=i0["iters"], converged=i0["converged"],
                            true_rel_residual=i0["true_rel_residual"]),
         "runs": runs, "speedup_vs_plain": i0["seconds"] / best["seconds"],
-        "train_s": t_train, "train_loss": loss, "precond_apply_ms": 1e3 * t_pc, "build_V_s": t_bv, **prep, "tree": st,
+        "train_s": t_train, "train_loss": loss, "precond_apply_ms": t_apply, "seed_runs": seed_runs,
+        "stencil_train_s": t_train_st, "stencil_fit_residual": loss_st, "build_V_s": t_bv, **prep, "tree": st,
     }
     print(json.dumps(out), flush=True)
 
@@ -352,6 +374,7 @@ def main():
     ap.add_argument("--pc-features", type=int, default=8)
     ap.add_argument("--pc-hidden", type=int, default=256)
     ap.add_argument("--pc-steps", type=int, default=1500)
+    ap.add_argument("--pc-seeds", type=int, default=3, help="training seeds whose solves are reported")
     ap.add_argument("--solve", action="store_true",
                     help="instead of the apply benchmark: Dirichlet solve on the 12,288 x 512 cube (config 5)")
     ap.add_argument("--rtol", type=float, default=1e-8)

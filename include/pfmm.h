@@ -272,33 +272,38 @@ void pfmm_batch_destroy(pfmm_batch* b);
 
 /*
  * Learned temporal-block preconditioner (not part of the paper, whose GMRES
- * is unpreconditioned).  A small FP32 perceptron N (3 x features -> hidden
- * -> hidden -> 1, tanh, no biases) maps the local space-time neighbourhood
- * of a residual r to the correction z(j, k) = s N(x): with u = r / (D s)
+ * is unpreconditioned).  It maps the local space-time neighbourhood of a
+ * residual r to the correction z(j, k) = s (c . x + N(x)): with u = r / (D s)
  * (D the diagonal of V_h, s the root mean square of r / D), for each lag
- * f < features the inputs are u(step j - f, k), the mean of u(j - f, .)
+ * f < features the inputs x are u(step j - f, k), the mean of u(j - f, .)
  * over the 3 edge neighbours of triangle k and its mean over their own
- * neighbours other than k.  The weights are independent of the mesh, so a
+ * neighbours other than k (input index 3 f + ring).  c is a linear stencil
+ * fitted by least squares; N is a small FP32 perceptron (3 x features ->
+ * hidden -> hidden -> 1, tanh, no biases) fitted to what c leaves; with
+ * hidden = 0 there is no N.  The weights are independent of the mesh, so a
  * preconditioner trained on one tree can be applied on another.
  *
- * pfmm_precond_create: random (Glorot-uniform, seeded) weights on a device;
- *   features (time lags) 1..32, hidden 1..256.
+ * pfmm_precond_create: stencil zero, random (Glorot-uniform, seeded)
+ *   perceptron weights on a device; features (time lags) 1..32, hidden
+ *   0..256.
  * pfmm_precond_train: runs a plain FP64 GMRES solve of V_h x = b on tree t
  *   to 1e-10, takes x_k at n_snap iterations spread over the solve and
  *   n_snap of its Krylov basis vectors v_j, forms the pairs
- *   (r = V_h e, e) for e = x* - x_k and e = v_j, and fits N to them (mean squared error of
- *   the pairs normalised by their r, Adam, `steps` minibatches of `batch`
- *   samples, learning rate lr, seeded sampling).  Synchronous; allocates its
- *   workspace for the call.  final_loss (may be NULL) gets the last batch's
- *   loss.
- * pfmm_precond_apply: z = s N(x(v)) for one vector v on tree t (device,
- *   natural order, v and z distinct); synchronous on `stream`.
+ *   (r = V_h e, e) for e = x* - x_k and e = v_j, fits c by least squares on
+ *   about 2^20 samples of the pairs normalised by their s (seeded sampling),
+ *   then N to the remaining error (mean squared error, Adam with a cosine
+ *   decay of the step size from lr, `steps` minibatches of `batch` samples;
+ *   skipped when hidden = 0).  Synchronous; allocates its workspace for the
+ *   call.  final_loss (may be NULL) gets the perceptron's last batch loss,
+ *   or with hidden = 0 the mean squared residual of the stencil fit.
+ * pfmm_precond_apply: z for one vector v on tree t (device, natural order,
+ *   v and z distinct); synchronous on `stream`.
  * pfmm_precond_save / _load: a small binary file of the weights: four int32
- *   (0x4d4c5031, version 3, features, hidden), then W1 (3 features x hidden,
- *   row-major, input index 3 f + ring), W2 (hidden x hidden, row-major, input
+ *   (0x4d4c5031, version 4, features, hidden), then c (3 features), W1
+ *   (3 features x hidden, row-major), W2 (hidden x hidden, row-major, input
  *   first) and w3 (hidden), all FP32 little-endian.
  * Errors: PFMM_EINVAL, PFMM_ENOMEM, PFMM_EDEVICE, PFMM_ENOTCONV (training
- *   solve did not converge).
+ *   solve did not converge), PFMM_ENONFINITE (degenerate normal equations).
  */
 typedef struct pfmm_precond pfmm_precond;
 pfmm_status pfmm_precond_create(int32_t device, int32_t features, int32_t hidden, uint64_t seed, pfmm_precond** out);

@@ -10,8 +10,13 @@
 //   x_{3f + 1} = mean of u(j - f, k') over the 3 edge neighbours k' of k,
 //   x_{3f + 2} = mean of u(j - f, k'') over the neighbours k'' of those
 //                neighbours, k'' != k (the second ring, with multiplicity),
-// and the correction is z(j, k) = s N(x) with
-//   N(x) = w3 . tanh(W2^T tanh(W1^T x))   (no biases: N is odd).
+// and the correction is z(j, k) = s (c . x + N(x)) with
+//   N(x) = w3 . tanh(W2^T tanh(W1^T x))   (no biases: N is odd),
+// c . x a linear space-time stencil.  c is the least-squares fit of the
+// pairs (convex: the same c for every seed); N is then trained on what c
+// leaves, so the stencil is the deterministic part of the map and the
+// perceptron a correction to it.  With hidden width 0 the preconditioner is
+// the stencil alone.
 // The rings are symmetric in the neighbours, so N does not depend on how
 // the mesh numbers its triangles or orders their edges.  V_h is block
 // lower-triangular in time, so the history carries the temporal part of
@@ -40,6 +45,7 @@ struct pfmm_precond {
     float* W1 = nullptr;     // F x H
     float* W2 = nullptr;     // H x H
     float* w3 = nullptr;     // H
+    float* wl = nullptr;     // F: the linear stencil c (zero until trained)
     float* W1p = nullptr;    // packed for inference: Fp x Hp (Fp = F rounded up to 4)
     _Float16* W2t = nullptr; // Hp x Hp (FP16, transposed)
     float* w3p = nullptr;    // Hp
@@ -204,8 +210,8 @@ __device__ __forceinline__ float fast_tanh(float x) {
 template <int NCT>
 __global__ void __launch_bounds__(256) k_mlp_mfma(const float* __restrict__ U, const double* __restrict__ rms,
                                                   const float* __restrict__ W1p, const _Float16* __restrict__ W2t,
-                                                  const float* __restrict__ w3p, double* __restrict__ z, int64_t ex,
-                                                  int64_t n, int F, int Fp) {
+                                                  const float* __restrict__ w3p, const float* __restrict__ wl,
+                                                  double* __restrict__ z, int64_t ex, int64_t n, int F, int Fp) {
     constexpr int Hp = 64 * NCT, AS = Hp + 4;
     const int XS = Fp + 1;
     extern __shared__ float smf[];
@@ -290,10 +296,34 @@ __global__ void __launch_bounds__(256) k_mlp_mfma(const float* __restrict__ U, c
             if (li == 0) red[wv * kMR + rt * 16 + 4 * lk + q] = t;
         }
     __syncthreads();
-    if (threadIdx.x < kMR && i0 + threadIdx.x < n) {
+    if (threadIdx.x < kMR && i0 + threadIdx.x < n) {   // plus the linear stencil c . x
         const int r = threadIdx.x;
-        z[i0 + r] = s * (double)(red[r] + red[kMR + r] + red[2 * kMR + r] + red[3 * kMR + r]);
+        float lin = 0.f;
+        for (int f = 0; f < F; ++f) lin += wl[f] * X[r * XS + f];
+        z[i0 + r] = s * ((double)(red[r] + red[kMR + r] + red[2 * kMR + r] + red[3 * kMR + r]) + (double)lin);
     }
+}
+
+// The stencil alone (hidden width 0): z(i) = s c . x(i), same summation order
+// over the features as the perceptron kernel's linear term.
+__global__ void __launch_bounds__(kT) k_lin_apply(const float* __restrict__ U, const double* __restrict__ rms,
+                                                   const float* __restrict__ wl, double* __restrict__ z, int64_t ex,
+                                                   int64_t n, int F) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    float lin = 0.f;
+    for (int f = 0; f < F; ++f) {
+        const int lag = f / kRings, ring = f - lag * kRings;
+        const int64_t q = i - (int64_t)lag * ex;
+        lin += wl[f] * (q >= 0 ? U[ring * n + q] : 0.f);
+    }
+    z[i] = rms[0] * (double)lin;
+}
+
+// T[b] -= y[b]
+__global__ void k_sub_f(float* __restrict__ T, const float* __restrict__ y, int B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) T[b] -= y[b];
 }
 
 // ---------------------------------------------------------------- training
@@ -424,6 +454,11 @@ pfmm_status precond_apply(const pfmm_precond* pc, const double* v, double* z, co
     if (precond_rms(v, D, ex, n, part, st) != PFMM_OK) return PFMM_EDEVICE;
     float* U = (float*)(part + 1024);
     hipLaunchKernelGGL(k_rings, dim3(nblk(n)), dim3(kT), 0, st, v, D, part, adj, ex, n, U);
+    if (pc->H == 0) {
+        hipLaunchKernelGGL(k_lin_apply, dim3(nblk(n)), dim3(kT), 0, st, U, part, pc->wl, z, ex, n, pc->F);
+        HIP_CHECK(hipGetLastError());
+        return PFMM_OK;
+    }
     const int Hp = pc->Hp, Fp = (pc->F + 3) & ~3;
     hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)Hp * std::max(Hp, Fp))), dim3(kT), 0, st, pc->W1, pc->W2, pc->w3,
                        pc->W1p, pc->W2t, pc->w3p, pc->F, Fp, pc->H, Hp);
@@ -431,14 +466,14 @@ pfmm_status precond_apply(const pfmm_precond* pc, const double* v, double* z, co
                        (size_t)kMR * (Fp + 1) * sizeof(float);
     const dim3 g(nblk(n, kMR));
     if (Hp == 64)
-        hipLaunchKernelGGL(k_mlp_mfma<1>, g, dim3(256), shm, st, U, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
-                           pc->F, Fp);
+        hipLaunchKernelGGL(k_mlp_mfma<1>, g, dim3(256), shm, st, U, part, pc->W1p, pc->W2t, pc->w3p, pc->wl, z,
+                           ex, n, pc->F, Fp);
     else if (Hp == 128)
-        hipLaunchKernelGGL(k_mlp_mfma<2>, g, dim3(256), shm, st, U, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
-                           pc->F, Fp);
+        hipLaunchKernelGGL(k_mlp_mfma<2>, g, dim3(256), shm, st, U, part, pc->W1p, pc->W2t, pc->w3p, pc->wl, z,
+                           ex, n, pc->F, Fp);
     else
-        hipLaunchKernelGGL(k_mlp_mfma<4>, g, dim3(256), shm, st, U, part, pc->W1p, pc->W2t, pc->w3p, z, ex, n,
-                           pc->F, Fp);
+        hipLaunchKernelGGL(k_mlp_mfma<4>, g, dim3(256), shm, st, U, part, pc->W1p, pc->W2t, pc->w3p, pc->wl, z,
+                           ex, n, pc->F, Fp);
     HIP_CHECK(hipGetLastError());
     return PFMM_OK;
 }
@@ -447,7 +482,7 @@ pfmm_status precond_apply(const pfmm_precond* pc, const double* v, double* z, co
 pfmm_status precond_fit(pfmm_precond* pc, const double* R, const double* E, int npair, const double* D,
                         const int* adj, int64_t ex, int64_t n, int steps, int batch, float lr, uint64_t seed,
                         hipStream_t st) {
-    const int F = pc->F, H = pc->H, B = batch;
+    const int F = pc->F, H = std::max(pc->H, 1), B = batch;   // (buffers of width 1 when hidden is 0)
     std::vector<void*> tmp;
     struct Free { std::vector<void*>& v; ~Free() { for (void* p : v) (void)hipFree(p); } } fr{tmp};
     double *S, *part;
@@ -467,10 +502,77 @@ pfmm_status precond_fit(pfmm_precond* pc, const double* R, const double* E, int 
         if (precond_rms(R + (int64_t)p * n, D, ex, n, part, st) != PFMM_OK) return PFMM_EDEVICE;
         HIP_CHECK(hipMemcpyAsync(S + p, part, sizeof(double), hipMemcpyDeviceToDevice, st));
     }
+    // 1. the linear stencil c: least squares over about 2^20 samples drawn like
+    //    the minibatches (normal equations per batch in FP32 on the GPU, summed
+    //    in FP64 on the host), a ridge of 1e-8 trace / F, Cholesky
+    {
+        float *Gd, *rd, *ttd;
+        if (palloc(tmp, &Gd, (size_t)F * F) || palloc(tmp, &rd, (size_t)F) || palloc(tmp, &ttd, 1))
+            return PFMM_ENOMEM;
+        std::vector<double> G((size_t)F * F, 0.0), r(F, 0.0), c(F, 0.0);
+        std::vector<float> hG((size_t)F * F), hr(F);
+        double tt = 0.0;
+        float htt = 0.f;
+        const int chunks = std::max(1, (1 << 20) / B);
+        for (int ch = 0; ch < chunks; ++ch) {
+            hipLaunchKernelGGL(k_gather, dim3(nblk(B)), dim3(kT), 0, st, R, E, S, D, npair, ex, n, F,
+                               seed ^ 0x6c73717561726573ull, ch, B, adj, X, T);
+            gemm<true, false>(X, X, Gd, F, F, B, false, st);   // X^T X
+            gemm<true, false>(X, T, rd, F, 1, B, false, st);   // X^T t
+            gemm<true, false>(T, T, ttd, 1, 1, B, false, st);  // t^T t
+            HIP_CHECK(hipMemcpyAsync(hG.data(), Gd, hG.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+            HIP_CHECK(hipMemcpyAsync(hr.data(), rd, hr.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+            HIP_CHECK(hipMemcpyAsync(&htt, ttd, sizeof(float), hipMemcpyDeviceToHost, st));
+            HIP_CHECK(hipStreamSynchronize(st));
+            for (size_t i = 0; i < G.size(); ++i) G[i] += hG[i];
+            for (int i = 0; i < F; ++i) r[i] += hr[i];
+            tt += htt;
+        }
+        double tr = 0.0;
+        for (int i = 0; i < F; ++i) tr += G[(size_t)i * F + i];
+        for (int i = 0; i < F; ++i) G[(size_t)i * F + i] += 1e-8 * tr / F + 1e-300;
+        // Cholesky G = L L^T in place (lower triangle), then two triangular solves
+        for (int j = 0; j < F; ++j) {
+            double d = G[(size_t)j * F + j];
+            for (int k = 0; k < j; ++k) d -= G[(size_t)j * F + k] * G[(size_t)j * F + k];
+            if (!(d > 0.0)) return set_error(PFMM_ENONFINITE, "preconditioner stencil: normal equations not positive definite");
+            const double ljj = std::sqrt(d);
+            G[(size_t)j * F + j] = ljj;
+            for (int i = j + 1; i < F; ++i) {
+                double v = G[(size_t)i * F + j];
+                for (int k = 0; k < j; ++k) v -= G[(size_t)i * F + k] * G[(size_t)j * F + k];
+                G[(size_t)i * F + j] = v / ljj;
+            }
+        }
+        for (int i = 0; i < F; ++i) {
+            double v = r[i];
+            for (int k = 0; k < i; ++k) v -= G[(size_t)i * F + k] * c[k];
+            c[i] = v / G[(size_t)i * F + i];
+        }
+        for (int i = F - 1; i >= 0; --i) {
+            double v = c[i];
+            for (int k = i + 1; k < F; ++k) v -= G[(size_t)k * F + i] * c[k];
+            c[i] = v / G[(size_t)i * F + i];
+        }
+        std::vector<float> cf(F);
+        double rc = 0.0;
+        for (int i = 0; i < F; ++i) {
+            cf[i] = (float)c[i];
+            rc += r[i] * c[i];
+        }
+        HIP_CHECK(hipMemcpyAsync(pc->wl, cf.data(), F * sizeof(float), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        // mean squared residual of the fit: (t^T t - r^T c) / samples (normal equations)
+        pc->last_loss = (float)((tt - rc) / ((double)chunks * B));
+    }
+    if (pc->H == 0) return PFMM_OK;
+    // 2. the perceptron, on the targets minus the stencil's prediction
     float b1t = 1.f, b2t = 1.f;
     for (int it = 0; it < steps; ++it) {
         hipLaunchKernelGGL(k_gather, dim3(nblk(B)), dim3(kT), 0, st, R, E, S, D, npair, ex, n, F, seed, it, B, adj,
                            X, T);
+        gemm<false, false>(X, pc->wl, dy, B, 1, F, false, st);          // stencil prediction X c
+        hipLaunchKernelGGL(k_sub_f, dim3(nblk(B)), dim3(kT), 0, st, T, dy, B);
         gemm<false, false>(X, pc->W1, H1, B, H, F, false, st);          // H1 = tanh(X W1)
         hipLaunchKernelGGL(k_tanh, dim3(nblk((int64_t)B * H)), dim3(kT), 0, st, H1, (int64_t)B * H);
         gemm<false, false>(H1, pc->W2, H2, B, H, H, false, st);         // H2 = tanh(H1 W2)
@@ -486,12 +588,14 @@ pfmm_status precond_fit(pfmm_precond* pc, const double* R, const double* E, int 
         gemm<true, false>(X, G1, g1, F, H, B, false, st);                // g1 = X^T G1
         b1t *= 0.9f;
         b2t *= 0.999f;
-        hipLaunchKernelGGL(k_adam, dim3(nblk(sizes[0])), dim3(kT), 0, st, pc->W1, g1, m[0], m[3], (int64_t)sizes[0], lr, b1t, b2t);
-        hipLaunchKernelGGL(k_adam, dim3(nblk(sizes[1])), dim3(kT), 0, st, pc->W2, g2, m[1], m[4], (int64_t)sizes[1], lr, b1t, b2t);
-        hipLaunchKernelGGL(k_adam, dim3(nblk(sizes[2])), dim3(kT), 0, st, pc->w3, g3, m[2], m[5], (int64_t)sizes[2], lr, b1t, b2t);
+        // cosine decay of the step size to zero over the run (Loshchilov and Hutter)
+        const float lrt = 0.5f * lr * (1.f + std::cos(3.14159265f * (float)it / (float)steps));
+        hipLaunchKernelGGL(k_adam, dim3(nblk(sizes[0])), dim3(kT), 0, st, pc->W1, g1, m[0], m[3], (int64_t)sizes[0], lrt, b1t, b2t);
+        hipLaunchKernelGGL(k_adam, dim3(nblk(sizes[1])), dim3(kT), 0, st, pc->W2, g2, m[1], m[4], (int64_t)sizes[1], lrt, b1t, b2t);
+        hipLaunchKernelGGL(k_adam, dim3(nblk(sizes[2])), dim3(kT), 0, st, pc->w3, g3, m[2], m[5], (int64_t)sizes[2], lrt, b1t, b2t);
     }
     HIP_CHECK(hipGetLastError());
-    HIP_CHECK(hipMemcpyAsync(&pc->last_loss, loss, sizeof(float), hipMemcpyDeviceToHost, st));
+    if (steps > 0) HIP_CHECK(hipMemcpyAsync(&pc->last_loss, loss, sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     return PFMM_OK;
 }
@@ -505,8 +609,8 @@ extern "C" {
 pfmm_status pfmm_precond_create(int32_t device, int32_t features, int32_t hidden, uint64_t seed, pfmm_precond** out) {
     if (!out) return set_error(PFMM_EINVAL, "NULL output pointer");
     *out = nullptr;
-    if (features < 1 || features > 32 || hidden < 1 || hidden > kT)
-        return set_error(PFMM_EINVAL, "features must be in 1..32 and hidden in 1..256");
+    if (features < 1 || features > 32 || hidden < 0 || hidden > kT)
+        return set_error(PFMM_EINVAL, "features must be in 1..32 and hidden in 0..256");
     if (hipSetDevice(device) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
     pfmm_precond* p = new (std::nothrow) pfmm_precond();
     if (!p) return set_error(PFMM_ENOMEM, "host allocation failed");
@@ -529,12 +633,17 @@ pfmm_status pfmm_precond_create(int32_t device, int32_t features, int32_t hidden
         return PFMM_OK;
     };
     p->Hp = hidden <= 64 ? 64 : hidden <= 128 ? 128 : 256;
-    pfmm_status s = init(&p->W1, p->F, hidden, 1);
-    if (s == PFMM_OK) s = init(&p->W2, hidden, hidden, 2);
-    if (s == PFMM_OK) s = init(&p->w3, hidden, 1, 3);
-    if (s == PFMM_OK) s = palloc(p->owned, &p->W1p, (size_t)((p->F + 3) & ~3) * p->Hp);
-    if (s == PFMM_OK) s = palloc(p->owned, &p->W2t, (size_t)p->Hp * p->Hp);
-    if (s == PFMM_OK) s = palloc(p->owned, &p->w3p, (size_t)p->Hp);
+    pfmm_status s = palloc(p->owned, &p->wl, (size_t)p->F);
+    if (s == PFMM_OK && hipMemset(p->wl, 0, (size_t)p->F * sizeof(float)) != hipSuccess)
+        s = set_error(PFMM_EDEVICE, "hipMemset failed");
+    if (hidden > 0) {
+        if (s == PFMM_OK) s = init(&p->W1, p->F, hidden, 1);
+        if (s == PFMM_OK) s = init(&p->W2, hidden, hidden, 2);
+        if (s == PFMM_OK) s = init(&p->w3, hidden, 1, 3);
+        if (s == PFMM_OK) s = palloc(p->owned, &p->W1p, (size_t)((p->F + 3) & ~3) * p->Hp);
+        if (s == PFMM_OK) s = palloc(p->owned, &p->W2t, (size_t)p->Hp * p->Hp);
+        if (s == PFMM_OK) s = palloc(p->owned, &p->w3p, (size_t)p->Hp);
+    }
     if (s != PFMM_OK) {
         pfmm_precond_destroy(p);
         return s;
@@ -546,16 +655,19 @@ pfmm_status pfmm_precond_create(int32_t device, int32_t features, int32_t hidden
 pfmm_status pfmm_precond_save(const pfmm_precond* p, const char* path) {
     if (!p || !path) return set_error(PFMM_EINVAL, "NULL argument");
     if (hipSetDevice(p->device) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
-    std::vector<float> a((size_t)p->F * p->H), b((size_t)p->H * p->H), c(p->H);
-    if (hipMemcpy(a.data(), p->W1, a.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(b.data(), p->W2, b.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(c.data(), p->w3, c.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
-        return set_error(PFMM_EDEVICE, "hipMemcpy failed");
+    std::vector<float> l(p->F), a((size_t)p->F * p->H), b((size_t)p->H * p->H), c(p->H);
+    bool ok = hipMemcpy(l.data(), p->wl, l.size() * 4, hipMemcpyDeviceToHost) == hipSuccess;
+    if (ok && p->H > 0)
+        ok = hipMemcpy(a.data(), p->W1, a.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+             hipMemcpy(b.data(), p->W2, b.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+             hipMemcpy(c.data(), p->w3, c.size() * 4, hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) return set_error(PFMM_EDEVICE, "hipMemcpy failed");
     FILE* f = std::fopen(path, "wb");
     if (!f) return set_error(PFMM_EINVAL, std::string("cannot open ") + path);
-    const int32_t hdr[4] = {0x4d4c5031, 3, p->FT, p->H};   // magic, version, time lags, hidden
-    bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1 && std::fwrite(a.data(), 4, a.size(), f) == a.size() &&
-              std::fwrite(b.data(), 4, b.size(), f) == b.size() && std::fwrite(c.data(), 4, c.size(), f) == c.size();
+    const int32_t hdr[4] = {0x4d4c5031, 4, p->FT, p->H};   // magic, version, time lags, hidden
+    ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1 && std::fwrite(l.data(), 4, l.size(), f) == l.size() &&
+         std::fwrite(a.data(), 4, a.size(), f) == a.size() && std::fwrite(b.data(), 4, b.size(), f) == b.size() &&
+         std::fwrite(c.data(), 4, c.size(), f) == c.size();
     ok = (std::fclose(f) == 0) && ok;
     return ok ? PFMM_OK : set_error(PFMM_EINVAL, std::string("write failed: ") + path);
 }
@@ -566,22 +678,26 @@ pfmm_status pfmm_precond_load(const char* path, int32_t device, pfmm_precond** o
     FILE* f = std::fopen(path, "rb");
     if (!f) return set_error(PFMM_EINVAL, std::string("cannot open ") + path);
     int32_t hdr[4];
-    if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != 0x4d4c5031 || hdr[1] != 3 || hdr[2] < 1 || hdr[2] > 32 ||
-        hdr[3] < 1 || hdr[3] > kT) {
+    if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != 0x4d4c5031 || hdr[1] != 4 || hdr[2] < 1 || hdr[2] > 32 ||
+        hdr[3] < 0 || hdr[3] > kT) {
         std::fclose(f);
         return set_error(PFMM_EINVAL, std::string("not a preconditioner file: ") + path);
     }
-    std::vector<float> a((size_t)hdr[2] * kRings * hdr[3]), b((size_t)hdr[3] * hdr[3]), c(hdr[3]);
-    const bool ok = std::fread(a.data(), 4, a.size(), f) == a.size() && std::fread(b.data(), 4, b.size(), f) == b.size() &&
-                    std::fread(c.data(), 4, c.size(), f) == c.size();
+    const size_t F = (size_t)hdr[2] * kRings, H = (size_t)hdr[3];
+    std::vector<float> l(F), a(F * H), b(H * H), c(H);
+    const bool ok = std::fread(l.data(), 4, l.size(), f) == l.size() && std::fread(a.data(), 4, a.size(), f) == a.size() &&
+                    std::fread(b.data(), 4, b.size(), f) == b.size() && std::fread(c.data(), 4, c.size(), f) == c.size();
     std::fclose(f);
     if (!ok) return set_error(PFMM_EINVAL, std::string("truncated preconditioner file: ") + path);
     pfmm_precond* p = nullptr;
     pfmm_status s = pfmm_precond_create(device, hdr[2], hdr[3], 0, &p);
     if (s != PFMM_OK) return s;
-    if (hipMemcpy(p->W1, a.data(), a.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->W2, b.data(), b.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->w3, c.data(), c.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    bool cp = hipMemcpy(p->wl, l.data(), l.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    if (cp && H > 0)
+        cp = hipMemcpy(p->W1, a.data(), a.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(p->W2, b.data(), b.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(p->w3, c.data(), c.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    if (!cp) {
         pfmm_precond_destroy(p);
         return set_error(PFMM_EDEVICE, "hipMemcpy failed");
     }

@@ -74,6 +74,25 @@ def test_deterministic_and_errors():
     tree.close()
 
 
+@pytest.mark.parametrize("mode", ["stored", "toeplitz"])
+def test_nearfield_beside_farfield_equals_in_order(mode):
+    """The apply that runs the nearfield on a side stream (default) and the
+    in-order apply (stage timing on) give bitwise equal results, for V and K,
+    on a tree with a deep farfield (m = 6, matrix-core M2L on several levels)."""
+    print(f"[parity] side-stream nearfield vs in order, {mode}", flush=True)
+    v, t, tn, w = problem(6, 128, seed=9)
+    nf = P.NF_TOEPLITZ if mode == "toeplitz" else P.NF_STORED
+    tree = P.Tree(v, t, tn, P.default_params(m_t=6, m_x=6, operators=3, nearfield_mode=nf), device=0)
+    x = torch.from_numpy(w).to("cuda:0")
+    a, c = tree.apply_V(x), tree.apply_K(x)
+    tree.profile_enable(True)
+    b, d = tree.apply_V(x), tree.apply_K(x)
+    tree.profile_enable(False)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(c, d)
+    tree.close()
+
+
 @pytest.mark.parametrize("kind", ["V", "K"])
 def test_c1_mesh_degree6_matrix_cores(kind):
     """Degrees 6/6 on the 192 x 16 mesh: exercises the FP64 matrix-core M2L

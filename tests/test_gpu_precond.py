@@ -32,11 +32,25 @@ def _tree(n, E_t, seed, precision=P.FP64):
 def _read_weights(path):
     raw = open(path, "rb").read()
     magic, version, FT, H = np.frombuffer(raw[:16], "<i4")
-    assert magic == 0x4D4C5031 and version == 3
+    assert magic == 0x4D4C5031 and version == 4
     w = np.frombuffer(raw[16:], "<f4").astype(np.float64)
     F = 3 * FT
-    assert w.size == F * H + H * H + H
-    return FT, w[:F * H].reshape(F, H), w[F * H:F * H + H * H].reshape(H, H), w[F * H + H * H:]
+    assert w.size == F + F * H + H * H + H
+    c, w = w[:F], w[F:]
+    return FT, c, w[:F * H].reshape(F, H), w[F * H:F * H + H * H].reshape(H, H), w[F * H + H * H:]
+
+
+def _write_weights(path, FT, H, rng):
+    """A weights file in the library's format with random stencil and perceptron."""
+    F = 3 * FT
+    c = rng.uniform(-0.5, 0.5, F)
+    W1 = rng.uniform(-1, 1, (F, H)) * np.sqrt(6 / (F + H)) if H else np.zeros((F, 0))
+    W2 = rng.uniform(-1, 1, (H, H)) * np.sqrt(3 / H) if H else np.zeros((0, 0))
+    w3 = rng.uniform(-1, 1, H) * np.sqrt(6 / (H + 1)) if H else np.zeros(0)
+    with open(path, "wb") as f:
+        f.write(np.array([0x4D4C5031, 4, FT, H], "<i4").tobytes())
+        for a in (c, W1, W2, w3):
+            f.write(np.ascontiguousarray(a, "<f4").tobytes())
 
 
 def _rings(tris):
@@ -55,9 +69,10 @@ def _rings(tris):
 
 
 def _mlp_ref(path, v, tris, D, E_t):
-    """N as the kernel defines it: features and the first layer exact, the
-    second layer's inputs (first-layer activations, W2) rounded to FP16."""
-    FT, W1, W2, w3 = _read_weights(path)
+    """c . x + N(x) as the kernel defines it: features, stencil and the first
+    layer exact, the second layer's inputs (first-layer activations, W2)
+    rounded to FP16."""
+    FT, cl, W1, W2, w3 = _read_weights(path)
     ex = len(tris)
     u = v.reshape(E_t, ex) / D[None, :]
     s = np.sqrt(np.mean(u * u))
@@ -72,7 +87,7 @@ def _mlp_ref(path, v, tris, D, E_t):
     h1x = np.tanh(X @ W1)
     h1 = h1x.astype(np.float16).astype(np.float64)
     W2h = W2.astype(np.float16).astype(np.float64)
-    z = np.tanh(h1 @ W2h) @ w3
+    z = np.tanh(h1 @ W2h) @ w3 + X @ cl
     # The kernel rounds FP32 activations (first layer accumulated in FP32,
     # tanh through exp: absolute error well below 1e-5) to FP16.  Where the
     # exact activation lies within 1e-5 of a midpoint between two FP16 values
@@ -96,10 +111,11 @@ def test_inference_matches_numpy(tmp_path):
     h = (tn[-1] - tn[0]) / E_t
     ks = np.arange(len(t))
     D = panel_integrals(v, t, ks, ks, 0, h, 1.0)[:, 0]
-    for FT, H, seed in ((1, 8, 11), (6, 64, 12), (8, 256, 13)):
-        pc = P.Precond(device=0, features=FT, hidden=H, seed=seed)
+    rng = np.random.default_rng(14)
+    for FT, H in ((1, 8), (6, 64), (8, 256), (8, 0), (3, 0)):
         path = tmp_path / f"pc_{FT}_{H}.bin"
-        pc.save(path)
+        _write_weights(path, FT, H, rng)
+        pc = P.Precond(device=0, path=path)
         z = pc.apply(tree, torch.from_numpy(w).to("cuda:0")).cpu().numpy()
         ref, bound = _mlp_ref(path, w, t, D, E_t)
         d = np.abs(z - ref)
@@ -134,6 +150,15 @@ def test_training_lowers_the_loss_and_solves_converge():
               f"diff to plain GMRES {d:.2e} (plain: {i_ref['iters']} iterations)", flush=True)
         assert info["converged"] and info["true_rel_residual"] <= 1e-8
         assert d <= 1e-5
+    # the stencil alone (hidden width 0) is deterministic and converges too
+    st0 = P.Precond(device=0, features=8, hidden=0, seed=1)
+    tree_b, b_b = _tree(2, 256, 61)
+    l_s = st0.train(tree_b, b_b, n_snap=6, steps=0, batch=4096)
+    tree_b.close()
+    w0, i0 = tree.solve_V_precond(b, precond=st0, rtol=1e-8, max_iter=300)
+    print(f"[precond] stencil alone: fit residual {l_s:.3e}, {i0['iters']} inner iterations", flush=True)
+    assert np.isfinite(l_s) and i0["converged"] and i0["true_rel_residual"] <= 1e-8
+    st0.close()
     # save / load: the same weights give the same iterations
     with tempfile.TemporaryDirectory() as td:
         path = os.path.join(td, "pc.bin")
