@@ -157,8 +157,14 @@ void multidot(Workspace& ws, const double* V, int64_t ld, int ncols, const doubl
 
 // snaps (optional, ascending): iterations k at which x_k = V_k y_k is formed
 // into snap_x + i n (the training pairs of the learned preconditioner).
+// With n_snap > 0, the iterates x_k at n_snap iteration counts spread over
+// the solve are written to snap_x (n_snap vectors; the counts, distinct, to
+// snaps_out).  They are formed after the loop: Givens rotations leave the
+// leading k x k block of R and the first k entries of the rotated right-hand
+// side as they were after step k, so x_k = V_k R_k^{-1} e_k.
 pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opts& o, pfmm_solve_info* info,
-                  Workspace& ws, hipStream_t st, const std::vector<int>* snaps = nullptr, double* snap_x = nullptr) {
+                  Workspace& ws, hipStream_t st, int n_snap = 0, double* snap_x = nullptr,
+                  std::vector<int>* snaps_out = nullptr) {
     const int64_t n = tree_dofs(t);
     const int m = o.max_iter;
     const int64_t ld = n;
@@ -229,21 +235,27 @@ pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opt
         k = j + 1;
         est = std::fabs(e[j + 1]) / beta;
         record(est);
-        if (snaps)
-            for (size_t si = 0; si < snaps->size(); ++si)
-                if ((*snaps)[si] == k) {
-                    std::vector<double> ys(k);
-                    for (int i = k - 1; i >= 0; --i) {
-                        double sum = e[i];
-                        for (int l = i + 1; l < k; ++l) sum -= Hij(i, l) * ys[l];
-                        ys[i] = sum / Hij(i, i);
-                    }
-                    HIP_CHECK(hipMemcpyAsync(ws.coef, ys.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
-                    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kBlock), 0, st, ws.basis, ld, k, ws.coef,
-                                       1.0, (const double*)nullptr, snap_x + (int64_t)si * n, n);
-                    HIP_CHECK(hipStreamSynchronize(st));   // ys is released at the end of this block
-                }
         if (est <= o.rtol || hn == 0.0) break;
+    }
+    if (n_snap > 0 && snap_x && snaps_out) {
+        snaps_out->clear();
+        for (int i = 0; i < n_snap; ++i) {
+            const int ks = std::max(1, (int)((double)(i + 1) * (k - 1) / (n_snap + 1)));
+            if (snaps_out->empty() || ks > snaps_out->back()) snaps_out->push_back(ks);
+        }
+        for (size_t si = 0; si < snaps_out->size(); ++si) {
+            const int ks = (*snaps_out)[si];
+            std::vector<double> ys(ks);
+            for (int i = ks - 1; i >= 0; --i) {
+                double sum = e[i];
+                for (int l = i + 1; l < ks; ++l) sum -= Hij(i, l) * ys[l];
+                ys[i] = sum / Hij(i, i);
+            }
+            HIP_CHECK(hipMemcpyAsync(ws.coef, ys.data(), ks * sizeof(double), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kBlock), 0, st, ws.basis, ld, ks, ws.coef, 1.0,
+                               (const double*)nullptr, snap_x + (int64_t)si * n, n);
+            HIP_CHECK(hipStreamSynchronize(st));   // ys is released at the end of this block
+        }
     }
     // x = V_k y with the triangular solve R y = e
     std::vector<double> y(k);
@@ -587,46 +599,33 @@ pfmm_status pfmm_precond_train(pfmm_precond* pc, pfmm_tree* t, const double* b_d
     hipStream_t st = (hipStream_t)stream;
     const int saved = tree_precision(t);
     (void)pfmm_set_precision(t, PFMM_FP64);
-    // 1. a plain FP64 solve to 1e-10, noting its length
+    // 1. a plain FP64 solve to 1e-10, with the iterates x_k at n_snap
+    //    iteration counts spread over it
     pfmm_solve_opts o;
     pfmm_default_solve_opts(&o);
     o.rtol = 1e-10;
     o.max_iter = 400;
-    Workspace ws;
+    Workspace ws, ws2;
     double *xs, *snap, *R, *E, *D;
-    pfmm_status s = PFMM_OK;
-    s = ws.alloc(&xs, (size_t)n);
+    pfmm_status s = ws.alloc(&xs, (size_t)n);
+    if (s == PFMM_OK) s = ws2.alloc(&snap, (size_t)n_snap * n);
     pfmm_solve_info i1{};
-    if (s == PFMM_OK) s = gmres(t, b_dev, xs, o, &i1, ws, st);
+    std::vector<int> snaps;
+    if (s == PFMM_OK) s = gmres(t, b_dev, xs, o, &i1, ws, st, n_snap, snap, &snaps);
     if (s != PFMM_OK) { (void)pfmm_set_precision(t, saved); return s; }
     if (i1.iters < 2) { (void)pfmm_set_precision(t, saved); return set_error(PFMM_EINVAL, "training solve too short"); }
-    // 2. the same solve again, taking x_k at n_snap iterations spread over it
-    std::vector<int> snaps;
-    for (int i = 0; i < n_snap; ++i) {
-        const int k = std::max(1, (int)((double)(i + 1) * (i1.iters - 1) / (n_snap + 1)));
-        if (snaps.empty() || k > snaps.back()) snaps.push_back(k);
-    }
     const int ns = (int)snaps.size();
     const int np = 2 * ns;   // error snapshots, then Krylov basis vectors
-    Workspace ws2;
-    s = ws2.alloc(&snap, (size_t)ns * n);
-    if (s == PFMM_OK) s = ws2.alloc(&R, (size_t)np * n);
+    s = ws2.alloc(&R, (size_t)np * n);
     if (s == PFMM_OK) s = ws2.alloc(&E, (size_t)np * n);
-    // Krylov basis vectors v_j of the first solve (columns 1.. of ws.basis),
-    // spread over it: exact pairs (V_h v_j, v_j) on the space GMRES explores
+    // 2. Krylov basis vectors v_j of the solve (columns 1.. of ws.basis),
+    //    spread over it: exact pairs (V_h v_j, v_j) on the space GMRES explores
     for (int i = 0; i < ns && s == PFMM_OK; ++i) {
         const int j = 1 + (int)((double)i * std::max(1, i1.iters - 1) / ns);
         hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, ws.basis + (int64_t)j * n,
                            E + (int64_t)(ns + i) * n, 1.0, n);
     }
     if (s == PFMM_OK) s = ws2.alloc(&D, (size_t)tree_triangles(t));
-    double* xtmp = nullptr;
-    if (s == PFMM_OK) s = ws2.alloc(&xtmp, (size_t)n);
-    pfmm_solve_info i2{};
-    if (s == PFMM_OK) {
-        Workspace ws3;
-        s = gmres(t, b_dev, xtmp, o, &i2, ws3, st, &snaps, snap);
-    }
     if (s != PFMM_OK) { (void)pfmm_set_precision(t, saved); return s; }
     // 3. pairs: e = x* - x_k (and the basis vectors above), r = V_h e
     for (int p = 0; p < np && s == PFMM_OK; ++p) {
