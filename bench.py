@@ -28,24 +28,29 @@ FP32_PEAK_TFS = 157.3     # dense FP32 matrix-core peak
 # HBM bytes per apply from rocprofv3 FETCH_SIZE / WRITE_SIZE runs on the
 # 3072 x 256, m = 6 workload (FP64 farfield), scaled by the same counters on a
 # plain 1 GiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Each entry
-# is valid only for the kernel source file it was taken on (sha256 prefix);
-# any change to that file reports null.
+# is valid only for the sources it was taken on (sha256 prefixes of the
+# kernel file and of the file that plans and launches it); any change to
+# them reports null.
 TRAFFIC = {
-    "m2l": {"file": "m2l_kernels.hpp", "sha256_prefix": "e38d10d4f4c24a9f", "config": 2, "precision": "fp64",
-            "bytes": 39727818752.0},
-    "k_near_apply": {"file": "near_apply.hpp", "sha256_prefix": "08c8c7d165c97ca7", "config": 2,
-                     "bytes": 54271160320.0},
+    "m2l": {"files": {"m2l_kernels.hpp": "e38d10d4f4c24a9f", "pfmm.hip": "856e6b14b9afaed8"}, "config": 2,
+            "precision": "fp64", "bytes": 39121072128.0},
+    "k_near_apply": {"files": {"near_apply.hpp": "08c8c7d165c97ca7", "pfmm.hip": "856e6b14b9afaed8"}, "config": 2,
+                     "bytes": 54272793600.0},
 }
 
 
 def measured_traffic(kernel, cfg, precision="fp64"):
+    """HBM bytes per apply from the rocprofv3 counters, while the sources the
+    counters were taken on (kernel and launch configuration) are unchanged."""
     import hashlib
     e = TRAFFIC.get(kernel)
     if e is None or e["bytes"] is None or e["config"] != cfg or e.get("precision", precision) != precision:
         return None
-    with open(os.path.join(ROOT, "paper_2106_15911_amd", "csrc", e["file"]), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
-    return e["bytes"] if sha == e["sha256_prefix"] else None
+    for name, prefix in e["files"].items():
+        with open(os.path.join(ROOT, "paper_2106_15911_amd", "csrc", name), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest()[:16] != prefix:
+                return None
+    return e["bytes"]
 
 
 def log(*a):
