@@ -92,6 +92,10 @@ typedef struct {
     int32_t  operators;      /* PFMM_OP_V | PFMM_OP_K.                             default both */
     int32_t  check_finite;   /* 1: reject non-finite mesh/time input.              default 1   */
     int32_t  nearfield_mode; /* pfmm_nearfield_mode.                               default STORED */
+    int32_t  nearfield_gemm; /* Toeplitz mode: 1 runs the leaf boxes whose leaves are
+                                time translates as GEMMs on the FP64 matrix cores
+                                (another summation order), 0 keeps the stored
+                                mode's order everywhere.                   default 1   */
     uint64_t device_mem_budget; /* bytes the tree may allocate; 0 = 90% of free memory */
 } pfmm_params;
 
@@ -107,7 +111,9 @@ typedef struct {
     uint64_t device_bytes;       /* device memory owned by the tree                  */
     int32_t  m2l_matrix_cores;   /* 1: M2L on FP64 matrix cores, 0: vector units,
                                     -1: not decided (host-only planning)           */
-    int32_t  reserved;
+    int32_t  near_gemm_groups;   /* Toeplitz nearfield: leaf spatial boxes whose
+                                    products run as GEMMs on the FP64 matrix cores
+                                    (0 in the stored mode, -1 host-only planning)  */
 } pfmm_stats;
 
 /* Fill *out with the default parameters above.  Returns PFMM_EINVAL on NULL. */

@@ -76,10 +76,12 @@ __global__ void __launch_bounds__(256) k_near_apply(const double* __restrict__ B
 __global__ void __launch_bounds__(256) k_near_toep(const double* __restrict__ table, const GroupDev* __restrict__ groups,
                                                    const int64_t* __restrict__ ru_off, const int* __restrict__ ru,
                                                    const double* __restrict__ wd, double* __restrict__ fd,
-                                                   NearLayout L) {
+                                                   NearLayout L, const int* __restrict__ sel, int64_t n_sel) {
     __shared__ double red[256];
     const int wv = threadIdx.x / kWave;
-    const int64_t rg = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
+    // row group: the idx-th of the selection sel[0, n_sel), or of all when sel is null
+    const int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
+    const int64_t rg = sel ? (idx < n_sel ? sel[idx] : L.n_rows) : idx;
     const int lane = threadIdx.x % kWave;
     double acc = 0.0;
     int nX = 1, cpi = 64, r = 0, cs = 0, kt = 0, t0 = 0;
@@ -130,4 +132,86 @@ __global__ void __launch_bounds__(256) k_near_toep(const double* __restrict__ ta
         for (int c = 0; c < cpi; ++c) s += red[wv * kWave + c * nX + lane];
         fd[(int64_t)kt * L.E_x + t0 + lane] += s;
     }
+}
+
+// Toeplitz nearfield of one assembly group (leaf spatial box, rows r < nX)
+// on the FP64 matrix cores.  The group's leaves are time translates: one per
+// interval [s0, s0 + s) over all steps, and source triangle u (table column)
+// contributes the steps jt in [s0 + a_u, s0 + b_u) clipped at 0, with
+// (a_u, b_u) depending on the leaf index modulo a period `per` (checked on
+// the host).  With k = d U + u over the time offsets d and the columns u,
+//   f[kt][r] += sum_k A[kt][k] T[k][r],
+//   A[kt][k] = w[kt - d][pos_u] if kt - d lies in that range, else 0,
+//   T[k][r]  = the distinct-integral table T[d][u][r] as stored (row k of
+//              length nX),
+// a dense GEMM: a wave owns 16 target steps and NT 16-column tiles of rows,
+// v_mfma_f64_16x16x4f64 with A[i][k] from lane i + 16 k and B[k][j] from
+// lane j + 16 k; D[i][j] in lane j + 16 (i % 4), register i / 4.
+struct NearGemmGroup {
+    int64_t toff, eoff;       // table offset (doubles), offset into the per-column records [phase][u]
+    int s, per, nX, U, K, tb; // interval length, period, rows, columns, K = (dmax + 1) U, first row position
+};
+
+// One workgroup per 16 target steps of a group; its 4 waves take
+// consecutive quarters of the K range and their partial tiles are added
+// through LDS in wave order (fixed order: deterministic results).
+template <int NT>
+__global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ table,
+                                                   const NearGemmGroup* __restrict__ gg, const int4* __restrict__ ue,
+                                                   const double* __restrict__ wd, double* __restrict__ fd, int E_x,
+                                                   int E_t) {
+    __shared__ double red[3][NT][4][kWave];
+    const NearGemmGroup G = gg[blockIdx.x];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int li = lane & 15, lk = lane >> 4;
+    const int kt0 = blockIdx.y * 16;
+    const int kt = kt0 + li;
+    const int s0 = (kt / G.s) * G.s;
+    const double* T = table + G.toff;
+    const int4* E = ue + G.eoff + (int64_t)((kt / G.s) % G.per) * G.U;   // this target step's phase
+    d4_t acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = d4_t{0.0, 0.0, 0.0, 0.0};
+    const int kq = ((G.K + 15) / 16) * 4;                 // K values per wave, a multiple of 4
+    const int kb = wv * kq, ke = min(G.K, kb + kq);
+    int d = (kb + lk) / G.U, u = (kb + lk) - ((kb + lk) / G.U) * G.U;   // (d, u) of this lane's k
+#pragma unroll 2
+    for (int k0 = kb; k0 < ke; k0 += 4) {
+        const int k = k0 + lk;
+        double a = 0.0, b[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) b[nt] = 0.0;
+        if (k < ke) {
+            const int4 e = E[u];   // (position, a_u, b_u)
+            const int jt = kt - d;
+            if (kt < E_t && jt >= 0 && jt >= s0 + e.y && jt < s0 + e.z) a = wd[(int64_t)jt * E_x + e.x];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int r = nt * 16 + li;
+                if (r < G.nX) b[nt] = T[(int64_t)k * G.nX + r];
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[nt], acc[nt], 0, 0, 0);
+        u += 4;
+        while (u >= G.U) {
+            u -= G.U;
+            ++d;
+        }
+    }
+    if (wv > 0)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[wv - 1][nt][q][lane] = acc[nt][q];
+    __syncthreads();
+    if (wv != 0) return;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = acc[nt][q] + red[0][nt][q][lane] + red[1][nt][q][lane] + red[2][nt][q][lane];
+            const int kk = kt0 + lk + 4 * q, r = nt * 16 + li;
+            if (kk < E_t && r < G.nX) fd[(int64_t)kk * E_x + G.tb + r] += v;
+        }
 }

@@ -798,6 +798,12 @@ struct pfmm_tree {
     int nf_mode = PFMM_NF_STORED;
     int64_t* ru_off = nullptr;    // Toeplitz nearfield: per leaf rectangle, offset into ru
     int* ru = nullptr;            // table columns u of the rectangles' source triangles
+    NearGemmGroup* ngg = nullptr; // Toeplitz groups applied as GEMMs, sorted by row tiles
+    int4* nue = nullptr;          // their per-column records (position, a_u, b_u, 0)
+    int ngg_start[5] = {0, 0, 0, 0, 0};   // groups with 1..4 row tiles: [ngg_start[t-1], ngg_start[t])
+    int* nsel = nullptr;          // row groups of the other groups (matrix-vector kernel)
+    int64_t n_sel = 0;
+    int nf_gemm = 1;              // pfmm_params.nearfield_gemm
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev;   // pairs per stage
@@ -1085,6 +1091,123 @@ bool plan_wide(const std::vector<int>& ks, int maxs, int waves, std::vector<int>
     }
     G_out = G;
     return true;
+}
+
+// Toeplitz nearfield groups that can run as GEMMs (k_near_gemm): the group's
+// leaves are one per interval of a fixed length s over all steps, and for
+// every table column u the source steps of a leaf (clipped at the leaf's
+// last step: later ones are causal zeros) form one range [s0 + a_u, s0 + b_u)
+// clipped at step 0, with (a_u, b_u) depending on the leaf only through its
+// index modulo a period of 1, 2, 4 or 8 (neighbouring leaves of a coarser
+// level span 2, 4, ... intervals).  All other groups keep the matrix-vector
+// kernel over their row groups.
+pfmm_status plan_near_gemm(pfmm_tree* t) {
+    const Plan& P = t->P;
+    const int ng = (int)P.groups.size();
+    std::vector<std::vector<int>> gl(ng);
+    for (int i = 0; i < (int)P.leaves.size(); ++i) gl[P.leaves[i].group].push_back(i);
+    std::vector<uint8_t> elig(ng, 0);
+    std::vector<NearGemmGroup> gg[4];
+    std::vector<std::vector<int4>> ue(4);
+    std::vector<int> lo, hi, cov;
+    for (int g = 0; g < ng && t->nf_gemm; ++g) {
+        const AsmGroup& A = P.groups[g];
+        std::vector<int>& L = gl[g];
+        if (L.empty()) continue;
+        std::sort(L.begin(), L.end(), [&](int x, int y) { return P.leaves[x].s0 < P.leaves[y].s0; });
+        const int s = P.leaves[L[0]].s1 - P.leaves[L[0]].s0;
+        const int nX = A.te - A.tb, U = A.usize;
+        bool ok = s > 0 && (int64_t)L.size() * s == P.E_t && nX >= 1 && nX <= 64 && U >= 1;
+        for (size_t i = 0; ok && i < L.size(); ++i)
+            ok = P.leaves[L[i]].s0 == (int)i * s && P.leaves[L[i]].s1 == (int)(i + 1) * s &&
+                 P.leaves[L[i]].tb == A.tb && P.leaves[L[i]].te == A.te;
+        for (int u = 0; ok && u < U; ++u) {
+            const int pos = P.upos[A.uoff + u];
+            ok = pos >= 0 && pos < P.E_x && P.umap[A.mapoff + pos] == u;
+        }
+        if (!ok) continue;
+        // source-step range of every column for leaf li: false if not one range
+        auto ranges = [&](int li) -> bool {
+            const LeafRec& R = P.leaves[li];
+            lo.assign(U, INT32_MAX);
+            hi.assign(U, INT32_MIN);
+            cov.assign(U, 0);
+            for (int q = R.rect0; q < R.rect1; ++q) {
+                const Rect& rc = P.rects[q];
+                for (int i = 0; i < P.set_size[rc.set]; ++i) {
+                    const int u = P.umap[A.mapoff + P.set_pos[P.set_off[rc.set] + i]];
+                    if (u < 0 || u >= U) return false;
+                    lo[u] = std::min(lo[u], rc.j0);
+                    hi[u] = std::max(hi[u], rc.j1);
+                    cov[u] += rc.j1 - rc.j0;
+                }
+            }
+            for (int u = 0; u < U; ++u)
+                if (cov[u] && cov[u] != hi[u] - lo[u]) return false;
+            return true;
+        };
+        int per_ok = 0;
+        std::vector<int> ar, br;
+        for (int per = 1; per <= 8 && !per_ok; per *= 2) {
+            if ((int)L.size() % per) break;
+            ar.assign((size_t)per * U, 0);
+            br.assign((size_t)per * U, 0);
+            bool bad = false;
+            for (int ph = 0; ph < per && !bad; ++ph) {   // reference: the last leaf of each phase
+                const int li = L[L.size() - per + ph];
+                if (!ranges(li)) { bad = true; break; }
+                const int s0 = P.leaves[li].s0, s1 = P.leaves[li].s1;
+                for (int u = 0; u < U; ++u) {
+                    const int h = cov[u] ? std::min(hi[u], s1) : 0;
+                    if (!cov[u] || lo[u] >= h) continue;
+                    ar[(size_t)ph * U + u] = lo[u] - s0;
+                    br[(size_t)ph * U + u] = h - s0;
+                    if ((s - 1) - (lo[u] - s0) > A.dmax) bad = true;   // time offsets inside the table
+                }
+            }
+            for (size_t i = 0; !bad && i < L.size(); ++i) {
+                if (!ranges(L[i])) { bad = true; break; }
+                const int ph = (int)(i % per), s0 = P.leaves[L[i]].s0, s1 = P.leaves[L[i]].s1;
+                for (int u = 0; u < U && !bad; ++u) {
+                    const int a = ar[(size_t)ph * U + u], b = br[(size_t)ph * U + u];
+                    const int elo = std::max(0, s0 + a), ehi = s0 + b;
+                    const bool want = a < b && elo < ehi;
+                    const int h = cov[u] ? std::min(hi[u], s1) : 0;
+                    const bool have = cov[u] && lo[u] < h;
+                    bad = want ? !(have && lo[u] == elo && h == ehi) : have;
+                }
+            }
+            if (!bad) per_ok = per;
+        }
+        if (!per_ok) continue;
+        elig[g] = 1;
+        const int nt = (nX + 15) / 16 - 1;
+        gg[nt].push_back(NearGemmGroup{A.toff, (int64_t)ue[nt].size(), s, per_ok, nX, U, (A.dmax + 1) * U, A.tb});
+        for (int ph = 0; ph < per_ok; ++ph)
+            for (int u = 0; u < U; ++u)
+                ue[nt].push_back(int4{P.upos[A.uoff + u], ar[(size_t)ph * U + u], br[(size_t)ph * U + u], 0});
+    }
+    std::vector<NearGemmGroup> all;
+    std::vector<int4> uall;
+    for (int nt = 0; nt < 4; ++nt) {
+        t->ngg_start[nt] = (int)all.size();
+        for (NearGemmGroup G : gg[nt]) {
+            G.eoff += (int64_t)uall.size();
+            all.push_back(G);
+        }
+        uall.insert(uall.end(), ue[nt].begin(), ue[nt].end());
+    }
+    t->ngg_start[4] = (int)all.size();
+    std::vector<int> sel;
+    for (size_t rg = 0; rg < P.rows.size(); ++rg)
+        if (!elig[P.leaves[P.rows[rg].leaf].group]) sel.push_back((int)rg);
+    t->n_sel = (int64_t)sel.size();
+    if (!all.empty()) {
+        PF_TRY(upload(t, &t->ngg, all.data(), all.size()));
+        PF_TRY(upload(t, &t->nue, uall.data(), uall.size()));
+    }
+    if (!sel.empty()) PF_TRY(upload(t, &t->nsel, sel.data(), sel.size()));
+    return PFMM_OK;
 }
 
 pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
@@ -1526,6 +1649,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
                 }
             PF_TRY(upload(t, &t->ru_off, roff.data(), roff.size()));
             PF_TRY(upload(t, &t->ru, ru.data(), ru.size()));
+            PF_TRY(plan_near_gemm(t));
         }
     }
     if (ops_mask & PFMM_OP_V) { PF_TRY(assemble_near(t, false, t->opV, st)); t->hasV = true; }
@@ -1570,9 +1694,23 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
     auto nearfield = [&](hipStream_t sn) {
         const int64_t nrg = (int64_t)P.rows.size();
         hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, sn, t->fn, 0.0, N);
-        if (nrg > 0 && t->nf_mode == PFMM_NF_TOEPLITZ)
-            hipLaunchKernelGGL(k_near_toep, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, sn,
-                               K ? t->opK.table : t->opV.table, t->groups, t->ru_off, t->ru, t->wd, t->fn, t->nl);
+        if (nrg > 0 && t->nf_mode == PFMM_NF_TOEPLITZ) {
+            const double* tab = K ? t->opK.table : t->opV.table;
+            const unsigned mt = (unsigned)((P.E_t + 15) / 16);
+            for (int c = 0; c < 4; ++c) {
+                const int g0 = t->ngg_start[c], g1 = t->ngg_start[c + 1];
+                if (g1 <= g0) continue;
+                const dim3 grid((unsigned)(g1 - g0), mt);
+                const NearGemmGroup* gp = t->ngg + g0;
+                if (c == 0) hipLaunchKernelGGL(k_near_gemm<1>, grid, dim3(256), 0, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 1) hipLaunchKernelGGL(k_near_gemm<2>, grid, dim3(256), 0, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 2) hipLaunchKernelGGL(k_near_gemm<3>, grid, dim3(256), 0, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 3) hipLaunchKernelGGL(k_near_gemm<4>, grid, dim3(256), 0, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
+            }
+            if (t->n_sel > 0)
+                hipLaunchKernelGGL(k_near_toep, dim3((unsigned)((t->n_sel + 3) / 4)), dim3(256), 0, sn, tab, t->groups,
+                                   t->ru_off, t->ru, t->wd, t->fn, t->nl, (const int*)t->nsel, t->n_sel);
+        }
         else if (nrg > 0)
             hipLaunchKernelGGL(k_near_apply, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, sn,
                                K ? t->opK.B : t->opV.B, t->wd, t->fn, t->nl);
@@ -1714,6 +1852,7 @@ void fill_stats(const Plan& P, uint64_t bytes, pfmm_stats* out, int m2l_mfma) {
     out->distinct_integrals = P.distinct;
     out->device_bytes = bytes;
     out->m2l_matrix_cores = m2l_mfma;
+    out->near_gemm_groups = m2l_mfma < 0 ? -1 : 0;   // set by the caller once decided
 }
 
 }  // namespace
@@ -1764,6 +1903,7 @@ pfmm_status pfmm_default_params(pfmm_params* out) {
     out->precision = PFMM_FP64;
     out->operators = PFMM_OP_V | PFMM_OP_K;
     out->check_finite = 1;
+    out->nearfield_gemm = 1;
     out->device_mem_budget = 0;
     return PFMM_OK;
 }
@@ -1826,6 +1966,7 @@ pfmm_status pfmm_build_tree(const double* vertices, int64_t n_vertices, const in
     t->prec = prm.precision;
     t->has_f32 = prm.precision == PFMM_MIXED_FP32 || prm.precision == PFMM_MIXED_BF16;
     t->nf_mode = prm.nearfield_mode;
+    t->nf_gemm = prm.nearfield_gemm;
     pfmm_status s = setup_device(t.get(), st, prm.operators);
     if (s != PFMM_OK) {
         pfmm_destroy(t.release());
@@ -1863,6 +2004,7 @@ pfmm_status pfmm_set_precision(pfmm_tree* t, int32_t precision) {
 pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out) {
     if (!t || !out) return fail(PFMM_EINVAL, "NULL argument");
     fill_stats(t->P, t->bytes, out, t->mfma_slots > 0 ? 1 : 0);
+    out->near_gemm_groups = t->ngg_start[4];
     return PFMM_OK;
 }
 

@@ -94,6 +94,7 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         msg = "unknown nearfield mode";
         return PFMM_EINVAL;
     }
+    if (p.nearfield_gemm != 0 && p.nearfield_gemm != 1) { msg = "nearfield_gemm must be 0 or 1"; return PFMM_EINVAL; }
     for (int64_t i = 0; i < nv && p.check_finite; ++i)
         if (!finite3(V + 3 * i)) { msg = "non-finite vertex"; return PFMM_ENONFINITE; }
     for (int64_t i = 0; i <= E_t && p.check_finite; ++i)

@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
                 ("n_max", ctypes.c_int32), ("c_st", ctypes.c_double), ("n_tr", ctypes.c_int32),
                 ("q_reg", ctypes.c_int32), ("q_sing", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("operators", ctypes.c_int32), ("check_finite", ctypes.c_int32), ("nearfield_mode", ctypes.c_int32),
-                ("device_mem_budget", ctypes.c_uint64)]
+                ("nearfield_gemm", ctypes.c_int32), ("device_mem_budget", ctypes.c_uint64)]
 
 
 class Stats(ctypes.Structure):
@@ -40,7 +40,7 @@ class Stats(ctypes.Structure):
                 ("leaves", ctypes.c_int64), ("near_entries", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
                 ("near_row_groups", ctypes.c_int64), ("distinct_integrals", ctypes.c_int64),
                 ("device_bytes", ctypes.c_uint64), ("m2l_matrix_cores", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("near_gemm_groups", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -2,9 +2,12 @@
 integrals per (leaf spatial box, step difference)) against the CPU oracle and
 against the stored-block mode on the same tree.
 
-The stored blocks are copies of the same distinct values and both products
-sum the same terms in the same order per lane, so the two modes must agree
-bit for bit; against the oracle the FP64 bar (1e-10 relative) applies."""
+The stored blocks are copies of the same distinct values.  Groups whose
+leaves are time translates run as GEMMs on the matrix cores (another
+summation order: the modes agree to 1e-13 relative); the others, and all
+groups with nearfield_gemm = 0, use a kernel with the stored mode's order
+(bit for bit equal).  Against the oracle the FP64 bar (1e-10 relative)
+applies."""
 import numpy as np
 import pytest
 
@@ -18,11 +21,16 @@ from workloads import config_problem
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
+TOL_MODES = 1e-13   # Toeplitz vs stored: same terms, FP64, summation order of the GEMM path
 
 
-def _apply(v, t, tn, w, kind, mode, **prm):
+def _mode_diff(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+def _apply(v, t, tn, w, kind, mode, gemm=1, **prm):
     op = 1 if kind == "V" else 2
-    tree = P.Tree(v, t, tn, P.default_params(operators=op, nearfield_mode=mode, **prm), device=0)
+    tree = P.Tree(v, t, tn, P.default_params(operators=op, nearfield_mode=mode, nearfield_gemm=gemm, **prm), device=0)
     x = torch.from_numpy(w).to("cuda:0")
     f = tree.apply_V(x) if kind == "V" else tree.apply_K(x)
     torch.cuda.synchronize()
@@ -43,7 +51,13 @@ def test_toeplitz_vs_oracle_and_stored(case, kind):
     v, t, tn, w = problem(c.pop("n"), c.pop("E_t"), seed=13)
     ft, st_t = _apply(v, t, tn, w, kind, P.NF_TOEPLITZ, **c)
     fs, st_s = _apply(v, t, tn, w, kind, P.NF_STORED, **c)
-    assert torch.equal(ft, fs)
+    fv, st_v = _apply(v, t, tn, w, kind, P.NF_TOEPLITZ, gemm=0, **c)
+    assert st_v["near_gemm_groups"] == 0 and torch.equal(fv, fs)
+    dm = _mode_diff(ft, fs)
+    print(f"[toeplitz] GEMM groups {st_t['near_gemm_groups']}, leaves {st_t['leaves']}: "
+          f"max rel diff to stored {dm:.2e}", flush=True)
+    assert dm <= TOL_MODES
+    assert st_s["near_gemm_groups"] == 0
     assert st_t["device_bytes"] < st_s["device_bytes"]
     r = reference(v, t, tn, w, kind, **c)
     g = ft.numpy()
@@ -53,13 +67,16 @@ def test_toeplitz_vs_oracle_and_stored(case, kind):
 
 
 def test_toeplitz_full_size():
-    """3072 triangles x 256 steps, degrees 6/6: bitwise equal to the stored
-    mode, sampled rows against the oracle, and without the 53.8 GB of blocks."""
+    """3072 triangles x 256 steps, degrees 6/6: equal to the stored mode to
+    1e-13 (GEMM path in use), sampled rows against the oracle, and without the
+    53.8 GB of blocks."""
     print("[toeplitz] full size", flush=True)
     v, t, tn, c, w = config_problem(2)
     ft, st_t = _apply(v, t, tn, w, "V", P.NF_TOEPLITZ)
     fs, st_s = _apply(v, t, tn, w, "V", P.NF_STORED)
-    assert torch.equal(ft, fs)
+    dm = _mode_diff(ft, fs)
+    print(f"[toeplitz] full size: GEMM groups {st_t['near_gemm_groups']}: max rel diff to stored {dm:.2e}", flush=True)
+    assert dm <= TOL_MODES and st_t["near_gemm_groups"] > 0
     assert st_s["device_bytes"] - st_t["device_bytes"] >= 8 * st_s["near_entries"] * 0.99
     tr = Tree(v, t, tn, 1.0, c["n_max"], c["c_st"], c["n_tr"])
     o = FMMOracle(tr, c["m_t"], c["m_x"], "V")
