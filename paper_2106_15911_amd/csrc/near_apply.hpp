@@ -154,13 +154,16 @@ struct NearGemmGroup {
 
 // One workgroup per 16 target steps of a group; its 4 waves take
 // consecutive quarters of the K range and their partial tiles are added
-// through LDS in wave order (fixed order: deterministic results).
+// through LDS in wave order (fixed order: deterministic results).  The
+// group's per-column records are copied to LDS first when they fit
+// (lds_records: capacity in records, 0 = read them from global memory).
 template <int NT>
 __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ table,
                                                    const NearGemmGroup* __restrict__ gg, const int4* __restrict__ ue,
                                                    const double* __restrict__ wd, double* __restrict__ fd, int E_x,
-                                                   int E_t) {
+                                                   int E_t, int lds_records) {
     __shared__ double red[3][NT][4][kWave];
+    extern __shared__ int4 srec[];
     const NearGemmGroup G = gg[blockIdx.x];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int li = lane & 15, lk = lane >> 4;
@@ -168,7 +171,14 @@ __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ ta
     const int kt = kt0 + li;
     const int s0 = (kt / G.s) * G.s;
     const double* T = table + G.toff;
-    const int4* E = ue + G.eoff + (int64_t)((kt / G.s) % G.per) * G.U;   // this target step's phase
+    const int nrec = G.per * G.U;
+    const int4* Eg = ue + G.eoff;
+    const bool in_lds = nrec <= lds_records;   // uniform over the workgroup
+    if (in_lds) {
+        for (int i = threadIdx.x; i < nrec; i += blockDim.x) srec[i] = Eg[i];
+        __syncthreads();
+    }
+    const int4* E = (in_lds ? srec : Eg) + ((kt / G.s) % G.per) * G.U;   // this target step's phase
     d4_t acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = d4_t{0.0, 0.0, 0.0, 0.0};

@@ -801,6 +801,7 @@ struct pfmm_tree {
     NearGemmGroup* ngg = nullptr; // Toeplitz groups applied as GEMMs, sorted by row tiles
     int4* nue = nullptr;          // their per-column records (position, a_u, b_u, 0)
     int ngg_start[5] = {0, 0, 0, 0, 0};   // groups with 1..4 row tiles: [ngg_start[t-1], ngg_start[t])
+    int ngg_rec[4] = {0, 0, 0, 0};        // per row-tile class: most per-column records of a group
     int* nsel = nullptr;          // row groups of the other groups (matrix-vector kernel)
     int64_t n_sel = 0;
     int nf_gemm = 1;              // pfmm_params.nearfield_gemm
@@ -1193,6 +1194,7 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
         t->ngg_start[nt] = (int)all.size();
         for (NearGemmGroup G : gg[nt]) {
             G.eoff += (int64_t)uall.size();
+            t->ngg_rec[nt] = std::max(t->ngg_rec[nt], G.per * G.U);
             all.push_back(G);
         }
         uall.insert(uall.end(), ue[nt].begin(), ue[nt].end());
@@ -1702,10 +1704,14 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
                 if (g1 <= g0) continue;
                 const dim3 grid((unsigned)(g1 - g0), mt);
                 const NearGemmGroup* gp = t->ngg + g0;
-                if (c == 0) hipLaunchKernelGGL(k_near_gemm<1>, grid, dim3(256), 0, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
-                if (c == 1) hipLaunchKernelGGL(k_near_gemm<2>, grid, dim3(256), 0, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
-                if (c == 2) hipLaunchKernelGGL(k_near_gemm<3>, grid, dim3(256), 0, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
-                if (c == 3) hipLaunchKernelGGL(k_near_gemm<4>, grid, dim3(256), 0, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
+                // per-column records in LDS while static (partial tiles: 6 KB per row tile) and dynamic
+                // LDS stay within 64 KB; larger groups read them from memory
+                const int lrec = std::min(t->ngg_rec[c], (65536 - 6144 * (c + 1)) / (int)sizeof(int4));
+                const size_t shm = (size_t)lrec * sizeof(int4);
+                if (c == 0) hipLaunchKernelGGL(k_near_gemm<1>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t, lrec);
+                if (c == 1) hipLaunchKernelGGL(k_near_gemm<2>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t, lrec);
+                if (c == 2) hipLaunchKernelGGL(k_near_gemm<3>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t, lrec);
+                if (c == 3) hipLaunchKernelGGL(k_near_gemm<4>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t, lrec);
             }
             if (t->n_sel > 0)
                 hipLaunchKernelGGL(k_near_toep, dim3((unsigned)((t->n_sel + 3) / 4)), dim3(256), 0, sn, tab, t->groups,
