@@ -1262,13 +1262,14 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         int* axd;
         PF_TRY(upload(t, &axd, ax.data(), ax.size()));
         t->sm = SepMaps{a, kp, ci, ki, axd, P.Nc, P.Nk, P.m_t, P.m_x};
-        // intervals per block of k_m2m_sep / k_l2l_sep: the largest of 4, 2, 1 whose LDS fits 64 KB
+        // intervals per block of k_m2m_sep / k_l2l_sep: the larger of 2, 1 whose LDS fits 64 KB
+        // (4 intervals per block measured slower: fewer, larger blocks, 2 resident per CU at m = 6)
         const size_t tabs = (size_t)(3 * nx1 * nx1) * sizeof(double);
         const int nt1 = P.m_t + 1;
         t->ki_m2m = t->ki_l2l = 0;
-        for (int KI = 4; KI >= 1 && !t->ki_m2m; KI /= 2)
+        for (int KI = 2; KI >= 1 && !t->ki_m2m; KI /= 2)
             if ((3 * (size_t)P.Nc * KI + 2 * KI * nt1 * nt1) * sizeof(double) + tabs <= 65536) t->ki_m2m = KI;
-        for (int KI = 4; KI >= 1 && !t->ki_l2l; KI /= 2)
+        for (int KI = 2; KI >= 1 && !t->ki_l2l; KI /= 2)
             if ((2 * (size_t)P.Nc * KI + 2 * KI * nt1 * nt1) * sizeof(double) + tabs <= 65536) t->ki_l2l = KI;
         if (!t->ki_m2m || !t->ki_l2l) return fail(PFMM_EUNSUPPORTED, "expansion degrees too large for the re-expansion kernels");
         // S2M / L2T leaf blocks (leaves hold at most 64 triangles): stage A_x in
