@@ -430,7 +430,8 @@ def main():
 
     def timed(precision, steps, warmup):
         """warmup untimed applies, then `steps` applies bracketed by device
-        synchronisation (the nearfield runs beside the farfield chain); then
+        synchronisation (in Toeplitz mode the nearfield runs beside the
+        farfield chain); then
         stage times from HIP events on the apply stream over max(3, steps / 4)
         further applies, whose stages the library runs one after another
         while timing them"""

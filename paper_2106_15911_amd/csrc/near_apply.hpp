@@ -4,16 +4,24 @@
 #pragma once
 
 // Nearfield product f[kt, rows] += B * w over the causal columns.  One wave
-// per row group; lane = (column slot, row); partial sums reduced in LDS.
+// per row group; lane = (column slot cs, row r), cpi = 64 / nX column slots;
+// partial sums reduced in LDS.  The source densities of a rectangle's columns
+// are gathered into a per-wave LDS buffer CH = 4 cpi floor(64 / cpi) <= 256
+// columns at a time (one gather per column instead of one per column and
+// lane group), so the vector memory path carries the block stream and little
+// else.  A lane's columns run in trips of four (cs + 4 cpi t + u cpi); a trip
+// never straddles a chunk, and the fma order per lane is the trip order.
 __global__ void __launch_bounds__(256) k_near_apply(const double* __restrict__ B, const double* __restrict__ wd,
                                                     double* __restrict__ fd, NearLayout L) {
     __shared__ double red[256];
+    __shared__ double xsh[256 / kWave][256];
     const int wv = threadIdx.x / kWave;
     const int64_t rg = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
     const int lane = threadIdx.x % kWave;
+    double* xs = xsh[wv];
     double acc = 0.0;
     int nX = 1, cpi = 64, r = 0, cs = 0, kt = 0, t0 = 0;
-    if (rg < L.n_rows) {
+    if (rg < L.n_rows) {   // uniform per wave: the whole wave stages, active lanes multiply
         const int leaf = L.rg_leaf[rg];
         kt = L.rg_kt[rg];
         nX = L.lf_nx[leaf];
@@ -21,38 +29,53 @@ __global__ void __launch_bounds__(256) k_near_apply(const double* __restrict__ B
         cpi = kWave / nX;
         cs = lane / nX;
         r = lane % nX;
-        if (cs < cpi) {
-            const double* blk = B + L.rg_boff[rg];
-            int64_t colbase = 0;
-            for (int q = L.lf_rect0[leaf]; q < L.lf_rect1[leaf]; ++q) {
-                const int j0 = L.rc_j0[q];
-                const int ns = min(L.rc_j1[q], kt + 1) - j0;
-                if (ns <= 0) continue;
-                const int S = L.set_size[L.rc_set[q]];
-                const int* pos = L.set_pos + L.set_off[L.rc_set[q]];
-                const int64_t total = (int64_t)ns * S;
-                int jt = j0, i = cs;
-                while (i >= S) { i -= S; ++jt; }
-                // four columns per trip with independent loads; the block stream
-                // is read once (non-temporal), the densities stay in L2
-                for (int64_t c = cs; c < total; c += 4 * cpi) {
-                    double bv[4], xv[4];
+        const int CH = 4 * cpi * (kWave / cpi);   // columns per chunk, a whole number of trips
+        const bool act = cs < cpi;
+        const double* blk = B + L.rg_boff[rg];
+        int64_t colbase = 0;
+        for (int q = L.lf_rect0[leaf]; q < L.lf_rect1[leaf]; ++q) {
+            const int j0 = L.rc_j0[q];
+            const int ns = min(L.rc_j1[q], kt + 1) - j0;
+            if (ns <= 0) continue;
+            const int S = L.set_size[L.rc_set[q]];
+            const int* pos = L.set_pos + L.set_off[L.rc_set[q]];
+            const int total = ns * S;   // at most E_t * E_x
+            for (int base = 0; base < total; base += CH) {
+                // the previous chunk's reads are done before the buffer is refilled
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int64_t cc = c + u * cpi;
-                        const bool ok = cc < total;
-                        const int64_t ce = ok ? cc : cs;
-                        bv[u] = __builtin_nontemporal_load(&blk[(colbase + ce) * nX + r]);
-                        xv[u] = wd[(int64_t)(ok ? jt : j0) * L.E_x + pos[ok ? i : 0]];
-                        bv[u] = ok ? bv[u] : 0.0;
-                        i += cpi;
-                        while (i >= S) { i -= S; ++jt; }
+                for (int k = 0; k < 4; ++k) {
+                    const int cl = lane + kWave * k;
+                    const int c = base + cl;
+                    if (cl < CH && c < total) {
+                        const int d = c / S;   // column c = (source step j0 + d, triangle pos[c - d S])
+                        xs[cl] = wd[(int64_t)(j0 + d) * L.E_x + pos[c - d * S]];
                     }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) acc = fma(bv[u], xv[u], acc);
                 }
-                colbase += total;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (act) {
+                    // four columns per trip with independent loads; the block
+                    // stream is read once (non-temporal)
+                    const int cend = min(total, base + CH);
+                    for (int c = base + cs; c < cend; c += 4 * cpi) {
+                        double bv[4], xv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int cc = c + u * cpi;
+                            const bool ok = cc < total;
+                            bv[u] = __builtin_nontemporal_load(&blk[(colbase + (ok ? cc : cs)) * nX + r]);
+                            xv[u] = ok ? xs[cc - base] : 0.0;
+                            bv[u] = ok ? bv[u] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc = fma(bv[u], xv[u], acc);
+                    }
+                }
             }
+            colbase += total;
         }
     }
     red[threadIdx.x] = acc;

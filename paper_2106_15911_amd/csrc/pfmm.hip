@@ -1605,7 +1605,12 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             if (lnx[i] > kWave) return fail(PFMM_EUNSUPPORTED, "a leaf holds more than 64 triangles (lower n_max)");
         }
         std::vector<int> j0(P.rects.size()), j1(P.rects.size()), rs(P.rects.size());
-        for (size_t i = 0; i < P.rects.size(); ++i) { j0[i] = P.rects[i].j0; j1[i] = P.rects[i].j1; rs[i] = P.rects[i].set; }
+        for (size_t i = 0; i < P.rects.size(); ++i) {
+            j0[i] = P.rects[i].j0; j1[i] = P.rects[i].j1; rs[i] = P.rects[i].set;
+            // the nearfield kernels count a rectangle's columns in 32 bits
+            if ((int64_t)(j1[i] - j0[i]) * P.set_size[rs[i]] > (int64_t)INT32_MAX)
+                return fail(PFMM_EUNSUPPORTED, "a nearfield rectangle has more than 2^31 - 1 columns");
+        }
         NearLayout& NL = t->nl;
         int *a1, *a2, *a4, *a5, *a6, *a7, *a8, *a9, *a10, *a11, *a12, *a13, *a14;
         int64_t* a3;
@@ -1686,14 +1691,17 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
     prof_begin(t, 0, st, ev);
     hipLaunchKernelGGL(k_permute_in, dim3(nb), dim3(256), 0, st, w, t->wd, t->inv_sigma, P.E_x, N);
     prof_end(t, st, ev);
-    // The nearfield product needs only the permuted densities: it runs on the
-    // side stream into fn while the farfield chain fills fd, and the two meet
-    // in the final permutation.  With stage timing on, or while st is being
-    // captured into a graph (batched applies, whose branches already run trees
-    // side by side), both run in order on st: same kernels, same results.
+    // The nearfield product needs only the permuted densities: in Toeplitz
+    // mode it runs on the side stream into fn while the farfield chain fills
+    // fd, and the two meet in the final permutation.  The stored-block product
+    // runs in order: it streams HBM at close to the read rate, and beside the
+    // upward pass it slowed that pass by more than it hid (measured).  With
+    // stage timing on, or while st is being captured into a graph (batched
+    // applies, whose branches already run trees side by side), both run in
+    // order on st: same kernels, same results.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(st, &cap));
-    const bool fork = !t->prof && cap == hipStreamCaptureStatusNone;
+    const bool fork = !t->prof && cap == hipStreamCaptureStatusNone && t->nf_mode == PFMM_NF_TOEPLITZ;
     auto nearfield = [&](hipStream_t sn) {
         const int64_t nrg = (int64_t)P.rows.size();
         hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, sn, t->fn, 0.0, N);

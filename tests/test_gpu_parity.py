@@ -76,9 +76,10 @@ def test_deterministic_and_errors():
 
 @pytest.mark.parametrize("mode", ["stored", "toeplitz"])
 def test_nearfield_beside_farfield_equals_in_order(mode):
-    """The apply that runs the nearfield on a side stream (default) and the
-    in-order apply (stage timing on) give bitwise equal results, for V and K,
-    on a tree with a deep farfield (m = 6, matrix-core M2L on several levels)."""
+    """The default apply (Toeplitz mode: nearfield on a side stream; stored
+    mode: in order) and the in-order apply with stage timing on give bitwise
+    equal results, for V and K, on a tree with a deep farfield (m = 6,
+    matrix-core M2L on several levels)."""
     print(f"[parity] side-stream nearfield vs in order, {mode}", flush=True)
     v, t, tn, w = problem(6, 128, seed=9)
     nf = P.NF_TOEPLITZ if mode == "toeplitz" else P.NF_STORED
