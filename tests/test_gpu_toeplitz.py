@@ -66,14 +66,31 @@ def test_toeplitz_vs_oracle_and_stored(case, kind):
     assert e <= TOL and m <= TOL, (e, m)
 
 
+@pytest.mark.parametrize("n,E_t,n_max", [(4, 64, 4), (6, 128, 8), (8, 64, 16), (4, 256, 64)])
+def test_stored_bitwise_equal_to_toeplitz_vector_kernel(n, E_t, n_max):
+    """Leaves of 1 to 64 triangles (n_max from 4 to 64): the stored-block
+    product (densities staged per wave in LDS) and the Toeplitz matrix-vector
+    kernel (one density gather per lane and column) take the same products
+    in the same order, so they agree bit for bit, V and K."""
+    print(f"[toeplitz] stored vs vector kernel n={n} E_t={E_t} n_max={n_max}", flush=True)
+    v, t, tn, w = problem(n, E_t, seed=29)
+    for kind in ("V", "K"):
+        fs, _ = _apply(v, t, tn, w, kind, P.NF_STORED, m_t=3, m_x=3, n_max=n_max)
+        fv, st = _apply(v, t, tn, w, kind, P.NF_TOEPLITZ, gemm=0, m_t=3, m_x=3, n_max=n_max)
+        assert st["near_gemm_groups"] == 0
+        assert torch.equal(fs, fv), (kind, _mode_diff(fs, fv))
+
+
 def test_toeplitz_full_size():
     """3072 triangles x 256 steps, degrees 6/6: equal to the stored mode to
-    1e-13 (GEMM path in use), sampled rows against the oracle, and without the
-    53.8 GB of blocks."""
+    1e-13 (GEMM path in use) and bit for bit with nearfield_gemm = 0, sampled
+    rows against the oracle, and without the 53.8 GB of blocks."""
     print("[toeplitz] full size", flush=True)
     v, t, tn, c, w = config_problem(2)
     ft, st_t = _apply(v, t, tn, w, "V", P.NF_TOEPLITZ)
     fs, st_s = _apply(v, t, tn, w, "V", P.NF_STORED)
+    fv, _ = _apply(v, t, tn, w, "V", P.NF_TOEPLITZ, gemm=0)
+    assert torch.equal(fv, fs)   # same products, same order per lane
     dm = _mode_diff(ft, fs)
     print(f"[toeplitz] full size: GEMM groups {st_t['near_gemm_groups']}: max rel diff to stored {dm:.2e}", flush=True)
     assert dm <= TOL_MODES and st_t["near_gemm_groups"] > 0
