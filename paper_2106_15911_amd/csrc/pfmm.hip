@@ -1545,11 +1545,18 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
                     per_cu = std::max<int>(1, (int)(160 * 1024 / std::max<size_t>(1, t->wide[q][v].shm)));
                 }
                 // Levels with fewer than 4 workgroups per CU split their source
-                // lists into ns shares (1..4): the share minimising the rounds
-                // of resident workgroups per share, ceil(wg ns / (ncu per_cu)) / ns,
-                // plus 2% per extra partial buffer to sum.
+                // lists into ns shares.  Wide kernels: enough shares for about
+                // eight rounds of resident workgroups, ns = ceil(8 slots / wg) <= 8
+                // (workgroup times vary with the list lengths, and finer shares
+                // balance them; at 3072 x 256, levels 5 and 6: 26.0 ms at 3 shares,
+                // 25.2 at 4, 25.4 at 6, 25.5 at 8).  Others (1..4): the share
+                // minimising the rounds of resident workgroups per share,
+                // ceil(wg ns / (ncu per_cu)) / ns, plus 2% per extra partial buffer.
                 D.nsplit_q[q] = 1;
-                if (wg < 4 * ncu) {
+                if (wg < 4 * ncu && D.m2l_nb[q]) {
+                    const int64_t slots = (int64_t)ncu * per_cu;
+                    D.nsplit_q[q] = (int)std::min<int64_t>(8, std::max<int64_t>(1, (8 * slots + wg - 1) / wg));
+                } else if (wg < 4 * ncu) {
                     double best = 1e30;
                     for (int ns = 1; ns <= 4; ++ns) {
                         const int64_t slots = (int64_t)ncu * per_cu;
