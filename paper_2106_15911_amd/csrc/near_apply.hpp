@@ -6,22 +6,33 @@
 // Nearfield product f[kt, rows] += B * w over the causal columns.  One wave
 // per row group; lane = (column slot cs, row r), cpi = 64 / nX column slots;
 // partial sums reduced in LDS.  The source densities of a rectangle's columns
-// are gathered into a per-wave LDS buffer CH = 4 cpi floor(64 / cpi) <= 256
-// columns at a time (one gather per column instead of one per column and
-// lane group), so the vector memory path carries the block stream and little
-// else.  A lane's columns run in trips of four (cs + 4 cpi t + u cpi); a trip
-// never straddles a chunk, and the fma order per lane is the trip order.
+// are gathered into LDS CH = 4 cpi floor(64 / cpi) <= 256 columns at a time
+// (one gather per column instead of one per column and lane group), so the
+// vector memory path carries the block stream and little else.  When the
+// workgroup's four row groups are steps of one leaf (consecutive in the row
+// list), the workgroup stages each chunk once for all four (the longest
+// row's columns); otherwise every wave stages its own.  A lane's columns run
+// in trips of four (cs + 4 cpi t + u cpi); a trip never straddles a chunk,
+// and the fma order per lane is the trip order either way.
 __global__ void __launch_bounds__(256) k_near_apply(const double* __restrict__ B, const double* __restrict__ wd,
                                                     double* __restrict__ fd, NearLayout L) {
     __shared__ double red[256];
     __shared__ double xsh[256 / kWave][256];
     const int wv = threadIdx.x / kWave;
-    const int64_t rg = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
+    const int64_t rg0 = (int64_t)blockIdx.x * (blockDim.x / kWave);
+    const int64_t rg = rg0 + wv;
     const int lane = threadIdx.x % kWave;
-    double* xs = xsh[wv];
     double acc = 0.0;
     int nX = 1, cpi = 64, r = 0, cs = 0, kt = 0, t0 = 0;
-    if (rg < L.n_rows) {   // uniform per wave: the whole wave stages, active lanes multiply
+    // one leaf for the whole workgroup?  (same answer in every thread)
+    bool one_leaf = rg0 + 3 < L.n_rows;
+    int ktmax = 0;
+    if (one_leaf) {
+        const int l0 = L.rg_leaf[rg0];
+        for (int k = 1; k < 4; ++k) one_leaf = one_leaf && L.rg_leaf[rg0 + k] == l0;
+        for (int k = 0; k < 4; ++k) ktmax = max(ktmax, L.rg_kt[rg0 + k]);
+    }
+    if (rg < L.n_rows) {   // uniform per wave (and per workgroup when one_leaf)
         const int leaf = L.rg_leaf[rg];
         kt = L.rg_kt[rg];
         nX = L.lf_nx[leaf];
@@ -32,31 +43,45 @@ __global__ void __launch_bounds__(256) k_near_apply(const double* __restrict__ B
         const int CH = 4 * cpi * (kWave / cpi);   // columns per chunk, a whole number of trips
         const bool act = cs < cpi;
         const double* blk = B + L.rg_boff[rg];
+        double* xs = one_leaf ? xsh[0] : xsh[wv];
         int64_t colbase = 0;
         for (int q = L.lf_rect0[leaf]; q < L.lf_rect1[leaf]; ++q) {
             const int j0 = L.rc_j0[q];
-            const int ns = min(L.rc_j1[q], kt + 1) - j0;
-            if (ns <= 0) continue;
             const int S = L.set_size[L.rc_set[q]];
             const int* pos = L.set_pos + L.set_off[L.rc_set[q]];
-            const int total = ns * S;   // at most E_t * E_x
-            for (int base = 0; base < total; base += CH) {
-                // the previous chunk's reads are done before the buffer is refilled
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int cl = lane + kWave * k;
-                    const int c = base + cl;
-                    if (cl < CH && c < total) {
+            const int ns = min(L.rc_j1[q], kt + 1) - j0;
+            const int total = ns > 0 ? ns * S : 0;   // this row group's columns (at most E_t * E_x)
+            // columns staged: this row group's, or the workgroup's longest
+            const int nsm = one_leaf ? min(L.rc_j1[q], ktmax + 1) - j0 : ns;
+            if (nsm <= 0) continue;
+            const int tstage = nsm * S;
+            for (int base = 0; base < tstage; base += CH) {
+                if (one_leaf) {
+                    __syncthreads();   // every wave is done with the previous chunk
+                    const int c = base + (int)threadIdx.x;
+                    if ((int)threadIdx.x < CH && c < tstage) {
                         const int d = c / S;   // column c = (source step j0 + d, triangle pos[c - d S])
-                        xs[cl] = wd[(int64_t)(j0 + d) * L.E_x + pos[c - d * S]];
+                        xs[threadIdx.x] = wd[(int64_t)(j0 + d) * L.E_x + pos[c - d * S]];
                     }
+                    __syncthreads();
+                } else {
+                    // the previous chunk's reads are done before the buffer is refilled
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int cl = lane + kWave * k;
+                        const int c = base + cl;
+                        if (cl < CH && c < tstage) {
+                            const int d = c / S;
+                            xs[cl] = wd[(int64_t)(j0 + d) * L.E_x + pos[c - d * S]];
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (act) {
+                if (act && base < total) {
                     // four columns per trip with independent loads; the block
                     // stream is read once (non-temporal)
                     const int cend = min(total, base + CH);
