@@ -1,12 +1,19 @@
-"""Benchmark: space-time DOF-matvecs/s of the pFMM single-layer apply on one MI355X.
+"""Benchmark: space-time DOF-matvecs/s of the pFMM single-layer apply on one
+MI355X, and the Dirichlet solve time against plain GMRES.
 
-Workload: the surface of the cube [-1,1]^3 with 16 x 16 squares per face
-(3072 triangles) x 256 uniform steps on [0, 1] (786,432 space-time DOFs),
-alpha = 1, Chebyshev degree 6 in space, Lagrange degree 6 in time, leaves
-below 64 elements, c_st = 0.9, n_tr = 5, FP64 everywhere; densities i.i.d.
-U(-1, 1) from seed 2.  A step is one full V_h apply (Algorithm 2) from a
-device-resident density to a device-resident result; tree build and
-nearfield assembly happen before the timed region and are reported apart.
+Default workload: the surface of the cube [-1,1]^3 with 16 x 16 squares per
+face (3072 triangles) x 1024 uniform steps on [0, 1] (3,145,728 space-time
+DOFs), alpha = 1, Chebyshev degree 6 in space, Lagrange degree 6 in time,
+leaves below 64 elements, c_st = 0.9, n_tr = 5; densities i.i.d. U(-1, 1)
+from seed 3.  A step is one full V_h apply (Algorithm 2) from a
+device-resident density to a device-resident result, FP64 throughout; tree
+build and nearfield assembly happen before the timed region and are
+reported apart.  The same tree also runs the FP32 and BF16-input farfields,
+whose error against the FP64 apply is measured (the "1e-6 rel err" of the
+metric).  Then, unless switched off: the 3072 x 256 workload as a secondary
+figure, and the Dirichlet solve on the 12,288-triangle x 512-step cube
+(learned preconditioner with FP32 inner applies against plain FP64 GMRES,
+both to an FP64 relative residual of 1e-8).
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits with a
 message.
@@ -25,55 +32,55 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3     # dense FP32 matrix-core peak
 
-# HBM bytes per apply from rocprofv3 FETCH_SIZE / WRITE_SIZE runs on the
-# 3072 x 256, m = 6 workload (FP64 farfield), scaled by the same counters on a
-# plain 1 GiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Each entry
-# is valid only for the sources it was taken on (sha256 prefixes of the
+# HBM bytes per apply from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (all
+# launches of the kernel in one apply), scaled by the same counters on a
+# plain 1 GiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Each
+# entry is valid only for the sources it was taken on (sha256 prefixes of the
 # kernel file and of the file that plans and launches it); any change to
 # them reports null.
-TRAFFIC = {
-    "m2l": {"files": {"m2l_kernels.hpp": "e38d10d4f4c24a9f", "pfmm.hip": "fd115eecd436e06d"}, "config": 2,
-            "precision": "fp64", "bytes": 39160588288.0},
-    "k_near_apply": {"files": {"near_apply.hpp": "874d6bbd4da69cef", "pfmm.hip": "fd115eecd436e06d"}, "config": 2,
-                     "bytes": 53940300800.0},
-}
+TRAFFIC = []
 
 
 def measured_traffic(kernel, cfg, precision="fp64"):
     """HBM bytes per apply from the rocprofv3 counters, while the sources the
     counters were taken on (kernel and launch configuration) are unchanged."""
     import hashlib
-    e = TRAFFIC.get(kernel)
-    if e is None or e["bytes"] is None or e["config"] != cfg or e.get("precision", precision) != precision:
-        return None
-    for name, prefix in e["files"].items():
-        with open(os.path.join(ROOT, "paper_2106_15911_amd", "csrc", name), "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest()[:16] != prefix:
-                return None
-    return e["bytes"]
+    for e in TRAFFIC:
+        if e["kernel"] != kernel or e["config"] != cfg or e.get("precision", precision) != precision:
+            continue
+        for name, prefix in e["files"].items():
+            with open(os.path.join(ROOT, "paper_2106_15911_amd", "csrc", name), "rb") as fh:
+                if hashlib.sha256(fh.read()).hexdigest()[:16] != prefix:
+                    return None
+        return e["bytes"]
+    return None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, w, per_level=12, leaves=12, seed=123):
-    """The CPU oracle's full V_h apply, timed on a bounded sample and scaled.
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    The oracle's apply is a loop over boxes: moments of every box (timed in
-    full), then per level the M2L and L2L of each box, then per leaf the L2T
-    and the nearfield blocks.  A random sample of boxes per level and of
-    leaves is timed and scaled by the number of boxes.
-    """
+
+def _oracle_sample(tr, o, w, rng, per_level, n_leaves, n_rows):
+    """One timed pass of the oracle's V_h apply on a bounded sample:
+    moments of every box (the upward pass, in full), M2L + L2L of
+    `per_level` random boxes per level, L2T of `n_leaves` random leaves, and
+    the nearfield of `n_rows` random rows, its panel integrals (assembly)
+    timed apart from the row sums (apply).  Returns the timings and the
+    estimate of one full apply (each sampled part scaled by its count)."""
     import numpy as np
-    from oracle.fmm import FMMOracle
-    from oracle.tree import Tree
-    from workloads import config_problem
-    v, t, tn, c, _ = config_problem(cfg)
-    rng = np.random.default_rng(seed)
+    N = tr.E_t * tr.E_x
     t0 = time.perf_counter()
-    tr = Tree(v, t, tn, 1.0, c["n_max"], c["c_st"], c["n_tr"])
-    o = FMMOracle(tr, c["m_t"], c["m_x"], "V")
     mu = o.moments(w)
     t_up = time.perf_counter() - t0
     est, timed, n_far = t_up, t_up, 0
@@ -90,30 +97,83 @@ def cpu_baseline(cfg, w, per_level=12, leaves=12, seed=123):
         timed += dt
         n_far += len(pick)
         est += dt * len(boxes) / len(pick)
-    pick = rng.choice(len(tr.leaves), leaves, replace=False)
-    memo = {}
+    pick = rng.choice(len(tr.leaves), n_leaves, replace=False)
     t0 = time.perf_counter()
     for i in pick:
         Z = tr.leaves[int(i)]
-        rows = tr.elements(Z)
-        f = o.l2t(Z, np.zeros((c["m_t"] + 1, o.Nk))).ravel()
-        for S in tr.nearfield(Z, memo):
-            f = f + o.near_block(Z, S) @ w[tr.elements(S)]
+        o.l2t(Z, np.zeros((o.m_t + 1, o.Nk)))
     dt = time.perf_counter() - t0
     timed += dt
-    est += dt * len(tr.leaves) / leaves
+    est += dt * len(tr.leaves) / n_leaves
+    # nearfield rows: entries (assembly) apart from the sums (apply)
+    leaf = tr.leaf_of_element()
+    by_id = {b.id: b for b in tr.leaves}
+    memo = {}
+    t_asm = t_near = 0.0
+    n_int = 0
+    for r in rng.choice(N, n_rows, replace=False):
+        Z = by_id[int(leaf[r])]
+        kt, kx = divmod(int(r), tr.E_x)
+        srcs = [S for S in tr.nearfield(Z, memo) if S.s0 <= kt]
+        dmax = kt - min(S.s0 for S in srcs)
+        jx_all = np.unique(np.concatenate([S.tris for S in srcs]))
+        t0 = time.perf_counter()
+        ent = o.entries(np.full(len(jx_all), kx), jx_all, dmax)
+        t_asm += time.perf_counter() - t0
+        n_int += ent.size
+        where = {int(j): i for i, j in enumerate(jx_all)}
+        t0 = time.perf_counter()
+        acc = 0.0
+        for S in srcs:
+            idx = np.array([where[int(j)] for j in S.tris])
+            for jt in range(S.s0, min(S.s1, kt + 1)):
+                acc += ent[idx, kt - jt] @ w[jt * tr.E_x + S.tris]
+        t_near += time.perf_counter() - t0
+    timed += t_near
+    est += t_near * N / n_rows
+    return dict(upward_s=t_up, timed_apply_s=timed, est_apply_s=est, n_far_boxes=n_far, n_leaves=int(n_leaves),
+                n_rows=int(n_rows), assembly_sample_s=t_asm, assembly_integrals=int(n_int))
+
+
+def cpu_baseline(cfg, w, distinct_integrals, per_level=8, leaves=8, rows=8, seed=123):
+    """The CPU oracle's V_h apply on the same workload and inputs, timed on a
+    bounded sample and scaled to one full apply, with all host threads and
+    with one thread; its nearfield assembly (the panel integrals) is timed
+    apart and scaled by the distinct integrals the tree needs, like the
+    GPU's assembly, which the timed GPU apply excludes too."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    import numpy as np
+    from oracle.fmm import FMMOracle
+    from oracle.tree import Tree
+    from workloads import config_problem
+    v, t, tn, c, _ = config_problem(cfg)
     N = len(w)
-    try:
-        from threadpoolctl import threadpool_info
-        blas = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        blas = 1
-    return {"value": N / est, "unit": "DOF-matvec/s", "cores": int(blas), "kind": "oracle",
-            "sample": (f"oracle V_h apply on {N} DOFs: tree + all moments ({t_up:.1f} s) in full; M2L+L2L of "
-                       f"{n_far} sampled boxes (up to {per_level} per level) and L2T+nearfield of {leaves} "
-                       f"sampled leaves ({timed - t_up:.1f} s), scaled by box counts; estimated full apply "
-                       f"{est:.0f} s"),
-            "timed_s": timed, "host_cpus": os.cpu_count()}
+    t0 = time.perf_counter()
+    tr = Tree(v, t, tn, 1.0, c["n_max"], c["c_st"], c["n_tr"])
+    t_tree = time.perf_counter() - t0
+    blas = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    runs = {}
+    for label, nthr in (("all_threads", blas), ("one_thread", 1)):
+        o = FMMOracle(tr, c["m_t"], c["m_x"], "V")
+        with threadpool_limits(limits=nthr):
+            runs[label] = _oracle_sample(tr, o, w, np.random.default_rng(seed), per_level, leaves, rows)
+        runs[label]["threads"] = nthr
+        runs[label]["value"] = N / runs[label]["est_apply_s"]
+        log(f"[bench] cpu oracle ({label}): {runs[label]}")
+    a = runs["all_threads"]
+    per_int = a["assembly_sample_s"] / max(a["assembly_integrals"], 1)
+    return {"value": a["value"], "unit": "DOF-matvec/s", "cores": int(blas), "kind": "oracle",
+            "sample": (f"oracle V_h apply on the same {N} DOFs: upward pass (moments of every box) in full "
+                       f"({a['upward_s']:.1f} s); M2L+L2L of {a['n_far_boxes']} random boxes (up to {per_level} per "
+                       f"level), L2T of {leaves} random leaves and the nearfield row sums of {rows} random rows, each "
+                       f"scaled by its count; estimated full apply {a['est_apply_s']:.0f} s; panel integrals of the "
+                       f"sampled rows timed apart (assembly)"),
+            "one_thread_value": runs["one_thread"]["value"], "one_thread_est_apply_s": runs["one_thread"]["est_apply_s"],
+            "timed_s": a["timed_apply_s"] + runs["one_thread"]["timed_apply_s"], "tree_s": t_tree,
+            "assembly": {"sampled_integrals": a["assembly_integrals"], "sampled_s": a["assembly_sample_s"],
+                         "s_per_integral": per_int, "tree_distinct_integrals": int(distinct_integrals),
+                         "est_full_s": per_int * distinct_integrals},
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(), "blas_threads": int(blas), "runs": runs}
 
 
 def oracle_rows(cfg, w, rows, seed=123):
@@ -265,26 +325,7 @@ def solve_bench(args):
         "train_s": t_train, "train_loss": loss, "precond_apply_ms": t_apply, "seed_runs": seed_runs,
         "stencil_train_s": t_train_st, "stencil_fit_residual": loss_st, "build_V_s": t_bv, **prep, "tree": st,
     }
-    print(json.dumps(out), flush=True)
-
-
-def supported_steps(v, t, e, P):
-    """The step count of the batched workload's problem: the supported count
-    nearest to the drawn E_t (ties to the larger).  Supported: the time
-    levels of the tree split evenly (equal intervals per level) and no leaf
-    holds more than 64 triangles (a time interval of one step is not
-    refined further, so coarse steps on a fine mesh can leave large leaves)."""
-    from workloads import uniform_time_nodes
-    for dist in range(0, 4 * e):
-        for ee in (e + dist, e - dist):
-            if ee < 8 or (dist == 0 and ee != e + dist) or ee % 8:
-                continue
-            try:
-                P.plan_stats(v, t, uniform_time_nodes(ee), P.default_params(operators=1))
-                return ee
-            except P.PfmmError:
-                continue
-    raise RuntimeError(f"no supported step count near {e}")
+    return out
 
 
 def batch_bench(args):
@@ -299,8 +340,7 @@ def batch_bench(args):
     t0 = time.perf_counter()
     for i, (n, e) in enumerate(batch_sizes(4, 48)):
         v, t = cube_surface_mesh(n)
-        ee = supported_steps(v, t, e, P)
-        probs.append((n, e, ee, v, t, densities(ee * len(t), 4000 + i)))
+        probs.append((n, e, e, v, t, densities(e * len(t), 4000 + i)))
     probs.sort(key=lambda p: -p[2] * len(p[4]))     # largest first (graph branches)
     log(f"[batch] sampled and sized 48 problems in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
@@ -350,10 +390,10 @@ def batch_bench(args):
         "dtype": {"fp64": "f64", "fp32": "f32 M2L + f64", "bf16": "bf16-input M2L + f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": ("48 independent V_h applies on cube surfaces, face grids n ~ U{4..32}, steps "
-                                "E_t ~ U{32..512} from default_rng(4), E_t rounded to the nearest multiple of 2^k "
-                                "whose time levels split evenly; m_t = m_x = 6, n_max 64, c_st 0.9, n_tr 5, "
-                                "Toeplitz nearfield"),
-                   "dofs": N, "problems": [[p[0], p[1], p[2]] for p in probs], "parallelism": "single GPU"},
+                                "E_t ~ U{32..512} from default_rng(4), as drawn (uneven time levels split at the "
+                                "middle step); m_t = m_x = 6, n_max 64, c_st 0.9, n_tr 5, Toeplitz nearfield"),
+                   "dofs": N, "problems": [[p[0], p[1]] for p in probs], "parallelism": "single GPU",
+                   "time_classes": [tr.stats()["n_time_classes"] for tr in trees]},
         "sequential_ms": ms_seq, "bitwise_equal_to_single_applies": same, "build_s": t_build, "device_bytes": mem,
     }
     print(json.dumps(out), flush=True)
@@ -367,7 +407,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3,
+                    help="2: 3072 x 256, 3: 3072 x 1024 (the default), 4: the 48-problem batch")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="farfield precision: fp64, or fp32 (M2L with FP32 inputs and accumulation; "
                          "the error against the FP64 apply on the same tree is measured and reported)")
@@ -382,6 +423,9 @@ def main():
     ap.add_argument("--pc-seeds", type=int, default=3, help="training seeds whose solves are reported")
     ap.add_argument("--solve", action="store_true",
                     help="instead of the apply benchmark: Dirichlet solve on the 12,288 x 512 cube (config 5)")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 3072 x 256 secondary measurement")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the Dirichlet solve measurement that follows the apply benchmark")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=300)
     args = ap.parse_args()
@@ -390,9 +434,8 @@ def main():
               "(distributing time slices over GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     if args.solve:
-        if args.config == 2:
-            args.config = 5
-        solve_bench(args)
+        args.config = 5
+        print(json.dumps(solve_bench(args)), flush=True)
         return
     if args.config == 4:
         batch_bench(args)
@@ -488,6 +531,16 @@ def main():
                                "(exact products, FP32 accumulation); everything else FP64")
     log(f"[bench] other precisions: {other_precision}")
     tree.set_precision(names[args.precision])
+    # the metric's "at 1e-6 rel err": the fastest farfield precision whose
+    # measured relative 2-norm error against the FP64 apply stays within 1e-6
+    cands = [("fp64", N / (ms_per_step * 1e-3) if args.precision == "fp64" else other_precision["fp64"]["value"], 0.0)]
+    for name in ("fp32", "bf16"):
+        e = (other_precision[name]["error"] if name in other_precision else mixed_err)["rel_2norm_vs_fp64"]
+        val = other_precision[name]["value"] if name in other_precision else N / (ms_per_step * 1e-3)
+        if e <= 1e-6:
+            cands.append((name, val, e))
+    best = max(cands, key=lambda q: q[1])
+    at_1e6 = {"precision": best[0], "value": best[1], "unit": "DOF-matvec/s", "rel_2norm_vs_fp64": best[2]}
 
     # the same product with the Toeplitz nearfield (no stored blocks), on a tree of its own
     toeplitz = None
@@ -557,7 +610,7 @@ def main():
         log(f"[bench] oracle rows check: {check}")
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.config, w)
+        cpu = cpu_baseline(args.config, w, st["distinct_integrals"])
         log(f"[bench] cpu baseline: {cpu}")
 
     out = {
@@ -580,6 +633,7 @@ def main():
                                    "bf16": "M2L with BF16 inputs and FP32 accumulation, rest FP64"}[args.precision]),
                    "dofs": N, "parallelism": "single GPU", "precision": args.precision},
         "mixed_error": mixed_err,
+        "at_1e-6_rel_err": at_1e6,
         "other_precision": other_precision,
         "toeplitz_nearfield": toeplitz,
         "roofline": roof,
@@ -590,8 +644,55 @@ def main():
         "oracle_check": check,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
     tree.close()
+    del x
+    torch.cuda.empty_cache()
+    if args.config == 3 and not args.no_secondary:
+        # the 3072 x 256 workload (FP64, stored nearfield) as a secondary figure
+        v2, t2, tn2, c2, w2 = config_problem(2)
+        prm2 = P.default_params(m_t=c2["m_t"], m_x=c2["m_x"], n_max=c2["n_max"], c_st=c2["c_st"],
+                                n_tr=c2["n_tr"], operators=1)
+        tree2 = P.Tree(v2, t2, tn2, prm2, device=0, stream=stream)
+        x2 = torch.from_numpy(w2).to(dev)
+        y2 = torch.empty_like(x2)
+        for _ in range(max(1, args.warmup)):
+            tree2.apply_V(x2, out=y2, stream=stream)
+        torch.cuda.synchronize()
+        n2 = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(n2):
+            tree2.apply_V(x2, out=y2, stream=stream)
+        torch.cuda.synchronize()
+        ms2 = 1e3 * (time.perf_counter() - t0) / n2
+        tree2.profile_enable(True)
+        for _ in range(3):
+            tree2.apply_V(x2, out=y2, stream=stream)
+        torch.cuda.synchronize()
+        p2 = tree2.profile_read()
+        st2 = tree2.stats()
+        m2l2 = p2["m2l"][0] / max(p2["m2l"][1], 1)
+        nf2 = p2["nearfield"][0] / max(p2["nearfield"][1], 1)
+        flop2 = 2.0 * (c2["m_t"] + 1) ** 2 * comb(c2["m_x"] + 6, 6) * st2["m2l_pairs"]
+        out["secondary"] = {
+            "workload": f"V_h apply, FP64, {len(t2)} triangles x {c2['n_steps']} steps (cube 16x16 squares/face), "
+                        f"m_t = m_x = 6, stored nearfield", "dofs": len(w2), "ms_per_step": ms2,
+            "value": len(w2) / (ms2 * 1e-3), "m2l_ms": m2l2, "m2l_frac_fp64_peak": flop2 / (m2l2 * 1e-3) / 1e12 / FP64_PEAK_TFS,
+            "nearfield_ms": nf2, "nearfield_GBs": (8.0 * st2["near_entries"] + 16.0 * len(w2)) / (nf2 * 1e-3) / 1e9,
+            "stages_ms_per_apply": {k: (vv[0] / max(vv[1], 1)) for k, vv in p2.items()}}
+        log(f"[bench] secondary: {out['secondary']}")
+        tree2.close()
+        del x2, y2
+        torch.cuda.empty_cache()
+    if not args.no_solve:
+        # the second half of the metric: GMRES time to solution, learned
+        # preconditioner + FP32 inner applies against plain FP64 GMRES
+        sargs = argparse.Namespace(**vars(args))
+        sargs.config = 5
+        sv = solve_bench(sargs)
+        out["solve"] = {k: sv[k] for k in ("metric", "value", "unit", "iterations", "converged", "true_rel_residual",
+                                           "plain_fp64", "speedup_vs_plain", "runs", "seed_runs", "train_s",
+                                           "precond_apply_ms", "config")}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

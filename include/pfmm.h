@@ -104,7 +104,8 @@ typedef struct {
     int32_t  n_levels_far;       /* levels >= 2 that carry expansions                */
     int64_t  boxes;              /* boxes of the tree (all levels)                   */
     int64_t  leaves;             /* leaf boxes                                       */
-    int64_t  near_entries;       /* stored causal nearfield entries per operator     */
+    int64_t  near_entries;       /* causal nearfield entries of one operator's blocks
+                                    (the block layout is the same for V_h and K_h)  */
     int64_t  m2l_pairs;          /* (target, source) pairs of all interaction lists  */
     int64_t  near_row_groups;    /* (leaf, time step) row groups of the nearfield    */
     int64_t  distinct_integrals; /* entries of the distinct panel-integral table    */
@@ -114,6 +115,17 @@ typedef struct {
     int32_t  near_gemm_groups;   /* Toeplitz nearfield: leaf spatial boxes whose
                                     products run as GEMMs on the FP64 matrix cores
                                     (0 in the stored mode, -1 host-only planning)  */
+    int32_t  n_time_classes;     /* largest number of distinct (target interval,
+                                    source interval) geometries of the M2L over the
+                                    levels >= 2 (2 when every level has equal
+                                    intervals: the offsets of 2 and 3 intervals)  */
+    int64_t  near_entries_V;     /* entries stored for V_h: near_entries if V_h is
+                                    built in the stored mode, else 0               */
+    int64_t  near_entries_K;     /* entries stored for K_h, likewise (coplanar zeros
+                                    included: K_h shares V_h's block layout)       */
+    int64_t  near_nonzero_K;     /* causal nearfield entries of K_h between panels
+                                    that are not coplanar (the others are exactly
+                                    zero): the entries K_h's product must read      */
 } pfmm_stats;
 
 /* Fill *out with the default parameters above.  Returns PFMM_EINVAL on NULL. */
@@ -198,11 +210,26 @@ pfmm_status pfmm_profile_read(pfmm_tree* t, double* ms, int64_t* counts, int32_t
  * Dirichlet solve (Section 2, system 02:linear:system; Section 5 solves it
  * with GMRES without preconditioner to a relative precision of 1e-8).
  */
+typedef struct pfmm_precond pfmm_precond;   /* learned preconditioner, below */
+
 typedef struct {
-    double  rtol;            /* stop when the GMRES residual estimate
+    double  rtol;            /* stop when the relative residual
                                 ||b - V_h w_k||_2 / ||b||_2 <= rtol.              default 1e-8 */
     int32_t max_iter;        /* Krylov dimension; no restart, 1..100000.         default 200  */
-    int32_t reserved;
+    int32_t inner_precision; /* pfmm_precision of the inner applies of the
+                                refinement solve (see pfmm_solve_V_precond); a
+                                reduced one needs a tree built in a MIXED mode.
+                                default PFMM_FP64 */
+    const double* x0_dev;    /* initial iterate (device, natural order, may equal
+                                w_dev: the solve then resumes in place), NULL =
+                                zero.  An iterate already within rtol returns it
+                                unchanged after 0 iterations.     default NULL */
+    const pfmm_precond* precond; /* learned preconditioner (pfmm_precond_create /
+                                _load / _train) for the refinement solve, NULL =
+                                none.                                 default NULL */
+    const char* precond_path;    /* weights file (pfmm_precond_save format) loaded
+                                for the call when precond is NULL; NULL = none.
+                                default NULL */
 } pfmm_solve_opts;
 
 typedef struct {
@@ -223,16 +250,23 @@ typedef struct {
 pfmm_status pfmm_default_solve_opts(pfmm_solve_opts* out);
 
 /*
- * Solve V_h w = b by GMRES from w_0 = 0 (no restart, FP64 Arnoldi with
- * classical Gram-Schmidt applied twice, Givens rotations).  b_dev and w_dev
- * are device arrays of n_steps * n_triangles doubles in the natural order and
- * must not alias.  o = NULL takes the defaults; info may be NULL.
- * Synchronous: returns after the solve has finished on `stream`.  Allocates
- * (max_iter + 1) Krylov vectors for the duration of the call and frees them.
- * Errors: PFMM_EINVAL (NULL, bad options, V not built), PFMM_ENOMEM (workspace
- * larger than free device memory), PFMM_ENONFINITE (b or an Arnoldi value not
- * finite), PFMM_ENOTCONV (max_iter reached; w_dev then holds the last
- * iterate and info is filled), PFMM_EDEVICE.
+ * Solve V_h w = b.  With the default options (no preconditioner, FP64 inner
+ * precision) this is GMRES as in Section 5: no restart, FP64 Arnoldi with
+ * classical Gram-Schmidt applied twice, Givens rotations, from w_0 = x0_dev
+ * (zero when NULL) on the residual b - V_h w_0, stopped when the estimate of
+ * ||b - V_h w_k||_2 / ||b||_2 reaches rtol.  With o->precond, o->precond_path
+ * or a reduced o->inner_precision it runs the FP64 iterative refinement of
+ * pfmm_solve_V_precond instead (judged by the FP64 residual), from x0_dev.
+ * b_dev and w_dev are device arrays of n_steps * n_triangles doubles in the
+ * natural order and must not alias.  o = NULL takes the defaults; info may
+ * be NULL.  Synchronous: returns after the solve has finished on `stream`.
+ * Allocates (max_iter + 1) Krylov vectors (about twice that for the
+ * refinement solve) for the duration of the call and frees them.
+ * Errors: PFMM_EINVAL (NULL, bad options, V not built, unreadable weights
+ * file), PFMM_ENOMEM (workspace larger than free device memory),
+ * PFMM_ENONFINITE (b, x0 or an Arnoldi value not finite), PFMM_ENOTCONV
+ * (max_iter reached; w_dev then holds the last iterate and info is filled),
+ * PFMM_EDEVICE.
  */
 pfmm_status pfmm_solve_V(pfmm_tree* t, const double* b_dev, double* w_dev, const pfmm_solve_opts* o,
                          pfmm_solve_info* info, void* stream);
@@ -252,7 +286,8 @@ pfmm_status pfmm_dirichlet_rhs(pfmm_tree* t, const double* g_dev, double* b_dev,
  * Solve the Dirichlet problem V_h w = (1/2 M_h + K_h) g for the projected
  * datum g (device, natural order, the p0 coefficients of the Dirichlet data;
  * M_h is the diagonal p0 x p0 mass matrix |gamma_k| h_t).  Needs both V_h and
- * K_h built.  Same conventions and errors as pfmm_solve_V; one more
+ * K_h built.  Same options (initial iterate, preconditioner, inner
+ * precision), conventions and errors as pfmm_solve_V; one more
  * right-hand-side vector is allocated for the call.
  */
 pfmm_status pfmm_solve_dirichlet(pfmm_tree* t, const double* g_dev, double* w_dev, const pfmm_solve_opts* o,
@@ -264,7 +299,8 @@ pfmm_status pfmm_solve_dirichlet(pfmm_tree* t, const double* g_dev, double* w_de
  * batch in one stream-ordered call: the applies are captured once into a HIP
  * graph whose branches run on up to 8 internal streams (tree i on branch
  * i mod 8, in batch order: put the largest problems first), and the graph is
- * replayed while the vector pointers stay the same (new pointers re-capture).
+ * replayed while the vector pointers and the trees' farfield precisions
+ * (pfmm_set_precision) stay the same (a change re-captures).
  * w_dev[i], f_dev[i]: device arrays of tree i's size, natural order, not
  * aliasing.  The batch keeps pointers to the trees: destroy it before them.
  * Stage profiling must be off for the trees of a batch.
@@ -311,7 +347,6 @@ void pfmm_batch_destroy(pfmm_batch* b);
  * Errors: PFMM_EINVAL, PFMM_ENOMEM, PFMM_EDEVICE, PFMM_ENOTCONV (training
  *   solve did not converge), PFMM_ENONFINITE (degenerate normal equations).
  */
-typedef struct pfmm_precond pfmm_precond;
 pfmm_status pfmm_precond_create(int32_t device, int32_t features, int32_t hidden, uint64_t seed, pfmm_precond** out);
 pfmm_status pfmm_precond_train(pfmm_precond* pc, pfmm_tree* t, const double* b_dev, int32_t n_snap, int32_t steps,
                                int32_t batch, float lr, uint64_t seed, float* final_loss, void* stream);
@@ -325,12 +360,15 @@ void pfmm_precond_destroy(pfmm_precond* pc);
  * Solve V_h w = b by iterative refinement in FP64 around flexible GMRES
  * (right preconditioning with pc, or none when pc is NULL), the inner
  * products applied in the farfield precision `inner_precision`
- * (pfmm_precision; the reduced ones need a mixed tree).  Every refinement
+ * (pfmm_precision; the reduced ones need a mixed tree); the refinement
+ * starts from o->x0_dev (zero when NULL; o->precond, o->precond_path and
+ * o->inner_precision are ignored here: the arguments decide).  Every refinement
  * step computes the true residual b - V_h w with the FP64 apply; the solve
  * stops when its norm relative to ||b|| reaches o->rtol, and it is judged by
  * that FP64 residual only.  Each inner solve stops at a relative reduction
  * of 1e-4 (or max_iter inner iterations).  If a refinement step fails to
- * halve the FP64 residual, the solve falls back to plain FP64 GMRES from the
+ * halve the FP64 residual, or the preconditioned inner solve produces a
+ * non-finite value, the solve falls back to plain FP64 GMRES from the
  * current iterate (info->precond_fallback = 1).  info->iters counts all
  * inner iterations (V_h applies), info->outer the refinement steps.  The
  * tree's precision setting is restored on return.  Workspace: about

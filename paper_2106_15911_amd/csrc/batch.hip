@@ -3,8 +3,8 @@
 // (all stages of Algorithm 2 for one tree) are captured once into a HIP
 // graph whose branches run on separate streams, so small problems overlap
 // each other and the large ones instead of queueing one after another; the
-// graph is replayed for every further call with the same vectors and
-// re-captured when the vectors change.
+// graph is replayed for every further call with the same vectors and tree
+// precisions, and re-captured when either changes.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -27,6 +27,8 @@ struct pfmm_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<const double*> key_w;      // vectors the graph was captured with
     std::vector<double*> key_f;
+    std::vector<int> key_prec;             // each tree's farfield precision at capture (the graph
+                                           // holds that precision's kernels and tables)
 };
 
 namespace {
@@ -47,6 +49,7 @@ void release_graph(pfmm_batch* b) {
     b->graph = nullptr;
     b->key_w.clear();
     b->key_f.clear();
+    b->key_prec.clear();
 }
 
 // Capture the applies of all trees into b->graph / b->exec (recorded on the
@@ -82,6 +85,8 @@ pfmm_status capture(pfmm_batch* b, const double* const* w, double* const* f) {
     HIP_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     b->key_w.assign(w, w + b->trees.size());
     b->key_f.assign(f, f + b->trees.size());
+    b->key_prec.resize(b->trees.size());
+    for (size_t i = 0; i < b->trees.size(); ++i) b->key_prec[i] = tree_precision(b->trees[i]);
     return PFMM_OK;
 }
 
@@ -136,7 +141,8 @@ pfmm_status pfmm_apply_V_batch(pfmm_batch* b, const double* const* w_dev, double
     if (hipSetDevice(b->device) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
     hipStream_t st = (hipStream_t)stream;
     bool same = b->exec != nullptr;
-    for (size_t i = 0; same && i < n; ++i) same = b->key_w[i] == w_dev[i] && b->key_f[i] == f_dev[i];
+    for (size_t i = 0; same && i < n; ++i)
+        same = b->key_w[i] == w_dev[i] && b->key_f[i] == f_dev[i] && b->key_prec[i] == tree_precision(b->trees[i]);
     if (!same) {
         const pfmm_status s = capture(b, w_dev, f_dev);
         if (s != PFMM_OK) return s;

@@ -609,11 +609,285 @@ __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, in
 }
 
 // Sum the per-share partial locals of a level whose interaction lists were
-// split over several workgroups (fixed order: share 0, 1, ...).
+// split over several workgroups (fixed order: share 0, 1, ...), with
+// Neumaier's compensated summation in FP64: the partial sums (each the FP32
+// matrix-core result of one share in the mixed modes) can cancel, and the
+// compensation keeps the folded value within one rounding of the exact sum
+// of the shares.
 __global__ void k_sum_parts(double* __restrict__ lam, const double* __restrict__ parts, int nparts, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double s = lam[i];
-    for (int p = 0; p < nparts; ++p) s += parts[(int64_t)p * n + i];
-    lam[i] = s;
+    double s = lam[i], c = 0.0;
+    for (int p = 0; p < nparts; ++p) {
+        const double x = parts[(int64_t)p * n + i];
+        const double u = s + x;
+        c += fabs(s) >= fabs(x) ? (s - u) + x : (x - u) + s;
+        s = u;
+    }
+    lam[i] = s + c;
 }
+
+// M2L on matrix cores for levels whose intervals differ in length or are
+// missing (time split points at the nearest step, Algorithm 1; partial
+// levels where leaves sit at several levels of one time range).  The
+// operator of eq. m2l depends on the target and source intervals through
+// their node differences only, so the pairs of a level fall into a few time
+// classes, each with its own 1D tables (eq. exp_coeffs_1d, same compact rows
+// as k_m2l_wide).  One launch handles one time offset D (2: every target
+// interval k >= 2 with source k - 2; 3: odd k with source k - 3): its columns
+// are the target intervals of the level, sorted by class on the host
+// (cols[i] = (k, class), padded with k = -1), so that a workgroup's 16 NB
+// columns span few classes.  A workgroup owns one target slot X, one row
+// group and one block of 16 NB columns; it walks X's interaction list one
+// source Y at a time and, per source, the classes of its columns
+// (cbr[cb] = first and last class of the block); the operator tile of
+// (Y, class) is generated from LDS and multiplies the columns of that class
+// (the others are masked to zero).  The results are added to lam, which the
+// caller zeroes before the first of the two launches (each (X, row, k) is
+// owned by one workgroup per launch, so the sum is deterministic).
+template <class T, int NB, int MAXS, int WAVES, bool RB = false>
+__global__ void __launch_bounds__(64 * WAVES) k_m2l_cls(
+    const T* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
+    const int* __restrict__ ocls, const int* __restrict__ off3, const T* __restrict__ E1c, int TSp,
+    const int* __restrict__ packinfo, const int* __restrict__ plan, int plan_stride, int Nc, int n_int, int mt,
+    int mx, int R, const int2* __restrict__ cols, const int2* __restrict__ cbr, int D, int ncb) {
+    static_assert(MAXS >= 1 && MAXS <= 4, "phase dispatch below is written for one to four slots");
+    using Tr = M2LTraits<T>;
+    using acc_t = typename Tr::acc_t;
+    constexpr int ES = sizeof(T);
+    extern __shared__ double smem[];
+    const int nt1 = mt + 1, nx1 = mx + 1;
+    const int BS = nx1 * (nx1 + 1) / 2;
+    const int Nc4 = (Nc + 3) & ~3;
+    // two buffers of the three 1D tables of one (source, class) phase, then
+    // the per-column table offsets and degrees
+    int4* sCol = (int4*)((char*)smem + 6 * TSp * ES);
+    const int lane = threadIdx.x % kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    int g, X, cb;
+    {
+        const int ng = gridDim.x, nxs = gridDim.y;
+        const int total = ng * nxs * gridDim.z;
+        const int lin = blockIdx.x + ng * (blockIdx.y + nxs * blockIdx.z);
+        const int per = total / kXcds;
+        const int lm = lin < per * kXcds ? (lin % kXcds) * per + lin / kXcds : lin;
+        g = lm % ng;
+        X = (lm / ng) % nxs;
+        cb = lm / (ng * nxs);
+    }
+    (void)ncb;
+    const int* gp = plan + (int64_t)g * plan_stride;
+    const int lr = lane & 15, lq = lane >> 4;
+    auto tri = [&](int k) { return k * nx1 - (k * (k - 1)) / 2; };
+    for (int c = threadIdx.x; c < Nc4 + 16; c += blockDim.x) {
+        int4 v = {0, 0, 0, 255};
+        if (c < Nc) {
+            const int ci = packinfo[c];
+            const int cbase = (ci & 15) * nt1 * BS;
+            v.x = ES * (cbase + tri((ci >> 4) & 15));
+            v.y = ES * (cbase + tri((ci >> 8) & 15));
+            v.z = ES * (cbase + tri((ci >> 12) & 15));
+            v.w = (ci >> 16) & 255;
+        }
+        sCol[c] = v;
+    }
+    // this lane's column (target interval and class) in every block nb
+    int kcol[NB], ccol[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int2 e = cols[(cb * NB + nb) * 16 + lr];
+        kcol[nb] = e.x;
+        ccol[nb] = e.y;
+    }
+    const int2 crange = cbr[cb];
+    const int cmin = __builtin_amdgcn_readfirstlane(crange.x);
+    const int ncr = __builtin_amdgcn_readfirstlane(crange.y - crange.x + 1);
+    const int sbeg = __builtin_amdgcn_readfirstlane(gp[2 * w]);
+    int tiles[MAXS], ks[MAXS], part[MAXS], rX[MAXS], rY[MAXS], rZ[MAXS], rD[MAXS];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        const int* e = gp + 2 * WAVES + (w * MAXS + i) * 3;
+        tiles[i] = __builtin_amdgcn_readfirstlane(e[0]);
+        ks[i] = __builtin_amdgcn_readfirstlane(e[1]);
+        part[i] = __builtin_amdgcn_readfirstlane(e[2]);
+        const int row = 16 * (tiles[i] >= 0 ? tiles[i] : 0) + lr;
+        const bool rv = tiles[i] >= 0 && row < Nc;
+        const int ri = rv ? packinfo[row] : 0;
+        const int b = ri & 15;
+        rX[i] = ES * (b * BS + ((ri >> 4) & 15));
+        rY[i] = ES * (b * BS + ((ri >> 8) & 15) + TSp);
+        rZ[i] = ES * (b * BS + ((ri >> 12) & 15) + 2 * TSp);
+        rD[i] = mx - (rv ? ((ri >> 16) & 255) : 255);
+    }
+    acc_t acc[MAXS][NB];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[i][nb] = acc_t{0, 0, 0, 0};
+    const int nR = 2 * R + 1;
+    const int sb = ptr[X], se = ptr[X + 1];
+    const int n_phase = (se - sb) * ncr;
+    const int pieces = TSp * ES / 1024;
+    auto stage = [&](int p) {
+        const int si = sb + p / ncr, c = cmin + p % ncr;
+        const int c3 = ocls[si];
+        char* dst = (char*)smem + (p & 1) * 3 * TSp * ES;
+        for (int q = w; q < 3 * pieces; q += WAVES) {
+            const int axis = q / pieces, pc = q - axis * pieces;
+            const int o = off3[3 * c3 + axis] + R;
+            const char* gsrc = (const char*)(E1c + (((int64_t)c * nR + o) * 2 + (axis == 0 ? 0 : 1)) * TSp) +
+                               pc * 1024 + 16 * lane;
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)gsrc,
+                                             (void __attribute__((address_space(3)))*)(dst + axis * TSp * ES + pc * 1024),
+                                             16, 0, 0);
+        }
+    };
+    // byte offsets of mu[Y][c][k - D] for K-step sbeg (columns without a
+    // target read offset 0 and are masked); loads past the slot return zero
+    int vb[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) vb[nb] = ((4 * sbeg + lq) * n_int + (kcol[nb] >= 0 ? kcol[nb] - D : 0)) * ES;
+    const int bstep = 4 * n_int * ES;
+    const int slot_bytes = Nc * n_int * ES;
+    const char* lds = (const char*)smem;
+    if (n_phase > 0) stage(0);
+    for (int p = 0; p < n_phase; ++p) {
+        const int Y = src[sb + p / ncr], c = cmin + p % ncr;
+        const int boff = (p & 1) * 3 * TSp * ES;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)(mu + (int64_t)Y * Nc * n_int), (short)0, slot_bytes, 0x00020000);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (p + 1 < n_phase) stage(p + 1);
+        T msk[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) msk[nb] = (kcol[nb] >= 0 && ccol[nb] == c) ? T(1) : T(0);
+        int pX[MAXS], pY[MAXS], pZ[MAXS];
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            pX[i] = boff + rX[i];
+            pY[i] = boff + rY[i];
+            pZ[i] = boff + rZ[i];
+        }
+        auto load = [&](T* bv, int s) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int vo = vb[nb] + (s - sbeg) * bstep;
+                if constexpr (ES == 8)
+                    bv[nb] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, 0, 0));
+                else
+                    bv[nb] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, 0, 0));
+            }
+        };
+        auto step = [&](auto nc, int4 col, const T* bv) {
+            constexpr int n = decltype(nc)::value;
+            T A[n];
+#pragma unroll
+            for (int i = 0; i < n; ++i) {
+                const T m = (col.w <= rD[i]) ? T(1) : T(0);
+                const T x = *(const T*)(lds + (pX[i] + col.x));
+                const T y = *(const T*)(lds + (pY[i] + col.y));
+                const T z = *(const T*)(lds + (pZ[i] + col.z));
+                A[i] = (x * y) * (z * m);
+                if constexpr (RB) A[i] = bf16_round(A[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < n; ++i)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[i][nb] = Tr::mfma(A[i], bv[nb] * msk[nb], acc[i][nb]);
+        };
+        int s = sbeg;
+        int4 cA = sCol[4 * s + lq], cB = sCol[4 * s + 4 + lq];
+        T bA[NB], bB[NB];
+        load(bA, s);
+        load(bB, s + 1);
+        auto phase = [&](auto nc, int s_end) {
+            for (; s + 1 < s_end; s += 2) {
+                step(nc, cA, bA);
+                cA = sCol[4 * s + 8 + lq];
+                load(bA, s + 2);
+                step(nc, cB, bB);
+                cB = sCol[4 * s + 12 + lq];
+                load(bB, s + 3);
+            }
+        };
+        if constexpr (MAXS >= 4) phase(std::integral_constant<int, 4>{}, ks[3]);
+        if constexpr (MAXS >= 3) phase(std::integral_constant<int, 3>{}, ks[2]);
+        if constexpr (MAXS >= 2) phase(std::integral_constant<int, 2>{}, ks[1]);
+        phase(std::integral_constant<int, 1>{}, ks[0]);
+        if (s < ks[0]) {
+            int na = 1;
+#pragma unroll
+            for (int i = 1; i < MAXS; ++i) na += ks[i] > s ? 1 : 0;
+            if (na == 1) step(std::integral_constant<int, 1>{}, cA, bA);
+            if constexpr (MAXS >= 2) if (na == 2) step(std::integral_constant<int, 2>{}, cA, bA);
+            if constexpr (MAXS >= 3) if (na == 3) step(std::integral_constant<int, 3>{}, cA, bA);
+            if constexpr (MAXS >= 4) if (na == 4) step(std::integral_constant<int, 4>{}, cA, bA);
+        }
+    }
+    // partial segments through LDS, added by the tiles' first segments in a fixed order
+    const int n_partial = gp[2 * WAVES + 3 * WAVES * MAXS];
+    const int* ptile = gp + 2 * WAVES + 3 * WAVES * MAXS + 1;
+    T* red = (T*)smem;   // [n_partial][4][64]
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i)
+            if (tiles[i] >= 0 && part[i] >= 0)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red[((int64_t)part[i] * 4 + r) * kWave + lane] = acc[i][nb][r];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            if (tiles[i] < 0 || part[i] >= 0) continue;
+            for (int q = 0; q < n_partial; ++q) {
+                if (ptile[q] != tiles[i]) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[i][nb][r] += red[((int64_t)q * 4 + r) * kWave + lane];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        if (tiles[i] < 0 || part[i] >= 0) continue;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            if (kcol[nb] < 0) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * tiles[i] + Tr::row(lq, r);
+                if (row >= Nc) continue;
+                double* out = lam + ((int64_t)X * Nc + row) * n_int + kcol[nb];
+                *out += (double)acc[i][nb][r];
+            }
+        }
+    }
+}
+
+// class-aware M2L: two column blocks of 16 per workgroup, two slots per wave, 16 waves
+constexpr int kClsNB = 2, kClsMaxs = 2, kClsWaves = 16;
+
+template <int Q>
+const void* cls_fn() {
+    return (const void*)k_m2l_cls<std::conditional_t<Q == 0, double, float>, kClsNB, kClsMaxs, kClsWaves, Q == 2>;
+}
+
+const void* cls_fn(int q) { return q == 0 ? cls_fn<0>() : (q == 1 ? cls_fn<1>() : cls_fn<2>()); }
+
+template <int Q>
+void launch_cls(dim3 grid, size_t shm, hipStream_t st, const void* mu, double* lam, const int* ptr, const int* src,
+                const int* ocls, const int* off3, const void* E1c, int TSp, const int* packinfo, const int* plan,
+                int plan_stride, int Nc, int n_int, int mt, int mx, int R, const int2* cols, const int2* cbr, int D,
+                int ncb) {
+    using T = std::conditional_t<Q == 0, double, float>;
+    hipLaunchKernelGGL((k_m2l_cls<T, kClsNB, kClsMaxs, kClsWaves, Q == 2>), grid, dim3(64 * kClsWaves), shm, st,
+                       (const T*)mu, lam, ptr, src, ocls, off3, (const T*)E1c, TSp, packinfo, plan, plan_stride, Nc,
+                       n_int, mt, mx, R, cols, cbr, D, ncb);
+}
+
+using ClsLaunch = void (*)(dim3, size_t, hipStream_t, const void*, double*, const int*, const int*, const int*,
+                           const int*, const void*, int, const int*, const int*, int, int, int, int, int, int,
+                           const int2*, const int2*, int, int);
+
+ClsLaunch cls_launcher(int q) { return q == 0 ? launch_cls<0> : (q == 1 ? launch_cls<1> : launch_cls<2>); }

@@ -60,7 +60,9 @@ __global__ void k_permute_in(const double* __restrict__ w, double* __restrict__ 
     wd[i] = w[t * E_x + inv_sigma[p]];
 }
 
-// f = far + near, back to the natural order
+// f = far + near, back to the natural order.  A sum of two FP64 terms is
+// rounded once, so it already equals what a compensated (Neumaier) sum
+// returns: no correction term is needed here.
 __global__ void k_permute_out(const double* __restrict__ fd, const double* __restrict__ fn, double* __restrict__ f,
                               const int* __restrict__ sigma, int E_x, int64_t N) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,7 +215,7 @@ __device__ __forceinline__ void sep_pass(const double* __restrict__ in, double* 
 }
 
 // M2M (eqs. temp_m2m, st_m2m) from level l+1 into the boxes of level l that
-// have children.  Block = (parent slot, KI parent intervals).  Per child:
+// have children (inner[xs * n_int_p + k] = 1).  Block = (parent slot, KI parent intervals).  Per child:
 // the temporal re-expansion of the child's two intervals per parent interval
 // (read straight from HBM, intervals contiguous), then the spatial
 // re-expansion as three 1D passes in LDS, accumulated over the children.
@@ -221,7 +223,7 @@ __global__ void __launch_bounds__(256) k_m2m_sep(const double* __restrict__ mu_c
                                                  const int* __restrict__ par_xs, const int* __restrict__ ch_ptr,
                                                  const int* __restrict__ ch, const double* __restrict__ qt,
                                                  const double* __restrict__ qx, SepMaps m, int n_int_p, int n_int_c,
-                                                 int KI) {
+                                                 int KI, const uint8_t* __restrict__ inner) {
     extern __shared__ double sm[];
     const int nt1 = m.mt + 1, nx1 = m.mx + 1, Nk = m.Nk, Nc = m.Nc;
     const int blk = Nc * KI;
@@ -269,9 +271,11 @@ __global__ void __launch_bounds__(256) k_m2m_sep(const double* __restrict__ mu_c
         sep_pass<false, true>(T, Acc, sq + 2 * nx1 * nx1, L.ax + 2 * Nk * nx1, L.kidx, 2, nt1, Nk, nx1, KI, nk);
     }
     __syncthreads();
+    // only boxes with children: a leaf parent keeps its S2M moments, an
+    // absent one its zeros
     for (int o = threadIdx.x; o < blk; o += blockDim.x) {
         const int kk = o % KI, c = o / KI;
-        if (kk >= nk) continue;
+        if (kk >= nk || !inner[(int64_t)xs * n_int_p + k0 + kk]) continue;
         mu_p[((int64_t)xs * Nc + c) * n_int_p + k0 + kk] = Acc[((int64_t)m.coef_a[c] * Nk + m.coef_kpos[c]) * KI + kk];
     }
 }
@@ -334,7 +338,9 @@ __global__ void __launch_bounds__(256) k_s2m_blk(const double* __restrict__ wd, 
                                                  const int* __restrict__ leaf_xs, const int64_t* __restrict__ ax_off,
                                                  const int* __restrict__ tb, const int* __restrict__ te,
                                                  const double* __restrict__ At, const double* __restrict__ Ax,
-                                                 SepMaps m, int n_int, int steps, int E_x, int KI, int stageA) {
+                                                 SepMaps m, int n_int, const int* __restrict__ ist,
+                                                 const int* __restrict__ ilen, const uint8_t* __restrict__ lflag,
+                                                 int E_x, int KI, int stageA) {
     extern __shared__ double sm[];
     const int nt1 = m.mt + 1, Nk = m.Nk, Nc = m.Nc;
     const int li = blockIdx.x, xs = leaf_xs[li];
@@ -352,16 +358,19 @@ __global__ void __launch_bounds__(256) k_s2m_blk(const double* __restrict__ wd, 
         double acc = 0.0;
         if (kk < nk) {
             const int k = k0 + kk;
-            const double* T = At + (int64_t)k * steps * nt1 + a;
-            const double* wr = wd + (int64_t)k * steps * E_x + t0 + r;
-            for (int j = 0; j < steps; ++j) acc += T[j * nt1] * wr[(int64_t)j * E_x];
+            const int j0 = ist[k], ns = lflag[(int64_t)li * n_int + k] ? ilen[k] : 0;
+            const double* T = At + (int64_t)j0 * nt1 + a;
+            const double* wr = wd + (int64_t)j0 * E_x + t0 + r;
+            for (int j = 0; j < ns; ++j) acc += T[j * nt1] * wr[(int64_t)j * E_x];
         }
         W[((int64_t)a * nX + r) * KI + kk] = acc;
     }
     __syncthreads();
+    // moments of the leaf boxes only (the slot's other intervals belong to
+    // boxes with children, filled by M2M, or to absent boxes, kept zero)
     for (int o = threadIdx.x; o < Nc * KI; o += blockDim.x) {
         const int kk = o % KI, c = o / KI;
-        if (kk >= nk) continue;
+        if (kk >= nk || !lflag[(int64_t)li * n_int + k0 + kk]) continue;
         const int a = m.coef_a[c], pp = m.coef_kpos[c];
         const double* wv = W + (int64_t)a * nX * KI + kk;
         double acc = 0.0;
@@ -379,7 +388,9 @@ __global__ void __launch_bounds__(256) k_l2t_blk(const double* __restrict__ lam,
                                                  const int* __restrict__ leaf_xs, const int64_t* __restrict__ ax_off,
                                                  const int* __restrict__ tb, const int* __restrict__ te,
                                                  const double* __restrict__ At, const double* __restrict__ Ax,
-                                                 SepMaps m, int n_int, int steps, int E_x, int KI, int stageA) {
+                                                 SepMaps m, int n_int, const int* __restrict__ ist,
+                                                 const int* __restrict__ ilen, const uint8_t* __restrict__ lflag,
+                                                 int maxlen, int E_x, int KI, int stageA) {
     extern __shared__ double sm[];
     const int nt1 = m.mt + 1, Nk = m.Nk, Nc = m.Nc;
     const int li = blockIdx.x, xs = leaf_xs[li];
@@ -408,14 +419,16 @@ __global__ void __launch_bounds__(256) k_l2t_blk(const double* __restrict__ lam,
         U[((int64_t)a * nX + r) * KI + kk] = acc;
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < nk * steps * nX; o += blockDim.x) {
+    // f at the steps of the leaf boxes (intervals where the slot is a leaf)
+    for (int o = threadIdx.x; o < nk * maxlen * nX; o += blockDim.x) {
         const int r = o % nX, rest = o / nX;
-        const int j = rest % steps, kk = rest / steps;
+        const int j = rest % maxlen, kk = rest / maxlen;
         const int k = k0 + kk;
-        const double* T = At + ((int64_t)k * steps + j) * nt1;
+        if (j >= ilen[k] || !lflag[(int64_t)li * n_int + k]) continue;
+        const double* T = At + ((int64_t)ist[k] + j) * nt1;
         double acc = 0.0;
         for (int a = 0; a < nt1; ++a) acc += T[a] * U[((int64_t)a * nX + r) * KI + kk];
-        fd[((int64_t)k * steps + j) * E_x + t0 + r] = acc;
+        fd[((int64_t)ist[k] + j) * E_x + t0 + r] = acc;
     }
 }
 
@@ -711,7 +724,16 @@ struct DevBuf {
 };
 
 struct DevLevel {
-    int l = 0, nx = 0, n_int = 0, steps = 0, n_leafx = 0, n_par = 0;
+    int l = 0, nx = 0, n_int = 0, n_leafx = 0, n_par = 0;
+    int* ist = nullptr;           // first step of interval k
+    int* ilen = nullptr;          // steps of interval k (0: absent)
+    int maxlen = 0;               // most steps of an interval
+    uint8_t* lflag = nullptr;     // [leaf slot][k]: (leaf_xs[li], k) is a leaf box
+    uint8_t* inner = nullptr;     // [slot][k]: (xs, k) has children
+    bool uniform = true;          // batched-in-time M2L kernels apply (Level::uniform)
+    int2* ccols[2] = {nullptr, nullptr};   // class-aware M2L: columns (k, class) per time offset 2, 3
+    int2* cbr[2] = {nullptr, nullptr};     // first and last class of each column block
+    int nccb[2] = {0, 0};                  // column blocks per time offset
     double* mu = nullptr;
     double* lam = nullptr;
     int* leaf_xs = nullptr;
@@ -775,6 +797,7 @@ struct pfmm_tree {
     size_t m2l_shm = 0;           // dynamic LDS of the matrix-core M2L
     // wide matrix-core M2L: [0] two interval blocks / two slots, [1] four blocks / one slot
     struct Wide { int* plan = nullptr; int G = 0, stride = 0; size_t shm = 0; bool ok = false; } wide[3][3];
+    Wide wcls[3];                 // class-aware M2L (levels with unequal or missing intervals), per precision
     int prec = PFMM_FP64;         // farfield precision of the next applies
     bool has_f32 = false;         // FP32/BF16 moments and tables allocated (tree built in a mixed mode)
     // wide M2L: compact 1D tables (entries with kappa + nu <= m_x per time pair),
@@ -1447,8 +1470,25 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
                 PF_TRY(upload(t, &W.plan, tab.data(), tab.size()));
                 W.ok = true;
             }
+        // class-aware M2L for levels whose intervals differ
+        bool any_cls = false;
+        for (int l = 2; l <= P.depth; ++l) any_cls = any_cls || !P.lev[l].uniform;
+        for (int q = 0; any_cls && q < (t->has_f32 ? 3 : 1); ++q) {
+            auto& W = t->wcls[q];
+            const size_t es = q == 0 ? sizeof(double) : sizeof(float);
+            const int tsp = q == 0 ? t->TSc64 : t->TSc32;
+            std::vector<int> tab;
+            int maxp = 0;
+            if (!plan_wide(ks, kClsMaxs, kClsWaves, tab, W.G, W.stride, maxp)) continue;
+            W.shm = std::max((size_t)6 * tsp * es + (size_t)(Nc4 + 16) * 4 * sizeof(int), (size_t)maxp * 4 * 64 * es);
+            if (W.shm > (size_t)lds_max) continue;
+            if (W.shm > 65536)
+                HIP_TRY(hipFuncSetAttribute(cls_fn(q), hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.shm));
+            PF_TRY(upload(t, &W.plan, tab.data(), tab.size()));
+            W.ok = true;
+        }
     }
-    // staged 1D tables of the matrix-core M2L: per (level, Delta, offset) the
+    // staged 1D tables of the matrix-core M2L: per (level, time class, offset) the
     // x table with C_ab folded in and the plain table for y and z, each padded
     // to TSp doubles so that 1 KB pieces can be copied straight into LDS
     std::vector<int64_t> e1s_off(P.depth + 1, 0);
@@ -1459,8 +1499,8 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             const FarLevel& FL = F.lv[l];
             const int nR = 2 * FL.R + 1;
             e1s_off[l] = (int64_t)E1s.size();
-            E1s.resize(E1s.size() + (size_t)2 * nR * 2 * TSp, 0.0);
-            for (int D = 0; D < 2; ++D)
+            E1s.resize(E1s.size() + (size_t)FL.ncls * nR * 2 * TSp, 0.0);
+            for (int D = 0; D < FL.ncls; ++D)   // time class (D = time offset - 2 on uniform levels)
                 for (int oi = 0; oi < nR; ++oi) {
                     const double* e = &F.E1[FL.e1_off + ((size_t)D * nR + oi) * TS];
                     double* x = &E1s[e1s_off[l] + (((size_t)D * nR + oi) * 2 + 0) * TSp];
@@ -1510,8 +1550,39 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         const Level& L = P.lev[l];
         const FarLevel& FL = F.lv[l];
         DevLevel& D = t->lv[l];
-        D.l = l; D.nx = L.nx(); D.n_int = L.n_int; D.steps = FL.steps;
+        D.l = l; D.nx = L.nx(); D.n_int = L.n_int;
         D.n_leafx = (int)FL.leaf_xs.size();
+        D.uniform = L.uniform;
+        for (int k = 0; k < L.n_int; ++k) D.maxlen = std::max(D.maxlen, FL.ilen[k]);
+        PF_TRY(upload(t, &D.ist, FL.istart.data(), FL.istart.size()));
+        PF_TRY(upload(t, &D.ilen, FL.ilen.data(), FL.ilen.size()));
+        PF_TRY(upload(t, &D.lflag, FL.leaf.data(), FL.leaf.size()));
+        PF_TRY(upload(t, &D.inner, FL.inner.data(), FL.inner.size()));
+        if (!L.uniform) {
+            if (!t->mfma_slots || !t->wcls[0].ok || (t->has_f32 && (!t->wcls[1].ok || !t->wcls[2].ok)))
+                return fail(PFMM_EUNSUPPORTED, "levels with unequal intervals need the matrix-core M2L "
+                                               "(degrees <= 15)");
+            // columns of the class-aware M2L: the target intervals of each time
+            // offset, sorted by class, in blocks of 16 kClsNB
+            for (int Dt = 2; Dt <= 3; ++Dt) {
+                std::vector<std::pair<int, int>> cl;   // (class, k)
+                for (int k = 0; k < L.n_int; ++k)
+                    if (L.cls[Dt - 2][k] >= 0) cl.emplace_back(L.cls[Dt - 2][k], k);
+                std::stable_sort(cl.begin(), cl.end());
+                const int per = 16 * kClsNB;
+                const int nblk = (int)((cl.size() + per - 1) / per);
+                std::vector<int2> cols((size_t)nblk * per, int2{-1, -1});
+                std::vector<int2> br(nblk);
+                for (size_t i = 0; i < cl.size(); ++i) cols[i] = int2{cl[i].second, cl[i].first};
+                for (int b = 0; b < nblk; ++b) {
+                    const size_t lo = (size_t)b * per, hi = std::min(cl.size(), lo + per);
+                    br[b] = int2{cl[lo].first, cl[hi - 1].first};
+                }
+                D.nccb[Dt - 2] = nblk;
+                PF_TRY(upload(t, &D.ccols[Dt - 2], cols.data(), cols.size()));
+                PF_TRY(upload(t, &D.cbr[Dt - 2], br.data(), br.size()));
+            }
+        }
         D.at_off = FL.at_off; D.qt_off = FL.qt_off; D.qx_off = FL.qx_off; D.n_off = FL.n_off;
         D.e1_off = FL.e1_off; D.cab_off = FL.cab_off; D.R = FL.R; D.e1s_off = e1s_off[l];
         PF_TRY(upload(t, &D.off3, FL.off3.data(), FL.off3.size()));
@@ -1531,6 +1602,10 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             for (int q = 0; q < 2; ++q) {
                 int64_t wg = (int64_t)D.nx * ((D.n_int + 63) / 64) * (D.n_int > 32 ? 2 : 1);
                 D.m2l_nb[q] = 0;
+                if (!D.uniform) {   // class-aware M2L: whole source lists, no shares
+                    D.nsplit_q[q] = 1;
+                    continue;
+                }
                 if (t->mfma_slots && (q == 0 || t->has_f32)) {
                     for (int v = 2; v >= 0 && !D.m2l_nb[q]; --v)
                         if (t->wide[q][v].ok && (q == 0 || t->wide[2][v].ok) && D.n_int % (32 * kWideNB[v]) == 0 &&
@@ -1568,7 +1643,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             }
             D.nsplit = D.nsplit_q[0];
             if (nsplit_max > 1) PF_TRY(dalloc(t, &D.lam_parts, (size_t)(nsplit_max - 1) * D.nx * P.Nc * D.n_int));
-            if (t->has_f32 && D.m2l_nb[1]) {
+            if (t->has_f32 && (D.m2l_nb[1] || !D.uniform)) {
                 PF_TRY(dalloc(t, &D.mu32, (size_t)D.nx * P.Nc * D.n_int + 2));
                 HIP_TRY(hipMemset(D.mu32, 0, ((size_t)D.nx * P.Nc * D.n_int + 2) * sizeof(float)));
                 D.mu32 += 2;
@@ -1755,7 +1830,7 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
             const size_t shm = ((size_t)nt1 * 64 * KI + (t->stage_s2m ? 64 * (size_t)P.Nk : 0)) * sizeof(double);
             hipLaunchKernelGGL(k_s2m_blk, dim3(D.n_leafx, (D.n_int + KI - 1) / KI), dim3(256), shm, st, t->wd, D.mu,
                                D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, K ? t->AxK : t->Ax, t->sm, D.n_int,
-                               D.steps, P.E_x, KI, t->stage_s2m);
+                               D.ist, D.ilen, D.lflag, P.E_x, KI, t->stage_s2m);
         }
         prof_end(t, st, ev);
         // M2M, levels p-1 .. 2
@@ -1768,7 +1843,7 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
             const size_t shm = (3 * (size_t)P.Nc * KI + 3 * nx1 * nx1 + 2 * KI * nt1 * nt1) * sizeof(double);
             hipLaunchKernelGGL(k_m2m_sep, dim3(D.n_par, (D.n_int + KI - 1) / KI), dim3(256), shm, st, C.mu, D.mu,
                                D.par_xs, D.ch_ptr, D.ch, t->qt + C.qt_off, t->qx + C.qx_off, t->sm, D.n_int, C.n_int,
-                               KI);
+                               KI, D.inner);
         }
         prof_end(t, st, ev);
         // M2L, levels 2 .. p
@@ -1777,6 +1852,32 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
             DevLevel& D = t->lv[l];
             // q: 0 FP64, 1 FP32, 2 BF16 inputs; the per-level choices of the two
             // reduced precisions coincide (same kernel shapes), stored at index 1
+            if (!D.uniform) {
+                // class-aware M2L: zero the locals, then one launch per time offset
+                const int q = t->prec == PFMM_FP64 ? 0 : (t->prec == PFMM_MIXED_BF16 ? 2 : 1);
+                const auto& W = t->wcls[q];
+                const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
+                const int64_t row0 = D.e1s_off / t->TSp;
+                const void* m = D.mu;
+                const void* e1 = t->E1c + row0 * t->TSc64;
+                int tsp = t->TSc64;
+                if (q >= 1) {
+                    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl,
+                                       q == 2 ? 1 : 0);
+                    m = D.mu32;
+                    e1 = (q == 2 ? t->E1c16 : t->E1c32) + row0 * t->TSc32;
+                    tsp = t->TSc32;
+                }
+                hipLaunchKernelGGL(k_fill, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam, 0.0, nl);
+                for (int Dt = 2; Dt <= 3; ++Dt) {
+                    if (D.nccb[Dt - 2] == 0) continue;
+                    dim3 grid(W.G, D.nx, D.nccb[Dt - 2]);
+                    cls_launcher(q)(grid, W.shm, st, m, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3, e1, tsp,
+                                    t->packinfo, W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, D.ccols[Dt - 2],
+                                    D.cbr[Dt - 2], Dt, D.nccb[Dt - 2]);
+                }
+                continue;
+            }
             const int q = (t->prec != PFMM_FP64 && D.m2l_nb[1]) ? (t->prec == PFMM_MIXED_BF16 ? 2 : 1) : 0;
             const int ql = q > 0 ? 1 : 0;
             if (D.m2l_nb[ql]) {
@@ -1843,8 +1944,8 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
             const size_t shm = ((size_t)P.Nc * KI + (size_t)nt1 * 64 * KI + (t->stage_l2t ? 64 * (size_t)P.Nk : 0)) *
                                sizeof(double);
             hipLaunchKernelGGL(k_l2t_blk, dim3(D.n_leafx, (D.n_int + KI - 1) / KI), dim3(256), shm, st, D.lam, t->fd,
-                               D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, t->Ax, t->sm, D.n_int, D.steps,
-                               P.E_x, KI, t->stage_l2t);
+                               D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, t->Ax, t->sm, D.n_int, D.ist,
+                               D.ilen, D.lflag, D.maxlen, P.E_x, KI, t->stage_l2t);
         }
         prof_end(t, st, ev);
     }
@@ -1875,6 +1976,10 @@ void fill_stats(const Plan& P, uint64_t bytes, pfmm_stats* out, int m2l_mfma) {
     out->device_bytes = bytes;
     out->m2l_matrix_cores = m2l_mfma;
     out->near_gemm_groups = m2l_mfma < 0 ? -1 : 0;   // set by the caller once decided
+    out->n_time_classes = P.max_time_classes;
+    out->near_entries_V = 0;                          // set by the caller for a built tree
+    out->near_entries_K = 0;
+    out->near_nonzero_K = P.near_nonzero_K;
 }
 
 }  // namespace
@@ -2027,6 +2132,9 @@ pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out) {
     if (!t || !out) return fail(PFMM_EINVAL, "NULL argument");
     fill_stats(t->P, t->bytes, out, t->mfma_slots > 0 ? 1 : 0);
     out->near_gemm_groups = t->ngg_start[4];
+    const bool stored = t->nf_mode == PFMM_NF_STORED;
+    out->near_entries_V = t->hasV && stored ? t->P.near_entries : 0;
+    out->near_entries_K = t->hasK && stored ? t->P.near_entries : 0;
     return PFMM_OK;
 }
 

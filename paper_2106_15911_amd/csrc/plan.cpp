@@ -337,23 +337,45 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         for (size_t i = 0; i < L.present.size(); ++i)
             if (L.present[i]) { ++P.n_boxes; if (L.leaf[i]) ++P.n_leaves; }
     }
-    // the batched far-field kernels need, on every level >= 2, all intervals
-    // present with equal length and every spatial slot present in all of them
+    // M2L time classes per level >= 2, and whether the level is uniform
+    // (every interval present with one length, every slot in every interval,
+    // leaf status independent of the interval)
     for (int l = 2; l <= P.depth; ++l) {
-        const Level& L = P.lev[l];
+        Level& L = P.lev[l];
         const int len = L.iend[0] - L.istart[0];
+        L.uniform = true;
         for (int k = 0; k < L.n_int; ++k)
-            if (L.istart[k] < 0 || L.iend[k] - L.istart[k] != len) {
-                msg = "levels >= 2 must hold 2^l equal intervals (n_steps divisible by 2^depth)";
-                return PFMM_EUNSUPPORTED;
-            }
+            if (L.istart[k] < 0 || L.iend[k] - L.istart[k] != len) L.uniform = false;
         for (size_t i = 0; i < L.present.size(); ++i)
-            if (!L.present[i]) { msg = "levels >= 2 must be full (every spatial box in every interval)"; return PFMM_EUNSUPPORTED; }
-        for (int xs = 0; xs < L.nx(); ++xs)
+            if (!L.present[i]) L.uniform = false;
+        for (int xs = 0; xs < L.nx() && L.uniform; ++xs)
             for (int k = 1; k < L.n_int; ++k)
-                if (L.leaf[(size_t)xs * L.n_int + k] != L.leaf[(size_t)xs * L.n_int]) {
-                    msg = "leaf status must not depend on the interval"; return PFMM_EUNSUPPORTED;
+                if (L.leaf[(size_t)xs * L.n_int + k] != L.leaf[(size_t)xs * L.n_int]) L.uniform = false;
+        std::map<std::array<int, 4>, int> ids;   // (D, start_k - start_J, len_k, len_J) -> class
+        for (int D = 2; D <= 3; ++D) {
+            L.cls[D - 2].assign(L.n_int, -1);
+            if (L.uniform && L.n_int > D) {
+                // classes 0 and 1 are D = 2 and D = 3 (representatives k = D, J = 0)
+                L.cls_rep.push_back({D, 0});
+                L.cls_D.push_back(D);
+            }
+        }
+        for (int k = 2; k < L.n_int; ++k)
+            for (int D = 2; D <= 3; ++D) {
+                const int J = k - D;
+                if ((D == 3 && !(k & 1)) || J < 0 || L.istart[k] < 0 || L.istart[J] < 0) continue;
+                if (L.uniform) { L.cls[D - 2][k] = D - 2; continue; }
+                const std::array<int, 4> key = {D, L.istart[k] - L.istart[J], L.iend[k] - L.istart[k],
+                                                L.iend[J] - L.istart[J]};
+                auto it = ids.find(key);
+                if (it == ids.end()) {
+                    it = ids.emplace(key, (int)L.cls_rep.size()).first;
+                    L.cls_rep.push_back({k, J});
+                    L.cls_D.push_back(D);
                 }
+                L.cls[D - 2][k] = it->second;
+            }
+        P.max_time_classes = std::max(P.max_time_classes, (int)L.cls_rep.size());
     }
     P.has_far = P.depth >= 2;
 
@@ -522,6 +544,42 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         }
     }
     P.near_entries = boff;
+    // K_h entries between coplanar panels vanish ((x - y) . n_y = 0): count
+    // the others.  Panels are grouped by their plane (unit normal and offset,
+    // rounded); per source set, a histogram of its planes.
+    {
+        std::map<std::array<int64_t, 4>, int> plane_ids;
+        std::vector<int> plane(E_x);
+        for (int q = 0; q < E_x; ++q) {
+            const int t = P.inv_sigma[q];
+            const double* n = &P.normal[3 * t];
+            const double* c = &P.centroid[3 * t];
+            const double d = n[0] * c[0] + n[1] * c[1] + n[2] * c[2];
+            std::array<int64_t, 4> key = {std::llround(n[0] * 1e9), std::llround(n[1] * 1e9), std::llround(n[2] * 1e9),
+                                          std::llround(d / P.h0 * 1e9)};
+            plane[q] = plane_ids.emplace(key, (int)plane_ids.size()).first->second;
+        }
+        std::vector<std::map<int, int>> set_planes(P.set_off.size());
+        for (size_t st = 0; st < P.set_off.size(); ++st)
+            for (int i = 0; i < P.set_size[st]; ++i) ++set_planes[st][plane[P.set_pos[P.set_off[st] + i]]];
+        int64_t nz = 0;
+        for (const LeafRec& R : P.leaves) {
+            for (int r = R.rect0; r < R.rect1; ++r) {
+                const Rect& q = P.rects[r];
+                // non-coplanar (target, source) panel pairs of this rectangle
+                int64_t pairs = 0;
+                for (int tq = R.tb; tq < R.te; ++tq) {
+                    auto it = set_planes[q.set].find(plane[tq]);
+                    pairs += P.set_size[q.set] - (it == set_planes[q.set].end() ? 0 : it->second);
+                }
+                // causal step pairs (k_t >= j_t) of the leaf's steps and the rectangle's
+                int64_t steps = 0;
+                for (int kt = R.s0; kt < R.s1; ++kt) steps += std::max(0, std::min(q.j1, kt + 1) - q.j0);
+                nz += pairs * steps;
+            }
+        }
+        P.near_nonzero_K = nz;
+    }
     for (const LeafRec& R : P.leaves)
         if (R.te - R.tb > 64) {
             // the nearfield kernels give each row of a leaf one lane of a wave

@@ -28,6 +28,19 @@ struct Level {
     std::vector<int> parent;                // slot of the parent spatial box at l-1
     std::vector<int> octant;                // child octant bits (x<<2|y<<1|z) in the parent
     std::vector<uint8_t> present, leaf;     // [xs * n_int + k]
+    // M2L time classes (levels >= 2): the operator of eq. m2l depends on the
+    // target and source intervals only through their node differences, i.e.
+    // (start_k - start_J, len_k, len_J) in steps.  cls[D - 2][k] is the class
+    // of target interval k with source J = k - D (D = 2, 3 for odd k; -1 if
+    // there is none); cls_rep[c] = (k, J) a representative pair, cls_D[c] = D.
+    std::vector<int> cls[2];
+    std::vector<std::array<int, 2>> cls_rep;
+    std::vector<int> cls_D;
+    // every interval present with the same length, every slot in every
+    // interval, leaf status independent of the interval: the classes are
+    // exactly D = 2 (class 0) and D = 3 (class 1) and the batched-in-time
+    // M2L kernels apply
+    bool uniform = true;
     int nx() const { return (int)ix.size(); }
     bool box(int xs, int k) const { return present[(size_t)xs * n_int + k] != 0; }
     bool is_leaf(int xs, int k) const { return leaf[(size_t)xs * n_int + k] != 0; }
@@ -94,6 +107,7 @@ struct Plan {
 
     // counts
     int64_t n_boxes = 0, n_leaves = 0, near_entries = 0, m2l_pairs = 0, distinct = 0;
+    int64_t near_nonzero_K = 0;   // causal nearfield entries between panels that are not coplanar
 
     // nearfield
     std::vector<LeafRec> leaves;
@@ -109,6 +123,7 @@ struct Plan {
     // farfield levels (>= 2 and <= depth)
     int far_lo = 2;
     bool has_far = false;
+    int max_time_classes = 0;   // most M2L time classes on one level >= 2
 };
 
 // Build everything host-side.  Returns PFMM_OK or an error status with msg.

@@ -47,7 +47,7 @@ struct pfmm_precond {
     float* w3 = nullptr;     // H
     float* wl = nullptr;     // F: the linear stencil c (zero until trained)
     float* W1p = nullptr;    // packed for inference: Fp x Hp (Fp = F rounded up to 4)
-    _Float16* W2t = nullptr; // Hp x Hp (FP16, transposed)
+    float* W2t = nullptr;    // Hp x Hp (FP32, transposed)
     float* w3p = nullptr;    // Hp
     int Hp = 256;            // padded hidden width (64, 128 or 256)
     std::vector<void*> owned;
@@ -166,20 +166,19 @@ __global__ void __launch_bounds__(kT) k_ssq_final(double* __restrict__ part, int
 // which leaves N unchanged (tanh 0 = 0).  Packed operands, rebuilt from the
 // FP32 weights before every application:
 //   W1p [Fp][Hp] FP32,
-//   W2t [Hp][Hp] FP16, transposed (output unit first, input unit second),
+//   W2t [Hp][Hp] FP32, transposed (output unit first, input unit second),
 //   w3p [Hp]     FP32.
-typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
 typedef float f4v_t __attribute__((ext_vector_type(4)));
 
 constexpr int kMR = 64;          // DOFs (rows) per inference block, 4 waves
 
 __global__ void k_pack(const float* __restrict__ W1, const float* __restrict__ W2, const float* __restrict__ w3,
-                       float* __restrict__ W1p, _Float16* __restrict__ W2t, float* __restrict__ w3p, int F, int Fp,
+                       float* __restrict__ W1p, float* __restrict__ W2t, float* __restrict__ w3p, int F, int Fp,
                        int H, int Hp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < Hp * Hp) {
         const int j = i / Hp, a = i % Hp;                 // W2t[j][a] = W2[a][j]
-        W2t[i] = (_Float16)(j < H && a < H ? W2[a * H + j] : 0.f);
+        W2t[i] = j < H && a < H ? W2[a * H + j] : 0.f;
     }
     if (i < Fp * Hp) {
         const int f = i / Hp, h = i % Hp;
@@ -199,25 +198,25 @@ __device__ __forceinline__ float fast_tanh(float x) {
 //  1. features X[kMR][Fp + 1] (FP32, read from the ring fields U; the odd
 //     row stride spreads the rows over the LDS banks) into LDS;
 //  2. first layer on the matrix cores in FP32 (v_mfma_f32_16x16x4f32: exact
-//     products, FP32 accumulation); tanh, rounded to FP16 into A[kMR][Hp + 4]
-//     (LDS; the 4-element pad spreads the row starts over the banks);
-//  3. second layer on the matrix cores (v_mfma_f32_16x16x16f16: FP16 inputs,
-//     FP32 accumulation).
+//     products, FP32 accumulation); tanh into A[kMR][Hp + 1] (FP32, LDS; the
+//     odd row stride spreads the rows over the banks);
+//  3. second layer on the matrix cores in FP32 as well (FP32 inputs and
+//     accumulation: the network applied is the one trained, in FP32).
 //  In both layers wave w owns the hidden units [16 NCT w, 16 NCT (w+1)) for
 //  all 64 rows (4 x NCT tiles of 16 x 16);
 //  4. tanh and the output layer in FP32: the 16 lanes that hold one row's
 //     units reduce by shuffles, the 4 waves through LDS.
 template <int NCT>
 __global__ void __launch_bounds__(256) k_mlp_mfma(const float* __restrict__ U, const double* __restrict__ rms,
-                                                  const float* __restrict__ W1p, const _Float16* __restrict__ W2t,
+                                                  const float* __restrict__ W1p, const float* __restrict__ W2t,
                                                   const float* __restrict__ w3p, const float* __restrict__ wl,
                                                   double* __restrict__ z, int64_t ex, int64_t n, int F, int Fp) {
-    constexpr int Hp = 64 * NCT, AS = Hp + 4;
+    constexpr int Hp = 64 * NCT, AS = Hp + 1;
     const int XS = Fp + 1;
     extern __shared__ float smf[];
     float* red = smf;                                     // [4][kMR]
-    _Float16* A = (_Float16*)(red + 4 * kMR);             // [kMR][AS]
-    float* X = (float*)(A + kMR * AS);                    // [kMR][XS]
+    float* A = red + 4 * kMR;                             // [kMR][AS]
+    float* X = A + kMR * AS;                              // [kMR][XS]
     const int64_t i0 = (int64_t)blockIdx.x * kMR;
     const double s = rms[0];
     for (int e = threadIdx.x; e < kMR * Fp; e += 256) {  // lanes take consecutive rows: coalesced reads
@@ -255,7 +254,7 @@ __global__ void __launch_bounds__(256) k_mlp_mfma(const float* __restrict__ U, c
             for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    A[(rt * 16 + 4 * lk + q) * AS + (wv * NCT + ct) * 16 + li] = (_Float16)fast_tanh(c1[rt][ct][q]);
+                    A[(rt * 16 + 4 * lk + q) * AS + (wv * NCT + ct) * 16 + li] = fast_tanh(c1[rt][ct][q]);
     }
     __syncthreads();
     f4v_t acc[4][NCT];
@@ -263,17 +262,17 @@ __global__ void __launch_bounds__(256) k_mlp_mfma(const float* __restrict__ U, c
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = f4v_t{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < Hp; k0 += 16) {
-        h4_t b[NCT];
+    for (int k0 = 0; k0 < Hp; k0 += 4) {
+        float b[NCT];
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct)      // B[k][j] = W2[k][j]: lane j + 16 (k/4), element k % 4
-            b[ct] = *(const h4_t*)(W2t + (int64_t)((wv * NCT + ct) * 16 + li) * Hp + k0 + 4 * lk);
+        for (int ct = 0; ct < NCT; ++ct)      // B[k][j] = W2[k][j]: lane j + 16 k
+            b[ct] = W2t[(int64_t)((wv * NCT + ct) * 16 + li) * Hp + k0 + lk];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {      // A[i][k]: lane i + 16 (k/4), element k % 4
-            const h4_t a = *(const h4_t*)(A + (rt * 16 + li) * AS + k0 + 4 * lk);
+        for (int rt = 0; rt < 4; ++rt) {      // A[i][k]: lane i + 16 k
+            const float a = A[(rt * 16 + li) * AS + k0 + lk];
 #pragma unroll
             for (int ct = 0; ct < NCT; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b[ct], acc[rt][ct], 0, 0, 0);
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ct], acc[rt][ct], 0, 0, 0);
         }
     }
     // D[i][j]: lane j + 16 (i/4), element i % 4 -> this lane holds rows 4 lk + q of unit li of each tile
@@ -462,7 +461,7 @@ pfmm_status precond_apply(const pfmm_precond* pc, const double* v, double* z, co
     const int Hp = pc->Hp, Fp = (pc->F + 3) & ~3;
     hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)Hp * std::max(Hp, Fp))), dim3(kT), 0, st, pc->W1, pc->W2, pc->w3,
                        pc->W1p, pc->W2t, pc->w3p, pc->F, Fp, pc->H, Hp);
-    const size_t shm = 4 * kMR * sizeof(float) + (size_t)kMR * (Hp + 4) * sizeof(_Float16) +
+    const size_t shm = 4 * kMR * sizeof(float) + (size_t)kMR * (Hp + 1) * sizeof(float) +
                        (size_t)kMR * (Fp + 1) * sizeof(float);
     const dim3 g(nblk(n, kMR));
     if (Hp == 64)

@@ -169,6 +169,8 @@ pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opt
     const int m = o.max_iter;
     const int64_t ld = n;
     const int nb = (int)std::min<int64_t>(kMaxBlocks, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
+    const double* x0 = o.x0_dev;   // initial iterate (NULL = 0); may equal x
+    if (x0 && n_snap > 0) return set_error(PFMM_EINVAL, "internal: snapshots need a zero initial iterate");
     PS_TRY(ws.alloc(&ws.basis, (size_t)(m + 1) * n));
     PS_TRY(ws.alloc(&ws.partial, (size_t)kMaxBlocks * (m + 1)));
     PS_TRY(ws.alloc(&ws.col, (size_t)2 * (m + 1) + 1));
@@ -176,25 +178,51 @@ pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opt
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), e(m + 2, 0.0), hbuf(2 * (m + 1) + 1);
     auto Hij = [&](int i, int j) -> double& { return H[(size_t)j * (m + 1) + i]; };
 
-    // beta = ||b||, v_0 = b / beta
+    // bnorm = ||b||; r_0 = b - V_h x_0 in the first basis column (b when x_0 = 0)
     multidot(ws, b, ld, 1, b, n, nb, ws.col, st);
     HIP_CHECK(hipMemcpyAsync(hbuf.data(), ws.col, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
-    const double beta = std::sqrt(hbuf[0]);
+    const double bnorm = std::sqrt(hbuf[0]);
     if (info) { info->history_len = 0; info->iters = 0; }
     auto record = [&](double r) {
         if (info && info->history && info->history_len < info->history_cap) info->history[info->history_len++] = r;
     };
-    record(1.0);
-    if (!(beta > 0.0) || !std::isfinite(beta)) {
+    if (!(bnorm > 0.0) || !std::isfinite(bnorm)) {
+        record(1.0);
         hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, x, 0.0, n);
         HIP_CHECK(hipGetLastError());
         HIP_CHECK(hipStreamSynchronize(st));
-        if (!std::isfinite(beta)) return set_error(PFMM_ENONFINITE, "right-hand side is not finite");
+        if (!std::isfinite(bnorm)) return set_error(PFMM_ENONFINITE, "right-hand side is not finite");
         if (info) { info->converged = 1; info->rel_residual = 0.0; info->true_rel_residual = 0.0; }
         return PFMM_OK;
     }
-    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, ws.basis, 1.0 / beta, n);
+    double beta = bnorm;
+    if (x0) {
+        PS_TRY(tree_apply(t, false, x0, ws.basis, st));
+        hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, ws.basis, n);           // V x0 - b
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, ws.basis, ws.basis, -1.0, n);
+        multidot(ws, ws.basis, ld, 1, ws.basis, n, nb, ws.col, st);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipMemcpyAsync(hbuf.data(), ws.col, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        beta = std::sqrt(hbuf[0]);
+        if (!std::isfinite(beta)) return set_error(PFMM_ENONFINITE, "initial iterate gives a non-finite residual");
+    }
+    record(beta / bnorm);
+    if (x0 && beta <= o.rtol * bnorm) {
+        // the initial iterate already meets the tolerance: returned unchanged
+        if (x0 != x) HIP_CHECK(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        if (info) {
+            info->iters = 0;
+            info->rel_residual = beta / bnorm;
+            info->true_rel_residual = beta / bnorm;
+            info->converged = 1;
+        }
+        return PFMM_OK;
+    }
+    if (!(beta > 0.0)) return set_error(PFMM_ENOTCONV, "zero residual with rtol = 0");
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, x0 ? ws.basis : b, ws.basis, 1.0 / beta, n);
     e[0] = beta;
     int k = 0;
     double est = 1.0;
@@ -233,7 +261,7 @@ pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opt
         e[j + 1] = -sn[j] * e[j];
         e[j] = cs[j] * e[j];
         k = j + 1;
-        est = std::fabs(e[j + 1]) / beta;
+        est = std::fabs(e[j + 1]) / bnorm;
         record(est);
         if (est <= o.rtol || hn == 0.0) break;
     }
@@ -265,8 +293,8 @@ pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opt
         y[i] = s / Hij(i, i);
     }
     HIP_CHECK(hipMemcpyAsync(ws.coef, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kBlock), 0, st, ws.basis, ld, k, ws.coef, 1.0,
-                       (const double*)nullptr, x, n);
+    // x = x_0 + V_k y (element-wise, so x_0 may be x itself)
+    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kBlock), 0, st, ws.basis, ld, k, ws.coef, 1.0, x0, x, n);
     // true residual: V x - b in the first basis column (no longer needed)
     PS_TRY(tree_apply(t, false, x, ws.basis, st));
     hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, ws.basis, n);
@@ -277,7 +305,7 @@ pfmm_status gmres(pfmm_tree* t, const double* b, double* x, const pfmm_solve_opt
     if (info) {
         info->iters = k;
         info->rel_residual = est;
-        info->true_rel_residual = std::sqrt(hbuf[0]) / beta;
+        info->true_rel_residual = std::sqrt(hbuf[0]) / bnorm;
         info->converged = est <= o.rtol ? 1 : 0;
     }
     if (est > o.rtol)
@@ -397,17 +425,39 @@ pfmm_status solve_ir(pfmm_tree* t, const pfmm_precond* pc, int inner_prec, const
     };
     double nb_ = 0.0;
     PS_TRY(norm2(ws, b, n, st, nb_));
-    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, x, 0.0, n);
-    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, r, 1.0, n);
     if (!std::isfinite(nb_)) return set_error(PFMM_ENONFINITE, "right-hand side is not finite");
     if (!(nb_ > 0.0)) {
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, x, 0.0, n);
+        HIP_CHECK(hipStreamSynchronize(st));
         if (info) { info->converged = 1; info->rel_residual = 0.0; info->true_rel_residual = 0.0; }
         return PFMM_OK;
     }
     const int saved = tree_precision(t);
+    // r = b - V_h x (FP64) for the current x
+    auto residual = [&](double& res_out) -> pfmm_status {
+        (void)pfmm_set_precision(t, PFMM_FP64);
+        pfmm_status s2 = tree_apply(t, false, x, r, st);
+        (void)pfmm_set_precision(t, saved);
+        if (s2 != PFMM_OK) return s2;
+        hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, r, n);           // r = V x - b
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, r, r, -1.0, n);   // r = b - V x
+        double rn = 0.0;
+        s2 = norm2(ws, r, n, st, rn);
+        res_out = rn / nb_;
+        return s2;
+    };
     int iters = 0, outer = 0;
     double res = 1.0, prev = 2.0;
     pfmm_status status = PFMM_OK;
+    if (o.x0_dev) {
+        if (o.x0_dev != x)
+            HIP_CHECK(hipMemcpyAsync(x, o.x0_dev, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        PS_TRY(residual(res));
+        if (!std::isfinite(res)) return set_error(PFMM_ENONFINITE, "initial iterate gives a non-finite residual");
+    } else {
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, x, 0.0, n);
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, r, 1.0, n);
+    }
     bool fallback = false;
     while (true) {
         record(res);
@@ -416,29 +466,44 @@ pfmm_status solve_ir(pfmm_tree* t, const pfmm_precond* pc, int inner_prec, const
         prev = res;
         (void)pfmm_set_precision(t, inner_prec);
         status = fgmres(t, pc, D, r, dvec, std::max(1e-4, 0.5 * o.rtol / res), m, ws, Z, part, st, iters);
-        (void)pfmm_set_precision(t, PFMM_FP64);
+        (void)pfmm_set_precision(t, saved);
+        if (status == PFMM_ENONFINITE) {
+            // the preconditioned inner solve broke down (a non-finite
+            // preconditioner output): x and r are untouched, solve on plainly
+            status = PFMM_OK;
+            fallback = true;
+            break;
+        }
         if (status != PFMM_OK) break;
         // x += d; r = b - V_h x (FP64)
         hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, dvec, dvec, -1.0, n);
         hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, dvec, x, n);
-        status = tree_apply(t, false, x, r, st);
-        if (status != PFMM_OK) break;
-        hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, r, n);           // r = V x - b
-        hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, r, r, -1.0, n);   // r = b - V x
         ++outer;
-        double rn = 0.0;
-        status = norm2(ws, r, n, st, rn);
+        double rnew = 0.0;
+        status = residual(rnew);
         if (status != PFMM_OK) break;
-        res = rn / nb_;
-        if (!std::isfinite(res)) { status = set_error(PFMM_ENONFINITE, "non-finite residual"); break; }
+        if (!std::isfinite(rnew) || rnew > res) {
+            // the step made things worse: undo it (x -= d) and fall back
+            hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, dvec, dvec, -1.0, n);
+            hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(kBlock), 0, st, dvec, x, n);
+            status = residual(rnew);
+            if (status != PFMM_OK) break;
+            res = rnew;
+            fallback = true;
+            break;
+        }
+        res = rnew;
     }
     (void)pfmm_set_precision(t, saved);
     if (status != PFMM_OK) return status;
+    if (!std::isfinite(res)) return set_error(PFMM_ENONFINITE, "non-finite residual");
+    if (fallback && res <= o.rtol) fallback = false;
     if (fallback) {
         // plain FP64 GMRES on the current residual: x += V_h^{-1} r
         (void)pfmm_set_precision(t, PFMM_FP64);
         Workspace w2;
         pfmm_solve_opts o2 = o;
+        o2.x0_dev = nullptr;
         o2.rtol = std::min(1.0, o.rtol / res);
         pfmm_solve_info i2{};
         status = gmres(t, r, dvec, o2, &i2, w2, st);
@@ -475,35 +540,59 @@ pfmm_status check_opts(const pfmm_solve_opts* o, pfmm_solve_opts& out) {
     if (o) out = *o;
     if (!(out.rtol >= 0.0) || !std::isfinite(out.rtol)) return set_error(PFMM_EINVAL, "rtol must be finite and >= 0");
     if (out.max_iter < 1 || out.max_iter > 100000) return set_error(PFMM_EINVAL, "max_iter must be in 1..100000");
+    if (out.inner_precision != PFMM_FP64 && out.inner_precision != PFMM_MIXED_FP32 &&
+        out.inner_precision != PFMM_MIXED_BF16)
+        return set_error(PFMM_EINVAL, "unknown inner precision");
     return PFMM_OK;
 }
 
 pfmm_status solve_common(pfmm_tree* t, const double* b_or_g, double* w, const pfmm_solve_opts* o,
                          pfmm_solve_info* info, void* stream, bool dirichlet) {
     if (!t || !b_or_g || !w) return set_error(PFMM_EINVAL, "NULL argument");
+    if (b_or_g == w) return set_error(PFMM_EINVAL, "the right-hand side and the solution must not alias");
     if (!tree_has(t, PFMM_OP_V)) return set_error(PFMM_EINVAL, "V_h was not built for this tree");
     if (dirichlet && !tree_has(t, PFMM_OP_K)) return set_error(PFMM_EINVAL, "K_h was not built for this tree");
     pfmm_solve_opts opt;
     PS_TRY(check_opts(o, opt));
+    if (opt.x0_dev == b_or_g) return set_error(PFMM_EINVAL, "x0 must not alias the right-hand side");
     if (hipSetDevice(tree_device(t)) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
+    const bool refine = opt.precond || opt.precond_path || opt.inner_precision != PFMM_FP64;
+    if (refine) {
+        // the inner precision must be available on this tree
+        const int saved = tree_precision(t);
+        PS_TRY(pfmm_set_precision(t, opt.inner_precision));
+        (void)pfmm_set_precision(t, saved);
+    }
     const int64_t n = tree_dofs(t);
     size_t fr = 0, tot = 0;
     HIP_CHECK(hipMemGetInfo(&fr, &tot));
-    const uint64_t need = ((uint64_t)opt.max_iter + 2) * n * 8 + (uint64_t)kMaxBlocks * (opt.max_iter + 1) * 8;
+    const uint64_t need = (refine ? 2 * (uint64_t)opt.max_iter + 5 : (uint64_t)opt.max_iter + 2) * n * 8 +
+                          (uint64_t)kMaxBlocks * (opt.max_iter + 1) * 8;
     if (need > fr)
-        return set_error(PFMM_ENOMEM, "GMRES workspace needs " + std::to_string(need) + " bytes, " +
+        return set_error(PFMM_ENOMEM, "solve workspace needs " + std::to_string(need) + " bytes, " +
                                           std::to_string(fr) + " free (lower max_iter)");
+    // a weights file is loaded for the call
+    pfmm_precond* loaded = nullptr;
+    const pfmm_precond* pc = opt.precond;
+    if (!pc && opt.precond_path) {
+        const pfmm_status ls = pfmm_precond_load(opt.precond_path, tree_device(t), &loaded);
+        if (ls != PFMM_OK) return ls;
+        pc = loaded;
+    }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
     Workspace ws;
     const double* b = b_or_g;
+    pfmm_status s = PFMM_OK;
     if (dirichlet) {
-        PS_TRY(ws.alloc(&ws.b, (size_t)n));
-        PS_TRY(pfmm_dirichlet_rhs(t, b_or_g, ws.b, stream));
+        s = ws.alloc(&ws.b, (size_t)n);
+        if (s == PFMM_OK) s = pfmm_dirichlet_rhs(t, b_or_g, ws.b, stream);
         b = ws.b;
     }
-    pfmm_status s = gmres(t, b, w, opt, info, ws, st);
+    if (s == PFMM_OK) s = refine ? solve_ir(t, pc, opt.inner_precision, b, w, opt, info, st)
+                                 : gmres(t, b, w, opt, info, ws, st);
     const hipError_t e = hipStreamSynchronize(st);
+    if (loaded) pfmm_precond_destroy(loaded);
     if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (s == PFMM_OK && e != hipSuccess) return set_error(PFMM_EDEVICE, hipGetErrorString(e));
     return s;
@@ -518,6 +607,10 @@ pfmm_status pfmm_default_solve_opts(pfmm_solve_opts* out) {
     std::memset(out, 0, sizeof(*out));
     out->rtol = 1e-8;
     out->max_iter = 200;
+    out->inner_precision = PFMM_FP64;
+    out->x0_dev = nullptr;
+    out->precond = nullptr;
+    out->precond_path = nullptr;
     return PFMM_OK;
 }
 
@@ -547,9 +640,11 @@ pfmm_status pfmm_solve_dirichlet(pfmm_tree* t, const double* g_dev, double* w_de
 pfmm_status pfmm_solve_V_precond(pfmm_tree* t, const pfmm_precond* pc, int32_t inner_precision, const double* b_dev,
                                  double* w_dev, const pfmm_solve_opts* o, pfmm_solve_info* info, void* stream) {
     if (!t || !b_dev || !w_dev) return set_error(PFMM_EINVAL, "NULL argument");
+    if (b_dev == w_dev) return set_error(PFMM_EINVAL, "the right-hand side and the solution must not alias");
     if (!tree_has(t, PFMM_OP_V)) return set_error(PFMM_EINVAL, "V_h was not built for this tree");
     pfmm_solve_opts opt;
     PS_TRY(check_opts(o, opt));
+    if (opt.x0_dev == b_dev) return set_error(PFMM_EINVAL, "x0 must not alias the right-hand side");
     if (hipSetDevice(tree_device(t)) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
     // the inner precision must be available on this tree
     const int saved = tree_precision(t);
@@ -558,7 +653,7 @@ pfmm_status pfmm_solve_V_precond(pfmm_tree* t, const pfmm_precond* pc, int32_t i
     const int64_t n = tree_dofs(t);
     size_t fr = 0, tot = 0;
     HIP_CHECK(hipMemGetInfo(&fr, &tot));
-    const uint64_t need = (2 * (uint64_t)opt.max_iter + 4) * n * 8 + (uint64_t)kMaxBlocks * (opt.max_iter + 1) * 8;
+    const uint64_t need = (2 * (uint64_t)opt.max_iter + 5) * n * 8 + (uint64_t)kMaxBlocks * (opt.max_iter + 1) * 8;
     if (need > fr)
         return set_error(PFMM_ENOMEM, "solve workspace needs " + std::to_string(need) + " bytes, " +
                                           std::to_string(fr) + " free (lower max_iter)");

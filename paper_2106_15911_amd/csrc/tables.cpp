@@ -62,13 +62,28 @@ void build_far_tables(const Plan& P, FarTables& F) {
         FL.l = l;
         FL.nx = L.nx();
         FL.n_int = L.n_int;
-        FL.steps = L.iend[0] - L.istart[0];
+        FL.istart.assign(L.n_int, 0);
+        FL.ilen.assign(L.n_int, 0);
+        for (int k = 0; k < L.n_int; ++k)
+            if (L.istart[k] >= 0) { FL.istart[k] = L.istart[k]; FL.ilen[k] = L.iend[k] - L.istart[k]; }
+        FL.inner.assign((size_t)L.nx() * L.n_int, 0);
+        for (size_t i = 0; i < L.present.size(); ++i) FL.inner[i] = L.present[i] && !L.leaf[i];
         // ---------------- leaves, A_t, A_x
-        for (int xs = 0; xs < L.nx(); ++xs)
-            if (L.is_leaf(xs, 0)) FL.leaf_xs.push_back(xs);
+        for (int xs = 0; xs < L.nx(); ++xs) {
+            bool any = false;
+            for (int k = 0; k < L.n_int; ++k) any = any || (L.box(xs, k) && L.is_leaf(xs, k));
+            if (!any) continue;
+            FL.leaf_xs.push_back(xs);
+            for (int k = 0; k < L.n_int; ++k) FL.leaf.push_back(L.box(xs, k) && L.is_leaf(xs, k) ? 1 : 0);
+        }
         if (!FL.leaf_xs.empty()) {
+            // one row per time step (E_t rows): the integrals of the Lagrange
+            // basis of the step's interval on this level (zero where the
+            // interval is absent)
             FL.at_off = (int64_t)F.At.size();
+            F.At.resize(F.At.size() + (size_t)P.E_t * nt1, 0.0);
             for (int k = 0; k < L.n_int; ++k) {
+                if (L.istart[k] < 0) continue;
                 const double ta = P.tnodes[L.istart[k]], tb = P.tnodes[L.iend[k]];
                 for (int j = L.istart[k]; j < L.iend[k]; ++j) {
                     const double t0 = P.tnodes[j], t1 = P.tnodes[j + 1];
@@ -77,7 +92,7 @@ void build_far_tables(const Plan& P, FarTables& F) {
                         lagrange(xt, ta, tb, t0 + (t1 - t0) * gt[q], Lb.data());
                         for (int a = 0; a < nt1; ++a) row[a] += Lb[a] * (wt[q] * (t1 - t0));
                     }
-                    F.At.insert(F.At.end(), row.begin(), row.end());
+                    std::copy(row.begin(), row.end(), F.At.begin() + FL.at_off + (int64_t)j * nt1);
                 }
             }
             for (int xs : FL.leaf_xs) {
@@ -123,6 +138,10 @@ void build_far_tables(const Plan& P, FarTables& F) {
             FL.qt_off = (int64_t)F.qt.size();
             for (int k = 0; k < L.n_int; ++k) {
                 const int kp = k >> 1;
+                if (L.istart[k] < 0 || Lp.istart[kp] < 0) {   // absent interval: no re-expansion
+                    F.qt.insert(F.qt.end(), (size_t)nt1 * nt1, 0.0);
+                    continue;
+                }
                 const double ca = P.tnodes[L.istart[k]], cb = P.tnodes[L.iend[k]];
                 const double pa = P.tnodes[Lp.istart[kp]], pb = P.tnodes[Lp.iend[kp]];
                 std::vector<double> Lb(nt1);
@@ -185,15 +204,20 @@ void build_far_tables(const Plan& P, FarTables& F) {
         FL.n_off = (int)offs.size();
         const int R = (P.n_tr >= 0) ? P.n_tr : (1 << L.lx) - 1;
         const int nR = 2 * R + 1;
+        // one set of tables per time class (for uniform levels: class c is the
+        // time offset D = c + 2, representative pair (D, 0)); at least two
+        // classes are reserved so that uniform levels with fewer intervals keep
+        // the [D - 2] layout of the batched-in-time kernels
+        FL.ncls = std::max(2, (int)L.cls_rep.size());
         FL.e1_off = (int64_t)F.E1.size();
         FL.cab_off = (int64_t)F.Cab.size();
-        F.E1.resize(F.E1.size() + (size_t)2 * nR * nt1 * nt1 * nx1 * nx1, 0.0);
-        F.Cab.resize(F.Cab.size() + (size_t)2 * nt1 * nt1, 0.0);
+        F.E1.resize(F.E1.size() + (size_t)FL.ncls * nR * nt1 * nt1 * nx1 * nx1, 0.0);
+        F.Cab.resize(F.Cab.size() + (size_t)FL.ncls * nt1 * nt1, 0.0);
         double Tn[40][40];
         for (int n = 0; n <= mx; ++n) cheb_T(mx, xx[n], Tn[n]);
-        for (int D = 2; D <= 3; ++D) {
-            if (L.n_int <= D) continue;
-            const int k = D, J = 0;   // representative interval pair at distance D
+        for (int cl = 0; cl < (int)L.cls_rep.size(); ++cl) {
+            const int k = L.cls_rep[cl][0], J = L.cls_rep[cl][1];   // representative interval pair
+            const int D = cl + 2;   // table slot: (D - 2) = class
             const double ia = P.tnodes[L.istart[k]], ib = P.tnodes[L.iend[k]];
             const double ja = P.tnodes[L.istart[J]], jb = P.tnodes[L.iend[J]];
             for (int a = 0; a < nt1; ++a)

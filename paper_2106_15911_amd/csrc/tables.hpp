@@ -9,11 +9,16 @@ namespace pfmm {
 
 struct FarLevel {
     int l = 0;
-    int nx = 0, n_int = 0, steps = 0;   // slots, intervals, steps per interval
-    // leaves of this level: slot list; A_x row block offsets (doubles)
+    int nx = 0, n_int = 0;              // slots, intervals
+    std::vector<int> istart, ilen;      // steps of interval k (start, count; 0, 0 if absent)
+    // leaves of this level: slots that are leaves in at least one interval;
+    // leaf[li * n_int + k] = 1 if (leaf_xs[li], k) is a leaf box
     std::vector<int> leaf_xs;
+    std::vector<uint8_t> leaf;
+    // boxes with children: inner[xs * n_int + k] = 1 if (xs, k) is present and not a leaf
+    std::vector<uint8_t> inner;
     std::vector<int64_t> ax_off;        // per leaf slot, offset into Ax / AxK
-    int64_t at_off = 0;                 // A_t block: [n_int][steps][m_t+1]
+    int64_t at_off = 0;                 // A_t block: [E_t][m_t+1] (row j: step j in its interval of this level)
     // q^(t) for this level as the CHILD level: [n_int][m_t+1 (a_c)][m_t+1 (a_p)]
     int64_t qt_off = -1;
     // q^(x) per slot of this level as CHILD: [nx][3][m_x+1 (kappa)][m_x+1 (nu)]
@@ -23,8 +28,9 @@ struct FarLevel {
     int n_off = 0;                      // distinct offsets used
     std::vector<int> off3;              // per offset class: grid offset (target - source) per axis
     int R = 0;                          // largest |offset| per axis covered by E1
-    int64_t e1_off = 0;                 // E1 tables [2 (Delta)][n_off][3][m_t+1][m_t+1][m_x+1][m_x+1]
-    int64_t cab_off = 0;                // C_ab [2][m_t+1][m_t+1]
+    int ncls = 0;                       // M2L time classes (Level::cls_rep)
+    int64_t e1_off = 0;                 // E1 tables [ncls][2R+1][m_t+1][m_t+1][m_x+1][m_x+1]
+    int64_t cab_off = 0;                // C_ab [ncls][m_t+1][m_t+1]
     std::vector<int> children_ptr, children;   // for M2M: child slots (level l+1) of slot xs
 };
 

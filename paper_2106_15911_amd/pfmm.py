@@ -40,14 +40,17 @@ class Stats(ctypes.Structure):
                 ("leaves", ctypes.c_int64), ("near_entries", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
                 ("near_row_groups", ctypes.c_int64), ("distinct_integrals", ctypes.c_int64),
                 ("device_bytes", ctypes.c_uint64), ("m2l_matrix_cores", ctypes.c_int32),
-                ("near_gemm_groups", ctypes.c_int32)]
+                ("near_gemm_groups", ctypes.c_int32), ("n_time_classes", ctypes.c_int32),
+                ("near_entries_V", ctypes.c_int64), ("near_entries_K", ctypes.c_int64),
+                ("near_nonzero_K", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class SolveOpts(ctypes.Structure):
-    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("inner_precision", ctypes.c_int32),
+                ("x0_dev", ctypes.c_void_p), ("precond", ctypes.c_void_p), ("precond_path", ctypes.c_char_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -181,16 +184,21 @@ class Tree:
     def apply_K(self, u, out=None, stream=None):
         return self._apply(self.lib.pfmm_apply_K, u, out, stream)
 
-    def _solve(self, fn, rhs, out, rtol, max_iter, stream, raise_on_notconv):
+    def _solve(self, fn, rhs, out, rtol, max_iter, stream, raise_on_notconv, x0=None, precond=None,
+               precond_path=None, inner_precision=FP64):
         import torch
-        if rhs.dtype != torch.float64 or rhs.device != self.device or rhs.numel() != self.n_dofs:
-            raise ValueError(f"expected a float64 tensor of {self.n_dofs} entries on {self.device}")
-        rhs = rhs.contiguous()
+        for v in (rhs, x0):
+            if v is not None and (v.dtype != torch.float64 or v.device != self.device or v.numel() != self.n_dofs
+                                  or not v.is_contiguous()):
+                raise ValueError(f"expected a contiguous float64 tensor of {self.n_dofs} entries on {self.device}")
         if out is None:
             out = torch.empty_like(rhs)
         o = SolveOpts()
         _check(self.lib.pfmm_default_solve_opts(ctypes.byref(o)))
-        o.rtol, o.max_iter = rtol, max_iter
+        o.rtol, o.max_iter, o.inner_precision = rtol, max_iter, int(inner_precision)
+        o.x0_dev = x0.data_ptr() if x0 is not None else None
+        o.precond = precond.handle.value if precond is not None else None
+        o.precond_path = str(precond_path).encode() if precond_path is not None else None
         hist = (ctypes.c_double * (max_iter + 1))()
         info = SolveInfo()
         info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
@@ -206,25 +214,31 @@ class Tree:
         return out, d
 
     def solve_V_precond(self, b, precond=None, inner_precision=FP64, out=None, rtol=1e-8, max_iter=200, stream=None,
-                        raise_on_notconv=True):
+                        raise_on_notconv=True, x0=None):
         """FP64 iterative refinement around flexible GMRES with the learned preconditioner
         (None: no preconditioner) and inner applies in `inner_precision`; returns (w, info)."""
         h = precond.handle if precond is not None else None
         fn = lambda tree, rhs, x, o, info, st: self.lib.pfmm_solve_V_precond(tree, h, int(inner_precision), rhs, x, o,
                                                                              info, st)
-        return self._solve(fn, b, out, rtol, max_iter, stream, raise_on_notconv)
+        return self._solve(fn, b, out, rtol, max_iter, stream, raise_on_notconv, x0=x0)
 
-    def solve_V(self, b, out=None, rtol=1e-8, max_iter=200, stream=None, raise_on_notconv=True):
-        """GMRES solve of V_h w = b (device tensors, natural order); returns (w, info)."""
-        return self._solve(self.lib.pfmm_solve_V, b, out, rtol, max_iter, stream, raise_on_notconv)
+    def solve_V(self, b, out=None, rtol=1e-8, max_iter=200, stream=None, raise_on_notconv=True, x0=None,
+                precond=None, precond_path=None, inner_precision=FP64):
+        """Solve V_h w = b (device tensors, natural order): GMRES from x0 (None: 0), or the
+        refinement solve when a preconditioner or a reduced inner precision is given;
+        returns (w, info)."""
+        return self._solve(self.lib.pfmm_solve_V, b, out, rtol, max_iter, stream, raise_on_notconv, x0, precond,
+                           precond_path, inner_precision)
 
     def dirichlet_rhs(self, g, out=None, stream=None):
         """(1/2 M_h + K_h) g on the device (needs K_h)."""
         return self._apply(self.lib.pfmm_dirichlet_rhs, g, out, stream)
 
-    def solve_dirichlet(self, g, out=None, rtol=1e-8, max_iter=200, stream=None, raise_on_notconv=True):
-        """GMRES solve of V_h w = (1/2 M_h + K_h) g; returns (w, info)."""
-        return self._solve(self.lib.pfmm_solve_dirichlet, g, out, rtol, max_iter, stream, raise_on_notconv)
+    def solve_dirichlet(self, g, out=None, rtol=1e-8, max_iter=200, stream=None, raise_on_notconv=True, x0=None,
+                        precond=None, precond_path=None, inner_precision=FP64):
+        """Solve V_h w = (1/2 M_h + K_h) g, options as solve_V; returns (w, info)."""
+        return self._solve(self.lib.pfmm_solve_dirichlet, g, out, rtol, max_iter, stream, raise_on_notconv, x0,
+                           precond, precond_path, inner_precision)
 
     def stats(self):
         st = Stats()

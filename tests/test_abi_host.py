@@ -45,7 +45,11 @@ def _oracle_counts(n, E_t, n_max, n_tr):
 
 
 @pytest.mark.parametrize("n,E_t,n_max,n_tr", [(4, 16, 64, 5), (4, 16, 64, 1), (2, 8, 8, -1), (8, 64, 64, 2),
-                                              (4, 32, 16, 3)])
+                                              (4, 32, 16, 3),
+                                              # step counts whose time levels split unevenly (nearest-step
+                                              # split points of Algorithm 1; leaves on several levels)
+                                              (4, 20, 64, 5), (3, 37, 16, 3), (2, 70, 8, -1), (4, 33, 64, 2),
+                                              (5, 47, 32, 3)])
 def test_planner_counts_match_oracle(n, E_t, n_max, n_tr):
     v, t = cube_surface_mesh(n)
     st = P.plan_stats(v, t, uniform_time_nodes(E_t), P.default_params(n_max=n_max, n_tr=n_tr, m_t=3, m_x=3))
@@ -55,11 +59,42 @@ def test_planner_counts_match_oracle(n, E_t, n_max, n_tr):
 
 
 def test_planner_counts_second_workload():
-    """3072 triangles x 256 steps, n_tr = 5: the counts also match an independent tally."""
+    """3072 triangles x 256 steps, n_tr = 5: the counts also match an independent tally
+    (including the causal K_h entries between panels that are not coplanar)."""
     v, t = cube_surface_mesh(16)
     st = P.plan_stats(v, t, uniform_time_nodes(256), P.default_params())
     assert st["boxes"] == 92273 and st["leaves"] == 76288
     assert st["near_entries"] == 6725369088 and st["m2l_pairs"] == 11126496
+    assert st["near_nonzero_K"] == 4804862976
+    assert st["n_time_classes"] == 2
+
+
+def test_nonzero_K_count_matches_oracle():
+    """Causal nearfield entries of K_h between panels that are not coplanar:
+    the planner's count equals the oracle's tree and coplanarity test
+    (192 triangles x 16 steps, no spatial cut; 1,597,440 by an independent tally)."""
+    from oracle.dense import coplanar
+    v, t = cube_surface_mesh(4)
+    tn = uniform_time_nodes(16)
+    st = P.plan_stats(v, t, tn, P.default_params(m_t=4, m_x=4))
+    tr = Tree(v, t, tn, 1.0, 64, 0.9, 5)
+    memo = {}
+    cop = {}
+    nz = 0
+    for Z in tr.leaves:
+        kt = np.arange(Z.s0, Z.s1)
+        for S in tr.nearfield(Z, memo):
+            jt = np.arange(S.s0, S.s1)
+            steps = int(np.sum(kt[:, None] >= jt[None, :]))
+            pairs = 0
+            for k in Z.tris:
+                for j in S.tris:
+                    key = (int(k), int(j))
+                    if key not in cop:
+                        cop[key] = coplanar(v, t, int(k), int(j))
+                    pairs += 0 if cop[key] else 1
+            nz += steps * pairs
+    assert st["near_nonzero_K"] == nz == 1597440
 
 
 def test_error_codes():
@@ -87,15 +122,15 @@ def test_error_codes():
         P.plan_stats(v, flipped, tn)                     # inconsistent orientation
     assert e.value.status == -1
     v4, t4 = cube_surface_mesh(4)
-    with pytest.raises(P.PfmmError) as e:
-        P.plan_stats(v4, t4, uniform_time_nodes(20))     # 20 steps: level 3 intervals of 2 and 3 steps
-    assert e.value.status == -6
+    st = P.plan_stats(v4, t4, uniform_time_nodes(20))    # 20 steps: level 3 intervals of 2 and 3 steps
+    assert st["n_time_classes"] > 2
 
 
 def test_solve_entry_points_validate_without_gpu():
     lib = P.load_library()
     o = P.SolveOpts()
     assert lib.pfmm_default_solve_opts(o) == 0 and o.rtol == 1e-8 and o.max_iter == 200
+    assert o.inner_precision == P.FP64 and not o.x0_dev and not o.precond and o.precond_path is None
     assert lib.pfmm_default_solve_opts(None) == -1
     info = P.SolveInfo()
     for fn in (lib.pfmm_solve_V, lib.pfmm_solve_dirichlet):

@@ -68,3 +68,66 @@ def test_batch_errors():
     b.close()
     for t in trees:
         t.close()
+
+
+def test_batch_recaptures_on_precision_change():
+    """A batch captured while its trees ran the FP32 farfield must not keep
+    replaying FP32 after the trees are switched back to FP64."""
+    print("[batch] precision change", flush=True)
+    trees, ws = [], []
+    for i, (n, E_t) in enumerate(((4, 64), (2, 64))):
+        v, t, tn, w = problem(n, E_t, seed=70 + i)
+        trees.append(P.Tree(v, t, tn, P.default_params(operators=1, m_t=4, m_x=4, n_max=16,
+                                                       precision=P.MIXED_FP32), device=0))
+        ws.append(torch.from_numpy(w).to("cuda:0"))
+    ref64 = []
+    for t, w in zip(trees, ws):
+        t.set_precision(P.FP64)
+        ref64.append(t.apply_V(w))
+        t.set_precision(P.MIXED_FP32)
+    ref32 = [t.apply_V(w) for t, w in zip(trees, ws)]
+    torch.cuda.synchronize()
+    b = P.Batch(trees)
+    outs = [torch.empty_like(w) for w in ws]
+    b.apply_V(ws, outs)
+    torch.cuda.synchronize()
+    assert all(torch.equal(r, y) for r, y in zip(ref32, outs))
+    for t in trees:
+        t.set_precision(P.FP64)
+    b.apply_V(ws, outs)        # same vectors, new precision: must re-capture
+    torch.cuda.synchronize()
+    assert all(torch.equal(r, y) for r, y in zip(ref64, outs))
+    assert not all(torch.equal(r, y) for r, y in zip(ref32, outs))
+    b.close()
+    for t in trees:
+        t.close()
+
+
+def test_batch_matches_oracle():
+    """Every batched result against the CPU oracle pFMM on the same tree
+    (face grids of 3 and 5 squares: cube boxes that do not align with the
+    squares, so the padded boxes of Algorithm 1 are exercised; 21 steps:
+    time levels with intervals of different lengths)."""
+    import numpy as np
+    from oracle_ref import reference, rel_err
+    cases = [(3, 24, dict(m_t=4, m_x=4, n_max=16, n_tr=2)), (5, 8, dict(m_t=3, m_x=3, n_max=32, n_tr=3)),
+             (2, 32, dict(m_t=3, m_x=3, n_max=8, n_tr=-1)),
+             # a step count whose time levels split unevenly
+             (3, 21, dict(m_t=3, m_x=3, n_max=16, n_tr=2))]
+    trees, ws, refs = [], [], []
+    for i, (n, E_t, prm) in enumerate(cases):
+        v, t, tn, w = problem(n, E_t, seed=80 + i)
+        print(f"[batch-oracle] n={n} E_t={E_t} {prm}", flush=True)
+        trees.append(P.Tree(v, t, tn, P.default_params(operators=1, nearfield_mode=P.NF_TOEPLITZ, **prm), device=0))
+        ws.append(torch.from_numpy(w).to("cuda:0"))
+        refs.append(reference(v, t, tn, w, "V", **prm))
+    b = P.Batch(trees)
+    outs = b.apply_V(ws)
+    torch.cuda.synchronize()
+    for (n, E_t, _), y, r in zip(cases, outs, refs):
+        e = rel_err(y.cpu().numpy(), r)
+        print(f"[batch-oracle] n={n} E_t={E_t}: rel err {e:.3e}", flush=True)
+        assert np.isfinite(e) and e <= 1e-10
+    b.close()
+    for t in trees:
+        t.close()

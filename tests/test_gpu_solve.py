@@ -131,3 +131,72 @@ def test_split_trees_match_single_tree_dirichlet_solve():
     tv.close()
     assert torch.equal(b, b1)
     assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
+
+
+def test_initial_iterate_and_resume():
+    """Solve options: an initial iterate that already meets the tolerance is
+    returned unchanged after 0 iterations; a solve stopped at max_iter and
+    resumed in place from its last iterate reaches the same solution as an
+    uninterrupted one (both to a relative residual of 1e-14 on a 384-DOF
+    problem, where GMRES without restart ends within N steps)."""
+    print("[solve] x0 / resume n=2 E_t=8", flush=True)
+    v, t, tn, b = problem(2, 8, seed=4)
+    tree = P.Tree(v, t, tn, P.default_params(m_t=3, m_x=3, n_max=8, operators=1), device=0)
+    bd = torch.from_numpy(b).to("cuda:0")
+    w, i1 = tree.solve_V(bd, rtol=1e-10)
+    w_again, i0 = tree.solve_V(bd, rtol=1e-8, x0=w)
+    print(f"[solve] from the solution: {i0['iters']} iterations, residual {i0['true_rel_residual']:.2e}", flush=True)
+    assert i0["iters"] == 0 and i0["converged"] and torch.equal(w_again, w)
+    assert i0["true_rel_residual"] <= 1e-8
+    # interrupted + resumed (in place) vs uninterrupted
+    n = len(b)
+    w_full, i_full = tree.solve_V(bd, rtol=1e-14, max_iter=n)
+    wk, ik = tree.solve_V(bd, rtol=1e-14, max_iter=10, raise_on_notconv=False)
+    assert not ik["converged"] and ik["iters"] == 10
+    w_res, i_res = tree.solve_V(bd, out=wk, rtol=1e-14, max_iter=n, x0=wk)
+    d = (torch.linalg.norm(w_res - w_full) / torch.linalg.norm(w_full)).item()
+    print(f"[solve] full {i_full['iters']} iterations; 10 + {i_res['iters']} resumed; diff {d:.2e}; "
+          f"residuals {i_full['true_rel_residual']:.2e} {i_res['true_rel_residual']:.2e}", flush=True)
+    assert i_res["converged"] and i_res["true_rel_residual"] <= 1e-13
+    assert d <= 1e-12
+    # the first history entry of the resumed solve is the relative residual of x0
+    assert abs(i_res["history"][0] - ik["history"][-1]) <= 1e-6 * ik["history"][-1] + 1e-15
+    # a non-finite initial iterate is rejected
+    bad = w.clone()
+    bad[3] = float("inf")
+    with pytest.raises(P.PfmmError) as ex:
+        tree.solve_V(bd, x0=bad)
+    assert ex.value.status == -5
+    tree.close()
+
+
+def test_dirichlet_solve_with_preconditioner_options():
+    """pfmm_solve_dirichlet with a preconditioner and FP32 inner applies
+    (through the solve options) reaches the FP64 residual bar and the plain
+    solution, and an initial iterate is honoured there too."""
+    print("[solve] dirichlet + precond options n=3 E_t=64", flush=True)
+    v, t, tn, _ = problem(3, 64)
+    g = torch.from_numpy(project_source_datum(v, t, tn, (2.5, 0.0, 0.0), -0.1)).to("cuda:0")
+    tree = P.Tree(v, t, tn, P.default_params(m_t=4, m_x=4, n_max=16, n_tr=3, precision=P.MIXED_FP32), device=0)
+    tree.set_precision(P.FP64)
+    w_ref, i_ref = tree.solve_dirichlet(g, rtol=1e-8, max_iter=300)
+    pc = P.Precond(device=0, features=8, hidden=0)
+    b = tree.dirichlet_rhs(g)
+    pc.train(tree, b, n_snap=6, steps=0, batch=4096)
+    w, info = tree.solve_dirichlet(g, rtol=1e-8, max_iter=300, precond=pc, inner_precision=P.MIXED_FP32)
+    d = (torch.linalg.norm(w - w_ref) / torch.linalg.norm(w_ref)).item()
+    print(f"[solve] plain {i_ref['iters']} iterations; preconditioned + FP32 inner {info['iters']} "
+          f"({info['outer']} refinement steps), residual {info['true_rel_residual']:.2e}, diff {d:.2e}", flush=True)
+    assert info["converged"] and info["true_rel_residual"] <= 1e-8 and not info["precond_fallback"]
+    assert info["iters"] < i_ref["iters"]
+    assert d <= 1e-5
+    w2, info2 = tree.solve_dirichlet(g, rtol=1e-8, x0=w_ref, precond=pc)
+    assert info2["iters"] == 0 and torch.equal(w2, w_ref)
+    # FP32 inner applies need a mixed tree: a plain FP64 tree refuses them
+    tk = P.Tree(v, t, tn, P.default_params(m_t=4, m_x=4, n_max=16, n_tr=3), device=0)
+    with pytest.raises(P.PfmmError) as ex:
+        tk.solve_dirichlet(g, inner_precision=P.MIXED_FP32)
+    assert ex.value.status == -1
+    tk.close()
+    pc.close()
+    tree.close()

@@ -56,6 +56,48 @@ def test_causal_toeplitz_structure(small):
                 assert np.array_equal(blk, nxt)
 
 
+def test_regular_entries_from_absolute_times(small):
+    """Entries of the dense V_h for panel pairs that do not touch, computed
+    from the definition with the absolute time nodes t_j = j h: the double
+    time integral of G over steps k and j is the four-term combination
+    G2(t_k - t_{j-1}) - G2(t_k - t_j) - G2(t_{k-1} - t_{j-1}) + G2(t_{k-1} - t_j)
+    of the second antiderivative G2 (zero for s <= 0; pinned separately by
+    brute-force quadrature), summed over the regular space rule.  This does
+    not use the step-difference form the oracle assembles from, so it checks
+    causality (j > k gives 0) and the Toeplitz structure independently."""
+    from oracle.quadrature import classify
+    from oracle.timeint import G2
+    v, t, E_t, h, BV, BK = small
+    A = dense_matrix(v, t, E_t, h, ALPHA, "V", B=BV)
+    nt = len(t)
+    s_, t_, w_ = triangle_rule(4)
+    area, _, _ = geometry(v, t)
+    P = v[t]
+    rng = np.random.default_rng(3)
+    pairs = [(k, j) for k in range(nt) for j in range(nt) if classify(t[k], t[j]) == 0]
+    tn = np.arange(E_t + 1) * h
+
+    def g2(r, s):
+        return np.where(s > 0, G2(r, np.maximum(s, 1e-300), ALPHA), 0.0)
+
+    for i in rng.choice(len(pairs), 12, replace=False):
+        k, j = pairs[i]
+        xk = P[k, 0] + s_[:, None] * (P[k, 1] - P[k, 0]) + t_[:, None] * (P[k, 2] - P[k, 1])
+        xj = P[j, 0] + s_[:, None] * (P[j, 1] - P[j, 0]) + t_[:, None] * (P[j, 2] - P[j, 1])
+        W = (2 * area[k] * w_)[:, None] * (2 * area[j] * w_)[None, :]
+        r = np.linalg.norm(xk[:, None, :] - xj[None, :, :], axis=-1)
+        for kt in range(E_t):
+            for jt in range(E_t):
+                tf = (g2(r, tn[kt + 1] - tn[jt]) - g2(r, tn[kt + 1] - tn[jt + 1])
+                      - g2(r, tn[kt] - tn[jt]) + g2(r, tn[kt] - tn[jt + 1]))
+                ref = np.sum(W * tf)
+                got = A[kt * nt + k, jt * nt + j]
+                if jt > kt:
+                    assert got == 0.0 and ref == 0.0
+                else:
+                    assert abs(got - ref) <= 1e-10 * abs(ref), (k, j, kt, jt, got, ref)
+
+
 def test_block_symmetry_and_spd(small):
     v, t, E_t, h, BV, BK = small
     for d in range(2, E_t):

@@ -6,8 +6,9 @@
   children equal moments computed directly with the parent's basis; locals
   passed down and evaluated in a child equal the parent's locals evaluated
   there (eqs. temp_m2m, st_m2m and their transposes).
-* The expansion of eq. kernel_approx converges to the heat kernel on
-  admissible box pairs as the degrees grow.
+* The expansion of eq. kernel_approx approximates the heat kernel on
+  admissible box pairs with the expected error per degree (independent
+  brute-force values, within a factor 2) and converges as the degrees grow.
 * The pFMM product converges to the dense product V_h w (and K_h w) as the
   degrees grow, with no spatial cut (Algorithm 2 vs Section 2).
 """
@@ -88,40 +89,74 @@ def test_m2m_l2l_exact(kind):
             assert np.abs(parent_eval - child_eval).max() < 1e-12 * np.abs(parent_eval).max()
 
 
-def test_kernel_expansion_converges():
-    v, t = cube_surface_mesh(8)
-    tr = Tree(v, t, uniform_time_nodes(64), 1.0, 64, 0.9, 5)
-    Z = [b for b in tr.levels[tr.depth] if b.k == 7][0]
-    srcs = tr.interaction(Z)
-    assert srcs
-    rng = np.random.default_rng(1)
-    errs = []
-    for m in (2, 4, 6):
-        o = F.FMMOracle(tr, m, m, "V")
-        worst = 0.0
-        for S in srcs[:6]:
-            op = o.m2l_operator(Z, S)
-            lo_x, lo_y = tr.box_lower(Z), tr.box_lower(S)
-            H = tr.hx_padded(Z.level)
-            x = lo_x + 2 * H * rng.uniform(size=(20, 3))
-            y = lo_y + 2 * H * rng.uniform(size=(20, 3))
-            ta, tb = tr.interval(Z)
-            sa, sb = tr.interval(S)
-            tt = ta + (tb - ta) * rng.uniform(size=20)
-            tau = sa + (sb - sa) * rng.uniform(size=20)
-            exact = G(np.linalg.norm(x - y, axis=1), tt - tau, 1.0)
-            Tx = [F.cheb_T(m, (x[:, j] - lo_x[j]) / H - 1) for j in range(3)]
-            Ty = [F.cheb_T(m, (y[:, j] - lo_y[j]) / H - 1) for j in range(3)]
-            mi = o.mi
-            TX = Tx[0][mi[:, 0]] * Tx[1][mi[:, 1]] * Tx[2][mi[:, 2]]     # (N, 20)
-            TY = Ty[0][mi[:, 0]] * Ty[1][mi[:, 1]] * Ty[2][mi[:, 2]]
-            Lt = F.lagrange(o.tnodes(Z), tt)
-            Ltau = F.lagrange(o.tnodes(S), tau)
-            approx = np.einsum("bvak,vi,ki,bi,ai->i", op, TX, TY, Lt, Ltau)
-            worst = max(worst, np.abs(approx - exact).max() / np.abs(exact).max())
-        errs.append(worst)
-    assert errs[0] > errs[1] > errs[2]
-    assert errs[2] < 1e-2
+# Relative kernel-approximation error max|G - expansion| / max|G| on
+# admissible box pairs with spatial offsets (0,0,0), (1,0,0), (1,1,0) and
+# time offsets of 2 and 3 intervals, for box-size ratios
+# c = H^2 / (4 alpha h_t) = 0.25 and 0.5 (H, h_t the spatial and temporal
+# half-sizes, the ratio of eq. rel_h_t_h_x), m_t = m_x = m: values of an
+# independent brute-force evaluation of the truncated Chebyshev x Lagrange
+# interpolant of the heat kernel (eqs. kernel_approx, exp_coeffs_3d,
+# exp_coeffs_1d) against the kernel itself.
+P10_EXPECTED = {0.25: {2: 7e-2, 4: 8e-3, 6: 8e-4, 8: 6e-5}, 0.5: {2: 1.7e-1, 4: 2.9e-2, 6: 5.5e-3, 8: 6.4e-4}}
+
+
+def _expansion_error(o, tr, Z, S, rng, npts=200):
+    m = o.m_x
+    op = o.m2l_operator(Z, S)
+    lo_x, lo_y = tr.box_lower(Z), tr.box_lower(S)
+    H = tr.hx_padded(Z.level)
+    x = lo_x + 2 * H * rng.uniform(size=(npts, 3))
+    y = lo_y + 2 * H * rng.uniform(size=(npts, 3))
+    ta, tb = tr.interval(Z)
+    sa, sb = tr.interval(S)
+    tt = ta + (tb - ta) * rng.uniform(size=npts)
+    tau = sa + (sb - sa) * rng.uniform(size=npts)
+    exact = G(np.linalg.norm(x - y, axis=1), tt - tau, 1.0)
+    Tx = [F.cheb_T(m, (x[:, j] - lo_x[j]) / H - 1) for j in range(3)]
+    Ty = [F.cheb_T(m, (y[:, j] - lo_y[j]) / H - 1) for j in range(3)]
+    mi = o.mi
+    TX = Tx[0][mi[:, 0]] * Tx[1][mi[:, 1]] * Tx[2][mi[:, 2]]     # (N, npts)
+    TY = Ty[0][mi[:, 0]] * Ty[1][mi[:, 1]] * Ty[2][mi[:, 2]]
+    Lt = F.lagrange(o.tnodes(Z), tt)
+    Ltau = F.lagrange(o.tnodes(S), tau)
+    approx = np.einsum("bvak,vi,ki,bi,ai->i", op, TX, TY, Lt, Ltau)
+    return np.abs(approx - exact).max() / np.abs(exact).max()
+
+
+def test_kernel_expansion_error_values():
+    """The oracle's M2L operator, read as the kernel expansion it is, has the
+    expected approximation error (within a factor 2 either way, so a
+    misplaced scale factor such as lambda_k or C_ab fails) and converges as
+    m grows.  Cube 4 x 4 squares per face, 16 steps on [0, 1]: level 3 boxes
+    have c = 0.25, level 2 boxes c = 0.5."""
+    v, t = cube_surface_mesh(4)
+    tr = Tree(v, t, uniform_time_nodes(16), 1.0, 64, 0.9, -1)
+    for level, c in ((3, 0.25), (2, 0.5)):
+        b0 = tr.levels[level][0]
+        ta, tb = tr.interval(b0)
+        assert abs(tr.hx_padded(level) ** 2 / (4 * 1.0 * (tb - ta) / 2) - c) < 1e-12
+        pairs = []
+        for off in ((0, 0, 0), (1, 0, 0), (1, 1, 0)):
+            for D in (2, 3):
+                found = None
+                for Z in tr.levels[level]:
+                    for S in tr.interaction(Z):
+                        if tuple(np.subtract(Z.ix, S.ix)) == off and Z.k - S.k == D:
+                            found = (Z, S)
+                            break
+                    if found:
+                        break
+                assert found, (level, off, D)
+                pairs.append(found)
+        errs = []
+        for m in (2, 4, 6, 8):
+            o = F.FMMOracle(tr, m, m, "V")
+            rng = np.random.default_rng(1)
+            e = max(_expansion_error(o, tr, Z, S, rng) for Z, S in pairs)
+            errs.append(e)
+            ratio = e / P10_EXPECTED[c][m]
+            assert 0.5 <= ratio <= 2.0, (c, m, e, P10_EXPECTED[c][m])
+        assert all(errs[i] > 5 * errs[i + 1] for i in range(3)), errs
 
 
 def test_pfmm_converges_to_dense_V(c1):
