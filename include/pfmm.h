@@ -357,6 +357,26 @@ pfmm_status pfmm_precond_load(const char* path, int32_t device, pfmm_precond** o
 void pfmm_precond_destroy(pfmm_precond* pc);
 
 /*
+ * pfmm_precond_apply for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and result as pfmm_precond_apply, but it
+ * calls no hipMalloc / hipFree and does not synchronise: the work is only
+ * enqueued on `stream`.  Its scratch (the diagonal of V_h per triangle, the
+ * reduction partials and the three FP32 feature fields) is a device array of
+ * PFMM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; a tree needs 8 (round_up(n_triangles, 32) + 1024 +
+ * ceil(3 N / 2)) bytes of it (N = n_steps * n_triangles; about 8.4M DOFs fit),
+ * larger trees get PFMM_EINVAL.  All calls on one GPU share that GPU's array:
+ * calls that overlap on one device (different streams or threads) race; calls
+ * ordered on one stream do not.
+ * Errors: PFMM_EINVAL (NULL, aliasing, V not built, tree too large),
+ * PFMM_EDEVICE.
+ */
+#define PFMM_NOALLOC_SCRATCH_BYTES (96u << 20)
+pfmm_status pfmm_precond_apply_noalloc(const pfmm_precond* pc, pfmm_tree* t, const double* v_dev, double* z_dev,
+                                       void* stream);
+
+/*
  * Solve V_h w = b by iterative refinement in FP64 around flexible GMRES
  * (right preconditioning with pc, or none when pc is NULL), the inner
  * products applied in the farfield precision `inner_precision`

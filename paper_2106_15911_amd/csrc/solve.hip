@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -598,6 +599,35 @@ pfmm_status solve_common(pfmm_tree* t, const double* b_or_g, double* w, const pf
     return s;
 }
 
+// Scratch of pfmm_precond_apply_noalloc: the diagonal of V_h per triangle,
+// the reduction partials and the three FP32 feature fields of one vector.
+// One copy per GPU (each device holds the array from the library's first use
+// on it until the process ends).  Host code never passes `scratch` itself to
+// a kernel: it is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, looked up once per device.
+constexpr size_t kScratchDoubles = (size_t)PFMM_NOALLOC_SCRATCH_BYTES / sizeof(double);
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (looked up on the
+// first call for that device).
+pfmm_status scratch_address(int dev, double** out) {
+    if (dev < 0 || dev >= kMaxDevices) return set_error(PFMM_EDEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(PFMM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return PFMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -681,6 +711,34 @@ pfmm_status pfmm_precond_apply(const pfmm_precond* pc, pfmm_tree* t, const doubl
     if (s == PFMM_OK) s = precond_apply(pc, v_dev, z_dev, D, tree_adjacency(t), tree_triangles(t), tree_dofs(t), part, st);
     if (s == PFMM_OK && hipStreamSynchronize(st) != hipSuccess) s = set_error(PFMM_EDEVICE, "hipStreamSynchronize failed");
     return s;
+}
+
+pfmm_status pfmm_precond_apply_noalloc(const pfmm_precond* pc, pfmm_tree* t, const double* v_dev, double* z_dev,
+                                       void* stream) {
+    if (!pc || !t || !v_dev || !z_dev) return set_error(PFMM_EINVAL, "NULL argument");
+    if (!tree_has(t, PFMM_OP_V)) return set_error(PFMM_EINVAL, "V_h was not built for this tree");
+    if (v_dev == z_dev) return set_error(PFMM_EINVAL, "v and z must not alias");
+    const int64_t n = tree_dofs(t), ex = tree_triangles(t);
+    // layout: [0, ex) the diagonal D, then (from a 256-byte boundary) the
+    // partials and feature fields of precond_apply
+    const int64_t off = (ex + 31) & ~(int64_t)31;
+    const size_t need = (size_t)off + precond_scratch_doubles(n);
+    if (need > kScratchDoubles)
+        return set_error(PFMM_EINVAL, "tree too large for the no-allocation scratch: needs " +
+                                          std::to_string(need * sizeof(double)) + " bytes, limit " +
+                                          std::to_string((size_t)PFMM_NOALLOC_SCRATCH_BYTES));
+    const int dev = tree_device(t);
+    if (hipSetDevice(dev) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
+    double* base = nullptr;
+    PS_TRY(scratch_address(dev, &base));
+    // every scratch value is written before it is read (the diagonal covers all
+    // triangles, the partials all blocks, the fields all DOFs): nothing to clear
+    double* D = base;
+    double* part = base + off;
+    hipStream_t st = (hipStream_t)stream;
+    PS_TRY(tree_near_diag(t, D, st));
+    PS_TRY(precond_apply(pc, v_dev, z_dev, D, tree_adjacency(t), ex, n, part, st));
+    return PFMM_OK;
 }
 
 pfmm_status pfmm_precond_train(pfmm_precond* pc, pfmm_tree* t, const double* b_dev, int32_t n_snap, int32_t steps,

@@ -97,6 +97,7 @@ def load_library():
         "pfmm_precond_train": ([VP, VP, VP, I32, I32, I32, ctypes.c_float, ctypes.c_uint64,
                                 P(ctypes.c_float), VP], I32),
         "pfmm_precond_apply": ([VP, VP, VP, VP, VP], I32),
+        "pfmm_precond_apply_noalloc": ([VP, VP, VP, VP, VP], I32),
         "pfmm_precond_save": ([VP, ctypes.c_char_p], I32),
         "pfmm_precond_load": ([ctypes.c_char_p, I32, P(VP)], I32),
         "pfmm_precond_destroy": ([VP], None),
@@ -339,6 +340,19 @@ class Precond:
             out = torch.empty_like(v)
         _check(self.lib.pfmm_precond_apply(self.handle, tree.handle, ctypes.c_void_p(v.data_ptr()),
                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def apply_noalloc(self, tree, v, out, stream=None):
+        """As apply, through the entry point that allocates no device memory
+        (library-held scratch; stream-ordered, no synchronisation); `out` is
+        required."""
+        import torch
+        for x in (v, out):
+            if (x.dtype != torch.float64 or x.device != tree.device or x.numel() != tree.n_dofs
+                    or not x.is_contiguous()):
+                raise ValueError(f"expected contiguous float64 tensors of {tree.n_dofs} entries on {tree.device}")
+        _check(self.lib.pfmm_precond_apply_noalloc(self.handle, tree.handle, ctypes.c_void_p(v.data_ptr()),
+                                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
     def save(self, path):
