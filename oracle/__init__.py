@@ -9,7 +9,8 @@ Sources (Watschinger, Merta, Of, Zapletal, "A parallel fast multipole method
 for a space-time boundary element method for the heat equation"):
 
 * Section 2 — heat kernel (eq. heat_kernel), p0 x p0 Galerkin matrix V_h and
-  its block lower-triangular structure; the double-layer operator K.
+  its block lower-triangular structure; the double-layer operator K; the
+  representation formula u = V~w - Wu at interior points.
 * Section 3.1 — kernel expansion (eqs. kernel_approx, exp_coeffs_3d,
   def_r_j, def_d_ab, exp_coeffs_1d), box-size coupling (eq. rel_h_t_h_x).
 * Section 3.2 — Algorithm 1 (box cluster tree), split points and padding.
@@ -21,7 +22,8 @@ for a space-time boundary element method for the heat equation"):
 Modules: quadrature (Gauss rules and the singular panel-pair rules),
 timeint (analytic time integrals), dense (dense Galerkin assembly for tiny
 meshes), tree (Algorithm 1 and the lists), fmm (expansions and the apply),
-gmres (unpreconditioned GMRES).
+solve (unpreconditioned GMRES), represent (single- and double-layer
+potentials at interior points).
 
 Parity status per function is listed in the module headers; every function
 here is pinned by a ``-m "not gpu"`` test against a value fixed by the paper
