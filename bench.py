@@ -330,7 +330,10 @@ def solve_bench(args):
 
 def batch_bench(args):
     """48 independent cube problems (face grids 4..32, 32..512 steps, drawn
-    from seed 4) applied together: one captured graph per batch apply."""
+    from seed 4) applied together: one captured graph per batch apply, whose
+    M2L of the levels with unequal intervals runs as one cross-problem launch
+    per time offset; timed against the same applies one after another and
+    against a graph of whole per-tree applies."""
     import numpy as np
     import torch
     import paper_2106_15911_amd as P
@@ -373,16 +376,24 @@ def batch_bench(args):
     log(f"[batch] {N} DOFs, one apply per tree in sequence: {ms_seq:.1f} ms")
     b = P.Batch(trees)
     outs = [torch.empty_like(w) for w in ws]
-    for _ in range(max(1, args.warmup)):
-        b.apply_V(ws, outs, stream=stream)
-    torch.cuda.synchronize()
-    same = all(bool(torch.equal(a, c)) for a, c in zip(outs, outs_ref))
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b.apply_V(ws, outs, stream=stream)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / args.steps
-    log(f"[batch] batched (captured graph): {ms:.1f} ms per batch apply; equal to single applies: {same}")
+
+    def run(cross):
+        b.set_cross_m2l(cross)
+        for _ in range(max(1, args.warmup)):
+            b.apply_V(ws, outs, stream=stream)
+        torch.cuda.synchronize()
+        eq = all(bool(torch.equal(a, c)) for a, c in zip(outs, outs_ref))
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.apply_V(ws, outs, stream=stream)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / args.steps, eq
+
+    ms_branches, same_b = run(False)
+    log(f"[batch] graph of whole applies per tree: {ms_branches:.1f} ms per batch apply; equal: {same_b}")
+    ms, same = run(True)
+    same = same and same_b
+    log(f"[batch] graph with the cross-problem M2L launch: {ms:.1f} ms per batch apply; equal to single applies: {same}")
     out = {
         "metric": "space-time DOF matvec/s of pFMM V_h, 48 batched problems (aggregate)",
         "value": N / (ms * 1e-3), "unit": "DOF-matvec/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -394,7 +405,8 @@ def batch_bench(args):
                                 "middle step); m_t = m_x = 6, n_max 64, c_st 0.9, n_tr 5, Toeplitz nearfield"),
                    "dofs": N, "problems": [[p[0], p[1]] for p in probs], "parallelism": "single GPU",
                    "time_classes": [tr.stats()["n_time_classes"] for tr in trees]},
-        "sequential_ms": ms_seq, "bitwise_equal_to_single_applies": same, "build_s": t_build, "device_bytes": mem,
+        "sequential_ms": ms_seq, "graph_whole_applies_ms": ms_branches,
+        "bitwise_equal_to_single_applies": same, "build_s": t_build, "device_bytes": mem,
     }
     print(json.dumps(out), flush=True)
     b.close()
@@ -424,6 +436,9 @@ def main():
     ap.add_argument("--solve", action="store_true",
                     help="instead of the apply benchmark: Dirichlet solve on the 12,288 x 512 cube (config 5)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3072 x 256 secondary measurement")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in M2L launch choices")
+    ap.add_argument("--autotune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"), "pfmm_autotune.json"),
+                    help="JSON cache of the M2L autotuner")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the Dirichlet solve measurement that follows the apply benchmark")
     ap.add_argument("--rtol", type=float, default=1e-8)
@@ -460,6 +475,13 @@ def main():
     t_build = time.perf_counter() - t0
     st = tree.stats()
     log(f"[bench] built config {args.config}: {st} in {t_build:.2f} s")
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        n_t, n_c = tree.autotune(args.autotune_cache, stream=stream)
+        tune = {"levels_timed": n_t, "levels_cached": n_c, "seconds": time.perf_counter() - t0,
+                "cache": args.autotune_cache}
+        log(f"[bench] autotune: {tune}")
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device=dev)
@@ -640,6 +662,7 @@ def main():
         "other_kernels": other,
         "stages_ms_per_apply": {k: (vv[0] / max(vv[1], 1)) for k, vv in prof.items()},
         "build_s": t_build,
+        "autotune": tune,
         "tree": st,
         "oracle_check": check,
         "cpu_baseline": cpu,
@@ -653,6 +676,8 @@ def main():
         prm2 = P.default_params(m_t=c2["m_t"], m_x=c2["m_x"], n_max=c2["n_max"], c_st=c2["c_st"],
                                 n_tr=c2["n_tr"], operators=1)
         tree2 = P.Tree(v2, t2, tn2, prm2, device=0, stream=stream)
+        if not args.no_autotune:
+            tree2.autotune(args.autotune_cache, stream=stream)
         x2 = torch.from_numpy(w2).to(dev)
         y2 = torch.empty_like(x2)
         for _ in range(max(1, args.warmup)):

@@ -182,6 +182,31 @@ pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void*
  */
 pfmm_status pfmm_set_precision(pfmm_tree* t, int32_t precision);
 
+/*
+ * Autotuner of the M2L launch configuration (eq. m2l on the matrix cores;
+ * the paper's kernels are CPU code, so these choices are this library's
+ * own).  For every level >= 2 with equal intervals and each farfield
+ * precision the tree holds (FP64; FP32, whose choice BF16 shares), it times
+ * the candidate configurations on this device -- interval blocks per
+ * workgroup (32, 64 or 128 intervals) and interaction-list shares (1, 2, 3,
+ * 4, 6, 8; 1..4 for levels with fewer than 32 intervals) -- with one warm-up
+ * and three launches between HIP events each, and keeps the fastest for the
+ * tree's later applies.  The choices are cached in the text file cache_path
+ * (one JSON object; NULL: no cache), keyed by the device's architecture and
+ * compute-unit count and the level's shape (coefficients per box, intervals,
+ * slots, slot pairs of the interaction lists, precision); a later call for
+ * the same shapes applies the cached choices without timing.  Results of
+ * later applies change only by the summation order of the shares (FP64:
+ * ~1e-15 relative).  Levels with unequal intervals keep their class-aware
+ * kernel.  Synchronous on `stream`; may reallocate the tree's partial-locals
+ * buffer; not allowed while stage profiling is on.  n_tuned and n_cached
+ * (may be NULL) receive the (level, precision) pairs timed and those taken
+ * from the cache.
+ * Errors: PFMM_EINVAL (NULL tree, profiling on, cache not writable),
+ * PFMM_ENOMEM, PFMM_EDEVICE.
+ */
+pfmm_status pfmm_autotune(pfmm_tree* t, const char* cache_path, void* stream, int32_t* n_tuned, int32_t* n_cached);
+
 /* Counts and sizes of a built tree. */
 pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out);
 
@@ -310,6 +335,18 @@ pfmm_status pfmm_solve_dirichlet(pfmm_tree* t, const double* g_dev, double* w_de
 typedef struct pfmm_batch pfmm_batch;
 pfmm_status pfmm_batch_create(pfmm_tree* const* trees, int32_t n, pfmm_batch** out);
 pfmm_status pfmm_apply_V_batch(pfmm_batch* b, const double* const* w_dev, double* const* f_dev, void* stream);
+/*
+ * Cross-problem M2L of a batch (default on): the M2L of the levels whose
+ * intervals differ in length (class-aware kernel) runs for all trees of the
+ * batch in one launch per (precision, time offset) -- a 1D grid over every
+ * (tree, level) unit's workgroups -- between the trees' upward passes and
+ * nearfields and their downward passes, each in the graph's branches.
+ * Applies to batches whose trees share the degrees m_t, m_x; otherwise, and
+ * with enable = 0, every tree's apply runs whole in its branch.  Results
+ * are the same either way (bitwise).  Changing the setting re-captures on
+ * the next apply.  Errors: PFMM_EINVAL (NULL).
+ */
+pfmm_status pfmm_batch_set_cross_m2l(pfmm_batch* b, int32_t enable);
 void pfmm_batch_destroy(pfmm_batch* b);
 
 /*
@@ -397,6 +434,31 @@ pfmm_status pfmm_precond_apply_noalloc(const pfmm_precond* pc, pfmm_tree* t, con
  */
 pfmm_status pfmm_solve_V_precond(pfmm_tree* t, const pfmm_precond* pc, int32_t inner_precision, const double* b_dev,
                                  double* w_dev, const pfmm_solve_opts* o, pfmm_solve_info* info, void* stream);
+
+/*
+ * Representation formula at interior points (Section 2): for zero initial
+ * data, the solution inside the domain is u = V~ w - W u with the
+ * single-layer potential V~ (kernel G) of the Neumann trace w = alpha du/dn
+ * and the double-layer potential W (kernel alpha dG/dn_y) of the Dirichlet
+ * trace u.  For p0 x p0 traces on the tree's mesh and time grid (w from a
+ * Dirichlet solve, u the projected datum) this evaluates
+ *     out_i = (V~ w)(x_i, t_i) - (W u)(x_i, t_i)
+ * at n_points space-time points.  Time integrals are closed-form (first
+ * antiderivatives of G and G / (2 s)); each triangle's space integral uses
+ * the collapsed Gauss rule with q points per direction (1..16), accurate for
+ * points well inside the domain and less so as a point approaches the
+ * surface (points on the surface are not supported).  Direct summation:
+ * O(n_points N q^2) work, no tree expansions.
+ *  w_dev, u_dev  device, natural order, N = n_steps * n_triangles doubles;
+ *                either may be NULL (that potential is left out)
+ *  xt_dev        device, n_points x 4 doubles (x, y, z, t) row-major
+ *  out_dev       device, n_points doubles (overwritten)
+ * Asynchronous on `stream`; allocates nothing once the tree is built.
+ * Errors: PFMM_EINVAL (NULL tree / points / output, q or n_points out of
+ * range), PFMM_EDEVICE.
+ */
+pfmm_status pfmm_representation(pfmm_tree* t, const double* w_dev, const double* u_dev, const double* xt_dev,
+                                int64_t n_points, int32_t q, double* out_dev, void* stream);
 
 /* Release every host and device resource of the tree.  NULL is a no-op. */
 void pfmm_destroy(pfmm_tree* t);

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpfmm.so")
-SOURCES = ["plan.cpp", "tables.cpp", "pfmm.hip", "solve.hip", "batch.hip", "precond.hip"]
+SOURCES = ["plan.cpp", "tables.cpp", "pfmm.hip", "solve.hip", "batch.hip", "precond.hip", "represent.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

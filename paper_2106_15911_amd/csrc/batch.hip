@@ -1,8 +1,11 @@
 // Batched applies of independent problems: every tree of a batch applies V_h
 // to its own density in one stream-ordered call.  The per-problem applies
-// (all stages of Algorithm 2 for one tree) are captured once into a HIP
+// (the stages of Algorithm 2 for one tree) are captured once into a HIP
 // graph whose branches run on separate streams, so small problems overlap
-// each other and the large ones instead of queueing one after another; the
+// each other and the large ones instead of queueing one after another.  When
+// trees have levels with unequal intervals (the class-aware M2L), the M2L of
+// those levels of all trees runs as one cross-problem launch per (precision,
+// time offset) between the trees' upward and downward passes; the
 // graph is replayed for every further call with the same vectors and tree
 // precisions, and re-captured when either changes.
 #include <hip/hip_runtime.h>
@@ -29,6 +32,8 @@ struct pfmm_batch {
     std::vector<double*> key_f;
     std::vector<int> key_prec;             // each tree's farfield precision at capture (the graph
                                            // holds that precision's kernels and tables)
+    BatchM2L* xm = nullptr;                // cross-problem M2L of the levels with unequal intervals
+    bool use_xm = true;
 };
 
 namespace {
@@ -59,16 +64,36 @@ void release_graph(pfmm_batch* b) {
 pfmm_status capture(pfmm_batch* b, const double* const* w, double* const* f) {
     release_graph(b);
     hipStream_t st = b->cap;
+    const bool xm = b->xm && b->use_xm;
+    if (xm) {
+        const pfmm_status ps = batch_m2l_prepare(b->xm);   // unit descriptors for the current precisions
+        if (ps != PFMM_OK) return ps;
+    }
     HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     pfmm_status status = PFMM_OK;
-    hipError_t e = hipEventRecord(b->fork, st);
+    hipError_t e = hipSuccess;
     const int nb = (int)b->streams.size();
-    for (int s = 0; s < nb && e == hipSuccess; ++s) e = hipStreamWaitEvent(b->streams[s], b->fork, 0);
-    for (size_t i = 0; i < b->trees.size() && e == hipSuccess && status == PFMM_OK; ++i)
-        status = tree_apply(b->trees[i], false, w[i], f[i], b->streams[i % nb]);
-    for (int s = 0; s < nb && e == hipSuccess; ++s) {
-        e = hipEventRecord(b->joins[s], b->streams[s]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, b->joins[s], 0);
+    // fork the branch streams from st, run `body(tree, stream)` for every
+    // tree on branch i mod nb, join them back into st
+    auto branches = [&](auto body) {
+        if (e == hipSuccess) e = hipEventRecord(b->fork, st);
+        for (int s = 0; s < nb && e == hipSuccess; ++s) e = hipStreamWaitEvent(b->streams[s], b->fork, 0);
+        for (size_t i = 0; i < b->trees.size() && e == hipSuccess && status == PFMM_OK; ++i)
+            status = body(i, b->streams[i % nb]);
+        for (int s = 0; s < nb && e == hipSuccess; ++s) {
+            e = hipEventRecord(b->joins[s], b->streams[s]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, b->joins[s], 0);
+        }
+    };
+    if (!xm) {
+        branches([&](size_t i, hipStream_t sb) { return tree_apply(b->trees[i], false, w[i], f[i], sb); });
+    } else {
+        // upward passes and nearfields per tree, one M2L launch per (precision,
+        // time offset) for the levels with unequal intervals of all trees,
+        // then the downward passes per tree
+        branches([&](size_t i, hipStream_t sb) { return tree_apply_phase(b->trees[i], false, w[i], f[i], sb, 1); });
+        if (e == hipSuccess && status == PFMM_OK) status = batch_m2l_launch(b->xm, st);
+        branches([&](size_t i, hipStream_t sb) { return tree_apply_phase(b->trees[i], false, w[i], f[i], sb, 2); });
     }
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(st, &g);
@@ -127,6 +152,11 @@ pfmm_status pfmm_batch_create(pfmm_tree* const* trees, int32_t n, pfmm_batch** o
         pfmm_batch_destroy(b);
         return set_error(PFMM_EDEVICE, std::string("batch streams: ") + hipGetErrorString(e));
     }
+    const pfmm_status xs = batch_m2l_create(trees, n, &b->xm);
+    if (xs != PFMM_OK) {
+        pfmm_batch_destroy(b);
+        return xs;
+    }
     *out = b;
     return PFMM_OK;
 }
@@ -151,10 +181,20 @@ pfmm_status pfmm_apply_V_batch(pfmm_batch* b, const double* const* w_dev, double
     return PFMM_OK;
 }
 
+pfmm_status pfmm_batch_set_cross_m2l(pfmm_batch* b, int32_t enable) {
+    if (!b) return set_error(PFMM_EINVAL, "NULL batch");
+    if ((enable != 0) != b->use_xm) {
+        b->use_xm = enable != 0;
+        release_graph(b);   // the next apply re-captures
+    }
+    return PFMM_OK;
+}
+
 void pfmm_batch_destroy(pfmm_batch* b) {
     if (!b) return;
     (void)hipSetDevice(b->device);
     release_graph(b);
+    batch_m2l_destroy(b->xm);
     for (hipStream_t s : b->streams)
         if (s) (void)hipStreamDestroy(s);
     if (b->cap) (void)hipStreamDestroy(b->cap);

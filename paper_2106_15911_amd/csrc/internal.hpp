@@ -51,4 +51,33 @@ float precond_last_loss(const pfmm_precond* pc);
 // Stream-ordered applies without argument checks (natural order in and out).
 pfmm_status tree_apply(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st);
 
+// The apply in two phases around a batched M2L: phase 1 permutes, runs the
+// nearfield, the upward pass and the M2L of the levels with equal intervals
+// (the others prepared); phase 2 runs L2L, L2T and the final permutation.
+pfmm_status tree_apply_phase(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st, int phase);
+
+// Cross-problem M2L: the class-aware M2L of the levels with unequal or
+// missing intervals of all trees of a batch in one launch per (precision,
+// time offset).  create returns *out = NULL when the trees cannot share a
+// launch (different degrees, no matrix-core path) or have no such level;
+// prepare fills the unit descriptors for the trees' current precisions
+// (synchronous; outside graph capture); launch enqueues the launches.
+struct BatchM2L;
+pfmm_status batch_m2l_create(pfmm_tree* const* trees, int n, BatchM2L** out);
+pfmm_status batch_m2l_prepare(BatchM2L* b);
+pfmm_status batch_m2l_launch(BatchM2L* b, hipStream_t st);
+void batch_m2l_destroy(BatchM2L* b);
+
+// The tree's mesh and time grid on the device (natural triangle order).
+struct TreeGeom {
+    const double* verts;     // n_vertices x 3
+    const int* tris;         // n_tri x 3
+    const double* area;      // n_tri
+    const double* normal;    // n_tri x 3 (unit, outward)
+    const double* tnodes;    // n_steps + 1
+    int n_tri, n_steps;
+    double alpha, t_first, t_last;
+};
+pfmm_status tree_geometry(pfmm_tree* t, TreeGeom* out);
+
 }  // namespace pfmm

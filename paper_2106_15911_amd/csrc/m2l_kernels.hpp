@@ -645,17 +645,39 @@ __global__ void k_sum_parts(double* __restrict__ lam, const double* __restrict__
 // (the others are masked to zero).  The results are added to lam, which the
 // caller zeroes before the first of the two launches (each (X, row, k) is
 // owned by one workgroup per launch, so the sum is deterministic).
-template <class T, int NB, int MAXS, int WAVES, bool RB = false>
-__global__ void __launch_bounds__(64 * WAVES) k_m2l_cls(
-    const T* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
-    const int* __restrict__ ocls, const int* __restrict__ off3, const T* __restrict__ E1c, int TSp,
-    const int* __restrict__ packinfo, const int* __restrict__ plan, int plan_stride, int Nc, int n_int, int mt,
-    int mx, int R, const int2* __restrict__ cols, const int2* __restrict__ cbr, int D, int ncb) {
+// One level of one tree for the class-aware M2L (one time offset D).
+struct ClsUnit {
+    const void* mu;          // moments of the level (FP64, or FP32 / BF16 values)
+    double* lam;             // locals of the level (added to)
+    const int* ptr;          // interaction lists: CSR over target slots
+    const int* src;          //   source slot
+    const int* ocls;         //   spatial offset class
+    const int* off3;         // offsets per class
+    const void* E1c;         // compact 1D tables of the level [class][offset][x | yz]
+    const int2* cols;        // columns (k, class), padded with k = -1
+    const int2* cbr;         // first and last class per column block
+    int n_int, R, nx, nccb, D;
+    int wg0;                 // first workgroup of this unit in a batched launch
+};
+
+template <class T, int NB, int MAXS, int WAVES, bool RB>
+__device__ __forceinline__ void m2l_cls_body(
+    double* smem, const ClsUnit& U, int g, int X, int cb, int TSp, const int* __restrict__ packinfo,
+    const int* __restrict__ plan, int plan_stride, int Nc, int mt, int mx) {
     static_assert(MAXS >= 1 && MAXS <= 4, "phase dispatch below is written for one to four slots");
     using Tr = M2LTraits<T>;
     using acc_t = typename Tr::acc_t;
     constexpr int ES = sizeof(T);
-    extern __shared__ double smem[];
+    const T* __restrict__ mu = (const T*)U.mu;
+    double* __restrict__ lam = U.lam;
+    const int* __restrict__ ptr = U.ptr;
+    const int* __restrict__ src = U.src;
+    const int* __restrict__ ocls = U.ocls;
+    const int* __restrict__ off3 = U.off3;
+    const T* __restrict__ E1c = (const T*)U.E1c;
+    const int2* __restrict__ cols = U.cols;
+    const int2* __restrict__ cbr = U.cbr;
+    const int n_int = U.n_int, R = U.R, D = U.D;
     const int nt1 = mt + 1, nx1 = mx + 1;
     const int BS = nx1 * (nx1 + 1) / 2;
     const int Nc4 = (Nc + 3) & ~3;
@@ -664,18 +686,6 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_cls(
     int4* sCol = (int4*)((char*)smem + 6 * TSp * ES);
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    int g, X, cb;
-    {
-        const int ng = gridDim.x, nxs = gridDim.y;
-        const int total = ng * nxs * gridDim.z;
-        const int lin = blockIdx.x + ng * (blockIdx.y + nxs * blockIdx.z);
-        const int per = total / kXcds;
-        const int lm = lin < per * kXcds ? (lin % kXcds) * per + lin / kXcds : lin;
-        g = lm % ng;
-        X = (lm / ng) % nxs;
-        cb = lm / (ng * nxs);
-    }
-    (void)ncb;
     const int* gp = plan + (int64_t)g * plan_stride;
     const int lr = lane & 15, lq = lane >> 4;
     auto tri = [&](int k) { return k * nx1 - (k * (k - 1)) / 2; };
@@ -865,6 +875,45 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_cls(
     }
 }
 
+template <class T, int NB, int MAXS, int WAVES, bool RB = false>
+__global__ void __launch_bounds__(64 * WAVES) k_m2l_cls(ClsUnit U, int TSp, const int* __restrict__ packinfo,
+                                                       const int* __restrict__ plan, int plan_stride, int Nc, int mt,
+                                                       int mx) {
+    extern __shared__ double smem[];
+    // XCD-aware remap of the linear workgroup id (as k_m2l_wide)
+    const int ng = gridDim.x, nxs = gridDim.y;
+    const int total = ng * nxs * gridDim.z;
+    const int lin = blockIdx.x + ng * (blockIdx.y + nxs * blockIdx.z);
+    const int per = total / kXcds;
+    const int lm = lin < per * kXcds ? (lin % kXcds) * per + lin / kXcds : lin;
+    m2l_cls_body<T, NB, MAXS, WAVES, RB>(smem, U, lm % ng, (lm / ng) % nxs, lm / (ng * nxs), TSp, packinfo, plan,
+                                         plan_stride, Nc, mt, mx);
+}
+
+// The class-aware M2L of many (tree, level) units in one launch (trees of a
+// batch with the same degrees share the row-group plan): a 1D grid over the
+// units' workgroups, each finding its unit by binary search on wg0.
+template <class T, int NB, int MAXS, int WAVES, bool RB = false>
+__global__ void __launch_bounds__(64 * WAVES) k_m2l_cls_batch(const ClsUnit* __restrict__ units, int n_units, int G,
+                                                             int TSp, const int* __restrict__ packinfo,
+                                                             const int* __restrict__ plan, int plan_stride, int Nc,
+                                                             int mt, int mx) {
+    extern __shared__ double smem[];
+    const int total = gridDim.x;
+    const int lin = blockIdx.x;
+    const int per = total / kXcds;
+    const int lm = lin < per * kXcds ? (lin % kXcds) * per + lin / kXcds : lin;
+    int lo = 0, hi = n_units - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (units[mid].wg0 <= lm) lo = mid; else hi = mid - 1;
+    }
+    const ClsUnit U = units[lo];
+    const int loc = lm - U.wg0;
+    m2l_cls_body<T, NB, MAXS, WAVES, RB>(smem, U, loc % G, (loc / G) % U.nx, loc / (G * U.nx), TSp, packinfo, plan,
+                                         plan_stride, Nc, mt, mx);
+}
+
 // class-aware M2L: two column blocks of 16 per workgroup, two slots per wave, 16 waves
 constexpr int kClsNB = 2, kClsMaxs = 2, kClsWaves = 16;
 
@@ -873,21 +922,36 @@ const void* cls_fn() {
     return (const void*)k_m2l_cls<std::conditional_t<Q == 0, double, float>, kClsNB, kClsMaxs, kClsWaves, Q == 2>;
 }
 
-const void* cls_fn(int q) { return q == 0 ? cls_fn<0>() : (q == 1 ? cls_fn<1>() : cls_fn<2>()); }
-
 template <int Q>
-void launch_cls(dim3 grid, size_t shm, hipStream_t st, const void* mu, double* lam, const int* ptr, const int* src,
-                const int* ocls, const int* off3, const void* E1c, int TSp, const int* packinfo, const int* plan,
-                int plan_stride, int Nc, int n_int, int mt, int mx, int R, const int2* cols, const int2* cbr, int D,
-                int ncb) {
-    using T = std::conditional_t<Q == 0, double, float>;
-    hipLaunchKernelGGL((k_m2l_cls<T, kClsNB, kClsMaxs, kClsWaves, Q == 2>), grid, dim3(64 * kClsWaves), shm, st,
-                       (const T*)mu, lam, ptr, src, ocls, off3, (const T*)E1c, TSp, packinfo, plan, plan_stride, Nc,
-                       n_int, mt, mx, R, cols, cbr, D, ncb);
+const void* cls_batch_fn() {
+    return (const void*)k_m2l_cls_batch<std::conditional_t<Q == 0, double, float>, kClsNB, kClsMaxs, kClsWaves,
+                                        Q == 2>;
 }
 
-using ClsLaunch = void (*)(dim3, size_t, hipStream_t, const void*, double*, const int*, const int*, const int*,
-                           const int*, const void*, int, const int*, const int*, int, int, int, int, int, int,
-                           const int2*, const int2*, int, int);
+const void* cls_fn(int q) { return q == 0 ? cls_fn<0>() : (q == 1 ? cls_fn<1>() : cls_fn<2>()); }
+const void* cls_batch_fn(int q) { return q == 0 ? cls_batch_fn<0>() : (q == 1 ? cls_batch_fn<1>() : cls_batch_fn<2>()); }
+
+template <int Q>
+void launch_cls(dim3 grid, size_t shm, hipStream_t st, const ClsUnit& U, int TSp, const int* packinfo, const int* plan,
+                int plan_stride, int Nc, int mt, int mx) {
+    using T = std::conditional_t<Q == 0, double, float>;
+    hipLaunchKernelGGL((k_m2l_cls<T, kClsNB, kClsMaxs, kClsWaves, Q == 2>), grid, dim3(64 * kClsWaves), shm, st, U,
+                       TSp, packinfo, plan, plan_stride, Nc, mt, mx);
+}
+
+template <int Q>
+void launch_cls_batch(unsigned n_wg, size_t shm, hipStream_t st, const ClsUnit* units, int n_units, int G, int TSp,
+                      const int* packinfo, const int* plan, int plan_stride, int Nc, int mt, int mx) {
+    using T = std::conditional_t<Q == 0, double, float>;
+    hipLaunchKernelGGL((k_m2l_cls_batch<T, kClsNB, kClsMaxs, kClsWaves, Q == 2>), dim3(n_wg), dim3(64 * kClsWaves),
+                       shm, st, units, n_units, G, TSp, packinfo, plan, plan_stride, Nc, mt, mx);
+}
+
+using ClsLaunch = void (*)(dim3, size_t, hipStream_t, const ClsUnit&, int, const int*, const int*, int, int, int, int);
+using ClsBatchLaunch = void (*)(unsigned, size_t, hipStream_t, const ClsUnit*, int, int, int, const int*, const int*,
+                                int, int, int, int);
 
 ClsLaunch cls_launcher(int q) { return q == 0 ? launch_cls<0> : (q == 1 ? launch_cls<1> : launch_cls<2>); }
+ClsBatchLaunch cls_batch_launcher(int q) {
+    return q == 0 ? launch_cls_batch<0> : (q == 1 ? launch_cls_batch<1> : launch_cls_batch<2>);
+}

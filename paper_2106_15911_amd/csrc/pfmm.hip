@@ -344,38 +344,44 @@ __global__ void __launch_bounds__(256) k_s2m_blk(const double* __restrict__ wd, 
     extern __shared__ double sm[];
     const int nt1 = m.mt + 1, Nk = m.Nk, Nc = m.Nc;
     const int li = blockIdx.x, xs = leaf_xs[li];
-    const int t0 = tb[xs], nX = te[xs] - t0;
     const int k0 = blockIdx.y * KI, nk = min(KI, n_int - k0);
-    const double* A = Ax + ax_off[li];
-    double* W = sm;                                     // [nt1][nX][KI]
-    double* sAl = W + nt1 * nX * KI;                    // [nX][Nk] when staged
-    if (stageA)
-        for (int i = threadIdx.x; i < nX * Nk; i += blockDim.x) sAl[i] = A[i];
-    const double* sA = stageA ? sAl : A;
-    for (int o = threadIdx.x; o < nt1 * nX * KI; o += blockDim.x) {
-        const int r = o % nX, rest = o / nX;
-        const int kk = rest % KI, a = rest / KI;
-        double acc = 0.0;
-        if (kk < nk) {
-            const int k = k0 + kk;
-            const int j0 = ist[k], ns = lflag[(int64_t)li * n_int + k] ? ilen[k] : 0;
-            const double* T = At + (int64_t)j0 * nt1 + a;
-            const double* wr = wd + (int64_t)j0 * E_x + t0 + r;
-            for (int j = 0; j < ns; ++j) acc += T[j * nt1] * wr[(int64_t)j * E_x];
+    // leaves of more than 64 triangles (single-step intervals) in row chunks
+    // of 64, accumulated by the thread that owns each moment (fixed order)
+    for (int r0 = 0; r0 < te[xs] - tb[xs]; r0 += 64) {
+        const int t0 = tb[xs] + r0, nX = min(64, te[xs] - t0);
+        const double* A = Ax + ax_off[li] + (int64_t)r0 * Nk;
+        double* W = sm;                                     // [nt1][nX][KI]
+        double* sAl = W + nt1 * nX * KI;                    // [nX][Nk] when staged
+        if (r0 > 0) __syncthreads();                        // the previous chunk is done with W and sAl
+        if (stageA)
+            for (int i = threadIdx.x; i < nX * Nk; i += blockDim.x) sAl[i] = A[i];
+        const double* sA = stageA ? sAl : A;
+        for (int o = threadIdx.x; o < nt1 * nX * KI; o += blockDim.x) {
+            const int r = o % nX, rest = o / nX;
+            const int kk = rest % KI, a = rest / KI;
+            double acc = 0.0;
+            if (kk < nk) {
+                const int k = k0 + kk;
+                const int j0 = ist[k], ns = lflag[(int64_t)li * n_int + k] ? ilen[k] : 0;
+                const double* T = At + (int64_t)j0 * nt1 + a;
+                const double* wr = wd + (int64_t)j0 * E_x + t0 + r;
+                for (int j = 0; j < ns; ++j) acc += T[j * nt1] * wr[(int64_t)j * E_x];
+            }
+            W[((int64_t)a * nX + r) * KI + kk] = acc;
         }
-        W[((int64_t)a * nX + r) * KI + kk] = acc;
-    }
-    __syncthreads();
-    // moments of the leaf boxes only (the slot's other intervals belong to
-    // boxes with children, filled by M2M, or to absent boxes, kept zero)
-    for (int o = threadIdx.x; o < Nc * KI; o += blockDim.x) {
-        const int kk = o % KI, c = o / KI;
-        if (kk >= nk || !lflag[(int64_t)li * n_int + k0 + kk]) continue;
-        const int a = m.coef_a[c], pp = m.coef_kpos[c];
-        const double* wv = W + (int64_t)a * nX * KI + kk;
-        double acc = 0.0;
-        for (int r = 0; r < nX; ++r) acc += wv[r * KI] * sA[r * Nk + pp];
-        mu[((int64_t)xs * Nc + c) * n_int + k0 + kk] = acc;
+        __syncthreads();
+        // moments of the leaf boxes only (the slot's other intervals belong to
+        // boxes with children, filled by M2M, or to absent boxes, kept zero)
+        for (int o = threadIdx.x; o < Nc * KI; o += blockDim.x) {
+            const int kk = o % KI, c = o / KI;
+            if (kk >= nk || !lflag[(int64_t)li * n_int + k0 + kk]) continue;
+            const int a = m.coef_a[c], pp = m.coef_kpos[c];
+            const double* wv = W + (int64_t)a * nX * KI + kk;
+            double acc = 0.0;
+            for (int r = 0; r < nX; ++r) acc += wv[r * KI] * sA[r * Nk + pp];
+            double* dst = mu + ((int64_t)xs * Nc + c) * n_int + k0 + kk;
+            if (r0 == 0) *dst = acc; else *dst += acc;
+        }
     }
 }
 
@@ -390,13 +396,15 @@ __global__ void __launch_bounds__(256) k_l2t_blk(const double* __restrict__ lam,
                                                  const double* __restrict__ At, const double* __restrict__ Ax,
                                                  SepMaps m, int n_int, const int* __restrict__ ist,
                                                  const int* __restrict__ ilen, const uint8_t* __restrict__ lflag,
-                                                 int maxlen, int E_x, int KI, int stageA) {
+                                                 const int2* __restrict__ chunks, int maxlen, int E_x, int KI,
+                                                 int stageA) {
     extern __shared__ double sm[];
     const int nt1 = m.mt + 1, Nk = m.Nk, Nc = m.Nc;
-    const int li = blockIdx.x, xs = leaf_xs[li];
-    const int t0 = tb[xs], nX = te[xs] - t0;
+    const int2 ch = chunks[blockIdx.x];       // (leaf slot, first row) of a chunk of <= 64 rows
+    const int li = ch.x, xs = leaf_xs[li];
+    const int t0 = tb[xs] + ch.y, nX = min(64, te[xs] - t0);
     const int k0 = blockIdx.y * KI, nk = min(KI, n_int - k0);
-    const double* A = Ax + ax_off[li];
+    const double* A = Ax + ax_off[li] + (int64_t)ch.y * Nk;
     double* L = sm;                                     // [nt1][Nk][KI]
     double* U = L + Nc * KI;                            // [nt1][nX][KI]
     double* sAl = U + nt1 * nX * KI;                    // [nX][Nk] when staged
@@ -729,6 +737,8 @@ struct DevLevel {
     int* ilen = nullptr;          // steps of interval k (0: absent)
     int maxlen = 0;               // most steps of an interval
     uint8_t* lflag = nullptr;     // [leaf slot][k]: (leaf_xs[li], k) is a leaf box
+    int2* lchunk = nullptr;       // S2M / L2T blocks: (leaf slot, first row) of <= 64 rows
+    int n_lchunk = 0;
     uint8_t* inner = nullptr;     // [slot][k]: (xs, k) has children
     bool uniform = true;          // batched-in-time M2L kernels apply (Level::uniform)
     int2* ccols[2] = {nullptr, nullptr};   // class-aware M2L: columns (k, class) per time offset 2, 3
@@ -749,6 +759,8 @@ struct DevLevel {
     int* m2l_cls = nullptr;
     double* ops = nullptr;
     double* lam_parts = nullptr;  // extra shares of a split interaction list
+    int parts_cap = 1;            // shares lam_parts holds room for (1 + extra buffers)
+    int64_t slot_pairs = 0;       // (target slot, source slot) pairs of the interaction lists
     int nsplit = 1;
     int nsplit_q[2] = {1, 1};     // per precision (0 FP64, 1 FP32): interaction-list shares
     int m2l_nb[2] = {0, 0};       // per precision: wide M2L interval blocks per workgroup; 0: k_m2l_mfma / k_m2l
@@ -818,6 +830,9 @@ struct pfmm_tree {
     int* umap = nullptr;
     NearOp opV, opK;
     bool hasV = false, hasK = false;
+    NearGeom geom{};              // mesh on the device (natural order)
+    double* tnodes_dev = nullptr; // time nodes on the device
+    bool geom_ok = false;
     int nf_mode = PFMM_NF_STORED;
     int64_t* ru_off = nullptr;    // Toeplitz nearfield: per leaf rectangle, offset into ru
     int* ru = nullptr;            // table columns u of the rectangles' source triangles
@@ -904,6 +919,27 @@ uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask, int pre
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+// Mesh geometry and time nodes on the device (uploaded once per tree).
+pfmm_status upload_geometry(pfmm_tree* t) {
+    if (t->geom_ok) return PFMM_OK;
+    const Plan& P = t->P;
+    NearGeom& G = t->geom;
+    double *verts, *area, *normal, *centroid, *maxedge;
+    int* tris;
+    PF_TRY(upload(t, &verts, P.verts.data(), P.verts.size()));
+    PF_TRY(upload(t, &tris, P.tris.data(), P.tris.size()));
+    PF_TRY(upload(t, &area, P.area.data(), P.area.size()));
+    PF_TRY(upload(t, &normal, P.normal.data(), P.normal.size()));
+    PF_TRY(upload(t, &centroid, P.centroid.data(), P.centroid.size()));
+    PF_TRY(upload(t, &maxedge, P.maxedge.data(), P.maxedge.size()));
+    PF_TRY(upload(t, &t->tnodes_dev, P.tnodes.data(), P.tnodes.size()));
+    G.verts = verts; G.tris = tris; G.area = area; G.normal = normal; G.centroid = centroid; G.maxedge = maxedge;
+    G.inv_sigma = t->inv_sigma;
+    G.h = P.h; G.alpha = P.alpha;
+    t->geom_ok = true;
+    return PFMM_OK;
+}
+
 pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
     Plan& P = t->P;
     const bool stored = t->nf_mode == PFMM_NF_STORED;
@@ -922,18 +958,8 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
     Q.q_sing = P.q_sing;
     // geometry
     static_assert(sizeof(TouchDev) == sizeof(TouchPair), "layout");
-    NearGeom G{};
-    double *verts, *area, *normal, *centroid, *maxedge;
-    int* tris;
-    PF_TRY(upload(t, &verts, P.verts.data(), P.verts.size()));
-    PF_TRY(upload(t, &tris, P.tris.data(), P.tris.size()));
-    PF_TRY(upload(t, &area, P.area.data(), P.area.size()));
-    PF_TRY(upload(t, &normal, P.normal.data(), P.normal.size()));
-    PF_TRY(upload(t, &centroid, P.centroid.data(), P.centroid.size()));
-    PF_TRY(upload(t, &maxedge, P.maxedge.data(), P.maxedge.size()));
-    G.verts = verts; G.tris = tris; G.area = area; G.normal = normal; G.centroid = centroid; G.maxedge = maxedge;
-    G.inv_sigma = t->inv_sigma;
-    G.h = P.h; G.alpha = P.alpha;
+    PF_TRY(upload_geometry(t));
+    const NearGeom G = t->geom;
     int* upos;
     PF_TRY(upload(t, &upos, P.upos.data(), P.upos.size()));
     // regular blocks
@@ -1482,8 +1508,10 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             if (!plan_wide(ks, kClsMaxs, kClsWaves, tab, W.G, W.stride, maxp)) continue;
             W.shm = std::max((size_t)6 * tsp * es + (size_t)(Nc4 + 16) * 4 * sizeof(int), (size_t)maxp * 4 * 64 * es);
             if (W.shm > (size_t)lds_max) continue;
-            if (W.shm > 65536)
+            if (W.shm > 65536) {
                 HIP_TRY(hipFuncSetAttribute(cls_fn(q), hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.shm));
+                HIP_TRY(hipFuncSetAttribute(cls_batch_fn(q), hipFuncAttributeMaxDynamicSharedMemorySize, (int)W.shm));
+            }
             PF_TRY(upload(t, &W.plan, tab.data(), tab.size()));
             W.ok = true;
         }
@@ -1557,6 +1585,12 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         PF_TRY(upload(t, &D.ist, FL.istart.data(), FL.istart.size()));
         PF_TRY(upload(t, &D.ilen, FL.ilen.data(), FL.ilen.size()));
         PF_TRY(upload(t, &D.lflag, FL.leaf.data(), FL.leaf.size()));
+        {
+            std::vector<int2> ch(FL.chunk_li.size());
+            for (size_t i = 0; i < ch.size(); ++i) ch[i] = int2{FL.chunk_li[i], FL.chunk_r0[i]};
+            D.n_lchunk = (int)ch.size();
+            PF_TRY(upload(t, &D.lchunk, ch.data(), ch.size()));
+        }
         PF_TRY(upload(t, &D.inner, FL.inner.data(), FL.inner.size()));
         if (!L.uniform) {
             if (!t->mfma_slots || !t->wcls[0].ok || (t->has_f32 && (!t->wcls[1].ok || !t->wcls[2].ok)))
@@ -1643,6 +1677,8 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             }
             D.nsplit = D.nsplit_q[0];
             if (nsplit_max > 1) PF_TRY(dalloc(t, &D.lam_parts, (size_t)(nsplit_max - 1) * D.nx * P.Nc * D.n_int));
+            D.parts_cap = nsplit_max;
+            D.slot_pairs = (int64_t)FL.m2l_src.size();
             if (t->has_f32 && (D.m2l_nb[1] || !D.uniform)) {
                 PF_TRY(dalloc(t, &D.mu32, (size_t)D.nx * P.Nc * D.n_int + 2));
                 HIP_TRY(hipMemset(D.mu32, 0, ((size_t)D.nx * P.Nc * D.n_int + 2) * sizeof(float)));
@@ -1684,7 +1720,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         for (size_t i = 0; i < nL; ++i) {
             const LeafRec& R = P.leaves[i];
             ltb[i] = R.tb; lnx[i] = R.te - R.tb; lr0[i] = R.rect0; lr1[i] = R.rect1; lg[i] = R.group;
-            if (lnx[i] > kWave) return fail(PFMM_EUNSUPPORTED, "a leaf holds more than 64 triangles (lower n_max)");
+            if (lnx[i] > kWave) return fail(PFMM_EINVAL, "internal: a nearfield row chunk holds more than 64 triangles");
         }
         std::vector<int> j0(P.rects.size()), j1(P.rects.size()), rs(P.rects.size());
         for (size_t i = 0; i < P.rects.size(); ++i) {
@@ -1765,14 +1801,126 @@ void prof_end(pfmm_tree* t, hipStream_t st, int idx) {
     if (idx >= 0) (void)hipEventRecord(t->ev[idx + 1], st);
 }
 
-pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t st) {
+// Precision index of the class-aware M2L (0 FP64, 1 FP32, 2 BF16 inputs)
+// for the tree's current farfield precision; cls_prep also converts the
+// level's moments for the reduced precisions and zeroes its locals (the
+// class-aware kernel adds into them), stream-ordered on st.
+int cls_q(const pfmm_tree* t) { return t->prec == PFMM_FP64 ? 0 : (t->prec == PFMM_MIXED_BF16 ? 2 : 1); }
+
+int cls_prep(pfmm_tree* t, int l, hipStream_t st) {
+    DevLevel& D = t->lv[l];
+    const int64_t nl = (int64_t)D.nx * t->P.Nc * D.n_int;
+    const int q = cls_q(t);
+    if (q >= 1)
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl,
+                           q == 2 ? 1 : 0);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam, 0.0, nl);
+    return q;
+}
+
+ClsUnit cls_unit(const pfmm_tree* t, int l, int Dt, int q) {
+    const DevLevel& D = t->lv[l];
+    const int64_t row0 = D.e1s_off / std::max(1, t->TSp);   // first table row of the level
+    ClsUnit U{};
+    U.mu = q ? (const void*)D.mu32 : (const void*)D.mu;
+    U.lam = D.lam;
+    U.ptr = D.m2l_ptr;
+    U.src = D.m2l_src;
+    U.ocls = D.m2l_cls;
+    U.off3 = D.off3;
+    U.E1c = q == 0 ? (const void*)(t->E1c + row0 * t->TSc64)
+                   : (const void*)((q == 2 ? t->E1c16 : t->E1c32) + row0 * t->TSc32);
+    U.cols = D.ccols[Dt - 2];
+    U.cbr = D.cbr[Dt - 2];
+    U.n_int = D.n_int;
+    U.R = D.R;
+    U.nx = D.nx;
+    U.nccb = D.nccb[Dt - 2];
+    U.D = Dt;
+    U.wg0 = 0;
+    return U;
+}
+
+// M2L (eq. m2l) of level l in the tree's current farfield precision, with
+// the level's kernel choice: the class-aware kernel for levels with unequal
+// or missing intervals, else the wide matrix-core kernel (interval blocks and
+// list shares per precision), the narrow one for levels with fewer than 32
+// intervals, or the vector-unit kernel above the matrix-core limits.
+void m2l_level(pfmm_tree* t, int l, hipStream_t st) {
+    const Plan& P = t->P;
+    DevLevel& D = t->lv[l];
+    const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
+    const int64_t row0 = D.e1s_off / std::max(1, t->TSp);   // first table row of the level
+    if (!D.uniform) {
+        // class-aware M2L: zero the locals, then one launch per time offset
+        const int q = cls_prep(t, l, st);
+        const auto& W = t->wcls[q];
+        for (int Dt = 2; Dt <= 3; ++Dt) {
+            if (D.nccb[Dt - 2] == 0) continue;
+            dim3 grid(W.G, D.nx, D.nccb[Dt - 2]);
+            cls_launcher(q)(grid, W.shm, st, cls_unit(t, l, Dt, q), q ? t->TSc32 : t->TSc64, t->packinfo, W.plan,
+                            W.stride, P.Nc, P.m_t, P.m_x);
+        }
+        return;
+    }
+    // q: 0 FP64, 1 FP32, 2 BF16 inputs; the per-level choices of the two
+    // reduced precisions coincide (same kernel shapes), stored at index 1
+    const int q = (t->prec != PFMM_FP64 && D.m2l_nb[1]) ? (t->prec == PFMM_MIXED_BF16 ? 2 : 1) : 0;
+    const int ql = q > 0 ? 1 : 0;
+    if (D.m2l_nb[ql]) {
+        const int v = D.m2l_nb[ql] == 4 ? 2 : (D.m2l_nb[ql] == 2 ? 1 : 0);
+        const auto& W = t->wide[q][v];
+        const int nsplit = D.nsplit_q[ql];
+        dim3 grid(W.G, D.nx, D.ncb[ql] * nsplit);
+        const void* m = D.mu;
+        const void* e1 = t->E1c + row0 * t->TSc64;
+        int tsp = t->TSc64;
+        if (q >= 1) {
+            hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl,
+                               q == 2 ? 1 : 0);
+            m = D.mu32;
+            e1 = (q == 2 ? t->E1c16 : t->E1c32) + row0 * t->TSc32;
+            tsp = t->TSc32;
+        }
+        wide_launcher(q, v)(grid, W.shm, st, m, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3, e1, tsp, t->packinfo,
+                            W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, nsplit, D.ncb[ql], D.lam_parts);
+        if (nsplit > 1)
+            hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam, D.lam_parts,
+                               nsplit - 1, nl);
+    } else if (t->mfma_slots) {
+        const size_t shm = t->m2l_shm;
+        const int halves = D.n_int > 32 ? 2 : 1;
+        dim3 grid(D.nx, (D.n_int + 63) / 64, halves * D.nsplit);
+        dim3 block(64 * kM2LWaves);
+        // share 0 writes lambda, share p >= 1 writes lam_parts + (p - 1) * (slots * Nc * n_int)
+        hipLaunchKernelGGL(k_m2l_mfma<kM2LSlots>, grid, block, shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls,
+                           D.off3, t->E1s + D.e1s_off, t->TSp, t->packinfo, t->tile_ks, t->slot_tile, t->n_partial,
+                           P.Nc, D.n_int, P.m_t, P.m_x, D.R, D.nsplit, halves, D.lam_parts);
+        if (D.nsplit > 1)
+            hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam, D.lam_parts,
+                               D.nsplit - 1, nl);
+    } else {
+        dim3 grid(D.nx, (D.n_int + kWave - 1) / kWave, t->F.n_chunks);
+        hipLaunchKernelGGL(k_m2l, grid, dim3(kWave), 0, st, D.mu, D.lam, D.ops, D.m2l_ptr, D.m2l_src, D.m2l_cls,
+                           t->chunk_cols, t->chunk_off, P.Nc, D.n_int, t->F.op_size);
+    }
+}
+
+// phase 0: the whole apply; phase 1: permutation, nearfield, upward pass and
+// the M2L of the levels with equal intervals (the others only prepared:
+// moments converted, locals zeroed); phase 2: L2L, L2T and the final
+// permutation.  Between phases 1 and 2 a batch runs the class-aware M2L of
+// all its trees in one launch per time offset.
+pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t st, int phase = 0) {
     Plan& P = t->P;
     const int64_t N = (int64_t)P.E_t * P.E_x;
     const unsigned nb = (unsigned)((N + 255) / 256);
     int ev;
-    prof_begin(t, 0, st, ev);
-    hipLaunchKernelGGL(k_permute_in, dim3(nb), dim3(256), 0, st, w, t->wd, t->inv_sigma, P.E_x, N);
-    prof_end(t, st, ev);
+    if (phase != 2) {
+        prof_begin(t, 0, st, ev);
+        hipLaunchKernelGGL(k_permute_in, dim3(nb), dim3(256), 0, st, w, t->wd, t->inv_sigma, P.E_x, N);
+        prof_end(t, st, ev);
+    }
     // The nearfield product needs only the permuted densities: in Toeplitz
     // mode it runs on the side stream into fn while the farfield chain fills
     // fd, and the two meet in the final permutation.  The stored-block product
@@ -1783,7 +1931,7 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
     // order on st: same kernels, same results.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(st, &cap));
-    const bool fork = !t->prof && cap == hipStreamCaptureStatusNone && t->nf_mode == PFMM_NF_TOEPLITZ;
+    const bool fork = phase == 0 && !t->prof && cap == hipStreamCaptureStatusNone && t->nf_mode == PFMM_NF_TOEPLITZ;
     auto nearfield = [&](hipStream_t sn) {
         const int64_t nrg = (int64_t)P.rows.size();
         hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, sn, t->fn, 0.0, N);
@@ -1818,9 +1966,14 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         nearfield(t->side);
         HIP_TRY(hipEventRecord(t->ev_join, t->side));
     }
-    if (t->low_leaves || !P.has_far)
+    if (phase == 1) {
+        prof_begin(t, 6, st, ev);
+        nearfield(st);
+        prof_end(t, st, ev);
+    }
+    if (phase != 2 && (t->low_leaves || !P.has_far))
         hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, st, t->fd, 0.0, N);
-    if (P.has_far) {
+    if (P.has_far && phase != 2) {
         // S2M
         prof_begin(t, 1, st, ev);
         for (int l = 2; l <= P.depth; ++l) {
@@ -1849,81 +2002,12 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
         // M2L, levels 2 .. p
         prof_begin(t, 3, st, ev);
         for (int l = 2; l <= P.depth; ++l) {
-            DevLevel& D = t->lv[l];
-            // q: 0 FP64, 1 FP32, 2 BF16 inputs; the per-level choices of the two
-            // reduced precisions coincide (same kernel shapes), stored at index 1
-            if (!D.uniform) {
-                // class-aware M2L: zero the locals, then one launch per time offset
-                const int q = t->prec == PFMM_FP64 ? 0 : (t->prec == PFMM_MIXED_BF16 ? 2 : 1);
-                const auto& W = t->wcls[q];
-                const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
-                const int64_t row0 = D.e1s_off / t->TSp;
-                const void* m = D.mu;
-                const void* e1 = t->E1c + row0 * t->TSc64;
-                int tsp = t->TSc64;
-                if (q >= 1) {
-                    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl,
-                                       q == 2 ? 1 : 0);
-                    m = D.mu32;
-                    e1 = (q == 2 ? t->E1c16 : t->E1c32) + row0 * t->TSc32;
-                    tsp = t->TSc32;
-                }
-                hipLaunchKernelGGL(k_fill, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam, 0.0, nl);
-                for (int Dt = 2; Dt <= 3; ++Dt) {
-                    if (D.nccb[Dt - 2] == 0) continue;
-                    dim3 grid(W.G, D.nx, D.nccb[Dt - 2]);
-                    cls_launcher(q)(grid, W.shm, st, m, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3, e1, tsp,
-                                    t->packinfo, W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, D.ccols[Dt - 2],
-                                    D.cbr[Dt - 2], Dt, D.nccb[Dt - 2]);
-                }
-                continue;
-            }
-            const int q = (t->prec != PFMM_FP64 && D.m2l_nb[1]) ? (t->prec == PFMM_MIXED_BF16 ? 2 : 1) : 0;
-            const int ql = q > 0 ? 1 : 0;
-            if (D.m2l_nb[ql]) {
-                const int v = D.m2l_nb[ql] == 4 ? 2 : (D.m2l_nb[ql] == 2 ? 1 : 0);
-                const auto& W = t->wide[q][v];
-                const int nsplit = D.nsplit_q[ql];
-                dim3 grid(W.G, D.nx, D.ncb[ql] * nsplit);
-                const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
-                const int64_t row0 = D.e1s_off / t->TSp;   // first table row of the level
-                const void* m = D.mu;
-                const void* e1 = t->E1c + row0 * t->TSc64;
-                int tsp = t->TSc64;
-                if (q >= 1) {
-                    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl,
-                                       q == 2 ? 1 : 0);
-                    m = D.mu32;
-                    e1 = (q == 2 ? t->E1c16 : t->E1c32) + row0 * t->TSc32;
-                    tsp = t->TSc32;
-                }
-                wide_launcher(q, v)(grid, W.shm, st, m, D.lam, D.m2l_ptr, D.m2l_src, D.m2l_cls, D.off3, e1, tsp,
-                                    t->packinfo, W.plan, W.stride, P.Nc, D.n_int, P.m_t, P.m_x, D.R, nsplit, D.ncb[ql],
-                                    D.lam_parts);
-                if (nsplit > 1)
-                    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam,
-                                       D.lam_parts, nsplit - 1, nl);
-            } else if (t->mfma_slots) {
-                const size_t shm = t->m2l_shm;
-                const int halves = D.n_int > 32 ? 2 : 1;
-                dim3 grid(D.nx, (D.n_int + 63) / 64, halves * D.nsplit);
-                dim3 block(64 * kM2LWaves);
-                // share 0 writes lambda, share p >= 1 writes lam_parts + (p - 1) * (slots * Nc * n_int)
-                const int64_t nl = (int64_t)D.nx * P.Nc * D.n_int;
-                hipLaunchKernelGGL(k_m2l_mfma<kM2LSlots>, grid, block, shm, st, D.mu, D.lam, D.m2l_ptr, D.m2l_src,
-                                   D.m2l_cls, D.off3, t->E1s + D.e1s_off, t->TSp, t->packinfo, t->tile_ks,
-                                   t->slot_tile, t->n_partial, P.Nc, D.n_int, P.m_t, P.m_x, D.R, D.nsplit, halves,
-                                   D.lam_parts);
-                if (D.nsplit > 1)
-                    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam,
-                                       D.lam_parts, D.nsplit - 1, nl);
-            } else {
-                dim3 grid(D.nx, (D.n_int + kWave - 1) / kWave, t->F.n_chunks);
-                hipLaunchKernelGGL(k_m2l, grid, dim3(kWave), 0, st, D.mu, D.lam, D.ops, D.m2l_ptr, D.m2l_src,
-                                   D.m2l_cls, t->chunk_cols, t->chunk_off, P.Nc, D.n_int, t->F.op_size);
-            }
+            if (phase == 1 && !t->lv[l].uniform) cls_prep(t, l, st);
+            else m2l_level(t, l, st);
         }
         prof_end(t, st, ev);
+    }
+    if (P.has_far && phase != 1) {
         // L2L, levels 3 .. p
         prof_begin(t, 4, st, ev);
         for (int l = 3; l <= P.depth; ++l) {
@@ -1943,16 +2027,20 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
             const int KI = t->ki_l2t, nt1 = P.m_t + 1;
             const size_t shm = ((size_t)P.Nc * KI + (size_t)nt1 * 64 * KI + (t->stage_l2t ? 64 * (size_t)P.Nk : 0)) *
                                sizeof(double);
-            hipLaunchKernelGGL(k_l2t_blk, dim3(D.n_leafx, (D.n_int + KI - 1) / KI), dim3(256), shm, st, D.lam, t->fd,
+            hipLaunchKernelGGL(k_l2t_blk, dim3(D.n_lchunk, (D.n_int + KI - 1) / KI), dim3(256), shm, st, D.lam, t->fd,
                                D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, t->Ax, t->sm, D.n_int, D.ist,
-                               D.ilen, D.lflag, D.maxlen, P.E_x, KI, t->stage_l2t);
+                               D.ilen, D.lflag, D.lchunk, D.maxlen, P.E_x, KI, t->stage_l2t);
         }
         prof_end(t, st, ev);
+    }
+    if (phase == 1) {
+        HIP_TRY(hipGetLastError());
+        return PFMM_OK;
     }
     // nearfield
     if (fork) {
         HIP_TRY(hipStreamWaitEvent(st, t->ev_join, 0));
-    } else {
+    } else if (phase == 0) {
         prof_begin(t, 6, st, ev);
         nearfield(st);
         prof_end(t, st, ev);
@@ -1962,6 +2050,173 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
     prof_end(t, st, ev);
     HIP_TRY(hipGetLastError());
     return PFMM_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Launch configurations of the matrix-core M2L per (level, precision):
+// interval blocks per workgroup of the wide kernel (variant v: 32, 64, 128
+// intervals) and interaction-list shares.  Candidates are timed on the device
+// (one warm-up, then three launches between HIP events); the fastest is kept
+// and cached in a small JSON file keyed by the device and the level's shape.
+struct TuneEntry { std::string kernel; int nb = 0, shares = 1; double ms = 0.0; };
+
+std::map<std::string, TuneEntry> tune_read(const char* path) {
+    std::map<std::string, TuneEntry> m;
+    if (!path) return m;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return m;
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+        // "key": {"kernel": "name", "nb": N, "shares": S, "ms": T}
+        const char* a = std::strchr(line, '"');
+        if (!a) continue;
+        const char* b = std::strchr(a + 1, '"');
+        if (!b) continue;
+        std::string key(a + 1, b);
+        const char* k = std::strstr(b, "\"kernel\": \"");
+        if (!k) continue;
+        k += 11;
+        const char* ke = std::strchr(k, '"');
+        if (!ke) continue;
+        TuneEntry e;
+        e.kernel.assign(k, ke);
+        if (std::sscanf(ke, "\", \"nb\": %d, \"shares\": %d, \"ms\": %lf", &e.nb, &e.shares, &e.ms) != 3) continue;
+        m[key] = e;
+    }
+    std::fclose(f);
+    return m;
+}
+
+bool tune_write(const char* path, const std::map<std::string, TuneEntry>& m) {
+    if (!path) return true;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto& kv : m) {
+        std::fprintf(f, "\"%s\": {\"kernel\": \"%s\", \"nb\": %d, \"shares\": %d, \"ms\": %.6f}%s\n", kv.first.c_str(),
+                     kv.second.kernel.c_str(), kv.second.nb, kv.second.shares, kv.second.ms,
+                     ++i < m.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+// room for `shares` list shares of level D's partial locals
+pfmm_status ensure_parts(pfmm_tree* t, DevLevel& D, int shares) {
+    if (shares <= D.parts_cap) return PFMM_OK;
+    if (D.lam_parts) {
+        auto it = std::find(t->allocs.begin(), t->allocs.end(), (void*)D.lam_parts);
+        if (it != t->allocs.end()) t->allocs.erase(it);
+        t->bytes -= (uint64_t)(D.parts_cap - 1) * D.nx * t->P.Nc * D.n_int * sizeof(double);
+        HIP_TRY(hipFree(D.lam_parts));
+        D.lam_parts = nullptr;
+        D.parts_cap = 1;
+    }
+    PF_TRY(dalloc(t, &D.lam_parts, (size_t)(shares - 1) * D.nx * t->P.Nc * D.n_int));
+    D.parts_cap = shares;
+    return PFMM_OK;
+}
+
+pfmm_status autotune(pfmm_tree* t, const char* path, hipStream_t st, int* n_tuned, int* n_cached) {
+    const Plan& P = t->P;
+    *n_tuned = *n_cached = 0;
+    if (!P.has_far || !t->mfma_slots) return PFMM_OK;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, t->device));
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    std::map<std::string, TuneEntry> cache = tune_read(path);
+    const int saved = t->prec;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    pfmm_status status = PFMM_OK;
+    bool dirty = false;
+    for (int l = 2; l <= P.depth && status == PFMM_OK; ++l) {
+        DevLevel& D = t->lv[l];
+        if (!D.uniform) continue;
+        for (int ql = 0; ql < (t->has_f32 ? 2 : 1) && status == PFMM_OK; ++ql) {
+            // candidates of this (level, precision)
+            std::vector<std::pair<int, int>> cand;   // (variant or -1 for the narrow kernel, shares)
+            const bool wide = ql == 0 ? D.m2l_nb[0] != 0 : D.m2l_nb[1] != 0;
+            if (ql == 1 && !wide) continue;          // reduced precisions use the wide kernel only
+            if (wide) {
+                for (int v = 0; v < 3; ++v) {
+                    if (!t->wide[ql][v].ok || (ql == 1 && !t->wide[2][v].ok)) continue;
+                    if (D.n_int % (32 * kWideNB[v])) continue;
+                    for (int ns : {1, 2, 3, 4, 6, 8}) cand.emplace_back(v, ns);
+                }
+            } else {
+                for (int ns : {1, 2, 3, 4}) cand.emplace_back(-1, ns);
+            }
+            if (cand.empty()) continue;
+            char key[256];
+            std::snprintf(key, sizeof(key), "%s:%dcu|Nc=%d|mt=%d|mx=%d|nint=%d|nx=%d|pairs=%lld|%s", arch.c_str(),
+                          prop.multiProcessorCount, P.Nc, P.m_t, P.m_x, D.n_int, D.nx, (long long)D.slot_pairs,
+                          ql ? "fp32" : "fp64");
+            auto apply_choice = [&](int v, int ns) -> pfmm_status {
+                PF_TRY(ensure_parts(t, D, ns));
+                if (v >= 0) {
+                    D.m2l_nb[ql] = kWideNB[v];
+                    D.ncb[ql] = D.n_int / (32 * kWideNB[v]);
+                    D.nsplit_q[ql] = ns;
+                    if (ql == 0) D.nsplit = ns;
+                } else {
+                    D.nsplit_q[0] = D.nsplit = ns;
+                }
+                return PFMM_OK;
+            };
+            auto it = cache.find(key);
+            if (it != cache.end()) {
+                int v = -1;
+                for (int q = 0; q < 3; ++q) if (kWideNB[q] == it->second.nb) v = q;
+                const bool valid = (it->second.kernel == "k_m2l_wide") == wide &&
+                                   std::find(cand.begin(), cand.end(), std::make_pair(wide ? v : -1, it->second.shares)) !=
+                                       cand.end();
+                if (valid) {
+                    status = apply_choice(wide ? v : -1, it->second.shares);
+                    ++*n_cached;
+                    continue;
+                }
+            }
+            t->prec = ql ? PFMM_MIXED_FP32 : PFMM_FP64;
+            double best = 1e30;
+            std::pair<int, int> pick = cand[0];
+            for (const auto& c : cand) {
+                status = apply_choice(c.first, c.second);
+                if (status != PFMM_OK) break;
+                m2l_level(t, l, st);
+                hipError_t e = hipEventRecord(e0, st);
+                for (int r = 0; r < 3 && e == hipSuccess; ++r) m2l_level(t, l, st);
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess) e = hipGetLastError();
+                if (e != hipSuccess) { status = fail(PFMM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+                if (ms / 3.0 < best) { best = ms / 3.0; pick = c; }
+            }
+            if (status != PFMM_OK) break;
+            status = apply_choice(pick.first, pick.second);
+            TuneEntry te;
+            te.kernel = wide ? "k_m2l_wide" : "k_m2l_mfma";
+            te.nb = pick.first >= 0 ? kWideNB[pick.first] : 0;
+            te.shares = pick.second;
+            te.ms = best;
+            cache[key] = te;
+            dirty = true;
+            ++*n_tuned;
+        }
+    }
+    t->prec = saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status == PFMM_OK && dirty && !tune_write(path, cache))
+        return fail(PFMM_EINVAL, std::string("cannot write the autotune cache ") + path);
+    return status;
 }
 
 void fill_stats(const Plan& P, uint64_t bytes, pfmm_stats* out, int m2l_mfma) {
@@ -2009,6 +2264,103 @@ pfmm_status tree_near_diag(pfmm_tree* t, double* d_dev, hipStream_t st) {
 bool tree_has(const pfmm_tree* t, int op) { return op == PFMM_OP_V ? t->hasV : (op == PFMM_OP_K ? t->hasK : false); }
 const double* tree_mass(const pfmm_tree* t) { return t->mass; }
 pfmm_status tree_apply(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st) { return apply(t, K, x, y, st); }
+pfmm_status tree_apply_phase(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st, int phase) {
+    return apply(t, K, x, y, st, phase);
+}
+
+// ---------------------------------------------------------------- cross-problem M2L
+struct BatchM2L {
+    int device = 0;
+    std::vector<pfmm_tree*> trees;
+    ClsUnit* dev = nullptr;       // units grouped by (precision, time offset)
+    int cap = 0;
+    struct Seg { int q, D, off, n, wg; const pfmm_tree* ref; };
+    std::vector<Seg> segs;
+};
+
+pfmm_status batch_m2l_create(pfmm_tree* const* trees, int n, BatchM2L** out) {
+    *out = nullptr;
+    int units = 0;
+    for (int i = 0; i < n; ++i) {
+        const pfmm_tree* t = trees[i];
+        // one launch needs one row-group plan: the same degrees on the matrix-core path
+        if (!t->mfma_slots || t->P.m_t != trees[0]->P.m_t || t->P.m_x != trees[0]->P.m_x) return PFMM_OK;
+        for (int l = 2; l <= t->P.depth && t->P.has_far; ++l)
+            if (!t->lv[l].uniform) units += 2;
+    }
+    if (units == 0) return PFMM_OK;   // nothing to batch: every level has equal intervals
+    BatchM2L* b = new (std::nothrow) BatchM2L();
+    if (!b) return fail(PFMM_ENOMEM, "host allocation failed");
+    b->device = trees[0]->device;
+    b->trees.assign(trees, trees + n);
+    b->cap = units;
+    if (hipMalloc(&b->dev, (size_t)units * sizeof(ClsUnit)) != hipSuccess) {
+        delete b;
+        return fail(PFMM_ENOMEM, "hipMalloc failed for the batched M2L units");
+    }
+    *out = b;
+    return PFMM_OK;
+}
+
+pfmm_status batch_m2l_prepare(BatchM2L* b) {
+    std::vector<ClsUnit> host;
+    b->segs.clear();
+    for (int q = 0; q < 3; ++q)
+        for (int D = 2; D <= 3; ++D) {
+            BatchM2L::Seg sg{q, D, (int)host.size(), 0, 0, nullptr};
+            for (pfmm_tree* t : b->trees) {
+                if (cls_q(t) != q || !t->P.has_far) continue;
+                for (int l = 2; l <= t->P.depth; ++l) {
+                    const DevLevel& Dl = t->lv[l];
+                    if (Dl.uniform || Dl.nccb[D - 2] == 0) continue;
+                    if (!t->wcls[q].ok) return fail(PFMM_EDEVICE, "internal: class-aware M2L plan missing");
+                    if (!sg.ref) sg.ref = t;
+                    ClsUnit U = cls_unit(t, l, D, q);
+                    U.wg0 = sg.wg;
+                    sg.wg += t->wcls[q].G * U.nx * U.nccb;
+                    host.push_back(U);
+                    ++sg.n;
+                }
+            }
+            if (sg.n) b->segs.push_back(sg);
+        }
+    if ((int)host.size() > b->cap) return fail(PFMM_EINVAL, "internal: batched M2L units exceed their buffer");
+    if (!host.empty())
+        HIP_TRY(hipMemcpy(b->dev, host.data(), host.size() * sizeof(ClsUnit), hipMemcpyHostToDevice));
+    return PFMM_OK;
+}
+
+pfmm_status batch_m2l_launch(BatchM2L* b, hipStream_t st) {
+    for (const auto& sg : b->segs) {
+        const pfmm_tree* r = sg.ref;
+        const auto& W = r->wcls[sg.q];
+        cls_batch_launcher(sg.q)((unsigned)sg.wg, W.shm, st, b->dev + sg.off, sg.n, W.G, sg.q ? r->TSc32 : r->TSc64,
+                                 r->packinfo, W.plan, W.stride, r->P.Nc, r->P.m_t, r->P.m_x);
+    }
+    HIP_TRY(hipGetLastError());
+    return PFMM_OK;
+}
+
+void batch_m2l_destroy(BatchM2L* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->dev) (void)hipFree(b->dev);
+    delete b;
+}
+pfmm_status tree_geometry(pfmm_tree* t, TreeGeom* out) {
+    PF_TRY(upload_geometry(t));
+    out->verts = t->geom.verts;
+    out->tris = t->geom.tris;
+    out->area = t->geom.area;
+    out->normal = t->geom.normal;
+    out->tnodes = t->tnodes_dev;
+    out->n_tri = t->P.E_x;
+    out->n_steps = t->P.E_t;
+    out->alpha = t->P.alpha;
+    out->t_first = t->P.tnodes.front();
+    out->t_last = t->P.tnodes.back();
+    return PFMM_OK;
+}
 
 }  // namespace pfmm
 
@@ -2126,6 +2478,17 @@ pfmm_status pfmm_set_precision(pfmm_tree* t, int32_t precision) {
         return PFMM_OK;
     }
     return fail(PFMM_EINVAL, "unknown precision");
+}
+
+pfmm_status pfmm_autotune(pfmm_tree* t, const char* cache_path, void* stream, int32_t* n_tuned, int32_t* n_cached) {
+    if (!t) return fail(PFMM_EINVAL, "NULL tree");
+    if (t->prof) return fail(PFMM_EINVAL, "stage profiling is on");
+    if (hipSetDevice(t->device) != hipSuccess) return fail(PFMM_EDEVICE, "hipSetDevice failed");
+    int a = 0, b = 0;
+    const pfmm_status s = autotune(t, cache_path, as_stream(stream), &a, &b);
+    if (n_tuned) *n_tuned = a;
+    if (n_cached) *n_cached = b;
+    return s;
 }
 
 pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out) {

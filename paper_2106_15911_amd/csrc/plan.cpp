@@ -457,7 +457,7 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         set_ids.emplace(std::move(key), id);
         return id;
     };
-    std::map<std::pair<int, int>, int> group_of;   // (l, xs) -> group
+    std::map<std::array<int, 3>, int> group_of;   // (l, xs, row chunk) -> group
     for (int l = 0; l <= P.depth; ++l) {
         const Level& L = P.lev[l];
         for (int xs = 0; xs < L.nx(); ++xs)
@@ -513,17 +513,28 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
                     }
                 }
                 R.rect1 = (int)P.rects.size();
-                auto g = group_of.find({l, xs});
-                if (g == group_of.end()) {
-                    AsmGroup G;
-                    G.l = l; G.xs = xs; G.tb = R.tb; G.te = R.te; G.dmax = 0;
-                    G.uoff = 0; G.usize = 0; G.toff = 0; G.mapoff = 0;
-                    int id = (int)P.groups.size();
-                    P.groups.push_back(G);
-                    g = group_of.emplace(std::make_pair(l, xs), id).first;
+                // The nearfield kernels give each row of a leaf one lane of a
+                // wave: a leaf with more than 64 triangles (one whose interval
+                // has a single step, where Algorithm 1 stops refining) becomes
+                // several row chunks of at most 64 triangles, each with its own
+                // assembly group (same sources, its own rows of the table).
+                const int nch = (R.te - R.tb + 63) / 64;
+                for (int ch = 0; ch < nch; ++ch) {
+                    LeafRec Rc = R;
+                    Rc.tb = R.tb + (int)((int64_t)(R.te - R.tb) * ch / nch);
+                    Rc.te = R.tb + (int)((int64_t)(R.te - R.tb) * (ch + 1) / nch);
+                    auto g = group_of.find({l, xs, ch});
+                    if (g == group_of.end()) {
+                        AsmGroup G;
+                        G.l = l; G.xs = xs; G.tb = Rc.tb; G.te = Rc.te; G.dmax = 0;
+                        G.uoff = 0; G.usize = 0; G.toff = 0; G.mapoff = 0;
+                        int id = (int)P.groups.size();
+                        P.groups.push_back(G);
+                        g = group_of.emplace(std::array<int, 3>{l, xs, ch}, id).first;
+                    }
+                    Rc.group = g->second;
+                    P.leaves.push_back(Rc);
                 }
-                R.group = g->second;
-                P.leaves.push_back(R);
             }
     }
 
@@ -580,12 +591,6 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         }
         P.near_nonzero_K = nz;
     }
-    for (const LeafRec& R : P.leaves)
-        if (R.te - R.tb > 64) {
-            // the nearfield kernels give each row of a leaf one lane of a wave
-            msg = "a leaf holds more than 64 triangles (lower n_max or use more time steps)";
-            return PFMM_EUNSUPPORTED;
-        }
 
     // ------------------------------------------------------------ assembly groups
     {

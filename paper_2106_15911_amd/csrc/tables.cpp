@@ -95,6 +95,11 @@ void build_far_tables(const Plan& P, FarTables& F) {
                     std::copy(row.begin(), row.end(), F.At.begin() + FL.at_off + (int64_t)j * nt1);
                 }
             }
+            for (size_t li = 0; li < FL.leaf_xs.size(); ++li)
+                for (int r0 = 0; r0 < L.te[FL.leaf_xs[li]] - L.tb[FL.leaf_xs[li]]; r0 += 64) {
+                    FL.chunk_li.push_back((int)li);
+                    FL.chunk_r0.push_back(r0);
+                }
             for (int xs : FL.leaf_xs) {
                 FL.ax_off.push_back((int64_t)F.Ax.size());
                 double lo[3];

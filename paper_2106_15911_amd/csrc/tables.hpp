@@ -18,6 +18,8 @@ struct FarLevel {
     // boxes with children: inner[xs * n_int + k] = 1 if (xs, k) is present and not a leaf
     std::vector<uint8_t> inner;
     std::vector<int64_t> ax_off;        // per leaf slot, offset into Ax / AxK
+    // S2M / L2T blocks: (leaf slot index, first row) of row chunks of at most 64 triangles
+    std::vector<int> chunk_li, chunk_r0;
     int64_t at_off = 0;                 // A_t block: [E_t][m_t+1] (row j: step j in its interval of this level)
     // q^(t) for this level as the CHILD level: [n_int][m_t+1 (a_c)][m_t+1 (a_p)]
     int64_t qt_off = -1;

@@ -81,6 +81,8 @@ def load_library():
         "pfmm_apply_V": ([VP, VP, VP, VP], I32),
         "pfmm_apply_K": ([VP, VP, VP, VP], I32),
         "pfmm_tree_stats": ([VP, P(Stats)], I32),
+        "pfmm_autotune": ([VP, ctypes.c_char_p, VP, P(I32), P(I32)], I32),
+        "pfmm_representation": ([VP, VP, VP, VP, I64, I32, VP, VP], I32),
         "pfmm_plan_stats": ([dp, I64, ip, I64, dp, I64, P(Params), P(Stats)], I32),
         "pfmm_profile_enable": ([VP, I32], I32),
         "pfmm_set_precision": ([VP, I32], I32),
@@ -93,6 +95,7 @@ def load_library():
         "pfmm_batch_create": ([P(VP), I32, P(VP)], I32),
         "pfmm_apply_V_batch": ([VP, P(VP), P(VP), VP], I32),
         "pfmm_batch_destroy": ([VP], None),
+        "pfmm_batch_set_cross_m2l": ([VP, I32], I32),
         "pfmm_precond_create": ([I32, I32, I32, ctypes.c_uint64, P(VP)], I32),
         "pfmm_precond_train": ([VP, VP, VP, I32, I32, I32, ctypes.c_float, ctypes.c_uint64,
                                 P(ctypes.c_float), VP], I32),
@@ -241,6 +244,33 @@ class Tree:
         return self._solve(self.lib.pfmm_solve_dirichlet, g, out, rtol, max_iter, stream, raise_on_notconv, x0,
                            precond, precond_path, inner_precision)
 
+    def representation(self, w, u, xt, q=4, out=None, stream=None):
+        """(V~ w - W u)(x_i, t_i) at the rows (x, y, z, t) of xt (float64 device tensor, M x 4);
+        w or u may be None."""
+        import torch
+        for v in (w, u):
+            if v is not None and (v.dtype != torch.float64 or v.device != self.device or v.numel() != self.n_dofs
+                                  or not v.is_contiguous()):
+                raise ValueError(f"expected a contiguous float64 tensor of {self.n_dofs} entries on {self.device}")
+        if xt.dtype != torch.float64 or xt.device != self.device or xt.dim() != 2 or xt.shape[1] != 4:
+            raise ValueError("xt must be a float64 (M, 4) tensor on the tree's device")
+        xt = xt.contiguous()
+        if out is None:
+            out = torch.empty(xt.shape[0], dtype=torch.float64, device=self.device)
+        _check(self.lib.pfmm_representation(self.handle, ctypes.c_void_p(w.data_ptr()) if w is not None else None,
+                                            ctypes.c_void_p(u.data_ptr()) if u is not None else None,
+                                            ctypes.c_void_p(xt.data_ptr()), xt.shape[0], int(q),
+                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def autotune(self, cache_path=None, stream=None):
+        """Time the M2L launch choices per level and precision (cached in cache_path);
+        returns (levels timed, levels taken from the cache)."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.pfmm_autotune(self.handle, str(cache_path).encode() if cache_path else None,
+                                      _stream_ptr(stream), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def stats(self):
         st = Stats()
         _check(self.lib.pfmm_tree_stats(self.handle, ctypes.byref(st)))
@@ -298,6 +328,10 @@ class Batch:
         fp = (ctypes.c_void_p * len(ws))(*[y.data_ptr() for y in outs])
         _check(self.lib.pfmm_apply_V_batch(self.handle, wp, fp, _stream_ptr(stream)))
         return outs
+
+    def set_cross_m2l(self, enable):
+        """One M2L launch across the trees (levels with unequal intervals) or whole applies per tree."""
+        _check(self.lib.pfmm_batch_set_cross_m2l(self.handle, 1 if enable else 0))
 
     def close(self):
         if getattr(self, "handle", None):

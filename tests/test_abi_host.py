@@ -49,7 +49,9 @@ def _oracle_counts(n, E_t, n_max, n_tr):
                                               # step counts whose time levels split unevenly (nearest-step
                                               # split points of Algorithm 1; leaves on several levels)
                                               (4, 20, 64, 5), (3, 37, 16, 3), (2, 70, 8, -1), (4, 33, 64, 2),
-                                              (5, 47, 32, 3)])
+                                              (5, 47, 32, 3),
+                                              # single-step leaves of 96 triangles (refinement stops at one step)
+                                              (8, 4, 64, 5), (8, 3, 64, 5)])
 def test_planner_counts_match_oracle(n, E_t, n_max, n_tr):
     v, t = cube_surface_mesh(n)
     st = P.plan_stats(v, t, uniform_time_nodes(E_t), P.default_params(n_max=n_max, n_tr=n_tr, m_t=3, m_x=3))

@@ -131,3 +131,38 @@ def test_batch_matches_oracle():
     b.close()
     for t in trees:
         t.close()
+
+
+@pytest.mark.parametrize("mode", [P.NF_STORED, P.NF_TOEPLITZ])
+def test_cross_problem_m2l_equals_single_applies(mode):
+    """Trees with unequal time intervals (21, 37, 47 and 70 steps) and one
+    with equal ones: the batch's cross-problem M2L launch gives, bit for bit,
+    each tree's own apply, in FP64 and with the FP32 farfield, and so does
+    the batch with the cross-problem launch switched off."""
+    sizes = [(3, 21, dict(m_t=4, m_x=4, n_max=16)), (2, 37, dict(m_t=4, m_x=4, n_max=8)),
+             (4, 47, dict(m_t=4, m_x=4)), (2, 70, dict(m_t=4, m_x=4, n_max=8, n_tr=-1)),
+             (4, 32, dict(m_t=4, m_x=4))]
+    trees, ws = [], []
+    for i, (n, E_t, prm) in enumerate(sizes):
+        v, t, tn, w = problem(n, E_t, seed=60 + i)
+        trees.append(P.Tree(v, t, tn, P.default_params(operators=1, nearfield_mode=mode, precision=P.MIXED_FP32,
+                                                       **prm), device=0))
+        ws.append(torch.from_numpy(w).to("cuda:0"))
+    print(f"[batch-xm] mode {mode}: time classes {[tr.stats()['n_time_classes'] for tr in trees]}", flush=True)
+    b = P.Batch(trees)
+    for prec in (P.FP64, P.MIXED_FP32):
+        for tr in trees:
+            tr.set_precision(prec)
+        ref = [tr.apply_V(w) for tr, w in zip(trees, ws)]
+        torch.cuda.synchronize()
+        for cross in (True, False, True):
+            b.set_cross_m2l(cross)
+            outs = [torch.full_like(w, float("nan")) for w in ws]
+            for rep in range(2):
+                b.apply_V(ws, outs)
+                torch.cuda.synchronize()
+                for r, y in zip(ref, outs):
+                    assert torch.equal(r, y), (prec, cross, rep)
+    b.close()
+    for tr in trees:
+        tr.close()

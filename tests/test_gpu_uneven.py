@@ -74,3 +74,20 @@ def test_uneven_larger_tree_sampled_rows():
     err = np.abs(f[rows] - vals).max() / np.abs(vals).max()
     print(f"[uneven] 768 x 479 rows max rel err {err:.3e}", flush=True)
     assert err <= 1e-10
+
+
+def test_single_step_leaves_of_more_than_64_triangles():
+    """768 triangles x 3 steps: refinement stops at intervals of one step, so
+    leaves hold 96 triangles (the nearfield and S2M/L2T kernels take them in
+    row chunks of at most 64); V_h and K_h against the oracle."""
+    v, t, tn, w = problem(8, 3, seed=97)
+    prm = dict(m_t=3, m_x=3)
+    tree = P.Tree(v, t, tn, P.default_params(**prm), device=0)
+    x = torch.from_numpy(w).to("cuda:0")
+    for kind in ("V", "K"):
+        f = (tree.apply_V(x) if kind == "V" else tree.apply_K(x)).cpu().numpy()
+        r = reference(v, t, tn, w, kind, **prm)
+        e = rel_err(f, r)
+        print(f"[uneven] 768 x 3 {kind}: rel err {e:.3e}", flush=True)
+        assert np.isfinite(e) and e <= 1e-10
+    tree.close()
