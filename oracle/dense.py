@@ -20,7 +20,33 @@ formula (tests/test_oracle_dense.py).
 import numpy as np
 
 from . import quadrature as Q
-from .timeint import time_factors_all, time_factor, needs_singular_rule
+from .timeint import time_factors_all, time_factor, time_factor_steps, needs_singular_rule
+
+
+class _TimeSpec:
+    """The time integrals a set of entries needs: offsets d = 0..dmax of
+    uniform steps h (Toeplitz form), or explicit step pairs (kt, jt) of a
+    time grid with steps of any length."""
+
+    def __init__(self, dmax, h, tnodes=None, pairs=None):
+        self.tn = None if tnodes is None else np.asarray(tnodes, dtype=np.float64)
+        self.pairs = None if pairs is None else [(int(a), int(b)) for a, b in pairs]
+        self.dmax, self.h = dmax, h
+        self.n = len(self.pairs) if self.pairs is not None else dmax + 1
+
+    def offset(self, i):
+        return self.pairs[i][0] - self.pairs[i][1] if self.pairs is not None else i
+
+    def factor(self, r, i, alpha, kind):
+        if self.pairs is None:
+            return time_factor(r, i, self.h, alpha, kind)
+        kt, jt = self.pairs[i]
+        return time_factor_steps(r, self.tn[kt], self.tn[kt + 1], self.tn[jt], self.tn[jt + 1], kt - jt, alpha, kind)
+
+    def factors_all(self, r, alpha, kind):
+        if self.pairs is None:
+            return time_factors_all(r, self.dmax, self.h, alpha, kind)
+        return np.stack([self.factor(r, i, alpha, kind) for i in range(self.n)])
 
 
 def geometry(verts, tris):
@@ -40,25 +66,29 @@ def coplanar(verts, tris, k, j):
             and abs(np.dot(cen[0] - cen[1], nrm[1])) < 1e-10 * L)
 
 
-def _integrand_sum(dvec, W, nrm_j, dlist, h, alpha, kind):
+def _integrand_sum(dvec, W, nrm_j, ilist, ts, alpha, kind):
     r = np.linalg.norm(dvec, axis=1)
     vals = []
-    for d in dlist:
-        tf = time_factor(r, d, h, alpha, kind)
+    for i in ilist:
+        tf = ts.factor(r, i, alpha, kind)
         if kind == "K":
             tf = tf * (dvec @ nrm_j)
         vals.append(np.sum(W * tf))
     return np.array(vals)
 
 
-def panel_integrals(verts, tris, ks, js, dmax, h, alpha, kind="V", q_reg=4, q_sing=5):
-    """Entries B[d][k, j] for the listed panel pairs and d = 0..dmax.
+def panel_integrals(verts, tris, ks, js, dmax, h, alpha, kind="V", q_reg=4, q_sing=5, tnodes=None, pairs=None):
+    """Entries B[d][k, j] for the listed panel pairs and d = 0..dmax
+    (uniform steps h); or, with `pairs` a list of step pairs (kt, jt),
+    kt >= jt, of the time grid `tnodes` (steps of any length), the entries
+    of those step pairs.
 
-    Returns an array of shape (len(ks), dmax + 1).
+    Returns an array of shape (len(ks), dmax + 1) or (len(ks), len(pairs)).
     """
+    ts = _TimeSpec(dmax, h, tnodes, pairs)
     ks = np.asarray(ks, dtype=np.int64)
     js = np.asarray(js, dtype=np.int64)
-    out = np.zeros((len(ks), dmax + 1))
+    out = np.zeros((len(ks), ts.n))
     area, nrm, cen = geometry(verts, tris)
     nshared = np.array([Q.classify(tris[k], tris[j]) for k, j in zip(ks, js)])
     copl = np.zeros(len(ks), dtype=bool)
@@ -79,27 +109,27 @@ def panel_integrals(verts, tris, ks, js, dmax, h, alpha, kind="V", q_reg=4, q_si
         dv = xq[k][:, :, None, :] - xq[j][:, None, :, :]                  # (c, q2, q2, 3)
         r = np.linalg.norm(dv, axis=-1)
         W = wq[k][:, :, None] * wq[j][:, None, :]
-        tf = time_factors_all(r, dmax, h, alpha, kind)                    # (D, c, q2, q2)
+        tf = ts.factors_all(r, alpha, kind)                              # (D, c, q2, q2)
         if kind == "K":
             tf = tf * np.einsum("cpqx,cx->cpq", dv, nrm[j])[None]
         vals = np.einsum("dcpq,cpq->cd", tf, W)
         touching = nshared[idx] > 0
-        for d in range(dmax + 1):
-            if needs_singular_rule(d):
-                vals[touching, d] = 0.0   # replaced below
+        for it in range(ts.n):
+            if needs_singular_rule(ts.offset(it)):
+                vals[touching, it] = 0.0   # replaced below
         out[idx] = vals
 
     # touching pairs: singular rules (identical for all d, edge/vertex for d<=1)
     for i in np.nonzero((nshared > 0) & ~copl)[0]:
         k, j = int(ks[i]), int(js[i])
         if nshared[i] == 3:
-            dl = list(range(dmax + 1))
+            il = list(range(ts.n))
         else:
-            dl = [d for d in range(dmax + 1) if needs_singular_rule(d)]
-        if not dl:
+            il = [it for it in range(ts.n) if needs_singular_rule(ts.offset(it))]
+        if not il:
             continue
         dvec, W = Q.pair_rule(verts, tris, k, j, True, q_reg, q_sing)
-        out[i, dl] = _integrand_sum(dvec, W, nrm[j], dl, h, alpha, kind)
+        out[i, il] = _integrand_sum(dvec, W, nrm[j], il, ts, alpha, kind)
     return out
 
 
@@ -123,6 +153,29 @@ def dense_matrix(verts, tris, n_steps, h, alpha, kind="V", q_reg=4, q_sing=5, B=
         for jt in range(kt + 1):
             A[kt * nt:(kt + 1) * nt, jt * nt:(jt + 1) * nt] = B[kt - jt]
     return A
+
+
+def dense_matrix_steps(verts, tris, tnodes, alpha, kind="V", q_reg=4, q_sing=5):
+    """Full V_h or K_h (natural time-major order) on a time grid whose steps
+    may differ in length (block (kt, jt) from the absolute step pair; zero
+    for jt > kt)."""
+    tn = np.asarray(tnodes, dtype=np.float64)
+    E_t, nt = len(tn) - 1, len(tris)
+    pairs = [(kt, jt) for kt in range(E_t) for jt in range(kt + 1)]
+    kk, jj = np.meshgrid(np.arange(nt), np.arange(nt), indexing="ij")
+    vals = panel_integrals(verts, tris, kk.ravel(), jj.ravel(), 0, 0.0, alpha, kind, q_reg, q_sing,
+                           tnodes=tn, pairs=pairs)                      # (nt*nt, n_pairs)
+    A = np.zeros((E_t * nt, E_t * nt))
+    for i, (kt, jt) in enumerate(pairs):
+        A[kt * nt:(kt + 1) * nt, jt * nt:(jt + 1) * nt] = vals[:, i].reshape(nt, nt)
+    return A
+
+
+def mass_diag_steps(verts, tris, tnodes):
+    """Diagonal p0 x p0 mass matrix |gamma_k| (t_{j+1} - t_j) (natural order, length E_t E_x)."""
+    area = geometry(verts, tris)[0]
+    h = np.diff(np.asarray(tnodes, dtype=np.float64))
+    return (h[:, None] * area[None, :]).ravel()
 
 
 def mass_diag(verts, tris, n_steps, h):

@@ -130,6 +130,16 @@ class FMMOracle:
         pn, pk = np.nonzero(deg[:, None] + deg[None, :] <= m_x)
         self._pn, self._pk = pn, pk
 
+    def _time_key(self, Z, S):
+        """What the M2L operator's time dependence sees of a box pair: the
+        step offsets and lengths for uniform steps, else the node
+        differences (rounded to 2^-40 T)."""
+        tr = self.tr
+        if tr.uniform:
+            return (Z.s0 - S.s0, Z.s1 - Z.s0, S.s1 - S.s0)
+        q = lambda x: int(round(x / tr.T * 2.0 ** 40))
+        return (q(tr.t[Z.s0] - tr.t[S.s0]), q(tr.t[Z.s1] - tr.t[Z.s0]), q(tr.t[S.s1] - tr.t[S.s0]))
+
     # ---------------- temporal tables
     def tnodes(self, b):
         ta, tb = self.tr.interval(b)
@@ -218,7 +228,7 @@ class FMMOracle:
     def m2l_operator(self, Z, S):
         """Op[b, nu, a, kappa] of eq. m2l for target box Z and source box S."""
         tr = self.tr
-        key = (Z.level, tuple(np.subtract(Z.ix, S.ix)), Z.s0 - S.s0, Z.s1 - Z.s0, S.s1 - S.s0)
+        key = (Z.level, tuple(np.subtract(Z.ix, S.ix))) + self._time_key(Z, S)
         if key in self._op_cache:
             return self._op_cache[key]
         H = tr.hx_padded(Z.level)
@@ -265,7 +275,7 @@ class FMMOracle:
         tr = self.tr
         H = tr.hx_padded(Z.level)
         r = (tr.box_lower(Z) - tr.box_lower(S)) / H
-        tkey = (Z.level, Z.s0 - S.s0, Z.s1 - Z.s0, S.s1 - S.s0)
+        tkey = (Z.level,) + self._time_key(Z, S)
         dt = self.tnodes(Z)[None, :] - self.tnodes(S)[:, None]          # [a, b]
         C = (4.0 * np.pi * self.alpha * dt) ** -1.5
         dab = 4.0 * self.alpha * dt / (H * H)
@@ -310,10 +320,27 @@ class FMMOracle:
         return panel_integrals(self.tr.verts, self.tr.tri, kx, jx, dmax, self.h, self.alpha,
                                self.kind, self.q_reg, self.q_sing)
 
+    def entries_steps(self, kx, jx, pairs):
+        """Entries of the panel pairs (kx[i], jx[i]) for the step pairs
+        (kt, jt), kt >= jt, of a time grid with steps of any length:
+        (len(kx), len(pairs))."""
+        return panel_integrals(self.tr.verts, self.tr.tri, kx, jx, 0, 0.0, self.alpha, self.kind, self.q_reg,
+                               self.q_sing, tnodes=self.tr.t, pairs=pairs)
+
     def near_block(self, Z, S):
         """Dense causal block V|_{Z x S} in time-major element order."""
         kt = np.arange(Z.s0, Z.s1)
         jt = np.arange(S.s0, S.s1)
+        if not self.tr.uniform:
+            pairs = [(a, b) for a in kt for b in jt if b <= a]
+            kx = np.repeat(Z.tris, len(S.tris))
+            jx = np.tile(S.tris, len(Z.tris))
+            blk = np.zeros((len(kt), len(Z.tris), len(jt), len(S.tris)))
+            if pairs:
+                ent = self.entries_steps(kx, jx, pairs).reshape(len(Z.tris), len(S.tris), len(pairs))
+                for i, (a, b) in enumerate(pairs):
+                    blk[a - Z.s0, :, b - S.s0, :] = ent[:, :, i]
+            return blk.reshape(len(kt) * len(Z.tris), len(jt) * len(S.tris))
         D = kt[:, None] - jt[None, :]
         dmax = int(max(D.max(), 0))
         kx = np.repeat(Z.tris, len(S.tris))
@@ -403,7 +430,11 @@ class FMMOracle:
             if srcs:
                 dmax = kt - min(S.s0 for S in srcs)
                 jx_all = np.unique(np.concatenate([S.tris for S in srcs]))
-                ent = self.entries(np.full(len(jx_all), kx), jx_all, dmax)     # (n, dmax+1)
+                if tr.uniform:
+                    ent = self.entries(np.full(len(jx_all), kx), jx_all, dmax)     # (n, dmax+1)
+                else:   # column kt - jt holds the step pair (kt, jt)
+                    ent = self.entries_steps(np.full(len(jx_all), kx), jx_all,
+                                             [(kt, kt - d) for d in range(dmax + 1)])
                 where = {int(j): i for i, j in enumerate(jx_all)}
                 for S in srcs:
                     idx = np.array([where[int(j)] for j in S.tris])

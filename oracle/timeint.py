@@ -148,3 +148,70 @@ def time_factors_all(r, dmax, h, alpha, kind):
 def needs_singular_rule(d):
     """Touching panel pairs use the singular spatial rules for d in {0, 1}."""
     return d <= 1
+
+
+# ---------------------------------------------------------------- steps of any length
+# For a time grid with steps of different lengths the double time integral
+# over target step k = [tk0, tk1] and source step j = [tj0, tj1] is the
+# four-term combination of the second antiderivative at the node differences,
+#     F(tk1 - tj0) - F(tk1 - tj1) - F(tk0 - tj0) + F(tk0 - tj1),   F(., s <= 0) = 0,
+# (with equal steps h and d = k - j this is the second difference above).
+# When the steps are separated (d >= 2 in step indices) and the same
+# cancellation test flags the closed form -- with h the longer of the two
+# steps and d the lag tk0 - tj0 in units of h -- the integral is evaluated
+# instead as int phi(s) g(s) ds over s in [tk0 - tj1, tk1 - tj0], phi the
+# overlap length of the two steps at lag s: a trapezoid (a hat for equal
+# steps) rising over the shorter step length, flat over the difference of the
+# lengths, falling over the shorter length; 16-point Gauss-Legendre per piece.
+
+def _trapezoid(r, tk0, tk1, tj0, tj1, alpha, kind):
+    g, w = gauss_legendre01(HAT_POINTS)
+    r = np.asarray(r, dtype=np.float64)[..., None]
+    hk, hj = tk1 - tk0, tj1 - tj0
+    hm = min(hk, hj)
+    a = tk0 - tj1
+    b = a + hm
+    c = b + abs(hk - hj)
+    e = tk1 - tj0
+
+    def f(s):
+        v = G(r, s, alpha)
+        return v / (2.0 * s) if kind == "K" else v
+
+    tot = hm * np.sum(w * (hm * g) * f(a + hm * g), axis=-1)            # rising piece
+    if c > b:
+        tot = tot + (c - b) * np.sum(w * hm * f(b + (c - b) * g), axis=-1)   # plateau
+    tot = tot + hm * np.sum(w * (hm * (1.0 - g)) * f(c + hm * g), axis=-1)   # falling piece
+    return tot
+
+
+def use_trapezoid(r, tk0, tk1, tj0, tj1, d, alpha, kind):
+    """Branch test for steps of any length (the test of use_hat with h the
+    longer step and d the lag in units of h); only for separated steps."""
+    r = np.asarray(r, dtype=np.float64)
+    if d < 2:
+        return np.zeros(r.shape, dtype=bool)
+    h = max(tk1 - tk0, tj1 - tj0)
+    lag = tk0 - tj0
+    big = (lag / h + 1.0) * (4.0 * np.pi * alpha * lag) ** 1.5
+    if kind == "V":
+        lhs = CANCEL_LIMIT * (4.0 * np.pi * alpha) * r * h
+    else:
+        big = 2.0 * (lag / h) * big
+        lhs = CANCEL_LIMIT * (4.0 * np.pi) * r * r * r
+    return lhs < big
+
+
+def time_factor_steps(r, tk0, tk1, tj0, tj1, d, alpha, kind):
+    """Double time integral of G (V) or G/(2s) (K, without the (x-y).n_y
+    factor) over target step [tk0, tk1] and source step [tj0, tj1] at
+    distance r; d = k - j >= 0 is the step-index offset (d >= 2: separated)."""
+    r = np.asarray(r, dtype=np.float64)
+    F = G2 if kind == "V" else K2
+    out = F(r, tk1 - tj0, alpha) - F(r, tk1 - tj1, alpha) - F(r, tk0 - tj0, alpha) + F(r, tk0 - tj1, alpha)
+    if d >= 2:
+        m = use_trapezoid(r, tk0, tk1, tj0, tj1, d, alpha, kind)
+        if np.any(m):
+            out = np.where(m, 0.0, out)
+            out[m] = _trapezoid(r[m], tk0, tk1, tj0, tj1, alpha, kind)
+    return out

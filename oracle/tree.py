@@ -64,11 +64,21 @@ class Tree:
         self.h0 = 0.5 * float((hi - lo).max())
         self.lo0 = self.center - self.h0
         self.T = float(self.t[-1] - self.t[0])
+        h = np.diff(self.t)
+        self.uniform = bool(np.all(np.abs(h - self.T / self.E_t) <= 1e-12 * self.T / self.E_t))
         self._build()
         self._pad()
         self._temporal_tree()
 
     # ------------------------------------------------------------ Algorithm 1
+    def _split(self, s0, s1):
+        """Split node of the steps [s0, s1): the node nearest to the time
+        midpoint (the midpoint itself when it is a node), the earlier of two
+        nodes equally near (within 1e-12 T)."""
+        tm = 0.5 * (self.t[s0] + self.t[s1])
+        d = np.abs(self.t[s0 + 1:s1] - tm)
+        return s0 + 1 + int(np.nonzero(d <= d.min() + 1e-12 * self.T)[0][0])
+
     def _build(self):
         root = Box(0, (0, 0, 0), 0, 0, self.E_t, np.arange(self.E_x), None)
         self.levels = [[root]]
@@ -84,7 +94,7 @@ class Tree:
                 if b.n_elements < self.n_max or b.s1 - b.s0 <= 1:
                     continue
                 b.leaf = False
-                mid = (b.s0 + b.s1) // 2
+                mid = self._split(b.s0, b.s1)
                 halves = ((b.s0, mid, 2 * b.k), (mid, b.s1, 2 * b.k + 1))
                 if temporal:
                     for s0, s1, k in halves:
