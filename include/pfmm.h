@@ -70,7 +70,8 @@ typedef enum {
     PFMM_NF_TOEPLITZ = 1     /* uniform steps make a block entry depend on the
                                 triangles and the step difference only: keep
                                 the distinct values per (leaf spatial box, d)
-                                and read them at every apply (no block storage) */
+                                and read them at every apply (no block storage);
+                                needs uniform steps                          */
 } pfmm_nearfield_mode;
 
 /* which operators pfmm_build_tree assembles (bit mask) */
@@ -142,10 +143,18 @@ pfmm_status pfmm_default_params(pfmm_params* out);
  *  triangles   host, n_triangles x 3 int32, 0-based vertex indices; the
  *              surface must be closed and consistently oriented (outward
  *              normals by the right-hand rule)
- *  time_nodes  host, n_steps + 1 strictly increasing doubles; the steps must
- *              be uniform (relative deviation <= 1e-12), and n_steps must be
- *              divisible by 2^depth of the resulting tree, otherwise
- *              PFMM_EUNSUPPORTED
+ *  time_nodes  host, n_steps + 1 strictly increasing doubles.  Any step
+ *              count: Algorithm 1 halves a time interval at the node nearest
+ *              its midpoint (the earlier of two equally near), so intervals
+ *              of one level may differ in length and leaves may sit on
+ *              several levels of one time range.  Steps may differ in length
+ *              (graded or adaptive grids, Section 3.2): then every stored
+ *              nearfield entry is integrated for its own step pair and the
+ *              M2L operators for each pair of interval lengths and distance;
+ *              PFMM_NF_TOEPLITZ then returns PFMM_EUNSUPPORTED, and so do
+ *              the learned preconditioner's calls (its features assume one
+ *              step length).  Steps equal to within 1e-12 relative count as
+ *              uniform.
  *  p           parameters (NULL = defaults)
  *  device      HIP device ordinal
  *  stream      hipStream_t as void* used for the assembly

@@ -18,8 +18,12 @@ int tree_device(const pfmm_tree* t);
 int64_t tree_dofs(const pfmm_tree* t);            // E_t * E_x
 int64_t tree_triangles(const pfmm_tree* t);       // E_x
 bool tree_has(const pfmm_tree* t, int op);        // PFMM_OP_V / PFMM_OP_K built
-// Diagonal of the p0 x p0 mass matrix per triangle, |gamma_k| h_t (device, E_x doubles).
-const double* tree_mass(const pfmm_tree* t);
+// The p0 x p0 mass matrix is diagonal, |gamma_kx| (t_{kt+1} - t_kt): the
+// triangle areas (device, E_x doubles, natural order) and the step lengths
+// (device, E_t doubles).
+const double* tree_area(const pfmm_tree* t);
+const double* tree_steps(const pfmm_tree* t);
+bool tree_uniform_steps(const pfmm_tree* t);
 
 // Stage profiling (pfmm_profile_enable) switched on.
 bool tree_profiling(const pfmm_tree* t);

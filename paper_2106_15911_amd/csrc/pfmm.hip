@@ -476,50 +476,31 @@ __device__ __forceinline__ bool coplanar(const NearGeom& G, int a, int b) {
     return fabs(1.0 - fabs(dn)) < 1e-10 && fabs(dc) < 1e-10 * L;
 }
 
-// Regular panel pairs: tensor collapsed-Gauss rule, all d = 0..dmax.
-template <bool K, int DMAX>
-__global__ void k_near_regular(double* __restrict__ table, const GroupDev* __restrict__ groups,
-                               const int* __restrict__ blk_group, const int64_t* __restrict__ blk_base,
-                               const int* __restrict__ upos, NearGeom G, QuadRules Q) {
-    const int g = blk_group[blockIdx.x];
-    const GroupDev gr = groups[g];
-    const int nX = gr.te - gr.tb;
-    const int64_t idx = blk_base[blockIdx.x] + threadIdx.x;
-    if (idx >= (int64_t)nX * gr.usize) return;
-    const int r = (int)(idx % nX), u = (int)(idx / nX);
-    const int kx = G.inv_sigma[gr.tb + r];
-    const int jx = G.inv_sigma[upos[gr.uoff + u]];
-    double acc[DMAX + 1];
-#pragma unroll
-    for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0;
-    if (kx != jx && !(K && coplanar(G, kx, jx))) {
-        double P[3][3], S[3][3];
-        tri_vertices(G, kx, P);
-        tri_vertices(G, jx, S);
-        const double* ny = G.normal + 3 * jx;
-        const double aP = 2.0 * G.area[kx], aS = 2.0 * G.area[jx];
-        const int q = Q.q_reg;
-        for (int i1 = 0; i1 < q; ++i1)
-            for (int j1 = 0; j1 < q; ++j1) {
-                const double s1 = Q.g_reg[i1], t1 = Q.g_reg[i1] * Q.g_reg[j1];
-                const double w1 = aP * (Q.w_reg[i1] * Q.w_reg[j1] * Q.g_reg[i1]);
-                double x[3];
-                for (int c = 0; c < 3; ++c) x[c] = P[0][c] + s1 * (P[1][c] - P[0][c]) + t1 * (P[2][c] - P[1][c]);
-                for (int i2 = 0; i2 < q; ++i2)
-                    for (int j2 = 0; j2 < q; ++j2) {
-                        const double s2 = Q.g_reg[i2], t2 = Q.g_reg[i2] * Q.g_reg[j2];
-                        const double w2 = aS * (Q.w_reg[i2] * Q.w_reg[j2] * Q.g_reg[i2]);
-                        double dv[3];
-                        for (int c = 0; c < 3; ++c) dv[c] = x[c] - (S[0][c] + s2 * (S[1][c] - S[0][c]) + t2 * (S[2][c] - S[1][c]));
-                        accumulate_point<K, DMAX>(acc, dv, ny, w1 * w2, gr.dmax, G.h, G.alpha, Q);
-                    }
-            }
-    }
-    double* out = table + gr.toff;
-    for (int d = 0; d <= gr.dmax && d <= DMAX; ++d) out[((int64_t)d * gr.usize + u) * nX + r] = acc[d];
+// Point pairs (x - y, weight) of the tensor collapsed-Gauss rule on two
+// regular panels, passed to f(dv, W).
+template <class Fn>
+__device__ __forceinline__ void regular_points(const NearGeom& G, const QuadRules& Q, int kx, int jx, Fn&& f) {
+    double P[3][3], S[3][3];
+    tri_vertices(G, kx, P);
+    tri_vertices(G, jx, S);
+    const double aP = 2.0 * G.area[kx], aS = 2.0 * G.area[jx];
+    const int q = Q.q_reg;
+    for (int i1 = 0; i1 < q; ++i1)
+        for (int j1 = 0; j1 < q; ++j1) {
+            const double s1 = Q.g_reg[i1], t1 = Q.g_reg[i1] * Q.g_reg[j1];
+            const double w1 = aP * (Q.w_reg[i1] * Q.w_reg[j1] * Q.g_reg[i1]);
+            double x[3];
+            for (int c = 0; c < 3; ++c) x[c] = P[0][c] + s1 * (P[1][c] - P[0][c]) + t1 * (P[2][c] - P[1][c]);
+            for (int i2 = 0; i2 < q; ++i2)
+                for (int j2 = 0; j2 < q; ++j2) {
+                    const double s2 = Q.g_reg[i2], t2 = Q.g_reg[i2] * Q.g_reg[j2];
+                    const double w2 = aS * (Q.w_reg[i2] * Q.w_reg[j2] * Q.g_reg[i2]);
+                    double dv[3];
+                    for (int c = 0; c < 3; ++c) dv[c] = x[c] - (S[0][c] + s2 * (S[1][c] - S[0][c]) + t2 * (S[2][c] - S[1][c]));
+                    f(dv, w1 * w2);
+                }
+        }
 }
-
-struct TouchDev { int group, r, u, nshared; };
 
 __constant__ double c_edge_tets[6][3][3] = {
     {{0, 1, 0}, {1, 0, 0}, {1, 0, 1}},
@@ -531,11 +512,138 @@ __constant__ double c_edge_tets[6][3][3] = {
 };
 __constant__ double c_hex[6][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 0}, {-1, -1}, {0, -1}};
 
+// Point pairs of the singular rules for touching panels (nshared = 3:
+// identical, 2: common edge, 1: common vertex), passed to f(dv, W).
+template <class Fn>
+__device__ __forceinline__ void singular_points(const NearGeom& G, const QuadRules& Q, int kx, int jx, int nshared,
+                                                Fn&& f) {
+    const int q = Q.q_sing;
+    const int* ta = G.tris + 3 * kx;
+    const int* tb = G.tris + 3 * jx;
+    if (nshared == 3) {
+        double P[3][3];
+        tri_vertices(G, kx, P);
+        const double a2 = 2.0 * G.area[kx];
+        for (int sct = 0; sct < 6; ++sct) {
+            const double va0 = c_hex[sct][0], va1 = c_hex[sct][1];
+            const double vb0 = c_hex[(sct + 1) % 6][0], vb1 = c_hex[(sct + 1) % 6][1];
+            for (int ir = 0; ir < q; ++ir)
+                for (int iu = 0; iu < q; ++iu) {
+                    const double rho = Q.g_sing[ir], u = Q.g_sing[iu];
+                    const double z1 = rho * (va0 + u * (vb0 - va0));
+                    const double z2 = rho * (va1 + u * (vb1 - va1));
+                    double dv[3];
+                    for (int c = 0; c < 3; ++c) dv[c] = -(z1 * (P[1][c] - P[0][c]) + z2 * (P[2][c] - P[1][c]));
+                    const double W = a2 * a2 * 0.5 * (1.0 - rho) * (1.0 - rho) * rho * (Q.w_sing[ir] * Q.w_sing[iu]);
+                    f(dv, W);
+                }
+        }
+    } else if (nshared == 2) {
+        int ia = 0;
+        for (int v = 0; v < 3; ++v) {
+            bool sh = false;
+            for (int w = 0; w < 3; ++w) sh |= ta[v] == tb[w];
+            if (!sh) ia = v;
+        }
+        int q2 = 0;
+        for (int w = 0; w < 3; ++w) {
+            bool sh = false;
+            for (int v = 0; v < 3; ++v) sh |= tb[w] == ta[v];
+            if (!sh) q2 = tb[w];
+        }
+        const double* E0 = G.verts + 3 * ta[(ia + 1) % 3];
+        const double* E1 = G.verts + 3 * ta[(ia + 2) % 3];
+        const double* P2 = G.verts + 3 * ta[ia];
+        const double* Q2 = G.verts + 3 * q2;
+        double e[3], c1[3], c2[3];
+        for (int c = 0; c < 3; ++c) { e[c] = E1[c] - E0[c]; c1[c] = P2[c] - E1[c]; c2[c] = Q2[c] - E1[c]; }
+        const double aa = 2.0 * G.area[kx] * 2.0 * G.area[jx];
+        for (int tt = 0; tt < 6; ++tt) {
+            const double (*tv)[3] = c_edge_tets[tt];
+            const double det = fabs(tv[0][0] * (tv[1][1] * tv[2][2] - tv[1][2] * tv[2][1])
+                                    - tv[0][1] * (tv[1][0] * tv[2][2] - tv[1][2] * tv[2][0])
+                                    + tv[0][2] * (tv[1][0] * tv[2][1] - tv[1][1] * tv[2][0]));
+            for (int ir = 0; ir < q; ++ir)
+                for (int i1 = 0; i1 < q; ++i1)
+                    for (int i2 = 0; i2 < q; ++i2) {
+                        const double rho = Q.g_sing[ir], u1 = Q.g_sing[i1], u2 = Q.g_sing[i2];
+                        double p[3];
+                        for (int c = 0; c < 3; ++c)
+                            p[c] = rho * (tv[0][c] + u1 * (tv[1][c] - tv[0][c]) + (u1 * u2) * (tv[2][c] - tv[1][c]));
+                        double dv[3];
+                        for (int c = 0; c < 3; ++c) dv[c] = -p[0] * e[c] + p[1] * c1[c] - p[2] * c2[c];
+                        const double W = aa * det * (1.0 - rho) * rho * rho * u1 * (Q.w_sing[ir] * Q.w_sing[i1] * Q.w_sing[i2]);
+                        f(dv, W);
+                    }
+        }
+    } else {
+        int va = 0, vb = 0;
+        for (int v = 0; v < 3; ++v)
+            for (int w = 0; w < 3; ++w)
+                if (ta[v] == tb[w]) { va = v; vb = w; }
+        const double* V0 = G.verts + 3 * ta[va];
+        const double* P1 = G.verts + 3 * ta[(va + 1) % 3];
+        const double* P2 = G.verts + 3 * ta[(va + 2) % 3];
+        const double* Q1 = G.verts + 3 * tb[(vb + 1) % 3];
+        const double* Q2 = G.verts + 3 * tb[(vb + 2) % 3];
+        double a1[3], b1[3], a2[3], b2[3];
+        for (int c = 0; c < 3; ++c) { a1[c] = P1[c] - V0[c]; b1[c] = P2[c] - P1[c]; a2[c] = Q1[c] - V0[c]; b2[c] = Q2[c] - Q1[c]; }
+        const double aa = 2.0 * G.area[kx] * 2.0 * G.area[jx];
+        for (int ix = 0; ix < q; ++ix)
+            for (int ie = 0; ie < q; ++ie)
+                for (int i1 = 0; i1 < q; ++i1)
+                    for (int i2 = 0; i2 < q; ++i2) {
+                        const double xi = Q.g_sing[ix], eta = Q.g_sing[ie];
+                        const double u1 = Q.g_sing[i1], u2 = Q.g_sing[i2];
+                        const double W = aa * xi * xi * xi * eta *
+                                         (Q.w_sing[ix] * Q.w_sing[ie] * Q.w_sing[i1] * Q.w_sing[i2]);
+                        double A1[3], A2[3], dA[3], dB[3];
+                        for (int c = 0; c < 3; ++c) {
+                            A1[c] = a1[c] + u1 * b1[c];
+                            A2[c] = a2[c] + u2 * b2[c];
+                            dA[c] = xi * (A1[c] - eta * A2[c]);
+                            dB[c] = xi * (eta * A1[c] - A2[c]);
+                        }
+                        f(dA, W);
+                        f(dB, W);
+                    }
+    }
+}
+
+// Regular panel pairs: tensor collapsed-Gauss rule, all d = 0..dmax.
+template <bool K, int DMAX>
+__global__ void k_near_regular(double* __restrict__ table, const GroupDev* __restrict__ groups,
+                               const int* __restrict__ blk_group, const int64_t* __restrict__ blk_base,
+                               const int* __restrict__ upos, NearGeom G, QuadRules Q, int d0) {
+    const int g = blk_group[blockIdx.x];
+    const GroupDev gr = groups[g];
+    const int nX = gr.te - gr.tb;
+    const int64_t idx = blk_base[blockIdx.x] + threadIdx.x;
+    if (idx >= (int64_t)nX * gr.usize || d0 > gr.dmax) return;
+    const int r = (int)(idx % nX), u = (int)(idx / nX);
+    const int kx = G.inv_sigma[gr.tb + r];
+    const int jx = G.inv_sigma[upos[gr.uoff + u]];
+    double acc[DMAX + 1];
+#pragma unroll
+    for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0;
+    if (kx != jx && !(K && coplanar(G, kx, jx))) {
+        const double* ny = G.normal + 3 * jx;
+        regular_points(G, Q, kx, jx, [&](const double* dv, double W) {
+            accumulate_point<K, DMAX>(acc, dv, ny, W, d0, gr.dmax, G.h, G.alpha, Q);
+        });
+    }
+    double* out = table + gr.toff;
+    for (int dd = 0; dd <= DMAX && d0 + dd <= gr.dmax; ++dd)
+        out[((int64_t)(d0 + dd) * gr.usize + u) * nX + r] = acc[dd];
+}
+
+struct TouchDev { int group, r, u, nshared; };
+
 // Touching panel pairs: identical (all d), common edge / vertex (d = 0, 1).
 template <bool K, int DMAX>
 __global__ void k_near_singular(double* __restrict__ table, const GroupDev* __restrict__ groups,
                                 const TouchDev* __restrict__ touch, int n_touch, const int* __restrict__ upos,
-                                NearGeom G, QuadRules Q) {
+                                NearGeom G, QuadRules Q, int d0) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_touch) return;
     const TouchDev tp = touch[i];
@@ -544,105 +652,18 @@ __global__ void k_near_singular(double* __restrict__ table, const GroupDev* __re
     const int kx = G.inv_sigma[gr.tb + tp.r];
     const int jx = G.inv_sigma[upos[gr.uoff + tp.u]];
     const int dlast = (tp.nshared == 3) ? gr.dmax : min(1, gr.dmax);
+    if (d0 > dlast) return;
     double acc[DMAX + 1];
 #pragma unroll
     for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0;
     const double* ny = G.normal + 3 * jx;
-    const int q = Q.q_sing;
-    if (!(K && coplanar(G, kx, jx))) {
-        const int* ta = G.tris + 3 * kx;
-        const int* tb = G.tris + 3 * jx;
-        if (tp.nshared == 3) {
-            double P[3][3];
-            tri_vertices(G, kx, P);
-            const double a2 = 2.0 * G.area[kx];
-            for (int sct = 0; sct < 6; ++sct) {
-                const double va0 = c_hex[sct][0], va1 = c_hex[sct][1];
-                const double vb0 = c_hex[(sct + 1) % 6][0], vb1 = c_hex[(sct + 1) % 6][1];
-                for (int ir = 0; ir < q; ++ir)
-                    for (int iu = 0; iu < q; ++iu) {
-                        const double rho = Q.g_sing[ir], u = Q.g_sing[iu];
-                        const double z1 = rho * (va0 + u * (vb0 - va0));
-                        const double z2 = rho * (va1 + u * (vb1 - va1));
-                        double dv[3];
-                        for (int c = 0; c < 3; ++c) dv[c] = -(z1 * (P[1][c] - P[0][c]) + z2 * (P[2][c] - P[1][c]));
-                        const double W = a2 * a2 * 0.5 * (1.0 - rho) * (1.0 - rho) * rho * (Q.w_sing[ir] * Q.w_sing[iu]);
-                        accumulate_point<K, DMAX>(acc, dv, ny, W, dlast, G.h, G.alpha, Q);
-                    }
-            }
-        } else if (tp.nshared == 2) {
-            int ia = 0;
-            for (int v = 0; v < 3; ++v) {
-                bool sh = false;
-                for (int w = 0; w < 3; ++w) sh |= ta[v] == tb[w];
-                if (!sh) ia = v;
-            }
-            int q2 = 0;
-            for (int w = 0; w < 3; ++w) {
-                bool sh = false;
-                for (int v = 0; v < 3; ++v) sh |= tb[w] == ta[v];
-                if (!sh) q2 = tb[w];
-            }
-            const double* E0 = G.verts + 3 * ta[(ia + 1) % 3];
-            const double* E1 = G.verts + 3 * ta[(ia + 2) % 3];
-            const double* P2 = G.verts + 3 * ta[ia];
-            const double* Q2 = G.verts + 3 * q2;
-            double e[3], c1[3], c2[3];
-            for (int c = 0; c < 3; ++c) { e[c] = E1[c] - E0[c]; c1[c] = P2[c] - E1[c]; c2[c] = Q2[c] - E1[c]; }
-            const double aa = 2.0 * G.area[kx] * 2.0 * G.area[jx];
-            for (int tt = 0; tt < 6; ++tt) {
-                const double (*tv)[3] = c_edge_tets[tt];
-                const double det = fabs(tv[0][0] * (tv[1][1] * tv[2][2] - tv[1][2] * tv[2][1])
-                                        - tv[0][1] * (tv[1][0] * tv[2][2] - tv[1][2] * tv[2][0])
-                                        + tv[0][2] * (tv[1][0] * tv[2][1] - tv[1][1] * tv[2][0]));
-                for (int ir = 0; ir < q; ++ir)
-                    for (int i1 = 0; i1 < q; ++i1)
-                        for (int i2 = 0; i2 < q; ++i2) {
-                            const double rho = Q.g_sing[ir], u1 = Q.g_sing[i1], u2 = Q.g_sing[i2];
-                            double p[3];
-                            for (int c = 0; c < 3; ++c)
-                                p[c] = rho * (tv[0][c] + u1 * (tv[1][c] - tv[0][c]) + (u1 * u2) * (tv[2][c] - tv[1][c]));
-                            double dv[3];
-                            for (int c = 0; c < 3; ++c) dv[c] = -p[0] * e[c] + p[1] * c1[c] - p[2] * c2[c];
-                            const double W = aa * det * (1.0 - rho) * rho * rho * u1 * (Q.w_sing[ir] * Q.w_sing[i1] * Q.w_sing[i2]);
-                            accumulate_point<K, DMAX>(acc, dv, ny, W, dlast, G.h, G.alpha, Q);
-                        }
-            }
-        } else {
-            int va = 0, vb = 0;
-            for (int v = 0; v < 3; ++v)
-                for (int w = 0; w < 3; ++w)
-                    if (ta[v] == tb[w]) { va = v; vb = w; }
-            const double* V0 = G.verts + 3 * ta[va];
-            const double* P1 = G.verts + 3 * ta[(va + 1) % 3];
-            const double* P2 = G.verts + 3 * ta[(va + 2) % 3];
-            const double* Q1 = G.verts + 3 * tb[(vb + 1) % 3];
-            const double* Q2 = G.verts + 3 * tb[(vb + 2) % 3];
-            double a1[3], b1[3], a2[3], b2[3];
-            for (int c = 0; c < 3; ++c) { a1[c] = P1[c] - V0[c]; b1[c] = P2[c] - P1[c]; a2[c] = Q1[c] - V0[c]; b2[c] = Q2[c] - Q1[c]; }
-            const double aa = 2.0 * G.area[kx] * 2.0 * G.area[jx];
-            for (int ix = 0; ix < q; ++ix)
-                for (int ie = 0; ie < q; ++ie)
-                    for (int i1 = 0; i1 < q; ++i1)
-                        for (int i2 = 0; i2 < q; ++i2) {
-                            const double xi = Q.g_sing[ix], eta = Q.g_sing[ie];
-                            const double u1 = Q.g_sing[i1], u2 = Q.g_sing[i2];
-                            const double W = aa * xi * xi * xi * eta *
-                                             (Q.w_sing[ix] * Q.w_sing[ie] * Q.w_sing[i1] * Q.w_sing[i2]);
-                            double A1[3], A2[3], dA[3], dB[3];
-                            for (int c = 0; c < 3; ++c) {
-                                A1[c] = a1[c] + u1 * b1[c];
-                                A2[c] = a2[c] + u2 * b2[c];
-                                dA[c] = xi * (A1[c] - eta * A2[c]);
-                                dB[c] = xi * (eta * A1[c] - A2[c]);
-                            }
-                            accumulate_point<K, DMAX>(acc, dA, ny, W, dlast, G.h, G.alpha, Q);
-                            accumulate_point<K, DMAX>(acc, dB, ny, W, dlast, G.h, G.alpha, Q);
-                        }
-        }
-    }
+    if (!(K && coplanar(G, kx, jx)))
+        singular_points(G, Q, kx, jx, tp.nshared, [&](const double* dv, double W) {
+            accumulate_point<K, DMAX>(acc, dv, ny, W, d0, dlast, G.h, G.alpha, Q);
+        });
     double* out = table + gr.toff;
-    for (int d = 0; d <= dlast && d <= DMAX; ++d) out[((int64_t)d * gr.usize + tp.u) * nX + tp.r] = acc[d];
+    for (int dd = 0; dd <= DMAX && d0 + dd <= dlast; ++dd)
+        out[((int64_t)(d0 + dd) * gr.usize + tp.u) * nX + tp.r] = acc[dd];
 }
 
 struct NearLayout {
@@ -694,6 +715,62 @@ __global__ void __launch_bounds__(256) k_near_expand(double* __restrict__ B, con
         for (int64_t c = cs; c < total; c += cpi) {
             const int d = kt - jt;
             out[(colbase + c) * nX + r] = T[((int64_t)d * gr.usize + um[pos[i]]) * nX + r];
+            i += cpi;
+            while (i >= S) { i -= S; ++jt; }
+        }
+        colbase += total;
+    }
+}
+
+// Steps of different lengths (no Toeplitz reuse): every stored entry
+// V_h[(kt, kx), (jt, jx)] integrated directly into the causal blocks, with
+// the same spatial rules as the table kernels (singular rules for the
+// identical panel at every lag and for panels sharing an edge or a vertex at
+// lags 0 and 1) and the time factor of the step pair.  One wave per row
+// group, lanes over (column slot, row) as in k_near_expand.
+template <bool K>
+__global__ void __launch_bounds__(256) k_near_direct(double* __restrict__ B, const double* __restrict__ tn,
+                                                     NearLayout L, NearGeom G, QuadRules Q) {
+    const int64_t rg = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (rg >= L.n_rows) return;
+    const int lane = threadIdx.x % kWave;
+    const int leaf = L.rg_leaf[rg], kt = L.rg_kt[rg];
+    const int nX = L.lf_nx[leaf];
+    const int cpi = kWave / nX;
+    const int cs = lane / nX, r = lane % nX;
+    if (cs >= cpi) return;
+    const int kx = G.inv_sigma[L.lf_tb[leaf] + r];
+    const double tk0 = tn[kt], tk1 = tn[kt + 1];
+    double* out = B + L.rg_boff[rg];
+    int64_t colbase = 0;
+    for (int q = L.lf_rect0[leaf]; q < L.lf_rect1[leaf]; ++q) {
+        const int j0 = L.rc_j0[q];
+        const int ns = min(L.rc_j1[q], kt + 1) - j0;
+        if (ns <= 0) continue;
+        const int S = L.set_size[L.rc_set[q]];
+        const int* pos = L.set_pos + L.set_off[L.rc_set[q]];
+        const int64_t total = (int64_t)ns * S;
+        int jt = j0, i = cs;
+        while (i >= S) { i -= S; ++jt; }
+        for (int64_t c = cs; c < total; c += cpi) {
+            const int jx = G.inv_sigma[pos[i]];
+            const int d = kt - jt;
+            const double tj0 = tn[jt], tj1 = tn[jt + 1];
+            double acc = 0.0;
+            if (!(K && coplanar(G, kx, jx))) {
+                const double* ny = G.normal + 3 * jx;
+                auto point = [&](const double* dv, double W) {
+                    const double rr = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+                    const double fac = K ? W * (dv[0] * ny[0] + dv[1] * ny[1] + dv[2] * ny[2]) : W;
+                    acc += fac * time_factor_pair<K>(rr, tk0, tk1, tj0, tj1, d, G.alpha, Q);
+                };
+                int nsh = 0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) nsh += G.tris[3 * kx + a] == G.tris[3 * jx + b];
+                if (nsh == 3 || (nsh > 0 && d <= 1)) singular_points(G, Q, kx, jx, nsh, point);
+                else regular_points(G, Q, kx, jx, point);
+            }
+            out[(colbase + c) * nX + r] = acc;
             i += cpi;
             while (i >= S) { i -= S; ++jt; }
         }
@@ -793,7 +870,8 @@ struct pfmm_tree {
     double* fn = nullptr;         // nearfield result, tree order
     hipStream_t side = nullptr;   // the nearfield runs here, beside the farfield chain
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    double* mass = nullptr;       // |gamma_k| h per triangle (natural order)
+    double* mass = nullptr;       // |gamma_k| per triangle (natural order)
+    double* hstep = nullptr;      // t_{k+1} - t_k per step
     double *At = nullptr, *Ax = nullptr, *AxK = nullptr, *qt = nullptr, *qx = nullptr;
     int* chunk_cols = nullptr;
     int64_t* chunk_off = nullptr;
@@ -960,6 +1038,19 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
     static_assert(sizeof(TouchDev) == sizeof(TouchPair), "layout");
     PF_TRY(upload_geometry(t));
     const NearGeom G = t->geom;
+    if (!P.uniform_steps) {
+        // steps of different lengths: stored blocks only (the planner refuses
+        // the Toeplitz mode), each entry integrated on its own
+        const int64_t nrg = (int64_t)P.rows.size();
+        if (nrg > 0) {
+            if (K) hipLaunchKernelGGL(k_near_direct<true>, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, op.B,
+                                      t->tnodes_dev, t->nl, G, Q);
+            else hipLaunchKernelGGL(k_near_direct<false>, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, op.B,
+                                    t->tnodes_dev, t->nl, G, Q);
+            HIP_TRY(hipGetLastError());
+        }
+        return PFMM_OK;
+    }
     int* upos;
     PF_TRY(upload(t, &upos, P.upos.data(), P.upos.size()));
     // regular blocks
@@ -972,15 +1063,15 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
         int64_t n = (int64_t)(A.te - A.tb) * A.usize;
         for (int64_t s = 0; s < n; s += 256) { bg.push_back((int)i); bb.push_back(s); }
     }
-    if (dmx > 31) return fail(PFMM_EUNSUPPORTED, "nearfield time offsets above 31 steps");
     int* d_bg;
     int64_t* d_bb;
     PF_TRY(upload(t, &d_bg, bg.data(), bg.size()));
     PF_TRY(upload(t, &d_bb, bb.data(), bb.size()));
+    // time offsets 0..dmax in passes of at most 32 (d0 = 0, 32, ...)
     const int dc = dmax_class(dmx);
 #define LAUNCH_REG(KK, DD) hipLaunchKernelGGL((k_near_regular<KK, DD>), dim3((unsigned)bg.size()), dim3(256), 0, st, \
-                                              op.table, t->groups, d_bg, d_bb, upos, G, Q)
-    if (!bg.empty()) {
+                                              op.table, t->groups, d_bg, d_bb, upos, G, Q, d0)
+    for (int d0 = 0; d0 <= dmx && !bg.empty(); d0 += dc + 1) {
         if (K) {
             if (dc == 7) LAUNCH_REG(true, 7); else if (dc == 15) LAUNCH_REG(true, 15); else LAUNCH_REG(true, 31);
         } else {
@@ -993,8 +1084,8 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
     PF_TRY(upload(t, (TouchPair**)&d_touch, P.touch.data(), P.touch.size()));
     const int nT = (int)P.touch.size();
 #define LAUNCH_SING(KK, DD) hipLaunchKernelGGL((k_near_singular<KK, DD>), dim3((nT + 63) / 64), dim3(64), 0, st, \
-                                               op.table, t->groups, d_touch, nT, upos, G, Q)
-    if (nT > 0) {
+                                               op.table, t->groups, d_touch, nT, upos, G, Q, d0)
+    for (int d0 = 0; d0 <= dmx && nT > 0; d0 += dc + 1) {
         if (K) {
             if (dc == 7) LAUNCH_SING(true, 7); else if (dc == 15) LAUNCH_SING(true, 15); else LAUNCH_SING(true, 31);
         } else {
@@ -1275,9 +1366,12 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
     HIP_TRY(hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming));
     {
-        std::vector<double> m(P.E_x);
-        for (int i = 0; i < P.E_x; ++i) m[i] = P.area[i] * P.h;
-        PF_TRY(upload(t, &t->mass, m.data(), m.size()));
+        // p0 mass diagonal |gamma_kx| (t_{kt+1} - t_kt): areas and step lengths
+        // (h itself on a uniform grid)
+        std::vector<double> hs(P.E_t);
+        for (int k = 0; k < P.E_t; ++k) hs[k] = P.uniform_steps ? P.h : P.tnodes[k + 1] - P.tnodes[k];
+        PF_TRY(upload(t, &t->mass, P.area.data(), P.area.size()));
+        PF_TRY(upload(t, &t->hstep, hs.data(), hs.size()));
     }
     // coefficient maps
     {
@@ -2255,6 +2349,8 @@ const int* tree_adjacency(const pfmm_tree* t) { return t->adj; }
 
 pfmm_status tree_near_diag(pfmm_tree* t, double* d_dev, hipStream_t st) {
     if (!t->hasV) return fail(PFMM_EINVAL, "V_h was not built for this tree");
+    if (!t->P.uniform_steps)
+        return fail(PFMM_EUNSUPPORTED, "the learned preconditioner needs uniform time steps");
     const int nl = (int)t->P.leaves.size();
     hipLaunchKernelGGL(k_near_diag, dim3((unsigned)((nl + 3) / 4)), dim3(256), 0, st, t->opV.table, t->groups,
                        t->umap, t->nl, (int)t->P.leaves.size(), t->inv_sigma, d_dev);
@@ -2262,7 +2358,9 @@ pfmm_status tree_near_diag(pfmm_tree* t, double* d_dev, hipStream_t st) {
     return PFMM_OK;
 }
 bool tree_has(const pfmm_tree* t, int op) { return op == PFMM_OP_V ? t->hasV : (op == PFMM_OP_K ? t->hasK : false); }
-const double* tree_mass(const pfmm_tree* t) { return t->mass; }
+const double* tree_area(const pfmm_tree* t) { return t->mass; }
+const double* tree_steps(const pfmm_tree* t) { return t->hstep; }
+bool tree_uniform_steps(const pfmm_tree* t) { return t->P.uniform_steps; }
 pfmm_status tree_apply(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st) { return apply(t, K, x, y, st); }
 pfmm_status tree_apply_phase(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st, int phase) {
     return apply(t, K, x, y, st, phase);

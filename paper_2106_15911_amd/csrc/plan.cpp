@@ -63,6 +63,19 @@ namespace {
 
 inline bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
+// Algorithm 1 halves a time interval at its midpoint; on a grid of steps the
+// split falls on the node nearest to the midpoint of [t_s0, t_s1] (the
+// earlier of two nodes equally near, within 1e-12 T), which for uniform
+// steps is the middle step, the earlier one for an odd count.
+int split_node(const double* tn, int s0, int s1, double T) {
+    const double tm = 0.5 * (tn[s0] + tn[s1]);
+    double best = INFINITY;
+    for (int j = s0 + 1; j < s1; ++j) best = std::min(best, std::fabs(tn[j] - tm));
+    for (int j = s0 + 1; j < s1; ++j)
+        if (std::fabs(tn[j] - tm) <= best + 1e-12 * T) return j;
+    return (s0 + s1) / 2;
+}
+
 struct SlotBuild {
     std::array<int, 3> ix;
     std::vector<int> tris;   // natural indices
@@ -105,10 +118,16 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         if (!(tn[i + 1] > tn[i])) { msg = "time nodes must be strictly increasing"; return PFMM_EINVAL; }
     const double Ttot = tn[E_t] - tn[0];
     const double h = Ttot / (double)E_t;
+    bool uniform_steps = true;
     for (int64_t i = 0; i < E_t; ++i)
-        if (std::fabs((tn[i + 1] - tn[i]) - h) > 1e-12 * h) { msg = "time steps must be uniform"; return PFMM_EUNSUPPORTED; }
+        if (std::fabs((tn[i + 1] - tn[i]) - h) > 1e-12 * h) uniform_steps = false;
+    if (!uniform_steps && p.nearfield_mode == PFMM_NF_TOEPLITZ) {
+        msg = "the Toeplitz nearfield needs uniform time steps";
+        return PFMM_EUNSUPPORTED;
+    }
 
     P = Plan();
+    P.uniform_steps = uniform_steps;
     P.E_x = (int)nt; P.E_t = (int)E_t; P.n_vert = (int)nv;
     P.alpha = p.alpha; P.T = Ttot; P.h = h;
     P.m_t = p.m_t; P.m_x = p.m_x; P.n_max = p.n_max; P.n_tr = p.n_tr;
@@ -214,7 +233,7 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         C.iend.assign(C.n_int, -1);
         for (int k = 0; k < L.n_int; ++k) {
             if (!int_ref[k]) continue;
-            int s0 = L.istart[k], s1 = L.iend[k], mid = (s0 + s1) / 2;
+            int s0 = L.istart[k], s1 = L.iend[k], mid = split_node(tn, s0, s1, Ttot);
             C.istart[2 * k] = s0; C.iend[2 * k] = mid;
             C.istart[2 * k + 1] = mid; C.iend[2 * k + 1] = s1;
         }
@@ -343,7 +362,7 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
     for (int l = 2; l <= P.depth; ++l) {
         Level& L = P.lev[l];
         const int len = L.iend[0] - L.istart[0];
-        L.uniform = true;
+        L.uniform = P.uniform_steps;
         for (int k = 0; k < L.n_int; ++k)
             if (L.istart[k] < 0 || L.iend[k] - L.istart[k] != len) L.uniform = false;
         for (size_t i = 0; i < L.present.size(); ++i)
@@ -351,7 +370,10 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         for (int xs = 0; xs < L.nx() && L.uniform; ++xs)
             for (int k = 1; k < L.n_int; ++k)
                 if (L.leaf[(size_t)xs * L.n_int + k] != L.leaf[(size_t)xs * L.n_int]) L.uniform = false;
-        std::map<std::array<int, 4>, int> ids;   // (D, start_k - start_J, len_k, len_J) -> class
+        // class key: (D, start_k - start_J, len_k, len_J), in steps for a
+        // uniform grid, else as times rounded to 2^-40 T
+        std::map<std::array<int64_t, 4>, int> ids;
+        auto tq = [&](int a, int b) { return (int64_t)std::llround((tn[b] - tn[a]) / Ttot * 1099511627776.0); };
         for (int D = 2; D <= 3; ++D) {
             L.cls[D - 2].assign(L.n_int, -1);
             if (L.uniform && L.n_int > D) {
@@ -365,8 +387,11 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
                 const int J = k - D;
                 if ((D == 3 && !(k & 1)) || J < 0 || L.istart[k] < 0 || L.istart[J] < 0) continue;
                 if (L.uniform) { L.cls[D - 2][k] = D - 2; continue; }
-                const std::array<int, 4> key = {D, L.istart[k] - L.istart[J], L.iend[k] - L.istart[k],
-                                                L.iend[J] - L.istart[J]};
+                const std::array<int64_t, 4> key =
+                    P.uniform_steps ? std::array<int64_t, 4>{D, L.istart[k] - L.istart[J], L.iend[k] - L.istart[k],
+                                                             L.iend[J] - L.istart[J]}
+                                    : std::array<int64_t, 4>{D, tq(L.istart[J], L.istart[k]), tq(L.istart[k], L.iend[k]),
+                                                             tq(L.istart[J], L.iend[J])};
                 auto it = ids.find(key);
                 if (it == ids.end()) {
                     it = ids.emplace(key, (int)L.cls_rep.size()).first;
@@ -621,8 +646,10 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
             toff += (int64_t)(G.dmax + 1) * (G.te - G.tb) * G.usize;
             G.mapoff = (int64_t)g * E_x;
         }
-        P.table_size = toff;
-        P.distinct = toff;
+        // steps of different lengths: no Toeplitz reuse, every stored entry
+        // is integrated on its own (no distinct-integral table)
+        P.table_size = P.uniform_steps ? toff : 0;
+        P.distinct = P.uniform_steps ? toff : P.near_entries;
         P.umap.assign(P.groups.size() * (size_t)E_x, -1);
         for (size_t g = 0; g < P.groups.size(); ++g) {
             const AsmGroup& G = P.groups[g];

@@ -30,7 +30,8 @@ struct Level {
     std::vector<uint8_t> present, leaf;     // [xs * n_int + k]
     // M2L time classes (levels >= 2): the operator of eq. m2l depends on the
     // target and source intervals only through their node differences, i.e.
-    // (start_k - start_J, len_k, len_J) in steps.  cls[D - 2][k] is the class
+    // (start_k - start_J, len_k, len_J) (in steps on a uniform grid, as times
+    // otherwise).  cls[D - 2][k] is the class
     // of target interval k with source J = k - D (D = 2, 3 for odd k; -1 if
     // there is none); cls_rep[c] = (k, J) a representative pair, cls_D[c] = D.
     std::vector<int> cls[2];
@@ -89,6 +90,7 @@ struct Plan {
     std::vector<int> tris;              // E_x x 3 (natural order)
     std::vector<int> adj;               // E_x x 3: triangle across edge (v_e, v_{e+1})
     std::vector<double> tnodes;         // E_t + 1
+    bool uniform_steps = true;          // all steps of length h = T / E_t (to 1e-12 h)
 
     // geometry (natural triangle order)
     std::vector<double> area, normal, centroid, maxedge;

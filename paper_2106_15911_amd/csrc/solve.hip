@@ -108,11 +108,12 @@ __global__ void __launch_bounds__(kBlock) k_scale(const double* x, double* y, do
     if (i < n) y[i] = a * x[i];
 }
 
-// b[i] += 1/2 M_h g: mass[k_x] = |gamma_kx| h_t for the index i = k_t E_x + k_x.
-__global__ void __launch_bounds__(kBlock) k_half_mass(const double* __restrict__ g, const double* __restrict__ mass,
-                                                       double* __restrict__ b, int64_t ex, int64_t n) {
+// b[i] += 1/2 M_h g: M_h[i, i] = |gamma_kx| (t_{kt+1} - t_kt) for the index i = k_t E_x + k_x.
+__global__ void __launch_bounds__(kBlock) k_half_mass(const double* __restrict__ g, const double* __restrict__ area,
+                                                       const double* __restrict__ hstep, double* __restrict__ b,
+                                                       int64_t ex, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) b[i] += 0.5 * mass[i % ex] * g[i];
+    if (i < n) b[i] += 0.5 * (area[i % ex] * hstep[i / ex]) * g[i];
 }
 
 // b[i] -= a[i]
@@ -651,8 +652,8 @@ pfmm_status pfmm_dirichlet_rhs(pfmm_tree* t, const double* g_dev, double* b_dev,
     const int64_t n = tree_dofs(t);
     hipStream_t st = (hipStream_t)stream;
     PS_TRY(tree_apply(t, true, g_dev, b_dev, st));
-    hipLaunchKernelGGL(k_half_mass, dim3(blocks_for(n)), dim3(kBlock), 0, st, g_dev, tree_mass(t), b_dev,
-                       tree_triangles(t), n);
+    hipLaunchKernelGGL(k_half_mass, dim3(blocks_for(n)), dim3(kBlock), 0, st, g_dev, tree_area(t), tree_steps(t),
+                       b_dev, tree_triangles(t), n);
     HIP_CHECK(hipGetLastError());
     return PFMM_OK;
 }

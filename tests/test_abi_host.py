@@ -30,9 +30,13 @@ def test_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
-def _oracle_counts(n, E_t, n_max, n_tr):
+def graded_nodes(n, T=1.0, p=1.7):
+    return T * (np.arange(n + 1) / n) ** p
+
+
+def _oracle_counts(n, E_t, n_max, n_tr, tn=None):
     v, t = cube_surface_mesh(n)
-    tr = Tree(v, t, uniform_time_nodes(E_t), 1.0, n_max, 0.9, n_tr)
+    tr = Tree(v, t, uniform_time_nodes(E_t) if tn is None else tn, 1.0, n_max, 0.9, n_tr)
     memo = {}
     near = 0
     for Z in tr.leaves:
@@ -58,6 +62,22 @@ def test_planner_counts_match_oracle(n, E_t, n_max, n_tr):
     ref = _oracle_counts(n, E_t, n_max, n_tr)
     for k, val in ref.items():
         assert st[k] == val, (k, st[k], val)
+
+
+@pytest.mark.parametrize("n,E_t,n_max,n_tr,p", [(4, 16, 64, 5, 1.7), (3, 37, 16, 3, 1.7), (2, 40, 8, -1, 2.5),
+                                                (4, 33, 64, 2, 0.6)])
+def test_planner_counts_match_oracle_graded_steps(n, E_t, n_max, n_tr, p):
+    """Graded steps t_j = (j / E_t)^p: Algorithm 1 splits at the node nearest
+    the time midpoint, so the tree differs from the uniform one; the counts
+    still match the oracle's, and every level >= 2 with more than one pair
+    of intervals has classes beyond the two of a uniform grid."""
+    v, t = cube_surface_mesh(n)
+    tn = graded_nodes(E_t, p=p)
+    st = P.plan_stats(v, t, tn, P.default_params(n_max=n_max, n_tr=n_tr, m_t=3, m_x=3))
+    ref = _oracle_counts(n, E_t, n_max, n_tr, tn)
+    for k, val in ref.items():
+        assert st[k] == val, (k, st[k], val)
+    assert st["n_time_classes"] > 2
 
 
 def test_planner_counts_second_workload():
@@ -107,9 +127,14 @@ def test_error_codes():
     assert e.value.status == -1
     bad = tn.copy()
     bad[3] += 0.01
+    P.plan_stats(v, t, bad)                              # steps of different lengths: stored nearfield
     with pytest.raises(P.PfmmError) as e:
-        P.plan_stats(v, t, bad)                          # non-uniform steps
-    assert e.value.status == -6
+        P.plan_stats(v, t, bad, P.default_params(nearfield_mode=P.NF_TOEPLITZ))
+    assert e.value.status == -6                          # no Toeplitz structure to use
+    bad[3] = bad[2]
+    with pytest.raises(P.PfmmError) as e:
+        P.plan_stats(v, t, bad)                          # repeated node
+    assert e.value.status == -1
     vn = v.copy()
     vn[0, 0] = np.nan
     with pytest.raises(P.PfmmError) as e:
