@@ -647,7 +647,8 @@ __global__ void k_sum_parts(double* __restrict__ lam, const double* __restrict__
 // owned by one workgroup per launch, so the sum is deterministic).
 // One level of one tree for the class-aware M2L (one time offset D).
 struct ClsUnit {
-    const void* mu;          // moments of the level (FP64, or FP32 / BF16 values)
+    const void* mu;          // moments gathered into column order [slot][coef][column]
+                             // (FP64, or FP32 / BF16 values)
     double* lam;             // locals of the level (added to)
     const int* ptr;          // interaction lists: CSR over target slots
     const int* src;          //   source slot
@@ -657,8 +658,24 @@ struct ClsUnit {
     const int2* cols;        // columns (k, class), padded with k = -1
     const int2* cbr;         // first and last class per column block
     int n_int, R, nx, nccb, D;
+    int ncp;                 // columns of the gathered moments (16 NB nccb)
     int wg0;                 // first workgroup of this unit in a batched launch
 };
+
+// mup[slot][c][i] = mu[slot][c][perm[i]] (0 where perm[i] < 0), converted to
+// T (rounded on to bfloat16 values when bf16 is set): the class-aware M2L's
+// B operand in column order.
+template <class T>
+__global__ void k_gather_cols(const double* __restrict__ mu, T* __restrict__ mup, const int* __restrict__ perm,
+                              int n_int, int ncp, int64_t n, int bf16) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t row = i / ncp;
+    const int k = perm[i - row * ncp];
+    const double v = k >= 0 ? mu[row * n_int + k] : 0.0;
+    if constexpr (sizeof(T) == 8) mup[i] = v;
+    else mup[i] = bf16 ? bf16_round((float)v) : (float)v;
+}
 
 template <class T, int NB, int MAXS, int WAVES, bool RB>
 __device__ __forceinline__ void m2l_cls_body(
@@ -701,13 +718,14 @@ __device__ __forceinline__ void m2l_cls_body(
         }
         sCol[c] = v;
     }
-    // this lane's column (target interval and class) in every block nb
+    // this lane's target interval in every sub-block nb, and the sub-block's
+    // class (one per sub-block, -1 for an empty one: uniform over the wave)
     int kcol[NB], ccol[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int2 e = cols[(cb * NB + nb) * 16 + lr];
         kcol[nb] = e.x;
-        ccol[nb] = e.y;
+        ccol[nb] = __builtin_amdgcn_readfirstlane(e.y);
     }
     const int2 crange = cbr[cb];
     const int cmin = __builtin_amdgcn_readfirstlane(crange.x);
@@ -752,26 +770,32 @@ __device__ __forceinline__ void m2l_cls_body(
                                              16, 0, 0);
         }
     };
-    // byte offsets of mu[Y][c][k - D] for K-step sbeg (columns without a
-    // target read offset 0 and are masked); loads past the slot return zero
+    // byte offsets of the gathered moments of column (cb NB + nb) 16 + lr
+    // for K-step sbeg (padding columns hold zeros); loads past the slot
+    // return zero
+    const int ncp = U.ncp;
     int vb[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) vb[nb] = ((4 * sbeg + lq) * n_int + (kcol[nb] >= 0 ? kcol[nb] - D : 0)) * ES;
-    const int bstep = 4 * n_int * ES;
-    const int slot_bytes = Nc * n_int * ES;
+    for (int nb = 0; nb < NB; ++nb) vb[nb] = ((4 * sbeg + lq) * ncp + (cb * NB + nb) * 16 + lr) * ES;
+    const int bstep = 4 * ncp * ES;
+    const int slot_bytes = Nc * ncp * ES;
+    (void)n_int;
+    (void)D;
     const char* lds = (const char*)smem;
     if (n_phase > 0) stage(0);
     for (int p = 0; p < n_phase; ++p) {
         const int Y = src[sb + p / ncr], c = cmin + p % ncr;
         const int boff = (p & 1) * 3 * TSp * ES;
         const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc((void*)(mu + (int64_t)Y * Nc * n_int), (short)0, slot_bytes, 0x00020000);
+            __builtin_amdgcn_make_buffer_rsrc((void*)(mu + (int64_t)Y * Nc * ncp), (short)0, slot_bytes, 0x00020000);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (p + 1 < n_phase) stage(p + 1);
-        T msk[NB];
+        // sub-blocks of another class skip their loads and products (a
+        // wave-uniform branch)
+        bool on[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) msk[nb] = (kcol[nb] >= 0 && ccol[nb] == c) ? T(1) : T(0);
+        for (int nb = 0; nb < NB; ++nb) on[nb] = ccol[nb] == c;
         int pX[MAXS], pY[MAXS], pZ[MAXS];
 #pragma unroll
         for (int i = 0; i < MAXS; ++i) {
@@ -783,7 +807,8 @@ __device__ __forceinline__ void m2l_cls_body(
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int vo = vb[nb] + (s - sbeg) * bstep;
-                if constexpr (ES == 8)
+                if (!on[nb]) bv[nb] = T(0);
+                else if constexpr (ES == 8)
                     bv[nb] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, 0, 0));
                 else
                     bv[nb] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, 0, 0));
@@ -802,9 +827,10 @@ __device__ __forceinline__ void m2l_cls_body(
                 if constexpr (RB) A[i] = bf16_round(A[i]);
             }
 #pragma unroll
-            for (int i = 0; i < n; ++i)
+            for (int nb = 0; nb < NB; ++nb)
+                if (on[nb])
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc[i][nb] = Tr::mfma(A[i], bv[nb] * msk[nb], acc[i][nb]);
+                    for (int i = 0; i < n; ++i) acc[i][nb] = Tr::mfma(A[i], bv[nb], acc[i][nb]);
         };
         int s = sbeg;
         int4 cA = sCol[4 * s + lq], cB = sCol[4 * s + 4 + lq];

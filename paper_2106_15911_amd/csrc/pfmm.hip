@@ -821,6 +821,10 @@ struct DevLevel {
     int2* ccols[2] = {nullptr, nullptr};   // class-aware M2L: columns (k, class) per time offset 2, 3
     int2* cbr[2] = {nullptr, nullptr};     // first and last class of each column block
     int nccb[2] = {0, 0};                  // column blocks per time offset
+    int ncp[2] = {0, 0};                   // columns (16 kClsNB nccb) per time offset
+    int* cperm[2] = {nullptr, nullptr};    // source interval k - D of each column (-1: padding)
+    double* mup[2] = {nullptr, nullptr};   // moments gathered into column order [slot][coef][column]
+    float* mup32[2] = {nullptr, nullptr};  // the same in FP32 (BF16 values for that mode)
     double* mu = nullptr;
     double* lam = nullptr;
     int* leaf_xs = nullptr;
@@ -1691,24 +1695,39 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
                 return fail(PFMM_EUNSUPPORTED, "levels with unequal intervals need the matrix-core M2L "
                                                "(degrees <= 15)");
             // columns of the class-aware M2L: the target intervals of each time
-            // offset, sorted by class, in blocks of 16 kClsNB
+            // offset, sorted by class into sub-blocks of 16 of one class (the
+            // last of a class padded with k = -1), NB sub-blocks to a column
+            // block; the moments are gathered into this column order before
+            // each launch, so a sub-block's B operand is one contiguous row
             for (int Dt = 2; Dt <= 3; ++Dt) {
                 std::vector<std::pair<int, int>> cl;   // (class, k)
                 for (int k = 0; k < L.n_int; ++k)
                     if (L.cls[Dt - 2][k] >= 0) cl.emplace_back(L.cls[Dt - 2][k], k);
                 std::stable_sort(cl.begin(), cl.end());
-                const int per = 16 * kClsNB;
-                const int nblk = (int)((cl.size() + per - 1) / per);
-                std::vector<int2> cols((size_t)nblk * per, int2{-1, -1});
-                std::vector<int2> br(nblk);
-                for (size_t i = 0; i < cl.size(); ++i) cols[i] = int2{cl[i].second, cl[i].first};
-                for (int b = 0; b < nblk; ++b) {
-                    const size_t lo = (size_t)b * per, hi = std::min(cl.size(), lo + per);
-                    br[b] = int2{cl[lo].first, cl[hi - 1].first};
+                std::vector<int2> cols;
+                for (size_t i = 0; i < cl.size(); ++i) {
+                    if (i > 0 && cl[i].first != cl[i - 1].first)
+                        while (cols.size() % 16) cols.push_back(int2{-1, cl[i - 1].first});
+                    cols.push_back(int2{cl[i].second, cl[i].first});
                 }
+                while (cols.size() % 16) cols.push_back(int2{-1, cl.back().first});
+                const int per = 16 * kClsNB;
+                while (cols.size() % per) cols.push_back(int2{-1, -1});   // empty sub-blocks
+                const int nblk = (int)(cols.size() / per);
+                std::vector<int2> br(nblk);
+                std::vector<int> perm(cols.size());
+                for (int b = 0; b < nblk; ++b) {
+                    int lo = INT32_MAX, hi = -1;
+                    for (int i = b * per; i < (b + 1) * per; ++i)
+                        if (cols[i].y >= 0) { lo = std::min(lo, cols[i].y); hi = std::max(hi, cols[i].y); }
+                    br[b] = int2{lo, hi};
+                }
+                for (size_t i = 0; i < cols.size(); ++i) perm[i] = cols[i].x >= 0 ? cols[i].x - Dt : -1;
                 D.nccb[Dt - 2] = nblk;
+                D.ncp[Dt - 2] = (int)cols.size();
                 PF_TRY(upload(t, &D.ccols[Dt - 2], cols.data(), cols.size()));
                 PF_TRY(upload(t, &D.cbr[Dt - 2], br.data(), br.size()));
+                PF_TRY(upload(t, &D.cperm[Dt - 2], perm.data(), perm.size()));
             }
         }
         D.at_off = FL.at_off; D.qt_off = FL.qt_off; D.qx_off = FL.qx_off; D.n_off = FL.n_off;
@@ -1773,10 +1792,15 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             if (nsplit_max > 1) PF_TRY(dalloc(t, &D.lam_parts, (size_t)(nsplit_max - 1) * D.nx * P.Nc * D.n_int));
             D.parts_cap = nsplit_max;
             D.slot_pairs = (int64_t)FL.m2l_src.size();
-            if (t->has_f32 && (D.m2l_nb[1] || !D.uniform)) {
+            if (t->has_f32 && D.m2l_nb[1]) {
                 PF_TRY(dalloc(t, &D.mu32, (size_t)D.nx * P.Nc * D.n_int + 2));
                 HIP_TRY(hipMemset(D.mu32, 0, ((size_t)D.nx * P.Nc * D.n_int + 2) * sizeof(float)));
                 D.mu32 += 2;
+            }
+            for (int Dt = 2; Dt <= 3 && !D.uniform; ++Dt) {
+                const size_t np = (size_t)D.nx * P.Nc * D.ncp[Dt - 2];
+                PF_TRY(dalloc(t, &D.mup[Dt - 2], np));
+                if (t->has_f32) PF_TRY(dalloc(t, &D.mup32[Dt - 2], np));
             }
         }
         PF_TRY(upload(t, &D.leaf_xs, FL.leaf_xs.data(), FL.leaf_xs.size()));
@@ -1905,9 +1929,17 @@ int cls_prep(pfmm_tree* t, int l, hipStream_t st) {
     DevLevel& D = t->lv[l];
     const int64_t nl = (int64_t)D.nx * t->P.Nc * D.n_int;
     const int q = cls_q(t);
-    if (q >= 1)
-        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.mu, D.mu32, nl,
-                           q == 2 ? 1 : 0);
+    for (int Dt = 2; Dt <= 3; ++Dt) {
+        if (D.nccb[Dt - 2] == 0) continue;
+        const int64_t np = (int64_t)D.nx * t->P.Nc * D.ncp[Dt - 2];
+        const dim3 g((unsigned)((np + 255) / 256));
+        if (q == 0)
+            hipLaunchKernelGGL(k_gather_cols<double>, g, dim3(256), 0, st, D.mu, D.mup[Dt - 2], D.cperm[Dt - 2],
+                               D.n_int, D.ncp[Dt - 2], np, 0);
+        else
+            hipLaunchKernelGGL(k_gather_cols<float>, g, dim3(256), 0, st, D.mu, D.mup32[Dt - 2], D.cperm[Dt - 2],
+                               D.n_int, D.ncp[Dt - 2], np, q == 2 ? 1 : 0);
+    }
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, D.lam, 0.0, nl);
     return q;
 }
@@ -1916,7 +1948,8 @@ ClsUnit cls_unit(const pfmm_tree* t, int l, int Dt, int q) {
     const DevLevel& D = t->lv[l];
     const int64_t row0 = D.e1s_off / std::max(1, t->TSp);   // first table row of the level
     ClsUnit U{};
-    U.mu = q ? (const void*)D.mu32 : (const void*)D.mu;
+    U.mu = q ? (const void*)D.mup32[Dt - 2] : (const void*)D.mup[Dt - 2];
+    U.ncp = D.ncp[Dt - 2];
     U.lam = D.lam;
     U.ptr = D.m2l_ptr;
     U.src = D.m2l_src;
