@@ -25,6 +25,9 @@ meshes), tree (Algorithm 1 and the lists), fmm (expansions and the apply),
 solve (unpreconditioned GMRES), represent (single- and double-layer
 potentials at interior points).
 
+Module p1: the double layer with p1-continuous trial functions in space,
+the mixed mass matrix and the FMM for it (Section 2).
+
 Parity status per function is listed in the module headers; every function
 here is pinned by a ``-m "not gpu"`` test against a value fixed by the paper
 or by mathematics other than this code.

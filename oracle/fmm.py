@@ -379,6 +379,10 @@ class FMMOracle:
                 f[tr.elements(b)] += self.l2t(b, lam_[b.id]).ravel()
         return f
 
+    def near_contrib(self, Z, S, w):
+        """Nearfield block of (Z, S) times the source values (rows of Z)."""
+        return self.near_block(Z, S) @ w[self.tr.elements(S)]
+
     def nearfield(self, w):
         tr = self.tr
         f = np.zeros(tr.E_t * tr.E_x)
@@ -386,8 +390,26 @@ class FMMOracle:
         for Z in tr.leaves:
             rows = tr.elements(Z)
             for S in tr.nearfield(Z, memo):
-                f[rows] += self.near_block(Z, S) @ w[tr.elements(S)]
+                f[rows] += self.near_contrib(Z, S, w)
         return f
+
+    def near_row(self, kt, kx, srcs, w):
+        """Nearfield part of row (k_t, k_x): every source element (j_t <= k_t)
+        of the source boxes srcs."""
+        tr = self.tr
+        dmax = kt - min(S.s0 for S in srcs)
+        jx_all = np.unique(np.concatenate([S.tris for S in srcs]))
+        if tr.uniform:
+            ent = self.entries(np.full(len(jx_all), kx), jx_all, dmax)     # (n, dmax+1)
+        else:   # column kt - jt holds the step pair (kt, jt)
+            ent = self.entries_steps(np.full(len(jx_all), kx), jx_all, [(kt, kt - d) for d in range(dmax + 1)])
+        where = {int(j): i for i, j in enumerate(jx_all)}
+        tot = 0.0
+        for S in srcs:
+            idx = np.array([where[int(j)] for j in S.tris])
+            for jt in range(S.s0, min(S.s1, kt + 1)):
+                tot += ent[idx, kt - jt] @ w[jt * tr.E_x + S.tris]
+        return tot
 
     # ---------------- row-sampled apply (for meshes too large for a full apply)
     def apply_rows(self, w, rows, mu=None):
@@ -428,16 +450,5 @@ class FMMOracle:
             # nearfield row: every source element (j_t <= k_t) of the leaf's nearfield boxes
             srcs = [S for S in tr.nearfield(Z, memo) if S.s0 <= kt]
             if srcs:
-                dmax = kt - min(S.s0 for S in srcs)
-                jx_all = np.unique(np.concatenate([S.tris for S in srcs]))
-                if tr.uniform:
-                    ent = self.entries(np.full(len(jx_all), kx), jx_all, dmax)     # (n, dmax+1)
-                else:   # column kt - jt holds the step pair (kt, jt)
-                    ent = self.entries_steps(np.full(len(jx_all), kx), jx_all,
-                                             [(kt, kt - d) for d in range(dmax + 1)])
-                where = {int(j): i for i, j in enumerate(jx_all)}
-                for S in srcs:
-                    idx = np.array([where[int(j)] for j in S.tris])
-                    for jt in range(S.s0, min(S.s1, kt + 1)):
-                        out[i] += ent[idx, kt - jt] @ w[jt * tr.E_x + S.tris]
+                out[i] += self.near_row(kt, kx, srcs, w)
         return out, mu

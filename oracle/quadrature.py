@@ -215,3 +215,85 @@ def pair_rule(verts, tris, k, j, singular, q_reg, q_sing):
         oa, ob = vertex_order(ta, tb)
         return vertex_rule(verts[list(oa)], verts[list(ob)], q_sing)
     return regular_rule(verts[ta], verts[tb], q_reg)
+
+
+# ---------------------------------------------------------------- p1 trial weights
+# For a trial function that is linear on the source triangle (p1-continuous
+# hat functions restricted to one panel) each rule above also needs the
+# barycentric coordinates lambda_i(y) of the source point.  With the
+# reference map y = Q0 + s (Q1 - Q0) + t (Q2 - Q1), 0 <= t <= s <= 1, they
+# are (1 - s, s - t, t).  The common-edge rule integrates the position x1
+# along the shared edge in closed form; lambda is affine in it, so its
+# average over that segment is its value at the segment's midpoint.  The
+# common-vertex rule keeps both points explicit.  The identical-panel rule
+# integrates the position out as an area: it is not extended (the double
+# layer vanishes on a panel with itself, as on every coplanar pair).
+
+def _bary(s, t):
+    return np.stack([1.0 - s, s - t, t], axis=1)
+
+
+def regular_rule_p1(P, Q, q):
+    """(x - y, W, lambda(y)) of the tensor collapsed-Gauss rule."""
+    s, t, w = triangle_rule(q)
+    x = map_ref(P, s, t)
+    y = map_ref(Q, s, t)
+    aP = tri_geometry(P)[0]
+    aQ = tri_geometry(Q)[0]
+    d = x[:, None, :] - y[None, :, :]
+    W = (2 * aP) * (2 * aQ) * w[:, None] * w[None, :]
+    lam_y = np.broadcast_to(_bary(s, t)[None, :, :], (len(s), len(s), 3))
+    return d.reshape(-1, 3), W.reshape(-1), lam_y.reshape(-1, 3)
+
+
+def edge_rule_p1(P, Q, q):
+    """edge_rule plus lambda(y) in the order (E0, E1, Q2) of Q.
+
+    In the variables v = (z, x2, y2) = (y1 - x1, x2, y2) the remaining
+    position x1 runs over [max(x2, y2 - z), min(1, 1 - z)] (x and y in the
+    reference triangle); y = (y1, y2) with y1 = x1 + z."""
+    d, W = edge_rule(P, Q, q)
+    g, _ = gauss_legendre01(q)
+    rho = np.repeat(g, q * q)
+    u1 = np.tile(np.repeat(g, q), q)
+    u2 = np.tile(g, q * q)
+    lams = []
+    for a, b, c in _EDGE_TETS:
+        p = rho[:, None] * (a[None, :] + u1[:, None] * (b - a)[None, :] + (u1 * u2)[:, None] * (c - b)[None, :])
+        z, x2, y2 = p[:, 0], p[:, 1], p[:, 2]
+        lo = np.maximum(x2, y2 - z)
+        hi = np.minimum(1.0, 1.0 - z)
+        y1 = 0.5 * (lo + hi) + z
+        lams.append(_bary(y1, y2))
+    return d, W, np.concatenate(lams)
+
+
+def vertex_rule_p1(P, Q, q):
+    """vertex_rule plus lambda(y) in the order (V, Q1, Q2) of Q.
+
+    First region: x = V + xi A1, y = V + xi eta A2 (reference coordinates
+    (xi eta, xi eta u2) of y); second: x = V + xi eta A1, y = V + xi A2."""
+    d, W = vertex_rule(P, Q, q)
+    g, _ = gauss_legendre01(q)
+    n = q ** 4
+    idx = np.indices((q, q, q, q)).reshape(4, n)
+    xi, eta, u2 = g[idx[0]], g[idx[1]], g[idx[3]]
+    la = _bary(xi * eta, xi * eta * u2)
+    lb = _bary(xi, xi * u2)
+    return d, W, np.concatenate([la, lb])
+
+
+def pair_rule_p1(verts, tris, k, j, singular, q_reg, q_sing):
+    """(x - y, W, lambda) for target triangle k and source j, lambda[:, i]
+    the barycentric coordinate of y for vertex tris[j][i]."""
+    ta, tb = tris[k], tris[j]
+    nshared = classify(ta, tb)
+    if nshared == 3:
+        raise ValueError("identical panels: no p1 rule (the double layer vanishes there)")
+    if singular and nshared in (1, 2):
+        oa, ob = edge_order(ta, tb) if nshared == 2 else vertex_order(ta, tb)
+        rule = edge_rule_p1 if nshared == 2 else vertex_rule_p1
+        d, W, lo = rule(verts[list(oa)], verts[list(ob)], q_sing)
+        cols = [list(ob).index(int(v)) for v in tb]      # column of each of tris[j]'s vertices
+        return d, W, lo[:, cols]
+    return regular_rule_p1(verts[ta], verts[tb], q_reg)
