@@ -74,8 +74,11 @@ typedef enum {
                                 needs uniform steps                          */
 } pfmm_nearfield_mode;
 
-/* which operators pfmm_build_tree assembles (bit mask) */
-enum { PFMM_OP_V = 1, PFMM_OP_K = 2 };
+/* which operators pfmm_build_tree assembles (bit mask).  PFMM_OP_K1: the
+   double layer with trial functions piecewise linear and continuous in space
+   (nodal hat functions at the mesh vertices, Section 2), stored nearfield
+   only */
+enum { PFMM_OP_V = 1, PFMM_OP_K = 2, PFMM_OP_K1 = 4 };
 
 typedef struct pfmm_tree pfmm_tree;   /* opaque */
 
@@ -90,7 +93,7 @@ typedef struct {
     int32_t  q_sing;         /* Gauss points per direction, touching panel pairs.  default 5   */
     int32_t  precision;      /* pfmm_precision of the applies; a MIXED tree also
                                 keeps the FP64 path (pfmm_set_precision).     default FP64 */
-    int32_t  operators;      /* PFMM_OP_V | PFMM_OP_K.                             default both */
+    int32_t  operators;      /* PFMM_OP_V | PFMM_OP_K | PFMM_OP_K1.          default V and K */
     int32_t  check_finite;   /* 1: reject non-finite mesh/time input.              default 1   */
     int32_t  nearfield_mode; /* pfmm_nearfield_mode.                               default STORED */
     int32_t  nearfield_gemm; /* Toeplitz mode: 1 runs the leaf boxes whose leaves are
@@ -127,6 +130,9 @@ typedef struct {
     int64_t  near_nonzero_K;     /* causal nearfield entries of K_h between panels
                                     that are not coplanar (the others are exactly
                                     zero): the entries K_h's product must read      */
+    int64_t  near_entries_K1;    /* entries stored for the p1 double layer: three
+                                    per source triangle and target element (its
+                                    local vertices), 0 if not built             */
 } pfmm_stats;
 
 /* Fill *out with the default parameters above.  Returns PFMM_EINVAL on NULL. */
@@ -179,6 +185,20 @@ pfmm_status pfmm_apply_V(pfmm_tree* t, const double* w_dev, double* f_dev, void*
 
 /* f = K_h u, same conventions as pfmm_apply_V (K must have been built). */
 pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void* stream);
+
+/*
+ * f = K_h u for the double layer with p1-continuous trial functions in space
+ * (Section 2: the Dirichlet datum's discretisation, nodal hat functions phi_v
+ * at the mesh vertices, p0 in time; tested with p0 x p0):
+ *   f[kt E_x + kx] = sum_{jt, v} K_h[(kt, kx), (jt, v)] u[jt n_vertices + v].
+ * u_dev: device, n_steps * n_vertices doubles (time-major, the vertex order
+ * of pfmm_build_tree); f_dev: n_steps * n_triangles doubles (natural order),
+ * overwritten.  The FMM is the double layer's with per-vertex S2M moments;
+ * the nearfield blocks hold three columns per source triangle.  Needs
+ * PFMM_OP_K1 at build.  Asynchronous on `stream`; u_dev, f_dev must not alias.
+ * Errors: PFMM_EINVAL (NULL, K1 not built), PFMM_EDEVICE.
+ */
+pfmm_status pfmm_apply_K1(pfmm_tree* t, const double* u_dev, double* f_dev, void* stream);
 
 /*
  * Select the farfield precision of the following applies of t (and of the
@@ -326,6 +346,23 @@ pfmm_status pfmm_dirichlet_rhs(pfmm_tree* t, const double* g_dev, double* b_dev,
  */
 pfmm_status pfmm_solve_dirichlet(pfmm_tree* t, const double* g_dev, double* w_dev, const pfmm_solve_opts* o,
                                  pfmm_solve_info* info, void* stream);
+
+/*
+ * The Dirichlet system with the datum in p1-continuous functions (Section 2,
+ * system 02:linear:system as discretised there): g_dev holds the
+ * coefficients per step and vertex of the projected datum (device,
+ * n_steps * n_vertices, time-major), M_h is the mixed mass matrix
+ *   M_h[(kt, kx), (jt, v)] = delta_{kt jt} (t_{kt+1} - t_kt) |gamma_kx| / 3
+ * for the vertices v of triangle kx, and K_h the p1 double layer
+ * (pfmm_apply_K1).  pfmm_dirichlet_rhs_p1 forms b = (1/2 M_h + K_h) g
+ * (n_steps * n_triangles, natural order; needs PFMM_OP_K1);
+ * pfmm_solve_dirichlet_p1 solves V_h w = b as pfmm_solve_V does (needs V_h
+ * and PFMM_OP_K1; same options, conventions and errors; one more
+ * right-hand-side vector is allocated for the call).
+ */
+pfmm_status pfmm_dirichlet_rhs_p1(pfmm_tree* t, const double* g_dev, double* b_dev, void* stream);
+pfmm_status pfmm_solve_dirichlet_p1(pfmm_tree* t, const double* g_dev, double* w_dev, const pfmm_solve_opts* o,
+                                    pfmm_solve_info* info, void* stream);
 
 /*
  * Batches of independent problems (trees on one device, each holding V_h).

@@ -6,8 +6,8 @@ this package only loads it and marshals arguments.
 """
 from .pfmm import (PfmmError, Params, SolveOpts, SolveInfo, Tree, Batch, Precond, default_params, plan_stats, lib_path,
                    load_library, STATUS_NAMES, PROFILE_STAGES, FP64, MIXED_FP32, MIXED_BF16, NF_STORED,
-                   NF_TOEPLITZ)
+                   NF_TOEPLITZ, OP_V, OP_K, OP_K1)
 
 __all__ = ["PfmmError", "Params", "SolveOpts", "SolveInfo", "Tree", "Batch", "Precond", "default_params", "plan_stats", "lib_path",
            "load_library", "STATUS_NAMES", "PROFILE_STAGES", "FP64", "MIXED_FP32", "MIXED_BF16", "NF_STORED",
-           "NF_TOEPLITZ"]
+           "NF_TOEPLITZ", "OP_V", "OP_K", "OP_K1"]

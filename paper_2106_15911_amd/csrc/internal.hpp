@@ -54,6 +54,10 @@ float precond_last_loss(const pfmm_precond* pc);
 
 // Stream-ordered applies without argument checks (natural order in and out).
 pfmm_status tree_apply(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st);
+// The p1 double layer (x: n_steps x n_vertices) and the mesh it needs.
+pfmm_status tree_apply_p1(pfmm_tree* t, const double* x, double* y, hipStream_t st);
+int tree_vertices(const pfmm_tree* t);
+const int* tree_tris(const pfmm_tree* t);   // device, natural order, n_triangles x 3
 
 // The apply in two phases around a batched M2L: phase 1 permutes, runs the
 // nearfield, the upward pass and the M2L of the levels with equal intervals

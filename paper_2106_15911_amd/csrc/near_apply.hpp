@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(256) k_near_apply(const double* __restrict__ B
                     const int c = base + (int)threadIdx.x;
                     if ((int)threadIdx.x < CH && c < tstage) {
                         const int d = c / S;   // column c = (source step j0 + d, triangle pos[c - d S])
-                        xs[threadIdx.x] = wd[(int64_t)(j0 + d) * L.E_x + pos[c - d * S]];
+                        xs[threadIdx.x] = wd[(int64_t)(j0 + d) * L.E_src + pos[c - d * S]];
                     }
                     __syncthreads();
                 } else {
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) k_near_apply(const double* __restrict__ B
                         const int c = base + cl;
                         if (cl < CH && c < tstage) {
                             const int d = c / S;
-                            xs[cl] = wd[(int64_t)(j0 + d) * L.E_x + pos[c - d * S]];
+                            xs[cl] = wd[(int64_t)(j0 + d) * L.E_src + pos[c - d * S]];
                         }
                     }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

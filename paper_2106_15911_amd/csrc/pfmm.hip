@@ -60,6 +60,19 @@ __global__ void k_permute_in(const double* __restrict__ w, double* __restrict__ 
     wd[i] = w[t * E_x + inv_sigma[p]];
 }
 
+// p1 trial functions: the vertex values u[jt][v] (natural order) as local
+// values per triangle position and vertex, w3[jt][3 p + i] = u[jt][vertex i
+// of the triangle at position p].
+__global__ void k_gather_p1(const double* __restrict__ u, double* __restrict__ w3, const int* __restrict__ inv_sigma,
+                            const int* __restrict__ tris, int n_v, int E_x, int64_t n3) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    const int64_t jt = i / (3 * (int64_t)E_x);
+    const int rem = (int)(i - jt * 3 * (int64_t)E_x);
+    const int p = rem / 3, c = rem - 3 * p;
+    w3[i] = u[jt * n_v + tris[3 * inv_sigma[p] + c]];
+}
+
 // f = far + near, back to the natural order.  A sum of two FP64 terms is
 // rounded once, so it already equals what a compensated (Neumaier) sum
 // returns: no correction term is needed here.
@@ -477,7 +490,9 @@ __device__ __forceinline__ bool coplanar(const NearGeom& G, int a, int b) {
 }
 
 // Point pairs (x - y, weight) of the tensor collapsed-Gauss rule on two
-// regular panels, passed to f(dv, W).
+// regular panels, passed to f(dv, W, lam) with lam the barycentric
+// coordinates of the source point y (in the order of the source triangle's
+// vertices; p0 kernels ignore them).
 template <class Fn>
 __device__ __forceinline__ void regular_points(const NearGeom& G, const QuadRules& Q, int kx, int jx, Fn&& f) {
     double P[3][3], S[3][3];
@@ -497,7 +512,8 @@ __device__ __forceinline__ void regular_points(const NearGeom& G, const QuadRule
                     const double w2 = aS * (Q.w_reg[i2] * Q.w_reg[j2] * Q.g_reg[i2]);
                     double dv[3];
                     for (int c = 0; c < 3; ++c) dv[c] = x[c] - (S[0][c] + s2 * (S[1][c] - S[0][c]) + t2 * (S[2][c] - S[1][c]));
-                    f(dv, w1 * w2);
+                    const double lam[3] = {1.0 - s2, s2 - t2, t2};
+                    f(dv, w1 * w2, lam);
                 }
         }
 }
@@ -513,7 +529,14 @@ __constant__ double c_edge_tets[6][3][3] = {
 __constant__ double c_hex[6][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 0}, {-1, -1}, {0, -1}};
 
 // Point pairs of the singular rules for touching panels (nshared = 3:
-// identical, 2: common edge, 1: common vertex), passed to f(dv, W).
+// identical, 2: common edge, 1: common vertex), passed to f(dv, W, lam).
+// lam: barycentric coordinates of y in the source triangle's vertex order.
+// The common-edge rule integrates the position along the shared edge in
+// closed form; lam is affine in it, so its average is its value at the
+// middle of that position's range.  The identical-panel rule integrates the
+// position out as an area and passes lam = (1/3, 1/3, 1/3): only its sum is
+// meaningful there (the double layer, the one kernel weighted by lam,
+// vanishes on a panel with itself).
 template <class Fn>
 __device__ __forceinline__ void singular_points(const NearGeom& G, const QuadRules& Q, int kx, int jx, int nshared,
                                                 Fn&& f) {
@@ -535,7 +558,8 @@ __device__ __forceinline__ void singular_points(const NearGeom& G, const QuadRul
                     double dv[3];
                     for (int c = 0; c < 3; ++c) dv[c] = -(z1 * (P[1][c] - P[0][c]) + z2 * (P[2][c] - P[1][c]));
                     const double W = a2 * a2 * 0.5 * (1.0 - rho) * (1.0 - rho) * rho * (Q.w_sing[ir] * Q.w_sing[iu]);
-                    f(dv, W);
+                    const double lam[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0};
+                    f(dv, W, lam);
                 }
         }
     } else if (nshared == 2) {
@@ -558,6 +582,13 @@ __device__ __forceinline__ void singular_points(const NearGeom& G, const QuadRul
         double e[3], c1[3], c2[3];
         for (int c = 0; c < 3; ++c) { e[c] = E1[c] - E0[c]; c1[c] = P2[c] - E1[c]; c2[c] = Q2[c] - E1[c]; }
         const double aa = 2.0 * G.area[kx] * 2.0 * G.area[jx];
+        // source vertex order (E0, E1, Q2) -> position in tb
+        int pe0 = 0, pe1 = 0, pq2 = 0;
+        for (int w = 0; w < 3; ++w) {
+            if (tb[w] == ta[(ia + 1) % 3]) pe0 = w;
+            else if (tb[w] == ta[(ia + 2) % 3]) pe1 = w;
+            else pq2 = w;
+        }
         for (int tt = 0; tt < 6; ++tt) {
             const double (*tv)[3] = c_edge_tets[tt];
             const double det = fabs(tv[0][0] * (tv[1][1] * tv[2][2] - tv[1][2] * tv[2][1])
@@ -573,7 +604,14 @@ __device__ __forceinline__ void singular_points(const NearGeom& G, const QuadRul
                         double dv[3];
                         for (int c = 0; c < 3; ++c) dv[c] = -p[0] * e[c] + p[1] * c1[c] - p[2] * c2[c];
                         const double W = aa * det * (1.0 - rho) * rho * rho * u1 * (Q.w_sing[ir] * Q.w_sing[i1] * Q.w_sing[i2]);
-                        f(dv, W);
+                        // p = (y1 - x1, x2, y2); x1 runs over [max(x2, y2 - z), min(1, 1 - z)]
+                        const double x1m = 0.5 * (fmax(p[1], p[2] - p[0]) + fmin(1.0, 1.0 - p[0]));
+                        const double y1 = x1m + p[0];
+                        double lam[3];
+                        lam[pe0] = 1.0 - y1;
+                        lam[pe1] = y1 - p[2];
+                        lam[pq2] = p[2];
+                        f(dv, W, lam);
                     }
         }
     } else {
@@ -604,43 +642,61 @@ __device__ __forceinline__ void singular_points(const NearGeom& G, const QuadRul
                             dA[c] = xi * (A1[c] - eta * A2[c]);
                             dB[c] = xi * (eta * A1[c] - A2[c]);
                         }
-                        f(dA, W);
-                        f(dB, W);
+                        // y = V0 + xi eta A2 (first region), V0 + xi A2 (second):
+                        // reference coordinates (s, s u2) with s = xi eta or xi
+                        double lA[3], lB[3];
+                        const double sA = xi * eta, sB = xi;
+                        lA[vb] = 1.0 - sA; lA[(vb + 1) % 3] = sA - sA * u2; lA[(vb + 2) % 3] = sA * u2;
+                        lB[vb] = 1.0 - sB; lB[(vb + 1) % 3] = sB - sB * u2; lB[(vb + 2) % 3] = sB * u2;
+                        f(dA, W, lA);
+                        f(dB, W, lB);
                     }
     }
 }
 
-// Regular panel pairs: tensor collapsed-Gauss rule, all d = 0..dmax.
-template <bool K, int DMAX>
+// Regular panel pairs: tensor collapsed-Gauss rule, d = d0 .. d0 + DMAX.
+// NC = 3: the double layer with p1 trial functions, one table column per
+// local vertex of the source triangle (column NC u + i of gr.usize = NC U).
+template <bool K, int DMAX, int NC = 1>
 __global__ void k_near_regular(double* __restrict__ table, const GroupDev* __restrict__ groups,
                                const int* __restrict__ blk_group, const int64_t* __restrict__ blk_base,
                                const int* __restrict__ upos, NearGeom G, QuadRules Q, int d0) {
     const int g = blk_group[blockIdx.x];
     const GroupDev gr = groups[g];
     const int nX = gr.te - gr.tb;
+    const int U = gr.usize / NC;
     const int64_t idx = blk_base[blockIdx.x] + threadIdx.x;
-    if (idx >= (int64_t)nX * gr.usize || d0 > gr.dmax) return;
+    if (idx >= (int64_t)nX * U || d0 > gr.dmax) return;
     const int r = (int)(idx % nX), u = (int)(idx / nX);
     const int kx = G.inv_sigma[gr.tb + r];
     const int jx = G.inv_sigma[upos[gr.uoff + u]];
-    double acc[DMAX + 1];
+    double acc[NC][DMAX + 1];
 #pragma unroll
-    for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0;
+    for (int i = 0; i < NC; ++i)
+#pragma unroll
+        for (int d = 0; d <= DMAX; ++d) acc[i][d] = 0.0;
     if (kx != jx && !(K && coplanar(G, kx, jx))) {
         const double* ny = G.normal + 3 * jx;
-        regular_points(G, Q, kx, jx, [&](const double* dv, double W) {
-            accumulate_point<K, DMAX>(acc, dv, ny, W, d0, gr.dmax, G.h, G.alpha, Q);
+        regular_points(G, Q, kx, jx, [&](const double* dv, double W, const double* lam) {
+            if constexpr (NC == 1) {
+                accumulate_point<K, DMAX>(acc[0], dv, ny, W, d0, gr.dmax, G.h, G.alpha, Q);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NC; ++i)
+                    accumulate_point<K, DMAX>(acc[i], dv, ny, W * lam[i], d0, gr.dmax, G.h, G.alpha, Q);
+            }
         });
     }
     double* out = table + gr.toff;
     for (int dd = 0; dd <= DMAX && d0 + dd <= gr.dmax; ++dd)
-        out[((int64_t)(d0 + dd) * gr.usize + u) * nX + r] = acc[dd];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) out[((int64_t)(d0 + dd) * gr.usize + NC * u + i) * nX + r] = acc[i][dd];
 }
 
 struct TouchDev { int group, r, u, nshared; };
 
 // Touching panel pairs: identical (all d), common edge / vertex (d = 0, 1).
-template <bool K, int DMAX>
+template <bool K, int DMAX, int NC = 1>
 __global__ void k_near_singular(double* __restrict__ table, const GroupDev* __restrict__ groups,
                                 const TouchDev* __restrict__ touch, int n_touch, const int* __restrict__ upos,
                                 NearGeom G, QuadRules Q, int d0) {
@@ -653,17 +709,26 @@ __global__ void k_near_singular(double* __restrict__ table, const GroupDev* __re
     const int jx = G.inv_sigma[upos[gr.uoff + tp.u]];
     const int dlast = (tp.nshared == 3) ? gr.dmax : min(1, gr.dmax);
     if (d0 > dlast) return;
-    double acc[DMAX + 1];
+    double acc[NC][DMAX + 1];
 #pragma unroll
-    for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0;
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int d = 0; d <= DMAX; ++d) acc[c][d] = 0.0;
     const double* ny = G.normal + 3 * jx;
     if (!(K && coplanar(G, kx, jx)))
-        singular_points(G, Q, kx, jx, tp.nshared, [&](const double* dv, double W) {
-            accumulate_point<K, DMAX>(acc, dv, ny, W, d0, dlast, G.h, G.alpha, Q);
+        singular_points(G, Q, kx, jx, tp.nshared, [&](const double* dv, double W, const double* lam) {
+            if constexpr (NC == 1) {
+                accumulate_point<K, DMAX>(acc[0], dv, ny, W, d0, dlast, G.h, G.alpha, Q);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    accumulate_point<K, DMAX>(acc[c], dv, ny, W * lam[c], d0, dlast, G.h, G.alpha, Q);
+            }
         });
     double* out = table + gr.toff;
     for (int dd = 0; dd <= DMAX && d0 + dd <= dlast; ++dd)
-        out[((int64_t)(d0 + dd) * gr.usize + tp.u) * nX + tp.r] = acc[dd];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[((int64_t)(d0 + dd) * gr.usize + NC * tp.u + c) * nX + tp.r] = acc[c][dd];
 }
 
 struct NearLayout {
@@ -683,6 +748,8 @@ struct NearLayout {
     const int* set_pos;
     int E_x;
     int64_t n_rows;
+    int E_src;               // stride of a source step in the density vector
+                             // (E_x; 3 E_x for the p1 double layer's local values)
 };
 
 // Expand the distinct-integral table into the causal block storage:
@@ -728,7 +795,7 @@ __global__ void __launch_bounds__(256) k_near_expand(double* __restrict__ B, con
 // identical panel at every lag and for panels sharing an edge or a vertex at
 // lags 0 and 1) and the time factor of the step pair.  One wave per row
 // group, lanes over (column slot, row) as in k_near_expand.
-template <bool K>
+template <bool K, int NC = 1>
 __global__ void __launch_bounds__(256) k_near_direct(double* __restrict__ B, const double* __restrict__ tn,
                                                      NearLayout L, NearGeom G, QuadRules Q) {
     const int64_t rg = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -753,15 +820,18 @@ __global__ void __launch_bounds__(256) k_near_direct(double* __restrict__ B, con
         int jt = j0, i = cs;
         while (i >= S) { i -= S; ++jt; }
         for (int64_t c = cs; c < total; c += cpi) {
-            const int jx = G.inv_sigma[pos[i]];
+            // column (jt, source position, local vertex) for NC = 3
+            const int jx = G.inv_sigma[pos[i] / NC];
+            const int iv = pos[i] % NC;
             const int d = kt - jt;
             const double tj0 = tn[jt], tj1 = tn[jt + 1];
             double acc = 0.0;
             if (!(K && coplanar(G, kx, jx))) {
                 const double* ny = G.normal + 3 * jx;
-                auto point = [&](const double* dv, double W) {
+                auto point = [&](const double* dv, double W, const double* lam) {
                     const double rr = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-                    const double fac = K ? W * (dv[0] * ny[0] + dv[1] * ny[1] + dv[2] * ny[2]) : W;
+                    double fac = K ? W * (dv[0] * ny[0] + dv[1] * ny[1] + dv[2] * ny[2]) : W;
+                    if constexpr (NC == 3) fac *= lam[iv];
                     acc += fac * time_factor_pair<K>(rr, tk0, tk1, tj0, tj1, d, G.alpha, Q);
                 };
                 int nsh = 0;
@@ -831,6 +901,9 @@ struct DevLevel {
     int64_t* ax_off = nullptr;
     int* tb = nullptr;
     int* te = nullptr;
+    int* tb3 = nullptr;           // 3 tb, 3 te and 3 ax_off: rows of the p1 double layer's S2M
+    int* te3 = nullptr;
+    int64_t* ax_off3 = nullptr;
     int* parent = nullptr;
     int* par_xs = nullptr;        // slots with children (non-leaf)
     int* ch_ptr = nullptr;
@@ -912,6 +985,18 @@ struct pfmm_tree {
     int* umap = nullptr;
     NearOp opV, opK;
     bool hasV = false, hasK = false;
+    // the double layer with p1 trial functions: expanded nearfield layout
+    // (three columns per source triangle), its groups and position map, the
+    // local values per (step, triangle position, vertex) in tree order, and
+    // the S2M table with three rows per triangle
+    NearLayout nl3{};
+    GroupDev* groups3 = nullptr;
+    int* umap3 = nullptr;
+    NearOp opK1;
+    bool hasK1 = false;
+    double* wd3 = nullptr;
+    double* AxK1 = nullptr;
+    int n_verts = 0;
     NearGeom geom{};              // mesh on the device (natural order)
     double* tnodes_dev = nullptr; // time nodes on the device
     bool geom_ok = false;
@@ -992,6 +1077,9 @@ uint64_t estimate_bytes(const Plan& P, const FarTables& F, int ops_mask, int pre
     }
     int nop = ((ops_mask & PFMM_OP_V) ? 1 : 0) + ((ops_mask & PFMM_OP_K) ? 1 : 0);
     b += (uint64_t)nop * ((nf_mode == PFMM_NF_STORED ? (uint64_t)P.near_entries * 8 : 0) + (uint64_t)P.table_size * 8);
+    if (ops_mask & PFMM_OP_K1)   // three columns per source triangle; local values; the S2M rows
+        b += (uint64_t)(P.p1.near_entries + P.p1.table_size + 3 * N) * 8 + P.p1.umap.size() * 4 +
+             P.p1.set_pos.size() * 4 + F.AxK1.size() * 8;
     if (nf_mode == PFMM_NF_TOEPLITZ) b += P.rects.size() * 8 + P.set_pos.size() * 4;
     b += P.umap.size() * 4 + P.set_pos.size() * 4 + P.upos.size() * 4;
     b += (F.At.size() + F.Ax.size() + F.AxK.size() + F.qt.size() + F.qx.size() + 4 * F.E1.size()) * 8;
@@ -1022,11 +1110,18 @@ pfmm_status upload_geometry(pfmm_tree* t) {
     return PFMM_OK;
 }
 
-pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
+// Nearfield entries of one operator: kind 0 V_h, 1 K_h (p0 trial
+// functions), 2 K_h with p1 trial functions (three table columns and block
+// columns per source triangle: its local vertices).
+pfmm_status assemble_near(pfmm_tree* t, int kind, NearOp& op, hipStream_t st) {
     Plan& P = t->P;
+    const bool K = kind >= 1, p1 = kind == 2;
     const bool stored = t->nf_mode == PFMM_NF_STORED;
-    PF_TRY(dalloc(t, &op.table, (size_t)P.table_size));
-    if (stored) PF_TRY(dalloc(t, &op.B, (size_t)P.near_entries));
+    PF_TRY(dalloc(t, &op.table, (size_t)(p1 ? P.p1.table_size : P.table_size)));
+    if (stored) PF_TRY(dalloc(t, &op.B, (size_t)(p1 ? P.p1.near_entries : P.near_entries)));
+    const GroupDev* groups = p1 ? t->groups3 : t->groups;
+    const int* umap = p1 ? t->umap3 : t->umap;
+    const NearLayout& NL = p1 ? t->nl3 : t->nl;
     // quadrature rules
     QuadRules Q{};
     std::vector<double> g, w;
@@ -1046,11 +1141,11 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
         // steps of different lengths: stored blocks only (the planner refuses
         // the Toeplitz mode), each entry integrated on its own
         const int64_t nrg = (int64_t)P.rows.size();
+        const dim3 grid((unsigned)((nrg + 3) / 4));
         if (nrg > 0) {
-            if (K) hipLaunchKernelGGL(k_near_direct<true>, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, op.B,
-                                      t->tnodes_dev, t->nl, G, Q);
-            else hipLaunchKernelGGL(k_near_direct<false>, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, op.B,
-                                    t->tnodes_dev, t->nl, G, Q);
+            if (p1) hipLaunchKernelGGL((k_near_direct<true, 3>), grid, dim3(256), 0, st, op.B, t->tnodes_dev, NL, G, Q);
+            else if (K) hipLaunchKernelGGL(k_near_direct<true>, grid, dim3(256), 0, st, op.B, t->tnodes_dev, NL, G, Q);
+            else hipLaunchKernelGGL(k_near_direct<false>, grid, dim3(256), 0, st, op.B, t->tnodes_dev, NL, G, Q);
             HIP_TRY(hipGetLastError());
         }
         return PFMM_OK;
@@ -1071,15 +1166,18 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
     int64_t* d_bb;
     PF_TRY(upload(t, &d_bg, bg.data(), bg.size()));
     PF_TRY(upload(t, &d_bb, bb.data(), bb.size()));
-    // time offsets 0..dmax in passes of at most 32 (d0 = 0, 32, ...)
-    const int dc = dmax_class(dmx);
-#define LAUNCH_REG(KK, DD) hipLaunchKernelGGL((k_near_regular<KK, DD>), dim3((unsigned)bg.size()), dim3(256), 0, st, \
-                                              op.table, t->groups, d_bg, d_bb, upos, G, Q, d0)
+    // time offsets 0..dmax in passes of at most 32 (d0 = 0, 32, ...); the
+    // three-column kernels in passes of 8
+    const int dc = p1 ? 7 : dmax_class(dmx);
+#define LAUNCH_REG(KK, DD, NC) hipLaunchKernelGGL((k_near_regular<KK, DD, NC>), dim3((unsigned)bg.size()), dim3(256), \
+                                                  0, st, op.table, groups, d_bg, d_bb, upos, G, Q, d0)
     for (int d0 = 0; d0 <= dmx && !bg.empty(); d0 += dc + 1) {
-        if (K) {
-            if (dc == 7) LAUNCH_REG(true, 7); else if (dc == 15) LAUNCH_REG(true, 15); else LAUNCH_REG(true, 31);
+        if (p1) {
+            LAUNCH_REG(true, 7, 3);
+        } else if (K) {
+            if (dc == 7) LAUNCH_REG(true, 7, 1); else if (dc == 15) LAUNCH_REG(true, 15, 1); else LAUNCH_REG(true, 31, 1);
         } else {
-            if (dc == 7) LAUNCH_REG(false, 7); else if (dc == 15) LAUNCH_REG(false, 15); else LAUNCH_REG(false, 31);
+            if (dc == 7) LAUNCH_REG(false, 7, 1); else if (dc == 15) LAUNCH_REG(false, 15, 1); else LAUNCH_REG(false, 31, 1);
         }
         HIP_TRY(hipGetLastError());
     }
@@ -1087,13 +1185,15 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
     TouchDev* d_touch;
     PF_TRY(upload(t, (TouchPair**)&d_touch, P.touch.data(), P.touch.size()));
     const int nT = (int)P.touch.size();
-#define LAUNCH_SING(KK, DD) hipLaunchKernelGGL((k_near_singular<KK, DD>), dim3((nT + 63) / 64), dim3(64), 0, st, \
-                                               op.table, t->groups, d_touch, nT, upos, G, Q, d0)
+#define LAUNCH_SING(KK, DD, NC) hipLaunchKernelGGL((k_near_singular<KK, DD, NC>), dim3((nT + 63) / 64), dim3(64), 0, \
+                                                   st, op.table, groups, d_touch, nT, upos, G, Q, d0)
     for (int d0 = 0; d0 <= dmx && nT > 0; d0 += dc + 1) {
-        if (K) {
-            if (dc == 7) LAUNCH_SING(true, 7); else if (dc == 15) LAUNCH_SING(true, 15); else LAUNCH_SING(true, 31);
+        if (p1) {
+            LAUNCH_SING(true, 7, 3);
+        } else if (K) {
+            if (dc == 7) LAUNCH_SING(true, 7, 1); else if (dc == 15) LAUNCH_SING(true, 15, 1); else LAUNCH_SING(true, 31, 1);
         } else {
-            if (dc == 7) LAUNCH_SING(false, 7); else if (dc == 15) LAUNCH_SING(false, 15); else LAUNCH_SING(false, 31);
+            if (dc == 7) LAUNCH_SING(false, 7, 1); else if (dc == 15) LAUNCH_SING(false, 15, 1); else LAUNCH_SING(false, 31, 1);
         }
         HIP_TRY(hipGetLastError());
     }
@@ -1101,8 +1201,8 @@ pfmm_status assemble_near(pfmm_tree* t, bool K, NearOp& op, hipStream_t st) {
     // expand into the causal blocks
     const int64_t nrg = (int64_t)P.rows.size();
     if (stored && nrg > 0) {
-        hipLaunchKernelGGL(k_near_expand, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, op.B, op.table, t->groups,
-                           t->umap, t->nl);
+        hipLaunchKernelGGL(k_near_expand, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, st, op.B, op.table, groups,
+                           umap, NL);
         HIP_TRY(hipGetLastError());
     }
     return PFMM_OK;
@@ -1439,6 +1539,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
     PF_TRY(upload(t, &t->At, F.At.data(), F.At.size()));
     PF_TRY(upload(t, &t->Ax, F.Ax.data(), F.Ax.size()));
     PF_TRY(upload(t, &t->AxK, F.AxK.data(), F.AxK.size()));
+    if (ops_mask & PFMM_OP_K1) PF_TRY(upload(t, &t->AxK1, F.AxK1.data(), F.AxK1.size()));
     PF_TRY(upload(t, &t->qt, F.qt.data(), F.qt.size()));
     PF_TRY(upload(t, &t->qx, F.qx.data(), F.qx.size()));
     PF_TRY(upload(t, &t->chunk_cols, F.chunk_cols.data(), F.chunk_cols.size()));
@@ -1807,6 +1908,16 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         PF_TRY(upload(t, &D.ax_off, FL.ax_off.data(), FL.ax_off.size()));
         PF_TRY(upload(t, &D.tb, L.tb.data(), L.tb.size()));
         PF_TRY(upload(t, &D.te, L.te.data(), L.te.size()));
+        if (ops_mask & PFMM_OP_K1) {
+            std::vector<int> tb3(L.tb), te3(L.te);
+            std::vector<int64_t> ao3(FL.ax_off);
+            for (auto& x : tb3) x *= 3;
+            for (auto& x : te3) x *= 3;
+            for (auto& x : ao3) x *= 3;
+            PF_TRY(upload(t, &D.tb3, tb3.data(), tb3.size()));
+            PF_TRY(upload(t, &D.te3, te3.data(), te3.size()));
+            PF_TRY(upload(t, &D.ax_off3, ao3.data(), ao3.size()));
+        }
         PF_TRY(upload(t, &D.parent, L.parent.data(), L.parent.size()));
         std::vector<int> par;
         for (int xs = 0; xs < L.nx(); ++xs)
@@ -1864,7 +1975,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         PF_TRY(upload(t, &a12, P.set_off.data(), P.set_off.size()));
         PF_TRY(upload(t, &a13, P.set_size.data(), P.set_size.size()));
         PF_TRY(upload(t, &a14, P.set_pos.data(), P.set_pos.size()));
-        NL = NearLayout{a1, a2, a3, a4, a5, a6, a7, a8, a9, a10, a11, a12, a13, a14, P.E_x, (int64_t)P.rows.size()};
+        NL = NearLayout{a1, a2, a3, a4, a5, a6, a7, a8, a9, a10, a11, a12, a13, a14, P.E_x, (int64_t)P.rows.size(), P.E_x};
         std::vector<GroupDev> gd(P.groups.size());
         for (size_t i = 0; i < P.groups.size(); ++i) {
             const AsmGroup& A = P.groups[i];
@@ -1872,6 +1983,34 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         }
         PF_TRY(upload(t, &t->groups, gd.data(), gd.size()));
         PF_TRY(upload(t, &t->umap, P.umap.data(), P.umap.size()));
+        if (ops_mask & PFMM_OP_K1) {
+            // the p1 double layer: the same row groups, leaves and rectangles
+            // over expanded source sets (position 3 p + i: local vertex i)
+            const Plan::P1Layout& L3 = P.p1;
+            for (size_t i = 0; i < P.rects.size(); ++i)
+                if ((int64_t)(j1[i] - j0[i]) * L3.set_size[rs[i]] > (int64_t)INT32_MAX)
+                    return fail(PFMM_EUNSUPPORTED, "a nearfield rectangle has more than 2^31 - 1 columns");
+            int64_t* b3;
+            int *o3, *z3, *p3;
+            PF_TRY(upload(t, &b3, L3.boff.data(), L3.boff.size()));
+            PF_TRY(upload(t, &o3, L3.set_off.data(), L3.set_off.size()));
+            PF_TRY(upload(t, &z3, L3.set_size.data(), L3.set_size.size()));
+            PF_TRY(upload(t, &p3, L3.set_pos.data(), L3.set_pos.size()));
+            t->nl3 = NL;
+            t->nl3.rg_boff = b3;
+            t->nl3.set_off = o3;
+            t->nl3.set_size = z3;
+            t->nl3.set_pos = p3;
+            t->nl3.E_src = 3 * P.E_x;
+            std::vector<GroupDev> g3(P.groups.size());
+            for (size_t i = 0; i < P.groups.size(); ++i) {
+                const AsmGroup& A = P.groups[i];
+                g3[i] = GroupDev{A.tb, A.te, A.dmax, 3 * A.usize, A.uoff, L3.toff[i], (int64_t)i * 3 * P.E_x};
+            }
+            PF_TRY(upload(t, &t->groups3, g3.data(), g3.size()));
+            PF_TRY(upload(t, &t->umap3, L3.umap.data(), L3.umap.size()));
+            PF_TRY(dalloc(t, &t->wd3, (size_t)3 * N));
+        }
         if (t->nf_mode == PFMM_NF_TOEPLITZ) {
             // per leaf rectangle: the table column u of every source triangle
             // (one list per distinct (group, set) pair)
@@ -1896,8 +2035,9 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             PF_TRY(plan_near_gemm(t));
         }
     }
-    if (ops_mask & PFMM_OP_V) { PF_TRY(assemble_near(t, false, t->opV, st)); t->hasV = true; }
-    if (ops_mask & PFMM_OP_K) { PF_TRY(assemble_near(t, true, t->opK, st)); t->hasK = true; }
+    if (ops_mask & PFMM_OP_V) { PF_TRY(assemble_near(t, 0, t->opV, st)); t->hasV = true; }
+    if (ops_mask & PFMM_OP_K) { PF_TRY(assemble_near(t, 1, t->opK, st)); t->hasK = true; }
+    if (ops_mask & PFMM_OP_K1) { PF_TRY(assemble_near(t, 2, t->opK1, st)); t->hasK1 = true; }
     HIP_TRY(hipStreamSynchronize(st));
     return PFMM_OK;
 }
@@ -2038,14 +2178,21 @@ void m2l_level(pfmm_tree* t, int l, hipStream_t st) {
 // moments converted, locals zeroed); phase 2: L2L, L2T and the final
 // permutation.  Between phases 1 and 2 a batch runs the class-aware M2L of
 // all its trees in one launch per time offset.
-pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t st, int phase = 0) {
+// kind: 0 V_h, 1 K_h, 2 K_h with p1 trial functions (w: vertex values,
+// n_steps x n_vertices).
+pfmm_status apply(pfmm_tree* t, int kind, const double* w, double* f, hipStream_t st, int phase = 0) {
     Plan& P = t->P;
+    const bool K = kind >= 1, p1 = kind == 2;
     const int64_t N = (int64_t)P.E_t * P.E_x;
     const unsigned nb = (unsigned)((N + 255) / 256);
     int ev;
     if (phase != 2) {
         prof_begin(t, 0, st, ev);
-        hipLaunchKernelGGL(k_permute_in, dim3(nb), dim3(256), 0, st, w, t->wd, t->inv_sigma, P.E_x, N);
+        if (p1)
+            hipLaunchKernelGGL(k_gather_p1, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, st, w, t->wd3,
+                               t->inv_sigma, t->geom.tris, t->n_verts, P.E_x, 3 * N);
+        else
+            hipLaunchKernelGGL(k_permute_in, dim3(nb), dim3(256), 0, st, w, t->wd, t->inv_sigma, P.E_x, N);
         prof_end(t, st, ev);
     }
     // The nearfield product needs only the permuted densities: in Toeplitz
@@ -2083,6 +2230,9 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
                 hipLaunchKernelGGL(k_near_toep, dim3((unsigned)((t->n_sel + 3) / 4)), dim3(256), 0, sn, tab, t->groups,
                                    t->ru_off, t->ru, t->wd, t->fn, t->nl, (const int*)t->nsel, t->n_sel);
         }
+        else if (nrg > 0 && p1)
+            hipLaunchKernelGGL(k_near_apply, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, sn, t->opK1.B, t->wd3,
+                               t->fn, t->nl3);
         else if (nrg > 0)
             hipLaunchKernelGGL(k_near_apply, dim3((unsigned)((nrg + 3) / 4)), dim3(256), 0, sn,
                                K ? t->opK.B : t->opV.B, t->wd, t->fn, t->nl);
@@ -2108,9 +2258,14 @@ pfmm_status apply(pfmm_tree* t, bool K, const double* w, double* f, hipStream_t 
             if (D.n_leafx == 0) continue;
             const int KI = t->ki_s2m, nt1 = P.m_t + 1;
             const size_t shm = ((size_t)nt1 * 64 * KI + (t->stage_s2m ? 64 * (size_t)P.Nk : 0)) * sizeof(double);
-            hipLaunchKernelGGL(k_s2m_blk, dim3(D.n_leafx, (D.n_int + KI - 1) / KI), dim3(256), shm, st, t->wd, D.mu,
-                               D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, K ? t->AxK : t->Ax, t->sm, D.n_int,
-                               D.ist, D.ilen, D.lflag, P.E_x, KI, t->stage_s2m);
+            if (p1)   // three rows per triangle: its local vertices
+                hipLaunchKernelGGL(k_s2m_blk, dim3(D.n_leafx, (D.n_int + KI - 1) / KI), dim3(256), shm, st, t->wd3,
+                                   D.mu, D.leaf_xs, D.ax_off3, D.tb3, D.te3, t->At + D.at_off, t->AxK1, t->sm,
+                                   D.n_int, D.ist, D.ilen, D.lflag, 3 * P.E_x, KI, t->stage_s2m);
+            else
+                hipLaunchKernelGGL(k_s2m_blk, dim3(D.n_leafx, (D.n_int + KI - 1) / KI), dim3(256), shm, st, t->wd,
+                                   D.mu, D.leaf_xs, D.ax_off, D.tb, D.te, t->At + D.at_off, K ? t->AxK : t->Ax,
+                                   t->sm, D.n_int, D.ist, D.ilen, D.lflag, P.E_x, KI, t->stage_s2m);
         }
         prof_end(t, st, ev);
         // M2M, levels p-1 .. 2
@@ -2362,6 +2517,7 @@ void fill_stats(const Plan& P, uint64_t bytes, pfmm_stats* out, int m2l_mfma) {
     out->near_entries_V = 0;                          // set by the caller for a built tree
     out->near_entries_K = 0;
     out->near_nonzero_K = P.near_nonzero_K;
+    out->near_entries_K1 = P.p1.built ? P.p1.near_entries : 0;
 }
 
 }  // namespace
@@ -2390,11 +2546,16 @@ pfmm_status tree_near_diag(pfmm_tree* t, double* d_dev, hipStream_t st) {
     HIP_TRY(hipGetLastError());
     return PFMM_OK;
 }
-bool tree_has(const pfmm_tree* t, int op) { return op == PFMM_OP_V ? t->hasV : (op == PFMM_OP_K ? t->hasK : false); }
+bool tree_has(const pfmm_tree* t, int op) {
+    return op == PFMM_OP_V ? t->hasV : (op == PFMM_OP_K ? t->hasK : (op == PFMM_OP_K1 ? t->hasK1 : false));
+}
 const double* tree_area(const pfmm_tree* t) { return t->mass; }
 const double* tree_steps(const pfmm_tree* t) { return t->hstep; }
 bool tree_uniform_steps(const pfmm_tree* t) { return t->P.uniform_steps; }
 pfmm_status tree_apply(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st) { return apply(t, K, x, y, st); }
+pfmm_status tree_apply_p1(pfmm_tree* t, const double* x, double* y, hipStream_t st) { return apply(t, 2, x, y, st); }
+int tree_vertices(const pfmm_tree* t) { return t->n_verts; }
+const int* tree_tris(const pfmm_tree* t) { return t->geom.tris; }
 pfmm_status tree_apply_phase(pfmm_tree* t, bool K, const double* x, double* y, hipStream_t st, int phase) {
     return apply(t, K, x, y, st, phase);
 }
@@ -2529,7 +2690,9 @@ pfmm_status pfmm_plan_stats(const double* vertices, int64_t n_vertices, const in
         pfmm_status s = build_plan(vertices, n_vertices, triangles, n_triangles, time_nodes, n_steps, prm, P, msg);
         if (s != PFMM_OK) return fail(s, msg);
         FarTables F;
-        build_far_tables(P, F);
+        const bool p1 = (prm.operators & PFMM_OP_K1) != 0;
+        build_far_tables(P, F, p1);
+        if (p1) build_p1_layout(P);
         fill_stats(P, estimate_bytes(P, F, prm.operators, prm.precision, prm.nearfield_mode), out, -1);
     } catch (const std::bad_alloc&) {
         return fail(PFMM_ENOMEM, "host allocation failed while planning");
@@ -2561,7 +2724,10 @@ pfmm_status pfmm_build_tree(const double* vertices, int64_t n_vertices, const in
         std::string msg;
         pfmm_status s = build_plan(vertices, n_vertices, triangles, n_triangles, time_nodes, n_steps, prm, t->P, msg);
         if (s != PFMM_OK) return fail(s, msg);
-        build_far_tables(t->P, t->F);
+        const bool p1 = (prm.operators & PFMM_OP_K1) != 0;
+        build_far_tables(t->P, t->F, p1);
+        if (p1) build_p1_layout(t->P);
+        t->n_verts = t->P.n_vert;
     } catch (const std::bad_alloc&) {
         return fail(PFMM_ENOMEM, "host allocation failed while planning");
     }
@@ -2600,6 +2766,13 @@ pfmm_status pfmm_apply_K(pfmm_tree* t, const double* u_dev, double* f_dev, void*
     return apply(t, true, u_dev, f_dev, as_stream(stream));
 }
 
+pfmm_status pfmm_apply_K1(pfmm_tree* t, const double* u_dev, double* f_dev, void* stream) {
+    if (!t || !u_dev || !f_dev) return fail(PFMM_EINVAL, "NULL argument");
+    if (!t->hasK1) return fail(PFMM_EINVAL, "the p1 double layer was not built for this tree");
+    if (hipSetDevice(t->device) != hipSuccess) return fail(PFMM_EDEVICE, "hipSetDevice failed");
+    return apply(t, 2, u_dev, f_dev, as_stream(stream));
+}
+
 pfmm_status pfmm_set_precision(pfmm_tree* t, int32_t precision) {
     if (!t) return fail(PFMM_EINVAL, "NULL tree");
     if (precision == PFMM_FP64) { t->prec = PFMM_FP64; return PFMM_OK; }
@@ -2629,6 +2802,7 @@ pfmm_status pfmm_tree_stats(const pfmm_tree* t, pfmm_stats* out) {
     const bool stored = t->nf_mode == PFMM_NF_STORED;
     out->near_entries_V = t->hasV && stored ? t->P.near_entries : 0;
     out->near_entries_K = t->hasK && stored ? t->P.near_entries : 0;
+    out->near_entries_K1 = t->hasK1 ? t->P.p1.near_entries : 0;
     return PFMM_OK;
 }
 

@@ -102,7 +102,11 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         msg = "unknown precision";
         return PFMM_EINVAL;
     }
-    if (p.operators & ~(PFMM_OP_V | PFMM_OP_K)) { msg = "unknown operator bits"; return PFMM_EINVAL; }
+    if (p.operators & ~(PFMM_OP_V | PFMM_OP_K | PFMM_OP_K1)) { msg = "unknown operator bits"; return PFMM_EINVAL; }
+    if ((p.operators & PFMM_OP_K1) && p.nearfield_mode == PFMM_NF_TOEPLITZ) {
+        msg = "the p1 double layer needs the stored nearfield";
+        return PFMM_EUNSUPPORTED;
+    }
     if (p.nearfield_mode != PFMM_NF_STORED && p.nearfield_mode != PFMM_NF_TOEPLITZ) {
         msg = "unknown nearfield mode";
         return PFMM_EINVAL;
@@ -684,6 +688,37 @@ pfmm_status build_plan(const double* V, int64_t nv, const int32_t* Tr, int64_t n
         std::stable_sort(P.touch.begin(), P.touch.end(), [](const TouchPair& a, const TouchPair& b) { return a.nshared > b.nshared; });
     }
     return PFMM_OK;
+}
+
+void build_p1_layout(Plan& P) {
+    Plan::P1Layout& L = P.p1;
+    L = Plan::P1Layout();
+    L.built = true;
+    for (size_t st = 0; st < P.set_off.size(); ++st) {
+        L.set_off.push_back((int)L.set_pos.size());
+        L.set_size.push_back(3 * P.set_size[st]);
+        for (int i = 0; i < P.set_size[st]; ++i)
+            for (int c = 0; c < 3; ++c) L.set_pos.push_back(3 * P.set_pos[P.set_off[st] + i] + c);
+    }
+    int64_t boff = 0;
+    for (const RowGroup& R : P.rows) {
+        L.boff.push_back(boff);
+        boff += 3 * R.ncols * (P.leaves[R.leaf].te - P.leaves[R.leaf].tb);
+    }
+    L.near_entries = boff;
+    int64_t toff = 0;
+    for (const AsmGroup& G : P.groups) {
+        L.toff.push_back(toff);
+        if (P.uniform_steps) toff += (int64_t)(G.dmax + 1) * (G.te - G.tb) * 3 * G.usize;
+    }
+    L.table_size = toff;
+    L.umap.assign(P.groups.size() * (size_t)3 * P.E_x, -1);
+    for (size_t g = 0; g < P.groups.size(); ++g) {
+        const AsmGroup& G = P.groups[g];
+        for (int i = 0; i < G.usize; ++i)
+            for (int c = 0; c < 3; ++c)
+                L.umap[g * (size_t)3 * P.E_x + 3 * P.upos[G.uoff + i] + c] = 3 * i + c;
+    }
 }
 
 }  // namespace pfmm

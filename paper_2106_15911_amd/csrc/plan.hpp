@@ -122,6 +122,21 @@ struct Plan {
     std::vector<TouchPair> touch;
     int64_t table_size = 0;                      // doubles of all distinct tables
 
+    // nearfield of the double layer with p1 trial functions (Section 2):
+    // every source triangle position p contributes three columns 3 p + i
+    // (its local vertices i); expanded source sets, block offsets per row
+    // group, and per assembly group the expanded table (usize3 = 3 usize
+    // columns) and position map (3 E_x entries per group)
+    struct P1Layout {
+        bool built = false;
+        std::vector<int> set_off, set_size, set_pos;   // expanded sets
+        std::vector<int64_t> boff;                     // per row group
+        int64_t near_entries = 0;
+        std::vector<int64_t> toff;                     // per assembly group
+        int64_t table_size = 0;
+        std::vector<int> umap;                         // groups x 3 E_x
+    } p1;
+
     // farfield levels (>= 2 and <= depth)
     int far_lo = 2;
     bool has_far = false;
@@ -132,6 +147,9 @@ struct Plan {
 pfmm_status build_plan(const double* V, int64_t nv, const int32_t* T, int64_t nt,
                        const double* tn, int64_t E_t, const pfmm_params& p,
                        Plan& P, std::string& msg);
+
+// Fill P.p1 from the p0 nearfield layout (call after build_plan).
+void build_p1_layout(Plan& P);
 
 // Gauss-Legendre nodes/weights on [0, 1] (Newton iteration on P_n).
 void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);

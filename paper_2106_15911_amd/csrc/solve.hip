@@ -116,6 +116,20 @@ __global__ void __launch_bounds__(kBlock) k_half_mass(const double* __restrict__
     if (i < n) b[i] += 0.5 * (area[i % ex] * hstep[i / ex]) * g[i];
 }
 
+// b[kt E_x + kx] += 1/2 (M_h g): the mixed p0 x p1 mass, (t_{kt+1} - t_kt)
+// |gamma_kx| / 3 times the sum of g over the three vertices of kx.
+__global__ void __launch_bounds__(kBlock) k_half_mass_p1(const double* __restrict__ g, const double* __restrict__ area,
+                                                          const double* __restrict__ hstep, const int* __restrict__ tris,
+                                                          double* __restrict__ b, int64_t ex, int n_v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t kt = i / ex;
+    const int kx = (int)(i - kt * ex);
+    const double* gk = g + kt * n_v;
+    const double sg = gk[tris[3 * kx]] + gk[tris[3 * kx + 1]] + gk[tris[3 * kx + 2]];
+    b[i] += 0.5 * (area[kx] * hstep[kt] / 3.0) * sg;
+}
+
 // b[i] -= a[i]
 __global__ void __launch_bounds__(kBlock) k_sub(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -548,12 +562,15 @@ pfmm_status check_opts(const pfmm_solve_opts* o, pfmm_solve_opts& out) {
     return PFMM_OK;
 }
 
+// dirichlet: 0 b given, 1 p0 datum g (b = (1/2 M_h + K_h) g), 2 p1 datum.
 pfmm_status solve_common(pfmm_tree* t, const double* b_or_g, double* w, const pfmm_solve_opts* o,
-                         pfmm_solve_info* info, void* stream, bool dirichlet) {
+                         pfmm_solve_info* info, void* stream, int dirichlet) {
     if (!t || !b_or_g || !w) return set_error(PFMM_EINVAL, "NULL argument");
     if (b_or_g == w) return set_error(PFMM_EINVAL, "the right-hand side and the solution must not alias");
     if (!tree_has(t, PFMM_OP_V)) return set_error(PFMM_EINVAL, "V_h was not built for this tree");
-    if (dirichlet && !tree_has(t, PFMM_OP_K)) return set_error(PFMM_EINVAL, "K_h was not built for this tree");
+    if (dirichlet == 1 && !tree_has(t, PFMM_OP_K)) return set_error(PFMM_EINVAL, "K_h was not built for this tree");
+    if (dirichlet == 2 && !tree_has(t, PFMM_OP_K1))
+        return set_error(PFMM_EINVAL, "the p1 double layer was not built for this tree");
     pfmm_solve_opts opt;
     PS_TRY(check_opts(o, opt));
     if (opt.x0_dev == b_or_g) return set_error(PFMM_EINVAL, "x0 must not alias the right-hand side");
@@ -588,7 +605,8 @@ pfmm_status solve_common(pfmm_tree* t, const double* b_or_g, double* w, const pf
     pfmm_status s = PFMM_OK;
     if (dirichlet) {
         s = ws.alloc(&ws.b, (size_t)n);
-        if (s == PFMM_OK) s = pfmm_dirichlet_rhs(t, b_or_g, ws.b, stream);
+        if (s == PFMM_OK)
+            s = dirichlet == 2 ? pfmm_dirichlet_rhs_p1(t, b_or_g, ws.b, stream) : pfmm_dirichlet_rhs(t, b_or_g, ws.b, stream);
         b = ws.b;
     }
     if (s == PFMM_OK) s = refine ? solve_ir(t, pc, opt.inner_precision, b, w, opt, info, st)
@@ -660,12 +678,30 @@ pfmm_status pfmm_dirichlet_rhs(pfmm_tree* t, const double* g_dev, double* b_dev,
 
 pfmm_status pfmm_solve_V(pfmm_tree* t, const double* b_dev, double* w_dev, const pfmm_solve_opts* o,
                          pfmm_solve_info* info, void* stream) {
-    return solve_common(t, b_dev, w_dev, o, info, stream, false);
+    return solve_common(t, b_dev, w_dev, o, info, stream, 0);
+}
+
+pfmm_status pfmm_dirichlet_rhs_p1(pfmm_tree* t, const double* g_dev, double* b_dev, void* stream) {
+    if (!t || !g_dev || !b_dev) return set_error(PFMM_EINVAL, "NULL argument");
+    if (!tree_has(t, PFMM_OP_K1)) return set_error(PFMM_EINVAL, "the p1 double layer was not built for this tree");
+    if (hipSetDevice(tree_device(t)) != hipSuccess) return set_error(PFMM_EDEVICE, "hipSetDevice failed");
+    const int64_t n = tree_dofs(t);
+    hipStream_t st = (hipStream_t)stream;
+    PS_TRY(tree_apply_p1(t, g_dev, b_dev, st));
+    hipLaunchKernelGGL(k_half_mass_p1, dim3(blocks_for(n)), dim3(kBlock), 0, st, g_dev, tree_area(t), tree_steps(t),
+                       tree_tris(t), b_dev, tree_triangles(t), tree_vertices(t), n);
+    HIP_CHECK(hipGetLastError());
+    return PFMM_OK;
+}
+
+pfmm_status pfmm_solve_dirichlet_p1(pfmm_tree* t, const double* g_dev, double* w_dev, const pfmm_solve_opts* o,
+                                    pfmm_solve_info* info, void* stream) {
+    return solve_common(t, g_dev, w_dev, o, info, stream, 2);
 }
 
 pfmm_status pfmm_solve_dirichlet(pfmm_tree* t, const double* g_dev, double* w_dev, const pfmm_solve_opts* o,
                                  pfmm_solve_info* info, void* stream) {
-    return solve_common(t, g_dev, w_dev, o, info, stream, true);
+    return solve_common(t, g_dev, w_dev, o, info, stream, 1);
 }
 
 pfmm_status pfmm_solve_V_precond(pfmm_tree* t, const pfmm_precond* pc, int32_t inner_precision, const double* b_dev,

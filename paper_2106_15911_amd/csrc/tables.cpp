@@ -42,7 +42,7 @@ double lam(int k) { return k == 0 ? 1.0 : 2.0; }
 
 }  // namespace
 
-void build_far_tables(const Plan& P, FarTables& F) {
+void build_far_tables(const Plan& P, FarTables& F, bool with_p1) {
     F = FarTables();
     const int mt = P.m_t, mx = P.m_x, nt1 = mt + 1, nx1 = mx + 1, Nk = P.Nk;
     const std::vector<double> xt = cheb_nodes(mt), xx = cheb_nodes(mx);
@@ -111,11 +111,12 @@ void build_far_tables(const Plan& P, FarTables& F) {
                     const double* B = &P.verts[3 * P.tris[3 * t + 1]];
                     const double* C = &P.verts[3 * P.tris[3 * t + 2]];
                     const double* n = &P.normal[3 * t];
-                    std::vector<double> rowV(Nk, 0.0), rowK(Nk, 0.0);
+                    std::vector<double> rowV(Nk, 0.0), rowK(Nk, 0.0), rowK1(3 * Nk, 0.0);
                     for (int i = 0; i < qx; ++i)
                         for (int jq = 0; jq < qx; ++jq) {
                             const double s = gx[i], tt = gx[i] * gx[jq];
                             const double wq = wx[i] * wx[jq] * gx[i] * 2.0 * P.area[t];
+                            const double lam[3] = {1.0 - s, s - tt, tt};   // barycentric coordinates
                             double Tj[3][40], dTj[3][40];
                             for (int d = 0; d < 3; ++d) {
                                 double y = A[d] + s * (B[d] - A[d]) + tt * (C[d] - B[d]);
@@ -127,13 +128,17 @@ void build_far_tables(const Plan& P, FarTables& F) {
                             for (int c = 0; c < Nk; ++c) {
                                 const int k1 = P.kidx_k[3 * c], k2 = P.kidx_k[3 * c + 1], k3 = P.kidx_k[3 * c + 2];
                                 rowV[c] += wq * Tj[0][k1] * Tj[1][k2] * Tj[2][k3];
-                                rowK[c] += wq * P.alpha * (n[0] * dTj[0][k1] * Tj[1][k2] * Tj[2][k3]
-                                                           + n[1] * Tj[0][k1] * dTj[1][k2] * Tj[2][k3]
-                                                           + n[2] * Tj[0][k1] * Tj[1][k2] * dTj[2][k3]);
+                                const double dk = wq * P.alpha * (n[0] * dTj[0][k1] * Tj[1][k2] * Tj[2][k3]
+                                                                  + n[1] * Tj[0][k1] * dTj[1][k2] * Tj[2][k3]
+                                                                  + n[2] * Tj[0][k1] * Tj[1][k2] * dTj[2][k3]);
+                                rowK[c] += dk;
+                                if (with_p1)
+                                    for (int v = 0; v < 3; ++v) rowK1[v * Nk + c] += lam[v] * dk;
                             }
                         }
                     F.Ax.insert(F.Ax.end(), rowV.begin(), rowV.end());
                     F.AxK.insert(F.AxK.end(), rowK.begin(), rowK.end());
+                    if (with_p1) F.AxK1.insert(F.AxK1.end(), rowK1.begin(), rowK1.end());
                 }
             }
         }

@@ -39,6 +39,10 @@ struct FarLevel {
 struct FarTables {
     std::vector<FarLevel> lv;           // indexed by level (entries < 2 unused)
     std::vector<double> At, Ax, AxK, qt, qx, E1, Cab;
+    // S2M of the double layer with p1 trial functions: three rows per
+    // triangle (local vertex i), alpha int lambda_i n.grad T_kappa; offsets
+    // 3 ax_off (built when requested)
+    std::vector<double> AxK1;
     // row chunks of the M2L operator (rows in coefficient order)
     int chunk = 32, n_chunks = 0;
     std::vector<int> chunk_cols;        // columns per chunk (staircase prefix)
@@ -46,6 +50,6 @@ struct FarTables {
     int64_t op_size = 0;                // doubles per operator (one class)
 };
 
-void build_far_tables(const Plan& P, FarTables& F);
+void build_far_tables(const Plan& P, FarTables& F, bool with_p1 = false);
 
 }  // namespace pfmm

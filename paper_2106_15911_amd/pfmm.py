@@ -16,7 +16,7 @@ _LIB = None
 STATUS_NAMES = {0: "PFMM_OK", -1: "PFMM_EINVAL", -2: "PFMM_ENOMEM", -3: "PFMM_EDEVICE",
                 -4: "PFMM_ENOTCONV", -5: "PFMM_ENONFINITE", -6: "PFMM_EUNSUPPORTED"}
 PROFILE_STAGES = ["permute", "s2m", "m2m", "m2l", "l2l", "l2t", "nearfield", "unpermute"]
-OP_V, OP_K = 1, 2
+OP_V, OP_K, OP_K1 = 1, 2, 4
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 NF_STORED, NF_TOEPLITZ = 0, 1
 
@@ -42,7 +42,7 @@ class Stats(ctypes.Structure):
                 ("device_bytes", ctypes.c_uint64), ("m2l_matrix_cores", ctypes.c_int32),
                 ("near_gemm_groups", ctypes.c_int32), ("n_time_classes", ctypes.c_int32),
                 ("near_entries_V", ctypes.c_int64), ("near_entries_K", ctypes.c_int64),
-                ("near_nonzero_K", ctypes.c_int64)]
+                ("near_nonzero_K", ctypes.c_int64), ("near_entries_K1", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -80,6 +80,9 @@ def load_library():
         "pfmm_build_tree": ([dp, I64, ip, I64, dp, I64, P(Params), I32, VP, P(VP)], I32),
         "pfmm_apply_V": ([VP, VP, VP, VP], I32),
         "pfmm_apply_K": ([VP, VP, VP, VP], I32),
+        "pfmm_apply_K1": ([VP, VP, VP, VP], I32),
+        "pfmm_dirichlet_rhs_p1": ([VP, VP, VP, VP], I32),
+        "pfmm_solve_dirichlet_p1": ([VP, VP, VP, P(SolveOpts), P(SolveInfo), VP], I32),
         "pfmm_tree_stats": ([VP, P(Stats)], I32),
         "pfmm_autotune": ([VP, ctypes.c_char_p, VP, P(I32), P(I32)], I32),
         "pfmm_representation": ([VP, VP, VP, VP, I64, I32, VP, VP], I32),
@@ -165,6 +168,7 @@ class Tree:
         self.lib = load_library()
         keep, args = _mesh_args(vertices, triangles, time_nodes)
         self.n_dofs = int(args[3]) * int(args[5])
+        self.n_vertex_dofs = int(args[1]) * int(args[5])    # p1 vectors: steps x vertices
         self.device = torch.device("cuda", device)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -172,13 +176,14 @@ class Tree:
                                             device, _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
 
-    def _apply(self, fn, x, out, stream):
+    def _apply(self, fn, x, out, stream, n_in=None):
         import torch
-        if x.dtype != torch.float64 or x.device != self.device or x.numel() != self.n_dofs:
-            raise ValueError(f"expected a float64 tensor of {self.n_dofs} entries on {self.device}")
+        n_in = self.n_dofs if n_in is None else n_in
+        if x.dtype != torch.float64 or x.device != self.device or x.numel() != n_in:
+            raise ValueError(f"expected a float64 tensor of {n_in} entries on {self.device}")
         x = x.contiguous()
         if out is None:
-            out = torch.empty_like(x)
+            out = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
         _check(fn(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
@@ -188,15 +193,23 @@ class Tree:
     def apply_K(self, u, out=None, stream=None):
         return self._apply(self.lib.pfmm_apply_K, u, out, stream)
 
+    def apply_K1(self, u, out=None, stream=None):
+        """The double layer with p1-continuous trial functions: u per (step, vertex), time-major."""
+        return self._apply(self.lib.pfmm_apply_K1, u, out, stream, n_in=self.n_vertex_dofs)
+
+    def dirichlet_rhs_p1(self, g, out=None, stream=None):
+        """(1/2 M_h + K_h) g for a p1 datum g (steps x vertices); needs OP_K1."""
+        return self._apply(self.lib.pfmm_dirichlet_rhs_p1, g, out, stream, n_in=self.n_vertex_dofs)
+
     def _solve(self, fn, rhs, out, rtol, max_iter, stream, raise_on_notconv, x0=None, precond=None,
-               precond_path=None, inner_precision=FP64):
+               precond_path=None, inner_precision=FP64, n_rhs=None):
         import torch
-        for v in (rhs, x0):
-            if v is not None and (v.dtype != torch.float64 or v.device != self.device or v.numel() != self.n_dofs
+        for v, n in ((rhs, self.n_dofs if n_rhs is None else n_rhs), (x0, self.n_dofs)):
+            if v is not None and (v.dtype != torch.float64 or v.device != self.device or v.numel() != n
                                   or not v.is_contiguous()):
-                raise ValueError(f"expected a contiguous float64 tensor of {self.n_dofs} entries on {self.device}")
+                raise ValueError(f"expected a contiguous float64 tensor of {n} entries on {self.device}")
         if out is None:
-            out = torch.empty_like(rhs)
+            out = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
         o = SolveOpts()
         _check(self.lib.pfmm_default_solve_opts(ctypes.byref(o)))
         o.rtol, o.max_iter, o.inner_precision = rtol, max_iter, int(inner_precision)
@@ -243,6 +256,12 @@ class Tree:
         """Solve V_h w = (1/2 M_h + K_h) g, options as solve_V; returns (w, info)."""
         return self._solve(self.lib.pfmm_solve_dirichlet, g, out, rtol, max_iter, stream, raise_on_notconv, x0,
                            precond, precond_path, inner_precision)
+
+    def solve_dirichlet_p1(self, g, out=None, rtol=1e-8, max_iter=200, stream=None, raise_on_notconv=True, x0=None,
+                           precond=None, precond_path=None, inner_precision=FP64):
+        """Solve V_h w = (1/2 M_h + K_h) g for a p1 datum g (steps x vertices); options as solve_V."""
+        return self._solve(self.lib.pfmm_solve_dirichlet_p1, g, out, rtol, max_iter, stream, raise_on_notconv, x0,
+                           precond, precond_path, inner_precision, n_rhs=self.n_vertex_dofs)
 
     def representation(self, w, u, xt, q=4, out=None, stream=None):
         """(V~ w - W u)(x_i, t_i) at the rows (x, y, z, t) of xt (float64 device tensor, M x 4);

@@ -119,6 +119,23 @@ def test_nonzero_K_count_matches_oracle():
     assert st["near_nonzero_K"] == nz == 1597440
 
 
+def test_p1_double_layer_planning():
+    """The p1 double layer stores three columns per source triangle (its
+    local vertices) in the stored-block layout of V_h; the Toeplitz mode
+    has no such layout and is refused."""
+    v, t = cube_surface_mesh(4)
+    tn = uniform_time_nodes(16)
+    st = P.plan_stats(v, t, tn, P.default_params(operators=P.OP_V | P.OP_K1, m_t=3, m_x=3))
+    assert st["near_entries_K1"] == 3 * st["near_entries"]
+    assert P.plan_stats(v, t, tn, P.default_params(m_t=3, m_x=3))["near_entries_K1"] == 0
+    with pytest.raises(P.PfmmError) as e:
+        P.plan_stats(v, t, tn, P.default_params(operators=P.OP_K1, nearfield_mode=P.NF_TOEPLITZ))
+    assert e.value.status == -6
+    with pytest.raises(P.PfmmError) as e:
+        P.plan_stats(v, t, tn, P.default_params(operators=8))
+    assert e.value.status == -1
+
+
 def test_error_codes():
     v, t = cube_surface_mesh(2)
     tn = uniform_time_nodes(8)

@@ -81,3 +81,39 @@ def project_source_flux(verts, tris, time_nodes, y_star, t_star=0.0, alpha=1.0, 
         vals = _heat(r2[None, :, :, None], s, alpha) * (-dn[None, :, :, None]) / (2.0 * np.where(s > 0, s, 1.0))
         out[j0:j1] = vals.reshape(j1 - j0, len(tris), -1) @ np.kron(w_tri, gtw)
     return out.ravel()
+
+
+def project_source_datum_p1(verts, tris, time_nodes, y_star, t_star=0.0, alpha=1.0, q=4, q_t=4):
+    """L2 projection of G(x - y*, t - t*) onto functions piecewise linear and
+    continuous in space (nodal hat functions phi_v) and piecewise constant in
+    time: per step, the p1 mass system sum_w (phi_v, phi_w) g_w = the step
+    mean of (G, phi_v).  Returns g per (step, vertex), time-major (length
+    E_t n_v)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    X, w_tri, T, gtw = _points(verts, tris, time_nodes, q, q_t)
+    nq = len(w_tri)
+    s = np.repeat(np.polynomial.legendre.leggauss(q)[0] * 0.5 + 0.5, q)
+    t = s * np.tile(np.polynomial.legendre.leggauss(q)[0] * 0.5 + 0.5, q)
+    lam = np.stack([1.0 - s, s - t, t])                      # barycentric coordinates of the points
+    P = verts[tris]
+    area = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+    nv, nt = len(verts), len(tris)
+    rows = np.repeat(tris, 3, axis=1).ravel()
+    cols = np.tile(tris, (1, 3)).ravel()
+    loc = np.array([[2.0, 1.0, 1.0], [1.0, 2.0, 1.0], [1.0, 1.0, 2.0]]) / 12.0
+    M = sp.csr_matrix(((area[:, None, None] * loc[None]).ravel(), (rows, cols)), shape=(nv, nv))
+    r2 = ((X - np.asarray(y_star, dtype=np.float64)) ** 2).sum(-1)
+    out = np.empty((len(T), nv))
+    lu = spla.splu(M.tocsc())
+    for j0, j1 in _time_chunks(len(T), r2.size * q_t):
+        vals = _heat(r2[None, :, :, None], (T[j0:j1] - t_star)[:, None, None, :], alpha) @ gtw   # (steps, E_x, nq)
+        # (G, phi_v) per step mean: sum over the triangles of |gamma| sum_q w_q G lambda_i
+        rhs = np.zeros((j1 - j0, nv))
+        for i in range(3):
+            contrib = (vals * (w_tri * lam[i])[None, None, :]).sum(-1) * area[None, :]          # (steps, E_x)
+            for k in range(j1 - j0):
+                np.add.at(rhs[k], tris[:, i], contrib[k])
+        for k in range(j1 - j0):
+            out[j0 + k] = lu.solve(rhs[k])
+    return out.ravel()
