@@ -1798,22 +1798,27 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             // columns of the class-aware M2L: the target intervals of each time
             // offset, sorted by class into sub-blocks of 16 of one class (the
             // last of a class padded with k = -1), NB sub-blocks to a column
-            // block; the moments are gathered into this column order before
-            // each launch, so a sub-block's B operand is one contiguous row
+            // block; a class's last block is filled up with empty sub-blocks
+            // (class -1, no loads or products) so that every block holds one
+            // class and a workgroup walks its sources once.  The moments are
+            // gathered into this column order before each launch, so a
+            // sub-block's B operand is one contiguous row
+            const int per = 16 * kClsNB;
             for (int Dt = 2; Dt <= 3; ++Dt) {
                 std::vector<std::pair<int, int>> cl;   // (class, k)
                 for (int k = 0; k < L.n_int; ++k)
                     if (L.cls[Dt - 2][k] >= 0) cl.emplace_back(L.cls[Dt - 2][k], k);
                 std::stable_sort(cl.begin(), cl.end());
                 std::vector<int2> cols;
+                auto close_class = [&](int c) {
+                    while (cols.size() % 16) cols.push_back(int2{-1, c});
+                    while (cols.size() % per) cols.push_back(int2{-1, -1});   // empty sub-blocks
+                };
                 for (size_t i = 0; i < cl.size(); ++i) {
-                    if (i > 0 && cl[i].first != cl[i - 1].first)
-                        while (cols.size() % 16) cols.push_back(int2{-1, cl[i - 1].first});
+                    if (i > 0 && cl[i].first != cl[i - 1].first) close_class(cl[i - 1].first);
                     cols.push_back(int2{cl[i].second, cl[i].first});
                 }
-                while (cols.size() % 16) cols.push_back(int2{-1, cl.back().first});
-                const int per = 16 * kClsNB;
-                while (cols.size() % per) cols.push_back(int2{-1, -1});   // empty sub-blocks
+                if (!cl.empty()) close_class(cl.back().first);
                 const int nblk = (int)(cols.size() / per);
                 std::vector<int2> br(nblk);
                 std::vector<int> perm(cols.size());
