@@ -232,11 +232,14 @@ __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ ta
     for (int nt = 0; nt < NT; ++nt) acc[nt] = d4_t{0.0, 0.0, 0.0, 0.0};
     const int kq = ((G.K + 15) / 16) * 4;                 // K values per wave, a multiple of 4
     const int kb = wv * kq, ke = min(G.K, kb + kq);
-    int d = (kb + lk) / G.U, u = (kb + lk) - ((kb + lk) / G.U) * G.U;   // (d, u) of this lane's k
-#pragma unroll 2
-    for (int k0 = kb; k0 < ke; k0 += 4) {
-        const int k = k0 + lk;
-        double a = 0.0, b[NT];
+    // Operands are fetched kPF K-steps ahead into a register ring (the
+    // density gather and the table row of a K-step do not depend on the
+    // products), so kPF gathers per lane are in flight while the matrix
+    // cores work; the products run in the same K order as without the ring.
+    constexpr int kPF = 4;
+    int d = (kb + lk) / G.U, u = (kb + lk) - ((kb + lk) / G.U) * G.U;   // (d, u) of the next fetch
+    auto fetch = [&](int k, double& a, double* b) {
+        a = 0.0;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) b[nt] = 0.0;
         if (k < ke) {
@@ -249,12 +252,23 @@ __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ ta
                 if (r < G.nX) b[nt] = T[(int64_t)k * G.nX + r];
             }
         }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[nt], acc[nt], 0, 0, 0);
         u += 4;
         while (u >= G.U) {
             u -= G.U;
             ++d;
+        }
+    };
+    double ra[kPF], rb[kPF][NT];
+#pragma unroll
+    for (int p = 0; p < kPF; ++p) fetch(kb + lk + 4 * p, ra[p], rb[p]);
+    for (int k0 = kb; k0 < ke; k0 += 4 * kPF) {
+#pragma unroll
+        for (int p = 0; p < kPF; ++p) {
+            if (k0 + 4 * p < ke)   // uniform over the wave
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[p], rb[p][nt], acc[nt], 0, 0, 0);
+            fetch(k0 + 4 * (p + kPF) + lk, ra[p], rb[p]);
         }
     }
     if (wv > 0)
