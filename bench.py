@@ -549,8 +549,8 @@ def main():
     if args.precision == "fp64":
         mixed_err = None
     other_precision["note"] = ("fp32: M2L with FP32 moments/operator entries and FP32 matrix-core accumulation; "
-                               "bf16: the same with moments, table and operator entries rounded to bfloat16 "
-                               "(exact products, FP32 accumulation); everything else FP64")
+                               "bf16: the same with moments, table and operator entries rounded to bfloat16 and "
+                               "multiplied on the BF16 matrix cores (FP32 accumulation); everything else FP64")
     log(f"[bench] other precisions: {other_precision}")
     tree.set_precision(names[args.precision])
     # the metric's "at 1e-6 rel err": the fastest farfield precision whose

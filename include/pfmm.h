@@ -58,9 +58,11 @@ typedef enum {
                                 intervals; nearfield, S2M, M2M, L2L, L2T, the
                                 locals and the final sum stay FP64           */
     PFMM_MIXED_BF16 = 2      /* as PFMM_MIXED_FP32 with moments, table entries
-                                and operator entries rounded to bfloat16 (the
-                                products are exact in FP32, accumulation FP32):
-                                the error of BF16 matrix-core inputs          */
+                                and operator entries rounded to bfloat16 and
+                                multiplied on the BF16 matrix cores with FP32
+                                accumulation (levels with equal intervals;
+                                levels with unequal ones multiply the same
+                                bfloat16 values on the FP32 matrix cores)    */
 } pfmm_precision;
 
 /* how the nearfield blocks (Section 3.4, eq. eval_sl_nf_block) are applied */

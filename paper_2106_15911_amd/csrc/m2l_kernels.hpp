@@ -314,6 +314,11 @@ __device__ __forceinline__ float bf16_round(float x) {
     return __uint_as_float(u & 0xffff0000u);
 }
 
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+// The bfloat16 bits of an FP32 value that already holds a bfloat16 value.
+__device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_uint(x) >> 16); }
+
 template <class T, int NB, int MAXS, int WAVES, bool RB = false>
 __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
     const T* __restrict__ mu, double* __restrict__ lam, const int* __restrict__ ptr, const int* __restrict__ src,
@@ -477,6 +482,55 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
                     accO[i][nb] = Tr::mfma(A3[i], bv[nb].x, accO[i][nb]);
                 }
         };
+        if constexpr (RB) {
+            // BF16 inputs on the BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k):
+            // four consecutive K-steps s..s+3 per product.  Lane (lr, lq)
+            // supplies in element e the operator entry and the moment of K
+            // index 4 (s + e) + lq, for A and B alike, so the product sums
+            // the same 16 K indices as four 16x16x4 steps.  A slot's entries
+            // past its segment end are zero (the moments there may belong to
+            // another wave's segment).  Slots are sorted by descending end.
+            for (int s = sbeg; s < ks[0]; s += 4) {
+                int4 cq[4];
+                s4_t bx[NB], by[NB];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    pair_t b[NB];
+                    load(b, s + e);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        bx[nb][e] = bf16_bits(b[nb].x);
+                        by[nb][e] = bf16_bits(b[nb].y);
+                    }
+                    cq[e] = sCol[4 * (s + e) + lq];
+                }
+#pragma unroll
+                for (int i = 0; i < MAXS; ++i) {
+                    if (ks[i] <= s) continue;   // uniform over the wave
+                    s4_t a2, a3;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int4 col = cq[e];
+                        const T msk = (col.w <= rD[i] && s + e < ks[i]) ? T(1) : T(0);
+                        const T x2 = *(const T*)(lds + (pX[i] + col.x));
+                        const T y2 = *(const T*)(lds + (pY[i] + col.y));
+                        const T z2 = *(const T*)(lds + (pZ[i] + col.z));
+                        const T x3 = *(const T*)(lds + (pX[i] + d3 + col.x));
+                        const T y3 = *(const T*)(lds + (pY[i] + d3 + col.y));
+                        const T z3 = *(const T*)(lds + (pZ[i] + d3 + col.z));
+                        a2[e] = bf16_bits(bf16_round((x2 * y2) * (z2 * msk)));
+                        a3[e] = bf16_bits(bf16_round((x3 * y3) * (z3 * msk)));
+                    }
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        accE[i][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, bx[nb], accE[i][nb], 0, 0, 0);
+                        accO[i][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, by[nb], accO[i][nb], 0, 0, 0);
+                        accO[i][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, bx[nb], accO[i][nb], 0, 0, 0);
+                    }
+                }
+            }
+            continue;
+        }
         // two operand sets used alternately; the set consumed at step s is
         // refilled with step s + 2 right after its products are issued
         int s = sbeg;
@@ -563,7 +617,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
 // [0] for levels with 32 intervals, [1] with a multiple of 64, [2] of 128
 // [precision: 0 FP64, 1 FP32, 2 BF16 inputs][variant]
 constexpr int kWideNB[3] = {1, 2, 4};
-constexpr int kWideMaxs[3][3] = {{2, 2, 1}, {2, 2, 2}, {2, 2, 2}};
+constexpr int kWideMaxs[3][3] = {{2, 2, 1}, {2, 2, 2}, {2, 2, 1}};
 constexpr int kWideWaves[3][3] = {{16, 16, 16}, {16, 16, 16}, {16, 16, 16}};
 constexpr bool kWideUseNB1 = true;   // levels with 32 intervals: wide form instead of k_m2l_mfma
 
