@@ -38,7 +38,13 @@ FP32_PEAK_TFS = 157.3     # dense FP32 matrix-core peak
 # entry is valid only for the sources it was taken on (sha256 prefixes of the
 # kernel file and of the file that plans and launches it); any change to
 # them reports null.
-TRAFFIC = []
+TRAFFIC = [
+    # profiles/hbm_traffic_v_apply_cube16x1024_m6.md
+    {"kernel": "m2l", "config": 3, "precision": "fp64", "bytes": 220.12e9,
+     "files": {"m2l_kernels.hpp": "b18923fc1afd85b9", "pfmm.hip": "6489596936f2fa33"}},
+    {"kernel": "k_near_apply", "config": 3, "bytes": 107.08e9,
+     "files": {"near_apply.hpp": "16994229533083a9", "pfmm.hip": "6489596936f2fa33"}},
+]
 
 
 def measured_traffic(kernel, cfg, precision="fp64"):
