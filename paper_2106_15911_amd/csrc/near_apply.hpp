@@ -187,90 +187,236 @@ __global__ void __launch_bounds__(256) k_near_toep(const double* __restrict__ ta
 // interval [s0, s0 + s) over all steps, and source triangle u (table column)
 // contributes the steps jt in [s0 + a_u, s0 + b_u) clipped at 0, with
 // (a_u, b_u) depending on the leaf index modulo a period `per` (checked on
-// the host).  With k = d U + u over the time offsets d and the columns u,
-//   f[kt][r] += sum_k A[kt][k] T[k][r],
-//   A[kt][k] = w[kt - d][pos_u] if kt - d lies in that range, else 0,
-//   T[k][r]  = the distinct-integral table T[d][u][r] as stored (row k of
-//              length nX),
-// a dense GEMM: a wave owns 16 target steps and NT 16-column tiles of rows,
-// v_mfma_f64_16x16x4f64 with A[i][k] from lane i + 16 k and B[k][j] from
-// lane j + 16 k; D[i][j] in lane j + 16 (i % 4), register i / 4.
+// the host).  Over the time offsets d and the columns u,
+//   f[kt][r] += sum_{u, d} A[kt][(u, d)] T[d][u][r],
+//   A[kt][(u, d)] = w[kt - d][pos_u] if kt - d lies in u's range, else 0,
+// with T the distinct-integral table as stored (row d U + u of length nX):
+// a dense GEMM with M = 16 target steps, N = the rows (NT 16-column tiles)
+// and K = the (u, d) pairs, on v_mfma_f64_16x16x4f64 (A[i][k] from lane
+// i + 16 k, B[k][j] from lane j + 16 k; D[i][j] in lane j + 16 (i % 4),
+// register i / 4).  A K-step takes four consecutive columns u (one per lane
+// row k) at one offset d, and the offsets of a column quad are consecutive
+// K-steps: the A operand of offset d + 1 is that of offset d moved one target
+// step on, w[kt - d - 1] = w[(kt - 1) - d], i.e. one lane along each 16-lane
+// row.  A DPP row shift does that move; the value entering lane 0 of a row
+// comes from a second register that holds the next 16 such values, so a
+// column quad costs two density gathers per 16 offsets instead of one per
+// offset.  The mask of a lane's own range is applied after the shift.
 struct NearGemmGroup {
     int64_t toff, eoff;       // table offset (doubles), offset into the per-column records [phase][u]
     int s, per, nX, U, K, tb; // interval length, period, rows, columns, K = (dmax + 1) U, first row position
 };
 
-// One workgroup per 16 target steps of a group; its 4 waves take
-// consecutive quarters of the K range and their partial tiles are added
-// through LDS in wave order (fixed order: deterministic results).  The
-// group's per-column records are copied to LDS first when they fit
-// (lds_records: capacity in records, 0 = read them from global memory).
+// Move the two 32-bit halves of a double by the DPP pattern CTRL; lanes
+// whose source lies outside their 16-lane row keep `old`.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double old, double src) {
+    const int2 o = __builtin_bit_cast(int2, old), s = __builtin_bit_cast(int2, src);
+    int2 r;
+    r.x = __builtin_amdgcn_update_dpp(o.x, s.x, CTRL, 0xf, 0xf, false);
+    r.y = __builtin_amdgcn_update_dpp(o.y, s.y, CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, r);
+}
+constexpr int kDppRowShr1 = 0x111;   // lane i of a row takes lane i - 1
+constexpr int kDppRowShl1 = 0x101;   // lane i of a row takes lane i + 1
+constexpr int kXcdsNear = 8;         // accelerator complex dies of an MI355X (one L2 each)
+
+// Per-column source range (a_u, b_u) of one phase as two 16-bit fields.
+__host__ __device__ inline int gemm_pack_range(int a, int b) {
+    return (int)((unsigned)(a + 32768) | ((unsigned)(b + 32768) << 16));
+}
+// Dynamic LDS of k_near_gemm for a group of U columns and period per: the
+// d range of every column quad (int2), the columns' density positions and
+// their packed ranges for every phase.
+inline int gemm_lds_bytes(int U, int per) { return 8 * ((U + 3) / 4) + 4 * U + 4 * per * U; }
+
+// One workgroup per 16 target steps of a group.  The workgroup copies the
+// group's records to LDS and finds, for each column quad, the offsets d at
+// which any of its 16 target steps has a source in range (offsets outside
+// are skipped, not multiplied by zero); then its 4 waves take consecutive
+// quarters of the column quads, run their (quad, offset) K-steps in order,
+// and add their partial tiles through LDS in wave order (fixed order:
+// deterministic results).  Operands are fetched kPF K-steps ahead into a
+// register ring.  Every fetch issues the same buffer loads (table row,
+// density for a quad's first offset, next 16 lane-0 values); a load that a
+// K-step does not need gets an offset past the buffer's end, which returns
+// zero without a memory access, so the number of loads in flight is the same
+// on every path and the waits can count them.
 template <int NT>
 __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ table,
-                                                   const NearGemmGroup* __restrict__ gg, const int4* __restrict__ ue,
+                                                   const NearGemmGroup* __restrict__ gg, const int* __restrict__ ue,
                                                    const double* __restrict__ wd, double* __restrict__ fd, int E_x,
-                                                   int E_t, int lds_records) {
+                                                   int E_t) {
     __shared__ double red[3][NT][4][kWave];
-    extern __shared__ int4 srec[];
-    const NearGemmGroup G = gg[blockIdx.x];
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int li = lane & 15, lk = lane >> 4;
-    const int kt0 = blockIdx.y * 16;
-    const int kt = kt0 + li;
-    const int s0 = (kt / G.s) * G.s;
-    const double* T = table + G.toff;
-    const int nrec = G.per * G.U;
-    const int4* Eg = ue + G.eoff;
-    const bool in_lds = nrec <= lds_records;   // uniform over the workgroup
-    if (in_lds) {
-        for (int i = threadIdx.x; i < nrec; i += blockDim.x) srec[i] = Eg[i];
-        __syncthreads();
+    extern __shared__ int2 rng[];   // [quads], then positions [U], then packed ranges [per][U]
+    // Workgroups are dealt to the 8 XCDs round-robin by linear id; remap so
+    // that XCD x runs all step blocks of group x, then of group x + 8, ...:
+    // a group's table stays in that XCD's L2 while its blocks run, and
+    // neighbouring groups (similar costs) go to different XCDs.
+    int gi, bi;
+    {
+        const int ng = gridDim.x, nb = gridDim.y;
+        const int lin = blockIdx.x + ng * blockIdx.y;
+        const int full = (ng / kXcdsNear) * kXcdsNear * nb;
+        if (lin < full) {
+            const int k = lin / kXcdsNear;
+            gi = (k / nb) * kXcdsNear + lin % kXcdsNear;
+            bi = k % nb;
+        } else {   // the last ng mod 8 groups, in order
+            gi = (ng / kXcdsNear) * kXcdsNear + (lin - full) / nb;
+            bi = (lin - full) % nb;
+        }
     }
-    const int4* E = (in_lds ? srec : Eg) + ((kt / G.s) % G.per) * G.U;   // this target step's phase
+    const NearGemmGroup G = gg[gi];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+    const int li = lane & 15, lk = lane >> 4;
+    const int kt0 = bi * 16;
+    const int kt = kt0 + li;
+    const int U = G.U, nX = G.nX;
+    const int nq = (U + 3) / 4;
+    const int dmax = G.K / U - 1;
+    int* spos = (int*)(rng + nq);
+    int* srec = spos + U;
+    const int* Eg = ue + G.eoff;
+    for (int i = threadIdx.x; i < (1 + G.per) * U; i += blockDim.x) spos[i] = Eg[i];
+    __syncthreads();
+    const int kend = min(kt0 + 16, E_t);
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+        // union over the quad's columns and the block's target steps of the
+        // offsets d with kt - d in range: per leaf interval met by the block,
+        // [first target - last source, last target - first source]
+        int lo = INT32_MAX, hi = -1;
+        for (int u = 4 * q; u < min(4 * q + 4, U); ++u) {
+            for (int k = kt0; k < kend;) {
+                const int lf = k / G.s, s0 = lf * G.s;
+                const int kl = min(kend, s0 + G.s) - 1;
+                const int e = srec[(lf % G.per) * U + u];
+                const int jlo = max(0, s0 + (e & 0xffff) - 32768), jhi = s0 + (int)((unsigned)e >> 16) - 32768;
+                const int dl = max(0, k - jhi + 1), dh = kl - jlo;
+                if (jlo < jhi && dl <= dh) {
+                    lo = min(lo, dl);
+                    hi = max(hi, dh);
+                }
+                k = kl + 1;
+            }
+        }
+        rng[q] = lo <= hi ? int2{lo, hi} : int2{1, 0};
+    }
+    __syncthreads();
+    const int s0k = (kt / G.s) * G.s;
+    const int* rec = srec + ((kt / G.s) % G.per) * U;   // this target step's phase
+    // buffers: the group's table, and the density rows the workgroup can read
+    // (offsets up to dmax + 16 steps back from its first target step)
+    constexpr int kOut = 0x7ffffff8;   // past the end of either buffer: loads return zero
+    const int r0 = max(0, kt0 - 16 - dmax), r1 = kend;
+    const __amdgpu_buffer_rsrc_t rsT = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(table + G.toff), (short)0, G.K * nX * (int)sizeof(double), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsW = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(wd + (int64_t)r0 * E_x), (short)0, (r1 - r0) * E_x * (int)sizeof(double), 0x00020000);
+    auto bload = [](__amdgpu_buffer_rsrc_t rs, int off) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    };
+    const int qpw = (nq + 3) / 4;
+    const int qb = wv * qpw, qe = min(nq, qb + qpw);
+    int nsteps = 0;
+    for (int q = qb; q < qe; ++q) {
+        const int2 r = rng[q];
+        nsteps += max(0, __builtin_amdgcn_readfirstlane(r.y) - __builtin_amdgcn_readfirstlane(r.x) + 1);
+    }
+    // (quad, offset) cursors: the fetch runs kPF K-steps ahead of the products
+    struct Cursor {
+        int q, d, lo, hi;
+    };
+    auto seek = [&](Cursor& c) {   // from quad c.q on, the first quad with offsets
+        for (; c.q < qe; ++c.q) {
+            const int2 r = rng[c.q];
+            c.lo = __builtin_amdgcn_readfirstlane(r.x);
+            c.hi = __builtin_amdgcn_readfirstlane(r.y);
+            if (c.lo <= c.hi) break;
+        }
+        c.d = c.lo;
+    };
+    auto advance = [&](Cursor& c) {
+        if (++c.d > c.hi) {
+            ++c.q;
+            seek(c);
+        }
+    };
+    constexpr int kPF = 4;
+    struct Slot {
+        double a, q, b[NT];   // A at a quad's first offset; the next 16 lane-0 values; table row values
+        int jlo, wid;         // this lane's source range [jlo, jlo + wid) for the quad's column
+    };
+    Slot ring[kPF];
+    Cursor fc{qb, 0, 1, 0}, cc{qb, 0, 1, 0};
+    seek(fc);
+    seek(cc);
+    int pos = 0;   // density position of the fetch cursor's column
+    auto fetch = [&](Slot& S) {
+        const bool live = fc.q < qe;   // uniform; past the wave's last K-step every load returns zero
+        const int u = 4 * fc.q + lk;
+        const bool uv = live && u < U;
+        const int j = fc.d - fc.lo;    // uniform
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int r = nt * 16 + li;
+            S.b[nt] = bload(rsT, (uv && r < nX) ? ((fc.d * U + u) * nX + r) * (int)sizeof(double) : kOut);
+        }
+        if (live && j == 0) {
+            int jl = 0, wdt = 0;
+            pos = 0;
+            if (uv) {
+                pos = spos[u];
+                const int e = rec[u];
+                if (kt < E_t) {
+                    jl = max(0, s0k + (e & 0xffff) - 32768);
+                    wdt = max(0, s0k + (int)((unsigned)e >> 16) - 32768 - jl);
+                }
+            }
+            S.jlo = jl;
+            S.wid = wdt;
+        }
+        const int ja = kt - fc.d, jq = kt0 - fc.d - 1 - li;
+        const bool na = uv && j == 0 && ja >= r0 && ja < r1;
+        const bool nq16 = uv && (j & 15) == 0 && jq >= r0 && jq < r1;
+        S.a = bload(rsW, na ? ((ja - r0) * E_x + pos) * (int)sizeof(double) : kOut);
+        S.q = bload(rsW, nq16 ? ((jq - r0) * E_x + pos) * (int)sizeof(double) : kOut);
+        if (live) advance(fc);
+    };
     d4_t acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = d4_t{0.0, 0.0, 0.0, 0.0};
-    const int kq = ((G.K + 15) / 16) * 4;                 // K values per wave, a multiple of 4
-    const int kb = wv * kq, ke = min(G.K, kb + kq);
-    // Operands are fetched kPF K-steps ahead into a register ring (the
-    // density gather and the table row of a K-step do not depend on the
-    // products), so kPF gathers per lane are in flight while the matrix
-    // cores work; the products run in the same K order as without the ring.
-    constexpr int kPF = 4;
-    int d = (kb + lk) / G.U, u = (kb + lk) - ((kb + lk) / G.U) * G.U;   // (d, u) of the next fetch
-    auto fetch = [&](int k, double& a, double* b) {
-        a = 0.0;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) b[nt] = 0.0;
-        if (k < ke) {
-            const int4 e = E[u];   // (position, a_u, b_u)
-            const int jt = kt - d;
-            if (kt < E_t && jt >= 0 && jt >= s0 + e.y && jt < s0 + e.z) a = wd[(int64_t)jt * E_x + e.x];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int r = nt * 16 + li;
-                if (r < G.nX) b[nt] = T[(int64_t)k * G.nX + r];
-            }
+    double A = 0.0, Q = 0.0;
+    int jlo = 0, wid = 0;
+    auto consume = [&](const Slot& S) {
+        const int j = cc.d - cc.lo;   // uniform
+        if (j == 0) {
+            A = S.a;
+            Q = S.q;
+            jlo = S.jlo;
+            wid = S.wid;
+        } else {
+            A = dpp_move<kDppRowShr1>(Q, A);
+            Q = (j & 15) == 0 ? S.q : dpp_move<kDppRowShl1>(Q, Q);
         }
-        u += 4;
-        while (u >= G.U) {
-            u -= G.U;
-            ++d;
-        }
+        const double am = (unsigned)(kt - cc.d - jlo) < (unsigned)wid ? A : 0.0;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, S.b[nt], acc[nt], 0, 0, 0);
+        advance(cc);
     };
-    double ra[kPF], rb[kPF][NT];
 #pragma unroll
-    for (int p = 0; p < kPF; ++p) fetch(kb + lk + 4 * p, ra[p], rb[p]);
-    for (int k0 = kb; k0 < ke; k0 += 4 * kPF) {
+    for (int p = 0; p < kPF; ++p) fetch(ring[p]);
+    int n0 = 0;
+    for (; n0 + kPF <= nsteps; n0 += kPF) {
 #pragma unroll
         for (int p = 0; p < kPF; ++p) {
-            if (k0 + 4 * p < ke)   // uniform over the wave
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[p], rb[p][nt], acc[nt], 0, 0, 0);
-            fetch(k0 + 4 * (p + kPF) + lk, ra[p], rb[p]);
+            consume(ring[p]);
+            fetch(ring[p]);
         }
     }
+#pragma unroll
+    for (int p = 0; p < kPF; ++p)
+        if (n0 + p < nsteps) consume(ring[p]);   // uniform over the wave
     if (wv > 0)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
@@ -284,6 +430,6 @@ __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ ta
         for (int q = 0; q < 4; ++q) {
             const double v = acc[nt][q] + red[0][nt][q][lane] + red[1][nt][q][lane] + red[2][nt][q][lane];
             const int kk = kt0 + lk + 4 * q, r = nt * 16 + li;
-            if (kk < E_t && r < G.nX) fd[(int64_t)kk * E_x + G.tb + r] += v;
+            if (kk < E_t && r < nX) fd[(int64_t)kk * E_x + G.tb + r] += v;
         }
 }

@@ -1004,9 +1004,9 @@ struct pfmm_tree {
     int64_t* ru_off = nullptr;    // Toeplitz nearfield: per leaf rectangle, offset into ru
     int* ru = nullptr;            // table columns u of the rectangles' source triangles
     NearGemmGroup* ngg = nullptr; // Toeplitz groups applied as GEMMs, sorted by row tiles
-    int4* nue = nullptr;          // their per-column records (position, a_u, b_u, 0)
+    int* nue = nullptr;           // their per-column records: U positions, then per x U packed (a_u, b_u)
     int ngg_start[5] = {0, 0, 0, 0, 0};   // groups with 1..4 row tiles: [ngg_start[t-1], ngg_start[t])
-    int ngg_rec[4] = {0, 0, 0, 0};        // per row-tile class: most per-column records of a group
+    int ngg_lds[4] = {0, 0, 0, 0};        // per row-tile class: most dynamic LDS bytes of a group
     int* nsel = nullptr;          // row groups of the other groups (matrix-vector kernel)
     int64_t n_sel = 0;
     int nf_gemm = 1;              // pfmm_params.nearfield_gemm
@@ -1353,7 +1353,7 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
     for (int i = 0; i < (int)P.leaves.size(); ++i) gl[P.leaves[i].group].push_back(i);
     std::vector<uint8_t> elig(ng, 0);
     std::vector<NearGemmGroup> gg[4];
-    std::vector<std::vector<int4>> ue(4);
+    std::vector<std::vector<int>> ue(4);
     std::vector<int> lo, hi, cov;
     for (int g = 0; g < ng && t->nf_gemm; ++g) {
         const AsmGroup& A = P.groups[g];
@@ -1362,7 +1362,11 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
         std::sort(L.begin(), L.end(), [&](int x, int y) { return P.leaves[x].s0 < P.leaves[y].s0; });
         const int s = P.leaves[L[0]].s1 - P.leaves[L[0]].s0;
         const int nX = A.te - A.tb, U = A.usize;
-        bool ok = s > 0 && (int64_t)L.size() * s == P.E_t && nX >= 1 && nX <= 64 && U >= 1;
+        // limits of k_near_gemm: its LDS copy of the records, 32-bit buffer offsets into the
+        // table and into the density rows one workgroup reads, 16-bit packed step ranges
+        bool ok = s > 0 && s < 32768 && A.dmax < 32768 && (int64_t)L.size() * s == P.E_t && nX >= 1 &&
+                  nX <= 64 && U >= 1 && (int64_t)(A.dmax + 1) * U * nX * 8 < INT32_MAX &&
+                  (int64_t)(A.dmax + 32) * P.E_x * 8 < INT32_MAX;
         for (size_t i = 0; ok && i < L.size(); ++i)
             ok = P.leaves[L[i]].s0 == (int)i * s && P.leaves[L[i]].s1 == (int)(i + 1) * s &&
                  P.leaves[L[i]].tb == A.tb && P.leaves[L[i]].te == A.te;
@@ -1424,21 +1428,22 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
             }
             if (!bad) per_ok = per;
         }
-        if (!per_ok) continue;
+        if (!per_ok || gemm_lds_bytes(U, per_ok) > 40960) continue;   // with 24 KB static: within 64 KB
         elig[g] = 1;
         const int nt = (nX + 15) / 16 - 1;
         gg[nt].push_back(NearGemmGroup{A.toff, (int64_t)ue[nt].size(), s, per_ok, nX, U, (A.dmax + 1) * U, A.tb});
+        for (int u = 0; u < U; ++u) ue[nt].push_back(P.upos[A.uoff + u]);
         for (int ph = 0; ph < per_ok; ++ph)
             for (int u = 0; u < U; ++u)
-                ue[nt].push_back(int4{P.upos[A.uoff + u], ar[(size_t)ph * U + u], br[(size_t)ph * U + u], 0});
+                ue[nt].push_back(gemm_pack_range(ar[(size_t)ph * U + u], br[(size_t)ph * U + u]));
     }
     std::vector<NearGemmGroup> all;
-    std::vector<int4> uall;
+    std::vector<int> uall;
     for (int nt = 0; nt < 4; ++nt) {
         t->ngg_start[nt] = (int)all.size();
         for (NearGemmGroup G : gg[nt]) {
             G.eoff += (int64_t)uall.size();
-            t->ngg_rec[nt] = std::max(t->ngg_rec[nt], G.per * G.U);
+            t->ngg_lds[nt] = std::max(t->ngg_lds[nt], gemm_lds_bytes(G.U, G.per));
             all.push_back(G);
         }
         uall.insert(uall.end(), ue[nt].begin(), ue[nt].end());
@@ -2222,14 +2227,12 @@ pfmm_status apply(pfmm_tree* t, int kind, const double* w, double* f, hipStream_
                 if (g1 <= g0) continue;
                 const dim3 grid((unsigned)(g1 - g0), mt);
                 const NearGemmGroup* gp = t->ngg + g0;
-                // per-column records in LDS while static (partial tiles: 6 KB per row tile) and dynamic
-                // LDS stay within 64 KB; larger groups read them from memory
-                const int lrec = std::min(t->ngg_rec[c], (65536 - 6144 * (c + 1)) / (int)sizeof(int4));
-                const size_t shm = (size_t)lrec * sizeof(int4);
-                if (c == 0) hipLaunchKernelGGL(k_near_gemm<1>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t, lrec);
-                if (c == 1) hipLaunchKernelGGL(k_near_gemm<2>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t, lrec);
-                if (c == 2) hipLaunchKernelGGL(k_near_gemm<3>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t, lrec);
-                if (c == 3) hipLaunchKernelGGL(k_near_gemm<4>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t, lrec);
+                // dynamic LDS: the largest group's quad ranges and records (at most 40 KB)
+                const size_t shm = (size_t)t->ngg_lds[c];
+                if (c == 0) hipLaunchKernelGGL(k_near_gemm<1>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 1) hipLaunchKernelGGL(k_near_gemm<2>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 2) hipLaunchKernelGGL(k_near_gemm<3>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 3) hipLaunchKernelGGL(k_near_gemm<4>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
             }
             if (t->n_sel > 0)
                 hipLaunchKernelGGL(k_near_toep, dim3((unsigned)((t->n_sel + 3) / 4)), dim3(256), 0, sn, tab, t->groups,
