@@ -473,6 +473,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
                     A3[i] = bf16_round(A3[i]);
                 }
             }
+            // raised wave priority while this wave issues its products: the
+            // arbiter then lets it issue them back to back instead of
+            // interleaving other waves' operand generation (about 1% faster)
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int i = 0; i < n; ++i)
 #pragma unroll
@@ -481,6 +485,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_wide(
                     accO[i][nb] = Tr::mfma(A2[i], bv[nb].y, accO[i][nb]);
                     accO[i][nb] = Tr::mfma(A3[i], bv[nb].x, accO[i][nb]);
                 }
+            __builtin_amdgcn_s_setprio(0);
         };
         if constexpr (RB) {
             // BF16 inputs on the BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k):
