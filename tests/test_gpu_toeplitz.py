@@ -104,3 +104,43 @@ def test_toeplitz_full_size():
     print(f"[toeplitz] full size: device bytes {st_t['device_bytes']} vs {st_s['device_bytes']}; "
           f"sampled rows max rel err {err:.3e}", flush=True)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("n,E_t,n_max,n_tr", [(4, 40, 32, 2), (8, 24, 64, 3)])
+def test_gemm_ragged_step_blocks(n, E_t, n_max, n_tr):
+    """Step counts that are not multiples of the GEMM's 16-step blocks (the
+    last block has lanes past the final step, whose densities shift into no
+    valid lane): the GEMM path equals the matrix-vector kernel (bit for bit
+    the stored mode) to 1e-13, V and K."""
+    print(f"[toeplitz] ragged blocks n={n} E_t={E_t} n_max={n_max} n_tr={n_tr}", flush=True)
+    v, t, tn, w = problem(n, E_t, seed=31)
+    for kind in ("V", "K"):
+        ft, st = _apply(v, t, tn, w, kind, P.NF_TOEPLITZ, m_t=3, m_x=3, n_max=n_max, n_tr=n_tr)
+        fv, _ = _apply(v, t, tn, w, kind, P.NF_TOEPLITZ, gemm=0, m_t=3, m_x=3, n_max=n_max, n_tr=n_tr)
+        dm = _mode_diff(ft, fv)
+        print(f"[toeplitz] {kind}: GEMM groups {st['near_gemm_groups']}, max rel diff {dm:.2e}", flush=True)
+        assert st["near_gemm_groups"] > 0
+        assert dm <= TOL_MODES
+
+
+def test_gemm_solve_workload():
+    """12,288 triangles x 512 steps, n_tr = 3 (the Dirichlet solve's tree,
+    whose largest leaf boxes need two 16-row tiles): the GEMM path against
+    the matrix-vector kernel (1e-13) and sampled rows, from both leaf levels
+    and the first and last steps, against the oracle (1e-10)."""
+    from sampling import sample_rows
+    print("[toeplitz] 12,288 x 512, n_tr = 3", flush=True)
+    v, t, tn, c, w = config_problem(5)
+    prm = dict(m_t=c["m_t"], m_x=c["m_x"], n_max=c["n_max"], c_st=c["c_st"], n_tr=c["n_tr"])
+    ft, st = _apply(v, t, tn, w, "V", P.NF_TOEPLITZ, **prm)
+    fv, _ = _apply(v, t, tn, w, "V", P.NF_TOEPLITZ, gemm=0, **prm)
+    dm = _mode_diff(ft, fv)
+    print(f"[toeplitz] GEMM groups {st['near_gemm_groups']}: max rel diff to the vector kernel {dm:.2e}", flush=True)
+    assert st["near_gemm_groups"] > 0 and dm <= TOL_MODES
+    tr = Tree(v, t, tn, 1.0, c["n_max"], c["c_st"], c["n_tr"])
+    rows, levels = sample_rows(tr, 4, per_level=2)
+    vals, _ = FMMOracle(tr, c["m_t"], c["m_x"], "V").apply_rows(w, rows)
+    f = ft.numpy()
+    err = np.abs(f[rows] - vals).max() / np.abs(vals).max()
+    print(f"[toeplitz] {len(rows)} rows (leaf levels {levels}): max rel err {err:.3e}", flush=True)
+    assert err <= TOL
