@@ -196,6 +196,22 @@ struct SepMaps {
     int Nc, Nk, mt, mx;
 };
 
+// Block of a (slot, interval block) grid (S2M, M2M, L2L).  Workgroups are
+// dealt to the 8 XCDs round-robin by linear id; remap so that each XCD runs
+// a contiguous range of slots with the interval blocks of a slot
+// consecutive: the blocks of one slot read and write neighbouring pieces of
+// the slot's [coefficient][interval] rows, which then meet in one L2
+// (measured at 3072 x 1024: S2M 1.30 -> 0.70 ms, M2M 1.98 -> 1.61, L2L
+// 1.69 -> 1.51; L2T, whose blocks are row chunks, 1.34 -> 1.39, kept in
+// grid order).
+__device__ __forceinline__ int2 slot_block() {
+    const int ns = gridDim.x, nb = gridDim.y;
+    const int lin = blockIdx.x + ns * blockIdx.y;
+    const int per = (ns * nb) / 8;
+    const int lm = lin < per * 8 ? (lin % 8) * per + lin / 8 : lin;
+    return int2{lm / nb, lm % nb};
+}
+
 // One 1D re-expansion pass along axis j over a [nt1][Nk][KI] block.
 // Forward (M2M): out[a][p] = sum_{t <= n_j(p)} Q_j[t][n_j(p)] in[a][p with n_j = t].
 // Transposed (L2L): out[a][p] = sum_{t >= n_j(p)} Q_j[n_j(p)][t] in[a][p with n_j = t].
@@ -246,8 +262,9 @@ __global__ void __launch_bounds__(256) k_m2m_sep(const double* __restrict__ mu_c
     double* sq = Acc + blk;            // Q of the current child: 3 x nx1 x nx1
     double* sqt = sq + 3 * nx1 * nx1;  // q_t of the block's child intervals: [2 KI][nt1][nt1]
     const SepMaps& L = m;
-    const int xs = par_xs[blockIdx.x];
-    const int k0 = blockIdx.y * KI;
+    const int2 sb = slot_block();
+    const int xs = par_xs[sb.x];
+    const int k0 = sb.y * KI;
     const int nk = min(KI, n_int_p - k0);
     for (int i = threadIdx.x; i < blk; i += blockDim.x) Acc[i] = 0.0;
     for (int i = threadIdx.x; i < 2 * nk * nt1 * nt1; i += blockDim.x)
@@ -310,8 +327,9 @@ __global__ void __launch_bounds__(256) k_l2l_sep(const double* __restrict__ lam_
     double* sq = U + blk;
     double* sqt = sq + 3 * nx1 * nx1;  // q_t of the block's child intervals: [2 KI][nt1][nt1]
     const SepMaps& L = m;
-    const int xs = blockIdx.x, ps = parent[xs];
-    const int kp0 = blockIdx.y * KI;               // first parent interval
+    const int2 sb = slot_block();
+    const int xs = sb.x, ps = parent[xs];
+    const int kp0 = sb.y * KI;                     // first parent interval
     const int nk = min(KI, n_int_p - kp0);
     for (int i = threadIdx.x; i < 3 * nx1 * nx1; i += blockDim.x) sq[i] = qx[(int64_t)xs * 3 * nx1 * nx1 + i];
     for (int i = threadIdx.x; i < 2 * nk * nt1 * nt1; i += blockDim.x)
@@ -356,8 +374,9 @@ __global__ void __launch_bounds__(256) k_s2m_blk(const double* __restrict__ wd, 
                                                  int E_x, int KI, int stageA) {
     extern __shared__ double sm[];
     const int nt1 = m.mt + 1, Nk = m.Nk, Nc = m.Nc;
-    const int li = blockIdx.x, xs = leaf_xs[li];
-    const int k0 = blockIdx.y * KI, nk = min(KI, n_int - k0);
+    const int2 sb = slot_block();
+    const int li = sb.x, xs = leaf_xs[li];
+    const int k0 = sb.y * KI, nk = min(KI, n_int - k0);
     // leaves of more than 64 triangles (single-step intervals) in row chunks
     // of 64, accumulated by the thread that owns each moment (fixed order)
     for (int r0 = 0; r0 < te[xs] - tb[xs]; r0 += 64) {
