@@ -40,10 +40,10 @@ FP32_PEAK_TFS = 157.3     # dense FP32 matrix-core peak
 # them reports null.
 TRAFFIC = [
     # profiles/hbm_traffic_v_apply_cube16x1024_m6.md
-    {"kernel": "m2l", "config": 3, "precision": "fp64", "bytes": 229.07e9,
-     "files": {"m2l_kernels.hpp": "9e0d70ef54fa5338", "pfmm.hip": "85b8d437778a23e8"}},
+    {"kernel": "m2l", "config": 3, "precision": "fp64", "bytes": 229.09e9,
+     "files": {"m2l_kernels.hpp": "9e0d70ef54fa5338", "pfmm.hip": "b25bda80949c3ff9"}},
     {"kernel": "k_near_apply", "config": 3, "bytes": 107.02e9,
-     "files": {"near_apply.hpp": "191246e98cddb3f5", "pfmm.hip": "85b8d437778a23e8"}},
+     "files": {"near_apply.hpp": "191246e98cddb3f5", "pfmm.hip": "b25bda80949c3ff9"}},
 ]
 
 
