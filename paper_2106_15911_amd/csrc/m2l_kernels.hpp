@@ -696,27 +696,35 @@ __global__ void k_sum_parts(double* __restrict__ lam, const double* __restrict__
 // interval k >= 2 with source k - 2; 3: odd k with source k - 3): its columns
 // are the target intervals of the level, sorted by class on the host
 // (cols[i] = (k, class), padded with k = -1), so that a workgroup's 16 NB
-// columns span few classes.  A workgroup owns one target slot X, one row
-// group and one block of 16 NB columns; it walks X's interaction list one
-// source Y at a time and, per source, the classes of its columns
-// (cbr[cb] = first and last class of the block); the operator tile of
-// (Y, class) is generated from LDS and multiplies the columns of that class
-// (the others are masked to zero).  The results are added to lam, which the
-// caller zeroes before the first of the two launches (each (X, row, k) is
-// owned by one workgroup per launch, so the sum is deterministic).
+// columns span few classes.  A level has few columns per class (one time
+// offset, a few of the 2^l intervals), so the operator tiles are shared
+// across target slots instead: the operator of a pair depends on the source
+// only through its spatial offset Y - X, and neighbouring target slots have
+// nearly the same offsets within the truncation radius.  A workgroup owns a
+// group of KT target slots (consecutive in the slots' Morton order), one row
+// group and one block of 16 NB columns; it walks the union of the group's
+// offsets (merged on the host: per offset, the source slot of each target
+// or -1) and, per offset, the classes of its columns (cbr[cb] = first and
+// last class of the block); the operator tile of (offset, class) is
+// generated from LDS once and multiplies the columns of that class of every
+// target that has a source at that offset.  The results are added to lam,
+// which the caller zeroes before the first of the two launches (each
+// (X, row, k) is owned by one workgroup per launch, and its products are
+// summed in the group's offset order: deterministic).
 // One level of one tree for the class-aware M2L (one time offset D).
 struct ClsUnit {
     const void* mu;          // moments gathered into column order [slot][coef][column]
                              // (FP64, or FP32 / BF16 values)
     double* lam;             // locals of the level (added to)
-    const int* ptr;          // interaction lists: CSR over target slots
-    const int* src;          //   source slot
-    const int* ocls;         //   spatial offset class
+    const int* tgx;          // target slots of each group [group][KT] (-1: none)
+    const int* tgptr;        // merged offsets of each group: CSR over groups
+    const int* tgcls;        //   spatial offset class
+    const int* tgsrc;        //   source slot of each target [entry][KT] (-1: none)
     const int* off3;         // offsets per class
     const void* E1c;         // compact 1D tables of the level [class][offset][x | yz]
     const int2* cols;        // columns (k, class), padded with k = -1
     const int2* cbr;         // first and last class per column block
-    int n_int, R, nx, nccb, D;
+    int n_int, R, ntg, nccb, D;   // ntg: target groups
     int ncp;                 // columns of the gathered moments (16 NB nccb)
     int wg0;                 // first workgroup of this unit in a batched launch
 };
@@ -736,9 +744,9 @@ __global__ void k_gather_cols(const double* __restrict__ mu, T* __restrict__ mup
     else mup[i] = bf16 ? bf16_round((float)v) : (float)v;
 }
 
-template <class T, int NB, int MAXS, int WAVES, bool RB>
+template <class T, int NB, int MAXS, int WAVES, int KT, bool RB>
 __device__ __forceinline__ void m2l_cls_body(
-    double* smem, const ClsUnit& U, int g, int X, int cb, int TSp, const int* __restrict__ packinfo,
+    double* smem, const ClsUnit& U, int g, int tg, int cb, int TSp, const int* __restrict__ packinfo,
     const int* __restrict__ plan, int plan_stride, int Nc, int mt, int mx) {
     static_assert(MAXS >= 1 && MAXS <= 4, "phase dispatch below is written for one to four slots");
     using Tr = M2LTraits<T>;
@@ -746,18 +754,15 @@ __device__ __forceinline__ void m2l_cls_body(
     constexpr int ES = sizeof(T);
     const T* __restrict__ mu = (const T*)U.mu;
     double* __restrict__ lam = U.lam;
-    const int* __restrict__ ptr = U.ptr;
-    const int* __restrict__ src = U.src;
-    const int* __restrict__ ocls = U.ocls;
     const int* __restrict__ off3 = U.off3;
     const T* __restrict__ E1c = (const T*)U.E1c;
     const int2* __restrict__ cols = U.cols;
     const int2* __restrict__ cbr = U.cbr;
-    const int n_int = U.n_int, R = U.R, D = U.D;
+    const int R = U.R;
     const int nt1 = mt + 1, nx1 = mx + 1;
     const int BS = nx1 * (nx1 + 1) / 2;
     const int Nc4 = (Nc + 3) & ~3;
-    // two buffers of the three 1D tables of one (source, class) phase, then
+    // two buffers of the three 1D tables of one (offset, class) phase, then
     // the per-column table offsets and degrees
     int4* sCol = (int4*)((char*)smem + 6 * TSp * ES);
     const int lane = threadIdx.x % kWave;
@@ -786,6 +791,9 @@ __device__ __forceinline__ void m2l_cls_body(
         kcol[nb] = e.x;
         ccol[nb] = __builtin_amdgcn_readfirstlane(e.y);
     }
+    int X[KT];
+#pragma unroll
+    for (int j = 0; j < KT; ++j) X[j] = __builtin_amdgcn_readfirstlane(U.tgx[tg * KT + j]);
     const int2 crange = cbr[cb];
     const int cmin = __builtin_amdgcn_readfirstlane(crange.x);
     const int ncr = __builtin_amdgcn_readfirstlane(crange.y - crange.x + 1);
@@ -806,18 +814,20 @@ __device__ __forceinline__ void m2l_cls_body(
         rZ[i] = ES * (b * BS + ((ri >> 12) & 15) + 2 * TSp);
         rD[i] = mx - (rv ? ((ri >> 16) & 255) : 255);
     }
-    acc_t acc[MAXS][NB];
+    acc_t acc[KT][MAXS][NB];
 #pragma unroll
-    for (int i = 0; i < MAXS; ++i)
+    for (int j = 0; j < KT; ++j)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[i][nb] = acc_t{0, 0, 0, 0};
+        for (int i = 0; i < MAXS; ++i)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[j][i][nb] = acc_t{0, 0, 0, 0};
     const int nR = 2 * R + 1;
-    const int sb = ptr[X], se = ptr[X + 1];
+    const int sb = U.tgptr[tg], se = U.tgptr[tg + 1];
     const int n_phase = (se - sb) * ncr;
     const int pieces = TSp * ES / 1024;
     auto stage = [&](int p) {
         const int si = sb + p / ncr, c = cmin + p % ncr;
-        const int c3 = ocls[si];
+        const int c3 = U.tgcls[si];
         char* dst = (char*)smem + (p & 1) * 3 * TSp * ES;
         for (int q = w; q < 3 * pieces; q += WAVES) {
             const int axis = q / pieces, pc = q - axis * pieces;
@@ -838,15 +848,21 @@ __device__ __forceinline__ void m2l_cls_body(
     for (int nb = 0; nb < NB; ++nb) vb[nb] = ((4 * sbeg + lq) * ncp + (cb * NB + nb) * 16 + lr) * ES;
     const int bstep = 4 * ncp * ES;
     const int slot_bytes = Nc * ncp * ES;
-    (void)n_int;
-    (void)D;
     const char* lds = (const char*)smem;
     if (n_phase > 0) stage(0);
     for (int p = 0; p < n_phase; ++p) {
-        const int Y = src[sb + p / ncr], c = cmin + p % ncr;
+        const int si = sb + p / ncr, c = cmin + p % ncr;
         const int boff = (p & 1) * 3 * TSp * ES;
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc((void*)(mu + (int64_t)Y * Nc * ncp), (short)0, slot_bytes, 0x00020000);
+        // the source slot of each target at this offset (-1: none; its
+        // loads and products are skipped, a wave-uniform branch)
+        int Y[KT];
+        __amdgpu_buffer_rsrc_t rs[KT];
+#pragma unroll
+        for (int j = 0; j < KT; ++j) {
+            Y[j] = __builtin_amdgcn_readfirstlane(U.tgsrc[(int64_t)si * KT + j]);
+            rs[j] = __builtin_amdgcn_make_buffer_rsrc((void*)(mu + (int64_t)(Y[j] >= 0 ? Y[j] : 0) * Nc * ncp),
+                                                      (short)0, slot_bytes, 0x00020000);
+        }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (p + 1 < n_phase) stage(p + 1);
@@ -862,18 +878,20 @@ __device__ __forceinline__ void m2l_cls_body(
             pY[i] = boff + rY[i];
             pZ[i] = boff + rZ[i];
         }
-        auto load = [&](T* bv, int s) {
+        auto load = [&](T (*bv)[NB], int s) {
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int vo = vb[nb] + (s - sbeg) * bstep;
-                if (!on[nb]) bv[nb] = T(0);
-                else if constexpr (ES == 8)
-                    bv[nb] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, 0, 0));
-                else
-                    bv[nb] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, 0, 0));
-            }
+            for (int j = 0; j < KT; ++j)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int vo = vb[nb] + (s - sbeg) * bstep;
+                    if (!on[nb] || Y[j] < 0) bv[j][nb] = T(0);
+                    else if constexpr (ES == 8)
+                        bv[j][nb] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs[j], vo, 0, 0));
+                    else
+                        bv[j][nb] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs[j], vo, 0, 0));
+                }
         };
-        auto step = [&](auto nc, int4 col, const T* bv) {
+        auto step = [&](auto nc, int4 col, T (*bv)[NB]) {
             constexpr int n = decltype(nc)::value;
             T A[n];
 #pragma unroll
@@ -886,14 +904,17 @@ __device__ __forceinline__ void m2l_cls_body(
                 if constexpr (RB) A[i] = bf16_round(A[i]);
             }
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                if (on[nb])
+            for (int j = 0; j < KT; ++j)
+                if (Y[j] >= 0)
 #pragma unroll
-                    for (int i = 0; i < n; ++i) acc[i][nb] = Tr::mfma(A[i], bv[nb], acc[i][nb]);
+                    for (int nb = 0; nb < NB; ++nb)
+                        if (on[nb])
+#pragma unroll
+                            for (int i = 0; i < n; ++i) acc[j][i][nb] = Tr::mfma(A[i], bv[j][nb], acc[j][i][nb]);
         };
         int s = sbeg;
         int4 cA = sCol[4 * s + lq], cB = sCol[4 * s + 4 + lq];
-        T bA[NB], bB[NB];
+        T bA[KT][NB], bB[KT][NB];
         load(bA, s);
         load(bB, s + 1);
         auto phase = [&](auto nc, int s_end) {
@@ -925,42 +946,48 @@ __device__ __forceinline__ void m2l_cls_body(
     const int* ptile = gp + 2 * WAVES + 3 * WAVES * MAXS + 1;
     T* red = (T*)smem;   // [n_partial][4][64]
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        __syncthreads();
+    for (int j = 0; j < KT; ++j)
 #pragma unroll
-        for (int i = 0; i < MAXS; ++i)
-            if (tiles[i] >= 0 && part[i] >= 0)
+        for (int nb = 0; nb < NB; ++nb) {
+            __syncthreads();
 #pragma unroll
-                for (int r = 0; r < 4; ++r) red[((int64_t)part[i] * 4 + r) * kWave + lane] = acc[i][nb][r];
-        __syncthreads();
+            for (int i = 0; i < MAXS; ++i)
+                if (tiles[i] >= 0 && part[i] >= 0)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) red[((int64_t)part[i] * 4 + r) * kWave + lane] = acc[j][i][nb][r];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < MAXS; ++i) {
+                if (tiles[i] < 0 || part[i] >= 0) continue;
+                for (int q = 0; q < n_partial; ++q) {
+                    if (ptile[q] != tiles[i]) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[j][i][nb][r] += red[((int64_t)q * 4 + r) * kWave + lane];
+                }
+            }
+        }
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        if (X[j] < 0) continue;
 #pragma unroll
         for (int i = 0; i < MAXS; ++i) {
             if (tiles[i] < 0 || part[i] >= 0) continue;
-            for (int q = 0; q < n_partial; ++q) {
-                if (ptile[q] != tiles[i]) continue;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[i][nb][r] += red[((int64_t)q * 4 + r) * kWave + lane];
-            }
-        }
-    }
+            for (int nb = 0; nb < NB; ++nb) {
+                if (kcol[nb] < 0) continue;
 #pragma unroll
-    for (int i = 0; i < MAXS; ++i) {
-        if (tiles[i] < 0 || part[i] >= 0) continue;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            if (kcol[nb] < 0) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * tiles[i] + Tr::row(lq, r);
-                if (row >= Nc) continue;
-                double* out = lam + ((int64_t)X * Nc + row) * n_int + kcol[nb];
-                *out += (double)acc[i][nb][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * tiles[i] + Tr::row(lq, r);
+                    if (row >= Nc) continue;
+                    double* out = lam + ((int64_t)X[j] * Nc + row) * U.n_int + kcol[nb];
+                    *out += (double)acc[j][i][nb][r];
+                }
             }
         }
     }
 }
 
-template <class T, int NB, int MAXS, int WAVES, bool RB = false>
+template <class T, int NB, int MAXS, int WAVES, int KT, bool RB = false>
 __global__ void __launch_bounds__(64 * WAVES) k_m2l_cls(ClsUnit U, int TSp, const int* __restrict__ packinfo,
                                                        const int* __restrict__ plan, int plan_stride, int Nc, int mt,
                                                        int mx) {
@@ -971,14 +998,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_cls(ClsUnit U, int TSp, cons
     const int lin = blockIdx.x + ng * (blockIdx.y + nxs * blockIdx.z);
     const int per = total / kXcds;
     const int lm = lin < per * kXcds ? (lin % kXcds) * per + lin / kXcds : lin;
-    m2l_cls_body<T, NB, MAXS, WAVES, RB>(smem, U, lm % ng, (lm / ng) % nxs, lm / (ng * nxs), TSp, packinfo, plan,
-                                         plan_stride, Nc, mt, mx);
+    m2l_cls_body<T, NB, MAXS, WAVES, KT, RB>(smem, U, lm % ng, (lm / ng) % nxs, lm / (ng * nxs), TSp, packinfo,
+                                             plan, plan_stride, Nc, mt, mx);
 }
 
 // The class-aware M2L of many (tree, level) units in one launch (trees of a
 // batch with the same degrees share the row-group plan): a 1D grid over the
 // units' workgroups, each finding its unit by binary search on wg0.
-template <class T, int NB, int MAXS, int WAVES, bool RB = false>
+template <class T, int NB, int MAXS, int WAVES, int KT, bool RB = false>
 __global__ void __launch_bounds__(64 * WAVES) k_m2l_cls_batch(const ClsUnit* __restrict__ units, int n_units, int G,
                                                              int TSp, const int* __restrict__ packinfo,
                                                              const int* __restrict__ plan, int plan_stride, int Nc,
@@ -995,22 +1022,28 @@ __global__ void __launch_bounds__(64 * WAVES) k_m2l_cls_batch(const ClsUnit* __r
     }
     const ClsUnit U = units[lo];
     const int loc = lm - U.wg0;
-    m2l_cls_body<T, NB, MAXS, WAVES, RB>(smem, U, loc % G, (loc / G) % U.nx, loc / (G * U.nx), TSp, packinfo, plan,
-                                         plan_stride, Nc, mt, mx);
+    m2l_cls_body<T, NB, MAXS, WAVES, KT, RB>(smem, U, loc % G, (loc / G) % U.ntg, loc / (G * U.ntg), TSp, packinfo,
+                                             plan, plan_stride, Nc, mt, mx);
 }
 
-// class-aware M2L: two column blocks of 16 per workgroup, two slots per wave, 16 waves
-constexpr int kClsNB = 2, kClsMaxs = 2, kClsWaves = 16;
+// class-aware M2L: one column block of 16 per workgroup, 16 waves, three
+// target slots per workgroup, two slots per wave (per precision: FP64, FP32,
+// BF16 inputs).  Measured on the 12,288 x 479 and 10,800 x 239 trees of the
+// 48-problem batch (M2L stage, FP64): one target, two blocks of 16 columns
+// 229 / 246 ms; two targets 223 / 218 ms; three 215 / 210 ms; four with one
+// slot per wave (two would spill) 271 / 264 ms
+constexpr int kClsNB = 1, kClsWaves = 16, kClsKT = 3;
+constexpr int kClsMaxs[3] = {2, 2, 2};
 
 template <int Q>
 const void* cls_fn() {
-    return (const void*)k_m2l_cls<std::conditional_t<Q == 0, double, float>, kClsNB, kClsMaxs, kClsWaves, Q == 2>;
+    return (const void*)k_m2l_cls<std::conditional_t<Q == 0, double, float>, kClsNB, kClsMaxs[Q], kClsWaves, kClsKT, Q == 2>;
 }
 
 template <int Q>
 const void* cls_batch_fn() {
-    return (const void*)k_m2l_cls_batch<std::conditional_t<Q == 0, double, float>, kClsNB, kClsMaxs, kClsWaves,
-                                        Q == 2>;
+    return (const void*)k_m2l_cls_batch<std::conditional_t<Q == 0, double, float>, kClsNB, kClsMaxs[Q], kClsWaves,
+                                        kClsKT, Q == 2>;
 }
 
 const void* cls_fn(int q) { return q == 0 ? cls_fn<0>() : (q == 1 ? cls_fn<1>() : cls_fn<2>()); }
@@ -1020,7 +1053,7 @@ template <int Q>
 void launch_cls(dim3 grid, size_t shm, hipStream_t st, const ClsUnit& U, int TSp, const int* packinfo, const int* plan,
                 int plan_stride, int Nc, int mt, int mx) {
     using T = std::conditional_t<Q == 0, double, float>;
-    hipLaunchKernelGGL((k_m2l_cls<T, kClsNB, kClsMaxs, kClsWaves, Q == 2>), grid, dim3(64 * kClsWaves), shm, st, U,
+    hipLaunchKernelGGL((k_m2l_cls<T, kClsNB, kClsMaxs[Q], kClsWaves, kClsKT, Q == 2>), grid, dim3(64 * kClsWaves), shm, st, U,
                        TSp, packinfo, plan, plan_stride, Nc, mt, mx);
 }
 
@@ -1028,7 +1061,7 @@ template <int Q>
 void launch_cls_batch(unsigned n_wg, size_t shm, hipStream_t st, const ClsUnit* units, int n_units, int G, int TSp,
                       const int* packinfo, const int* plan, int plan_stride, int Nc, int mt, int mx) {
     using T = std::conditional_t<Q == 0, double, float>;
-    hipLaunchKernelGGL((k_m2l_cls_batch<T, kClsNB, kClsMaxs, kClsWaves, Q == 2>), dim3(n_wg), dim3(64 * kClsWaves),
+    hipLaunchKernelGGL((k_m2l_cls_batch<T, kClsNB, kClsMaxs[Q], kClsWaves, kClsKT, Q == 2>), dim3(n_wg), dim3(64 * kClsWaves),
                        shm, st, units, n_units, G, TSp, packinfo, plan, plan_stride, Nc, mt, mx);
 }
 

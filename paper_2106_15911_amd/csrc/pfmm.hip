@@ -930,6 +930,13 @@ struct DevLevel {
     int* m2l_ptr = nullptr;
     int* m2l_src = nullptr;
     int* m2l_cls = nullptr;
+    // class-aware M2L (levels with unequal intervals): groups of kClsKT
+    // consecutive target slots and the merged offsets of each group
+    int* tg_x = nullptr;          // [group][kClsKT] target slots, -1 padded
+    int* tg_ptr = nullptr;        // CSR over groups
+    int* tg_cls = nullptr;        //   spatial offset class
+    int* tg_src = nullptr;        //   [entry][kClsKT] source slot per target, -1 where absent
+    int ntg = 0;
     double* ops = nullptr;
     double* lam_parts = nullptr;  // extra shares of a split interaction list
     int parts_cap = 1;            // shares lam_parts holds room for (1 + extra buffers)
@@ -1728,7 +1735,7 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
             const int tsp = q == 0 ? t->TSc64 : t->TSc32;
             std::vector<int> tab;
             int maxp = 0;
-            if (!plan_wide(ks, kClsMaxs, kClsWaves, tab, W.G, W.stride, maxp)) continue;
+            if (!plan_wide(ks, kClsMaxs[q], kClsWaves, tab, W.G, W.stride, maxp)) continue;
             W.shm = std::max((size_t)6 * tsp * es + (size_t)(Nc4 + 16) * 4 * sizeof(int), (size_t)maxp * 4 * 64 * es);
             if (W.shm > (size_t)lds_max) continue;
             if (W.shm > 65536) {
@@ -1958,6 +1965,45 @@ pfmm_status setup_device(pfmm_tree* t, hipStream_t st, int ops_mask) {
         PF_TRY(upload(t, &D.m2l_ptr, FL.m2l_ptr.data(), FL.m2l_ptr.size()));
         PF_TRY(upload(t, &D.m2l_src, FL.m2l_src.data(), FL.m2l_src.size()));
         PF_TRY(upload(t, &D.m2l_cls, FL.m2l_cls.data(), FL.m2l_cls.size()));
+        if (!L.uniform) {
+            // target groups of the class-aware M2L: kClsKT consecutive slots
+            // (Morton order: neighbours, with nearly the same offsets within
+            // the truncation radius); per group, the union of the targets'
+            // offset classes in increasing order with each target's source
+            const int KT = kClsKT;
+            const int ng = (L.nx() + KT - 1) / KT;
+            std::vector<int> gx((size_t)ng * KT, -1), gptr(ng + 1, 0), gcls, gsrc;
+            std::map<int, std::array<int, kClsKT>> merged;
+            for (int gi = 0; gi < ng; ++gi) {
+                merged.clear();
+                for (int j = 0; j < KT; ++j) {
+                    const int xs = gi * KT + j;
+                    if (xs >= L.nx()) break;
+                    gx[(size_t)gi * KT + j] = xs;
+                    for (int e = FL.m2l_ptr[xs]; e < FL.m2l_ptr[xs + 1]; ++e) {
+                        auto it = merged.find(FL.m2l_cls[e]);
+                        if (it == merged.end()) {
+                            std::array<int, kClsKT> none;
+                            none.fill(-1);
+                            it = merged.emplace(FL.m2l_cls[e], none).first;
+                        }
+                        it->second[j] = FL.m2l_src[e];
+                    }
+                }
+                for (const auto& kv : merged) {
+                    gcls.push_back(kv.first);
+                    gsrc.insert(gsrc.end(), kv.second.begin(), kv.second.end());
+                }
+                gptr[gi + 1] = (int)gcls.size();
+            }
+            D.ntg = ng;
+            PF_TRY(upload(t, &D.tg_x, gx.data(), gx.size()));
+            PF_TRY(upload(t, &D.tg_ptr, gptr.data(), gptr.size()));
+            if (!gcls.empty()) {
+                PF_TRY(upload(t, &D.tg_cls, gcls.data(), gcls.size()));
+                PF_TRY(upload(t, &D.tg_src, gsrc.data(), gsrc.size()));
+            }
+        }
         // explicit operators: only for the vector-unit M2L used above the matrix-core limits
         if (FL.n_off > 0 && t->mfma_slots == 0) {
             const int64_t total = (int64_t)FL.n_off * 2 * F.op_size;
@@ -2120,9 +2166,10 @@ ClsUnit cls_unit(const pfmm_tree* t, int l, int Dt, int q) {
     U.mu = q ? (const void*)D.mup32[Dt - 2] : (const void*)D.mup[Dt - 2];
     U.ncp = D.ncp[Dt - 2];
     U.lam = D.lam;
-    U.ptr = D.m2l_ptr;
-    U.src = D.m2l_src;
-    U.ocls = D.m2l_cls;
+    U.tgx = D.tg_x;
+    U.tgptr = D.tg_ptr;
+    U.tgcls = D.tg_cls;
+    U.tgsrc = D.tg_src;
     U.off3 = D.off3;
     U.E1c = q == 0 ? (const void*)(t->E1c + row0 * t->TSc64)
                    : (const void*)((q == 2 ? t->E1c16 : t->E1c32) + row0 * t->TSc32);
@@ -2130,7 +2177,7 @@ ClsUnit cls_unit(const pfmm_tree* t, int l, int Dt, int q) {
     U.cbr = D.cbr[Dt - 2];
     U.n_int = D.n_int;
     U.R = D.R;
-    U.nx = D.nx;
+    U.ntg = D.ntg;
     U.nccb = D.nccb[Dt - 2];
     U.D = Dt;
     U.wg0 = 0;
@@ -2153,7 +2200,7 @@ void m2l_level(pfmm_tree* t, int l, hipStream_t st) {
         const auto& W = t->wcls[q];
         for (int Dt = 2; Dt <= 3; ++Dt) {
             if (D.nccb[Dt - 2] == 0) continue;
-            dim3 grid(W.G, D.nx, D.nccb[Dt - 2]);
+            dim3 grid(W.G, D.ntg, D.nccb[Dt - 2]);
             cls_launcher(q)(grid, W.shm, st, cls_unit(t, l, Dt, q), q ? t->TSc32 : t->TSc64, t->packinfo, W.plan,
                             W.stride, P.Nc, P.m_t, P.m_x);
         }
@@ -2636,7 +2683,7 @@ pfmm_status batch_m2l_prepare(BatchM2L* b) {
                     if (!sg.ref) sg.ref = t;
                     ClsUnit U = cls_unit(t, l, D, q);
                     U.wg0 = sg.wg;
-                    sg.wg += t->wcls[q].G * U.nx * U.nccb;
+                    sg.wg += t->wcls[q].G * U.ntg * U.nccb;
                     host.push_back(U);
                     ++sg.n;
                 }
