@@ -183,11 +183,13 @@ __global__ void __launch_bounds__(256) k_near_toep(const double* __restrict__ ta
 }
 
 // Toeplitz nearfield of one assembly group (leaf spatial box, rows r < nX)
-// on the FP64 matrix cores.  The group's leaves are time translates: one per
-// interval [s0, s0 + s) over all steps, and source triangle u (table column)
-// contributes the steps jt in [s0 + a_u, s0 + b_u) clipped at 0, with
+// on the FP64 matrix cores.  The group's leaves cover all steps in order,
+// leaf i the steps [s0_i, s0_{i+1}), and source triangle u (table column)
+// contributes the steps jt in [s0_i + a_u, s0_i + b_u) clipped at 0, with
 // (a_u, b_u) depending on the leaf index modulo a period `per` (checked on
-// the host).  Over the time offsets d and the columns u,
+// the host; per is the number of leaves when every leaf has its own
+// ranges).  Leaves of one length s start at i s; otherwise their starts are
+// read from a list.  Over the time offsets d and the columns u,
 //   f[kt][r] += sum_{u, d} A[kt][(u, d)] T[d][u][r],
 //   A[kt][(u, d)] = w[kt - d][pos_u] if kt - d lies in u's range, else 0,
 // with T the distinct-integral table as stored (row d U + u of length nX):
@@ -204,7 +206,8 @@ __global__ void __launch_bounds__(256) k_near_toep(const double* __restrict__ ta
 // offset.  The mask of a lane's own range is applied after the shift.
 struct NearGemmGroup {
     int64_t toff, eoff;       // table offset (doubles), offset into the per-column records [phase][u]
-    int s, per, nX, U, K, tb; // interval length, period, rows, columns, K = (dmax + 1) U, first row position
+    int64_t stoff;            // offset of the leaf starts (per + 1 of them) in the start list; -1: i s
+    int s, per, nX, U, K, tb; // leaf length (when equal), period, rows, columns, K = (dmax + 1) U, first row position
 };
 
 // Move the two 32-bit halves of a double by the DPP pattern CTRL; lanes
@@ -225,13 +228,13 @@ constexpr int kXcdsNear = 8;         // accelerator complex dies of an MI355X (o
 __host__ __device__ inline int gemm_pack_range(int a, int b) {
     return (int)((unsigned)(a + 32768) | ((unsigned)(b + 32768) << 16));
 }
-// Dynamic LDS of k_near_gemm for a group of U columns and period per: the
-// d range of every column quad (int2), the columns' density positions and
-// their packed ranges for every phase.
-inline int gemm_lds_bytes(int U, int per) { return 8 * ((U + 3) / 4) + 4 * U + 4 * per * U; }
+// Dynamic LDS of k_near_gemm for a group of U columns whose 16-step blocks
+// meet at most nlb leaves: the d range of every column quad (int2), the
+// columns' density positions and their packed ranges for the block's leaves.
+inline int gemm_lds_bytes(int U, int nlb) { return 8 * ((U + 3) / 4) + 4 * U + 4 * nlb * U; }
 
 // One workgroup per 16 target steps of a group.  The workgroup copies the
-// group's records to LDS and finds, for each column quad, the offsets d at
+// records of the leaves its steps meet to LDS and finds, for each column quad, the offsets d at
 // which any of its 16 target steps has a source in range (offsets outside
 // are skipped, not multiplied by zero); then its 4 waves take consecutive
 // quarters of the column quads, run their (quad, offset) K-steps in order,
@@ -245,10 +248,10 @@ inline int gemm_lds_bytes(int U, int per) { return 8 * ((U + 3) / 4) + 4 * U + 4
 template <int NT>
 __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ table,
                                                    const NearGemmGroup* __restrict__ gg, const int* __restrict__ ue,
-                                                   const double* __restrict__ wd, double* __restrict__ fd, int E_x,
-                                                   int E_t) {
+                                                   const int* __restrict__ lst, const double* __restrict__ wd,
+                                                   double* __restrict__ fd, int E_x, int E_t) {
     __shared__ double red[3][NT][4][kWave];
-    extern __shared__ int2 rng[];   // [quads], then positions [U], then packed ranges [per][U]
+    extern __shared__ int2 rng[];   // [quads], then positions [U], then packed ranges [block leaves][U]
     // Workgroups are dealt to the 8 XCDs round-robin by linear id; remap so
     // that XCD x runs all step blocks of group x, then of group x + 8, ...:
     // a group's table stays in that XCD's L2 while its blocks run, and
@@ -275,22 +278,39 @@ __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ ta
     const int U = G.U, nX = G.nX;
     const int nq = (U + 3) / 4;
     const int dmax = G.K / U - 1;
-    int* spos = (int*)(rng + nq);
-    int* srec = spos + U;
-    const int* Eg = ue + G.eoff;
-    for (int i = threadIdx.x; i < (1 + G.per) * U; i += blockDim.x) spos[i] = Eg[i];
-    __syncthreads();
+    const int* ls = G.stoff >= 0 ? lst + G.stoff : nullptr;
+    // leaf of step k (k < E_t) and start of leaf i (i <= number of leaves)
+    auto leaf_of = [&](int k) {
+        if (!ls) return k / G.s;
+        int a = 0, b = G.per - 1;   // per = number of leaves here
+        while (a < b) {
+            const int m = (a + b + 1) / 2;
+            if (ls[m] <= k) a = m; else b = m - 1;
+        }
+        return a;
+    };
+    auto start_of = [&](int i) { return ls ? ls[i] : i * G.s; };
     const int kend = min(kt0 + 16, E_t);
+    const int li0 = leaf_of(kt0), nlb = leaf_of(kend - 1) - li0 + 1;
+    int* spos = (int*)(rng + nq);
+    int* srec = spos + U;   // [leaf - li0][u]
+    const int* Eg = ue + G.eoff;
+    for (int i = threadIdx.x; i < U; i += blockDim.x) spos[i] = Eg[i];
+    for (int i = threadIdx.x; i < nlb * U; i += blockDim.x) {
+        const int r = i / U;
+        srec[i] = Eg[U + ((li0 + r) % G.per) * U + (i - r * U)];
+    }
+    __syncthreads();
     for (int q = threadIdx.x; q < nq; q += blockDim.x) {
         // union over the quad's columns and the block's target steps of the
-        // offsets d with kt - d in range: per leaf interval met by the block,
+        // offsets d with kt - d in range: per leaf met by the block,
         // [first target - last source, last target - first source]
         int lo = INT32_MAX, hi = -1;
         for (int u = 4 * q; u < min(4 * q + 4, U); ++u) {
-            for (int k = kt0; k < kend;) {
-                const int lf = k / G.s, s0 = lf * G.s;
-                const int kl = min(kend, s0 + G.s) - 1;
-                const int e = srec[(lf % G.per) * U + u];
+            for (int k = kt0, lf = li0; k < kend; ++lf) {
+                const int s0 = start_of(lf);
+                const int kl = min(kend, start_of(lf + 1)) - 1;
+                const int e = srec[(lf - li0) * U + u];
                 const int jlo = max(0, s0 + (e & 0xffff) - 32768), jhi = s0 + (int)((unsigned)e >> 16) - 32768;
                 const int dl = max(0, k - jhi + 1), dh = kl - jlo;
                 if (jlo < jhi && dl <= dh) {
@@ -303,8 +323,9 @@ __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ ta
         rng[q] = lo <= hi ? int2{lo, hi} : int2{1, 0};
     }
     __syncthreads();
-    const int s0k = (kt / G.s) * G.s;
-    const int* rec = srec + ((kt / G.s) % G.per) * U;   // this target step's phase
+    const int lfk = leaf_of(min(kt, E_t - 1));        // this target step's leaf (lanes past E_t: masked)
+    const int s0k = start_of(lfk);
+    const int* rec = srec + (lfk - li0) * U;
     // buffers: the group's table, and the density rows the workgroup can read
     // (offsets up to dmax + 16 steps back from its first target step)
     constexpr int kOut = 0x7ffffff8;   // past the end of either buffer: loads return zero

@@ -1031,6 +1031,7 @@ struct pfmm_tree {
     int* ru = nullptr;            // table columns u of the rectangles' source triangles
     NearGemmGroup* ngg = nullptr; // Toeplitz groups applied as GEMMs, sorted by row tiles
     int* nue = nullptr;           // their per-column records: U positions, then per x U packed (a_u, b_u)
+    int* nlst = nullptr;          // leaf starts (and E_t) of the groups whose leaves differ in length
     int ngg_start[5] = {0, 0, 0, 0, 0};   // groups with 1..4 row tiles: [ngg_start[t-1], ngg_start[t])
     int ngg_lds[4] = {0, 0, 0, 0};        // per row-tile class: most dynamic LDS bytes of a group
     int* nsel = nullptr;          // row groups of the other groups (matrix-vector kernel)
@@ -1365,13 +1366,16 @@ bool plan_wide(const std::vector<int>& ks, int maxs, int waves, std::vector<int>
 }
 
 // Toeplitz nearfield groups that can run as GEMMs (k_near_gemm): the group's
-// leaves are one per interval of a fixed length s over all steps, and for
-// every table column u the source steps of a leaf (clipped at the leaf's
-// last step: later ones are causal zeros) form one range [s0 + a_u, s0 + b_u)
-// clipped at step 0, with (a_u, b_u) depending on the leaf only through its
-// index modulo a period of 1, 2, 4 or 8 (neighbouring leaves of a coarser
-// level span 2, 4, ... intervals).  All other groups keep the matrix-vector
-// kernel over their row groups.
+// leaves cover all steps in order (one leaf per time interval of the group's
+// level, of equal or unequal lengths), and for every table column u the
+// source steps of a leaf (clipped at the leaf's last step: later ones are
+// causal zeros) form one range [s0 + a_u, s0 + b_u) clipped at step 0.  With
+// leaves of one length s the ranges usually repeat with the leaf index
+// modulo a period of 1, 2, 4 or 8 (neighbouring leaves of a coarser level
+// span 2, 4, ... intervals) and one record set per phase is kept; otherwise
+// every leaf has its own (and, for unequal lengths, the leaf starts are
+// kept).  All other groups keep the matrix-vector kernel over their row
+// groups.
 pfmm_status plan_near_gemm(pfmm_tree* t) {
     const Plan& P = t->P;
     const int ng = (int)P.groups.size();
@@ -1380,22 +1384,30 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
     std::vector<uint8_t> elig(ng, 0);
     std::vector<NearGemmGroup> gg[4];
     std::vector<std::vector<int>> ue(4);
+    std::vector<int> lstart;                 // leaf starts of the groups with unequal leaves
+    int lds_max[4] = {0, 0, 0, 0};
     std::vector<int> lo, hi, cov;
     for (int g = 0; g < ng && t->nf_gemm; ++g) {
         const AsmGroup& A = P.groups[g];
         std::vector<int>& L = gl[g];
         if (L.empty()) continue;
         std::sort(L.begin(), L.end(), [&](int x, int y) { return P.leaves[x].s0 < P.leaves[y].s0; });
+        const int nl = (int)L.size();
         const int s = P.leaves[L[0]].s1 - P.leaves[L[0]].s0;
         const int nX = A.te - A.tb, U = A.usize;
-        // limits of k_near_gemm: its LDS copy of the records, 32-bit buffer offsets into the
-        // table and into the density rows one workgroup reads, 16-bit packed step ranges
-        bool ok = s > 0 && s < 32768 && A.dmax < 32768 && (int64_t)L.size() * s == P.E_t && nX >= 1 &&
-                  nX <= 64 && U >= 1 && (int64_t)(A.dmax + 1) * U * nX * 8 < INT32_MAX &&
-                  (int64_t)(A.dmax + 32) * P.E_x * 8 < INT32_MAX;
-        for (size_t i = 0; ok && i < L.size(); ++i)
-            ok = P.leaves[L[i]].s0 == (int)i * s && P.leaves[L[i]].s1 == (int)(i + 1) * s &&
-                 P.leaves[L[i]].tb == A.tb && P.leaves[L[i]].te == A.te;
+        // limits of k_near_gemm: 32-bit buffer offsets into the table and into
+        // the density rows one workgroup reads, 16-bit packed step ranges
+        bool ok = s > 0 && A.dmax < 32768 && nX >= 1 && nX <= 64 && U >= 1 &&
+                  (int64_t)(A.dmax + 1) * U * nX * 8 < INT32_MAX && (int64_t)(A.dmax + 32) * P.E_x * 8 < INT32_MAX;
+        bool equal = true;
+        int prev = 0;
+        for (int i = 0; ok && i < nl; ++i) {
+            const LeafRec& R = P.leaves[L[i]];
+            ok = R.s0 == prev && R.s1 > R.s0 && R.s1 - R.s0 < 32768 && R.tb == A.tb && R.te == A.te;
+            equal = equal && R.s1 - R.s0 == s;
+            prev = R.s1;
+        }
+        ok = ok && prev == P.E_t;
         for (int u = 0; ok && u < U; ++u) {
             const int pos = P.upos[A.uoff + u];
             ok = pos >= 0 && pos < P.E_x && P.umap[A.mapoff + pos] == u;
@@ -1423,13 +1435,13 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
         };
         int per_ok = 0;
         std::vector<int> ar, br;
-        for (int per = 1; per <= 8 && !per_ok; per *= 2) {
-            if ((int)L.size() % per) break;
+        for (int per = 1; equal && per <= 8 && !per_ok; per *= 2) {
+            if (nl % per) break;
             ar.assign((size_t)per * U, 0);
             br.assign((size_t)per * U, 0);
             bool bad = false;
             for (int ph = 0; ph < per && !bad; ++ph) {   // reference: the last leaf of each phase
-                const int li = L[L.size() - per + ph];
+                const int li = L[nl - per + ph];
                 if (!ranges(li)) { bad = true; break; }
                 const int s0 = P.leaves[li].s0, s1 = P.leaves[li].s1;
                 for (int u = 0; u < U; ++u) {
@@ -1440,9 +1452,9 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
                     if ((s - 1) - (lo[u] - s0) > A.dmax) bad = true;   // time offsets inside the table
                 }
             }
-            for (size_t i = 0; !bad && i < L.size(); ++i) {
+            for (int i = 0; !bad && i < nl; ++i) {
                 if (!ranges(L[i])) { bad = true; break; }
-                const int ph = (int)(i % per), s0 = P.leaves[L[i]].s0, s1 = P.leaves[L[i]].s1;
+                const int ph = i % per, s0 = P.leaves[L[i]].s0, s1 = P.leaves[L[i]].s1;
                 for (int u = 0; u < U && !bad; ++u) {
                     const int a = ar[(size_t)ph * U + u], b = br[(size_t)ph * U + u];
                     const int elo = std::max(0, s0 + a), ehi = s0 + b;
@@ -1454,10 +1466,47 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
             }
             if (!bad) per_ok = per;
         }
-        if (!per_ok || gemm_lds_bytes(U, per_ok) > 40960) continue;   // with 24 KB static: within 64 KB
+        if (!per_ok) {   // one record set per leaf
+            ar.assign((size_t)nl * U, 0);
+            br.assign((size_t)nl * U, 0);
+            bool bad = false;
+            for (int i = 0; !bad && i < nl; ++i) {
+                if (!ranges(L[i])) { bad = true; break; }
+                const int s0 = P.leaves[L[i]].s0, s1 = P.leaves[L[i]].s1;
+                for (int u = 0; u < U; ++u) {
+                    const int h = cov[u] ? std::min(hi[u], s1) : 0;
+                    if (!cov[u] || lo[u] >= h) continue;
+                    ar[(size_t)i * U + u] = lo[u] - s0;
+                    br[(size_t)i * U + u] = h - s0;
+                    if ((s1 - 1) - lo[u] > A.dmax) bad = true;   // time offsets inside the table
+                }
+            }
+            if (!bad) per_ok = nl;
+        }
+        if (!per_ok) continue;
+        // the most leaves one block of 16 target steps meets: its records are
+        // staged in LDS
+        int nlb = 0;
+        for (int b0 = 0, li = 0; b0 < P.E_t; b0 += 16) {
+            while (P.leaves[L[li]].s1 <= b0) ++li;
+            int lj = li;
+            const int last = std::min(b0 + 16, P.E_t) - 1;
+            while (P.leaves[L[lj]].s1 <= last) ++lj;
+            nlb = std::max(nlb, lj - li + 1);
+        }
+        const int lds = gemm_lds_bytes(U, nlb);
+        if (lds > 40960) continue;   // with 24 KB static: within 64 KB
         elig[g] = 1;
         const int nt = (nX + 15) / 16 - 1;
-        gg[nt].push_back(NearGemmGroup{A.toff, (int64_t)ue[nt].size(), s, per_ok, nX, U, (A.dmax + 1) * U, A.tb});
+        int64_t stoff = -1;
+        if (!equal) {
+            stoff = (int64_t)lstart.size();
+            for (int i = 0; i < nl; ++i) lstart.push_back(P.leaves[L[i]].s0);
+            lstart.push_back(P.E_t);
+        }
+        gg[nt].push_back(NearGemmGroup{A.toff, (int64_t)ue[nt].size(), stoff, s, per_ok, nX, U, (A.dmax + 1) * U,
+                                       A.tb});
+        lds_max[nt] = std::max(lds_max[nt], lds);
         for (int u = 0; u < U; ++u) ue[nt].push_back(P.upos[A.uoff + u]);
         for (int ph = 0; ph < per_ok; ++ph)
             for (int u = 0; u < U; ++u)
@@ -1467,9 +1516,9 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
     std::vector<int> uall;
     for (int nt = 0; nt < 4; ++nt) {
         t->ngg_start[nt] = (int)all.size();
+        t->ngg_lds[nt] = lds_max[nt];
         for (NearGemmGroup G : gg[nt]) {
             G.eoff += (int64_t)uall.size();
-            t->ngg_lds[nt] = std::max(t->ngg_lds[nt], gemm_lds_bytes(G.U, G.per));
             all.push_back(G);
         }
         uall.insert(uall.end(), ue[nt].begin(), ue[nt].end());
@@ -1483,6 +1532,7 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
         PF_TRY(upload(t, &t->ngg, all.data(), all.size()));
         PF_TRY(upload(t, &t->nue, uall.data(), uall.size()));
     }
+    if (!lstart.empty()) PF_TRY(upload(t, &t->nlst, lstart.data(), lstart.size()));
     if (!sel.empty()) PF_TRY(upload(t, &t->nsel, sel.data(), sel.size()));
     return PFMM_OK;
 }
@@ -2295,10 +2345,10 @@ pfmm_status apply(pfmm_tree* t, int kind, const double* w, double* f, hipStream_
                 const NearGemmGroup* gp = t->ngg + g0;
                 // dynamic LDS: the largest group's quad ranges and records (at most 40 KB)
                 const size_t shm = (size_t)t->ngg_lds[c];
-                if (c == 0) hipLaunchKernelGGL(k_near_gemm<1>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
-                if (c == 1) hipLaunchKernelGGL(k_near_gemm<2>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
-                if (c == 2) hipLaunchKernelGGL(k_near_gemm<3>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
-                if (c == 3) hipLaunchKernelGGL(k_near_gemm<4>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 0) hipLaunchKernelGGL(k_near_gemm<1>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->nlst, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 1) hipLaunchKernelGGL(k_near_gemm<2>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->nlst, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 2) hipLaunchKernelGGL(k_near_gemm<3>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->nlst, t->wd, t->fn, P.E_x, P.E_t);
+                if (c == 3) hipLaunchKernelGGL(k_near_gemm<4>, grid, dim3(256), shm, sn, tab, gp, t->nue, t->nlst, t->wd, t->fn, P.E_x, P.E_t);
             }
             if (t->n_sel > 0)
                 hipLaunchKernelGGL(k_near_toep, dim3((unsigned)((t->n_sel + 3) / 4)), dim3(256), 0, sn, tab, t->groups,

@@ -144,3 +144,48 @@ def test_gemm_solve_workload():
     err = np.abs(f[rows] - vals).max() / np.abs(vals).max()
     print(f"[toeplitz] {len(rows)} rows (leaf levels {levels}): max rel err {err:.3e}", flush=True)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("n,E_t,n_max,n_tr", [(4, 23, 16, 2), (4, 45, 32, 3)])
+def test_gemm_unequal_leaves(n, E_t, n_max, n_tr):
+    """Step counts whose time tree has leaves of unequal lengths (the split at
+    the step nearest the midpoint, Algorithm 1): the GEMM path, with per-leaf
+    source ranges and leaf starts, equals the matrix-vector kernel to 1e-13
+    and the dense oracle to 1e-10, V and K."""
+    print(f"[toeplitz] unequal leaves n={n} E_t={E_t} n_max={n_max} n_tr={n_tr}", flush=True)
+    v, t, tn, w = problem(n, E_t, seed=37)
+    prm = dict(m_t=3, m_x=3, n_max=n_max, n_tr=n_tr)
+    for kind in ("V", "K"):
+        ft, st = _apply(v, t, tn, w, kind, P.NF_TOEPLITZ, **prm)
+        fv, _ = _apply(v, t, tn, w, kind, P.NF_TOEPLITZ, gemm=0, **prm)
+        dm = _mode_diff(ft, fv)
+        r = reference(v, t, tn, w, kind, **prm)
+        e = float(np.abs(ft.numpy() - r).max() / np.abs(r).max())
+        print(f"[toeplitz] {kind}: GEMM groups {st['near_gemm_groups']}, diff to vector kernel {dm:.2e}, "
+              f"max rel err vs dense {e:.2e}", flush=True)
+        assert st["near_gemm_groups"] > 0
+        assert dm <= TOL_MODES and e <= TOL
+
+
+def test_gemm_unequal_leaves_larger_tree():
+    """3072 triangles x 479 steps (leaves of 3 and 4 steps, as in the batch's
+    largest drawn problems): GEMM path against the matrix-vector kernel
+    (1e-13) and sampled rows against the oracle (1e-10)."""
+    from sampling import sample_rows
+    from workloads import cube_surface_mesh, densities, uniform_time_nodes
+    print("[toeplitz] 3072 x 479", flush=True)
+    v, t = cube_surface_mesh(16)
+    tn = uniform_time_nodes(479)
+    w = densities(479 * len(t), 11)
+    prm = dict(m_t=4, m_x=4, n_max=64, n_tr=5)
+    ft, st = _apply(v, t, tn, w, "V", P.NF_TOEPLITZ, **prm)
+    fv, _ = _apply(v, t, tn, w, "V", P.NF_TOEPLITZ, gemm=0, **prm)
+    dm = _mode_diff(ft, fv)
+    print(f"[toeplitz] GEMM groups {st['near_gemm_groups']}: max rel diff to the vector kernel {dm:.2e}", flush=True)
+    assert st["near_gemm_groups"] > 0 and dm <= TOL_MODES
+    tr = Tree(v, t, tn, 1.0, prm["n_max"], 0.9, prm["n_tr"])
+    rows, levels = sample_rows(tr, 4, per_level=2)
+    vals, _ = FMMOracle(tr, prm["m_t"], prm["m_x"], "V").apply_rows(w, rows)
+    err = np.abs(ft.numpy()[rows] - vals).max() / np.abs(vals).max()
+    print(f"[toeplitz] {len(rows)} rows (leaf levels {levels}): max rel err {err:.3e}", flush=True)
+    assert err <= TOL
