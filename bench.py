@@ -182,20 +182,6 @@ def cpu_baseline(cfg, w, distinct_integrals, per_level=8, leaves=8, rows=8, seed
             "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(), "blas_threads": int(blas), "runs": runs}
 
 
-def oracle_rows(cfg, w, rows, seed=123):
-    """Sampled rows of the oracle product for an accuracy check of the timed result."""
-    import numpy as np
-    from oracle.fmm import FMMOracle
-    from oracle.tree import Tree
-    from workloads import config_problem
-    v, t, tn, c, _ = config_problem(cfg)
-    tr = Tree(v, t, tn, 1.0, c["n_max"], c["c_st"], c["n_tr"])
-    o = FMMOracle(tr, c["m_t"], c["m_x"], "V")
-    sample = np.random.default_rng(seed).choice(len(w), rows, replace=False)
-    vals, _ = o.apply_rows(w, sample)
-    return sample, vals
-
-
 def _dirichlet_rhs(cfg, P, torch, nf_mode, T=None):
     """Mesh, parameters and b = (1/2 M_h + K_h) g of the Dirichlet problem on
     one cube workload (g: p0 projection of G(x - (2.5,0,0), t + 0.1)), on
@@ -465,7 +451,6 @@ def main():
     ap.add_argument("--no-toeplitz", action="store_true", help="skip the Toeplitz-nearfield measurement")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
-    ap.add_argument("--check-rows", type=int, default=0, help="compare this many sampled rows with the oracle")
     ap.add_argument("--pc-features", type=int, default=8)
     ap.add_argument("--pc-hidden", type=int, default=256)
     ap.add_argument("--pc-steps", type=int, default=1500)
@@ -685,13 +670,6 @@ def main():
                            "traffic": measured_traffic("k_near_apply", args.config)},
              "m2l": {"ms": m2l_ms, "TFLOP/s": m2l_flop / (m2l_ms * 1e-3) / 1e12}}
 
-    check = None
-    if args.check_rows:
-        sample, vals = oracle_rows(args.config, w, args.check_rows)
-        fg = f.cpu().numpy()
-        err = float(np.abs(fg[sample] - vals).max() / np.abs(vals).max())
-        check = {"rows": int(args.check_rows), "max_rel_err_vs_oracle": err}
-        log(f"[bench] oracle rows check: {check}")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.config, w, st["distinct_integrals"])
@@ -726,7 +704,6 @@ def main():
         "build_s": t_build,
         "autotune": tune,
         "tree": st,
-        "oracle_check": check,
         "cpu_baseline": cpu,
     }
     tree.close()
