@@ -228,9 +228,10 @@ constexpr int kXcdsNear = 8;         // accelerator complex dies of an MI355X (o
 __host__ __device__ inline int gemm_pack_range(int a, int b) {
     return (int)((unsigned)(a + 32768) | ((unsigned)(b + 32768) << 16));
 }
-// Dynamic LDS of k_near_gemm for a group of U columns whose 16-step blocks
-// meet at most nlb leaves: the d range of every column quad (int2), the
-// columns' density positions and their packed ranges for the block's leaves.
+// Dynamic LDS of k_near_gemm for a group of U columns that stages nlb record
+// rows (the group's period, or the most leaves one 16-step block meets if
+// fewer): the d range of every column quad (int2), the columns' density
+// positions and their packed ranges.
 inline int gemm_lds_bytes(int U, int nlb) { return 8 * ((U + 3) / 4) + 4 * U + 4 * nlb * U; }
 
 // One workgroup per 16 target steps of a group.  The workgroup copies the
@@ -292,13 +293,18 @@ __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ ta
     auto start_of = [&](int i) { return ls ? ls[i] : i * G.s; };
     const int kend = min(kt0 + 16, E_t);
     const int li0 = leaf_of(kt0), nlb = leaf_of(kend - 1) - li0 + 1;
+    // staged records: one set per phase when the period is no longer than
+    // the run of leaves the block meets, else one per leaf of the run
+    const bool by_phase = G.per <= nlb;   // uniform over the workgroup
+    const int nrow = by_phase ? G.per : nlb;
+    auto row_of = [&](int lf) { return by_phase ? lf % G.per : lf - li0; };
     int* spos = (int*)(rng + nq);
-    int* srec = spos + U;   // [leaf - li0][u]
+    int* srec = spos + U;   // [row][u]
     const int* Eg = ue + G.eoff;
     for (int i = threadIdx.x; i < U; i += blockDim.x) spos[i] = Eg[i];
-    for (int i = threadIdx.x; i < nlb * U; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nrow * U; i += blockDim.x) {
         const int r = i / U;
-        srec[i] = Eg[U + ((li0 + r) % G.per) * U + (i - r * U)];
+        srec[i] = Eg[U + (by_phase ? r : (li0 + r) % G.per) * U + (i - r * U)];
     }
     __syncthreads();
     for (int q = threadIdx.x; q < nq; q += blockDim.x) {
@@ -310,7 +316,7 @@ __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ ta
             for (int k = kt0, lf = li0; k < kend; ++lf) {
                 const int s0 = start_of(lf);
                 const int kl = min(kend, start_of(lf + 1)) - 1;
-                const int e = srec[(lf - li0) * U + u];
+                const int e = srec[row_of(lf) * U + u];
                 const int jlo = max(0, s0 + (e & 0xffff) - 32768), jhi = s0 + (int)((unsigned)e >> 16) - 32768;
                 const int dl = max(0, k - jhi + 1), dh = kl - jlo;
                 if (jlo < jhi && dl <= dh) {
@@ -325,7 +331,7 @@ __global__ void __launch_bounds__(256) k_near_gemm(const double* __restrict__ ta
     __syncthreads();
     const int lfk = leaf_of(min(kt, E_t - 1));        // this target step's leaf (lanes past E_t: masked)
     const int s0k = start_of(lfk);
-    const int* rec = srec + (lfk - li0) * U;
+    const int* rec = srec + row_of(lfk) * U;
     // buffers: the group's table, and the density rows the workgroup can read
     // (offsets up to dmax + 16 steps back from its first target step)
     constexpr int kOut = 0x7ffffff8;   // past the end of either buffer: loads return zero

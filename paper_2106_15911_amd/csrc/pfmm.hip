@@ -1484,8 +1484,8 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
             if (!bad) per_ok = nl;
         }
         if (!per_ok) continue;
-        // the most leaves one block of 16 target steps meets: its records are
-        // staged in LDS
+        // the most leaves one block of 16 target steps meets: a workgroup
+        // stages their records, or one set per phase when the period is shorter
         int nlb = 0;
         for (int b0 = 0, li = 0; b0 < P.E_t; b0 += 16) {
             while (P.leaves[L[li]].s1 <= b0) ++li;
@@ -1494,7 +1494,7 @@ pfmm_status plan_near_gemm(pfmm_tree* t) {
             while (P.leaves[L[lj]].s1 <= last) ++lj;
             nlb = std::max(nlb, lj - li + 1);
         }
-        const int lds = gemm_lds_bytes(U, nlb);
+        const int lds = gemm_lds_bytes(U, std::min(nlb, per_ok));
         if (lds > 40960) continue;   // with 24 KB static: within 64 KB
         elig[g] = 1;
         const int nt = (nX + 15) / 16 - 1;
