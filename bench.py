@@ -40,10 +40,10 @@ FP32_PEAK_TFS = 157.3     # dense FP32 matrix-core peak
 # them reports null.
 TRAFFIC = [
     # profiles/hbm_traffic_v_apply_cube16x1024_m6.md
-    {"kernel": "m2l", "config": 3, "precision": "fp64", "bytes": 229.20e9,
-     "files": {"m2l_kernels.hpp": "7f71f6073bcde959", "pfmm.hip": "c5d4d9b695cf216c"}},
-    {"kernel": "k_near_apply", "config": 3, "bytes": 107.02e9,
-     "files": {"near_apply.hpp": "133c7c49a94fc87b", "pfmm.hip": "c5d4d9b695cf216c"}},
+    {"kernel": "m2l", "config": 3, "precision": "fp64", "bytes": 229.16e9,
+     "files": {"m2l_kernels.hpp": "7f71f6073bcde959", "pfmm.hip": "1c7e4fe0c9b84718"}},
+    {"kernel": "k_near_apply", "config": 3, "bytes": 107.03e9,
+     "files": {"near_apply.hpp": "30a329af442a5db2", "pfmm.hip": "1c7e4fe0c9b84718"}},
 ]
 
 
